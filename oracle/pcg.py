@@ -1,0 +1,269 @@
+"""Preconditioned conjugate-gradient minimisation of the multi-state Tsiper functional,
+FP64 (arXiv:1507.08157, Secs. III.A-III.C).
+
+The paper's own listings (its supplementary algorithms 1 and 2) are not available; the
+steps below follow the equations of the main text, and every choice the text leaves open
+is one of the documented readings:
+
+  * trial vectors P_i = (p_i, q_i) on the pattern M, Tsiper orthonormality
+    B_ij = 1/2 (<p_i, q_j> + <p_j, q_i>) = delta_ij (Eq. ortho), sign rule
+    q_i -> -q_i when <p_i, q_i> < 0 before orthonormalising (Sec. III.C), Gram-Schmidt in
+    index order;
+  * N_ij = 1/2 (<p_j, f^p_i> + <q_j, f^q_i>), symmetrised; omega = eig(N B^-1) (the
+    subspace matrix Q of Sec. III.C);
+  * gradient g_i = F_i - sum_j N_ij (q_j, p_j) (Sec. III.C, multi-state gradient; with
+    B_jj = 1 its coefficient carries the factor 1/2 of the functional);
+  * preconditioner: approximate solve of K^c H^u G - G H^o K^v = g by CG in the S metric to
+    a relative residual eps_tol (Sec. III.B, Eq. precond); none -> G = g;
+  * projection of every new direction by Pi(X) = mask_M(K^c S^u X S^o K^v) (Sec. III.A,
+    Eq. auxiliary: P = K^c S L S K^v with L arbitrary); P itself is never re-projected;
+  * Polak-Ribiere(+) conjugation, common step lambda for all states, exact line search on
+    Tr[N(lambda) B(lambda)^-1] (the sum functional, Eq. Tsiper_multiple, invariant under
+    re-orthonormalisation), F carried by linearity F += lambda F(d) and refreshed every
+    `refresh` iterations;
+  * stop when max |d omega| < tol_omega and max ||g_i|| < sqrt(tol_omega); final omega from
+    the subspace diagonalisation, vectors rotated to its eigenvectors.
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass, field
+
+import numpy as np
+import scipy.optimize
+
+
+@dataclass
+class Options:
+    n_states: int
+    precond: str = "cg"          # "cg" (Eq. precond solved by CG) or "none"
+    eps_tol: float = 1e-4
+    tol_omega: float = 1e-7
+    max_iter: int = 300
+    max_inner: int = 50
+    refresh: int = 10
+    restart: int = 20
+
+
+@dataclass
+class Result:
+    omega: np.ndarray
+    P: np.ndarray                # [2, n, nu, no]: p and q
+    F: np.ndarray
+    iterations: int
+    converged: bool
+    history: list = field(default_factory=list)
+    inner_iters: list = field(default_factory=list)
+
+
+class Solver:
+    def __init__(self, op, opts: Options):
+        self.op = op
+        self.o = opts
+
+    # -- metric helpers -------------------------------------------------------------------
+    def cov(self, X):
+        """S^u X S^o for a stack [k, nu, no] (then <X, Y> = sum X * cov(Y))."""
+        return np.einsum("ij,kjl,lm->kim", self.op.Su, X, self.op.So)
+
+    @staticmethod
+    def gram(X, Yc):
+        """[k1, k2] matrix of sum(X_a * Yc_b)."""
+        return np.einsum("aij,bij->ab", X, Yc)
+
+    # -- operator pieces ------------------------------------------------------------------
+    def apply(self, P):
+        fp, fq = self.op.apply(P[0], P[1])
+        return np.stack([fp, fq])
+
+    def project(self, X):
+        return np.stack([self.op.project(x) for x in X])
+
+    def precondition(self, g):
+        """Columns of g: [k, nu, no].  CG on L(G) = mask_M(K^c H^u G - G H^o K^v) = g,
+        S metric, G0 = 0, stop at ||r|| <= eps_tol ||g||, after max_inner steps, or on
+        non-positive curvature."""
+        if self.o.precond == "none":
+            return g.copy(), 0
+        G = np.zeros_like(g)
+        r = g.copy()
+        d = r.copy()
+        rr = np.einsum("kij,kij->k", r, self.cov(r))
+        rr0 = rr.copy()
+        active = rr0 > 0
+        steps = np.zeros(len(g), dtype=int)
+        it = 0
+        for it in range(self.o.max_inner):
+            active &= rr > (self.o.eps_tol ** 2) * rr0
+            if not np.any(active):
+                break
+            Ld = np.stack([self.op.T(x) for x in d])
+            dLd = np.einsum("kij,kij->k", d, self.cov(Ld))
+            active &= dLd > 0
+            if not np.any(active):
+                break
+            alpha = np.where(active, rr / np.where(active, dLd, 1.0), 0.0)
+            G += alpha[:, None, None] * d
+            r -= alpha[:, None, None] * Ld
+            rr_new = np.einsum("kij,kij->k", r, self.cov(r))
+            beta = np.where(active, rr_new / np.where(rr > 0, rr, 1.0), 0.0)
+            d = np.where(active[:, None, None], r + beta[:, None, None] * d, d)
+            rr = np.where(active, rr_new, rr)
+            steps += active
+        G = np.where((steps > 0)[:, None, None], G, g)
+        return G, int(steps.max()) if len(steps) else 0
+
+    # -- subspace algebra ------------------------------------------------------------------
+    def pq_gram(self, P):
+        """C_ij = <p_i, q_j>."""
+        return self.gram(P[0], self.cov(P[1]))
+
+    def n_matrix(self, P, F):
+        """N_ij = 1/2 (<p_j, f^p_i> + <q_j, f^q_i>), symmetrised."""
+        Nm = 0.5 * (self.gram(F[0], self.cov(P[0])) + self.gram(F[1], self.cov(P[1])))
+        return 0.5 * (Nm + Nm.T)
+
+    @staticmethod
+    def orthonormalise(C):
+        """Transforms (Tp, Tq) with p' = Tp p, q' = Tq q such that
+        1/2 (C'_ij + C'_ji) = delta_ij for C' = Tp C Tq^T.  Sign rule first (q_i -> -q_i
+        when C_ii < 0), then Gram-Schmidt in index order."""
+        n = C.shape[0]
+        Tp = np.eye(n)
+        Tq = np.eye(n)
+        for i in range(n):
+            if C[i, i] < 0:
+                Tq[i] = -Tq[i]
+        for i in range(n):
+            for j in range(i):
+                Cp = Tp @ C @ Tq.T
+                c = 0.5 * (Cp[i, j] + Cp[j, i])
+                Tp[i] -= c * Tp[j]
+                Tq[i] -= c * Tq[j]
+            Cp = Tp @ C @ Tq.T
+            b = Cp[i, i]
+            if not b > 0:
+                raise FloatingPointError("Tsiper metric not positive in Gram-Schmidt")
+            Tp[i] /= np.sqrt(b)
+            Tq[i] /= np.sqrt(b)
+        return Tp, Tq
+
+    @staticmethod
+    def transform(X, Tp, Tq):
+        return np.stack([np.einsum("ij,jkl->ikl", Tp, X[0]),
+                         np.einsum("ij,jkl->ikl", Tq, X[1])])
+
+    def combined_dot(self, X, Y):
+        """sum_i (<x^p_i, y^p_i> + <x^q_i, y^q_i>)."""
+        return float(np.sum(X[0] * self.cov(Y[0])) + np.sum(X[1] * self.cov(Y[1])))
+
+    # -- line search -------------------------------------------------------------------------
+    def line_coeffs(self, P, F, D, FD):
+        def nmat(Xa, Fb):
+            m = 0.5 * (self.gram(Fb[0], self.cov(Xa[0])) + self.gram(Fb[1], self.cov(Xa[1])))
+            return m
+
+        def bmat(Xa, Xb):
+            m = self.gram(Xa[0], self.cov(Xb[1]))      # <xa^p_i, xb^q_j>
+            return m
+
+        N0 = nmat(P, F)
+        N1 = nmat(D, F) + nmat(P, FD)
+        N2 = nmat(D, FD)
+        sym = lambda m: 0.5 * (m + m.T)  # noqa: E731
+        C0 = bmat(P, P)
+        C1 = bmat(P, D) + bmat(D, P)
+        C2 = bmat(D, D)
+        return [sym(N0), sym(N1), sym(N2)], [sym(C0), sym(C1), sym(C2)]
+
+    @staticmethod
+    def phi(lam, Nc, Bc):
+        Nl = Nc[0] + lam * Nc[1] + lam * lam * Nc[2]
+        Bl = Bc[0] + lam * Bc[1] + lam * lam * Bc[2]
+        try:
+            L = np.linalg.cholesky(Bl)
+        except np.linalg.LinAlgError:
+            return np.inf
+        Li = np.linalg.inv(L)
+        return float(np.trace(Li @ Nl @ Li.T))
+
+    def line_search(self, Nc, Bc, scale):
+        """argmin over lambda > 0 of Tr[N(lambda) B(lambda)^-1] inside the region where
+        B(lambda) stays positive definite: coarse log scan, then bounded Brent."""
+        lams = scale * np.geomspace(1e-8, 1e4, 241)
+        vals = np.array([self.phi(l, Nc, Bc) for l in lams])
+        first_bad = np.nonzero(~np.isfinite(vals))[0]
+        end = first_bad[0] if len(first_bad) else len(vals)
+        if end == 0:
+            return 0.0
+        k = int(np.argmin(vals[:end]))
+        lo = lams[k - 1] if k > 0 else 0.0
+        hi = lams[k + 1] if k + 1 < end else lams[k]
+        if hi <= lo:
+            return lams[k]
+        res = scipy.optimize.minimize_scalar(lambda l: self.phi(l, Nc, Bc), bounds=(lo, hi),
+                                             method="bounded",
+                                             options={"xatol": 1e-14 * max(hi, 1e-300)})
+        lam = float(res.x)
+        return lam if self.phi(lam, Nc, Bc) <= vals[k] else float(lams[k])
+
+    # -- driver --------------------------------------------------------------------------------
+    def solve(self, L0: np.ndarray) -> Result:
+        n = self.o.n_states
+        p0 = self.project(np.asarray(L0, dtype=np.float64)[:n])
+        P = np.stack([p0, p0.copy()])
+        Tp, Tq = self.orthonormalise(self.pq_gram(P))
+        P = self.transform(P, Tp, Tq)
+        F = self.apply(P)
+        hist = []
+        inner = []
+        omega_prev = None
+        d_prev = g_prev = G_prev = None
+        converged = False
+        it = 0
+        for it in range(self.o.max_iter + 1):
+            Nm = self.n_matrix(P, F)
+            omega = np.sort(np.linalg.eigvalsh(Nm))
+            g = F - np.stack([np.einsum("ij,jkl->ikl", Nm, P[1]),
+                              np.einsum("ij,jkl->ikl", Nm, P[0])])
+            gnorm = np.sqrt(np.einsum("sikl,sikl->i", g, np.stack([self.cov(g[0]),
+                                                                   self.cov(g[1])])))
+            hist.append(omega.copy())
+            if omega_prev is not None and np.max(np.abs(omega - omega_prev)) < self.o.tol_omega \
+                    and np.max(gnorm) < np.sqrt(self.o.tol_omega):
+                converged = True
+                break
+            if it == self.o.max_iter:
+                break
+            omega_prev = omega
+            G, ninner = self.precondition(g.reshape(2 * n, *g.shape[2:]))
+            inner.append(ninner)
+            G = self.project(G).reshape(g.shape)
+            if d_prev is None or it % self.o.restart == 0:
+                beta = 0.0
+            else:
+                beta = max(0.0, (self.combined_dot(G, g) - self.combined_dot(G, g_prev))
+                           / self.combined_dot(G_prev, g_prev))
+            D = -G + beta * d_prev if beta > 0 else -G
+            if self.combined_dot(D, g) >= 0:
+                D = -G
+            FD = self.apply(D)
+            Nc, Bc = self.line_coeffs(P, F, D, FD)
+            scale = 1.0 / np.sqrt(max(self.combined_dot(D, D), 1e-300))
+            lam = self.line_search(Nc, Bc, scale)
+            P = P + lam * D
+            F = F + lam * FD
+            if (it + 1) % self.o.refresh == 0:
+                F = self.apply(P)
+            Tp, Tq = self.orthonormalise(self.pq_gram(P))
+            P = self.transform(P, Tp, Tq)
+            F = self.transform(F, Tp, Tq)
+            d_prev = self.transform(D, Tp, Tq)
+            g_prev = self.transform(g, Tp, Tq)
+            G_prev = self.transform(G, Tp, Tq)
+        # subspace diagonalisation (B = I after Gram-Schmidt)
+        Nm = self.n_matrix(P, F)
+        w, U = np.linalg.eigh(Nm)
+        P = self.transform(P, U.T, U.T)
+        F = self.transform(F, U.T, U.T)
+        return Result(omega=w, P=P, F=F, iterations=it, converged=converged, history=hist,
+                      inner_iters=inner)

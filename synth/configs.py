@@ -1,0 +1,82 @@
+"""Named workloads.
+
+tiny   : 12 atoms, 20 bohr cube, 64^3, 24 o / 36 u functions, r_c 6, dense kernels,
+         8 occupied / 16 virtual states, 3 excitations (plain FP64 parity case).
+prec   : 200 atoms, 40 bohr, 128^3, 400 o / 600 u, r_c 7, kernels and M truncated at
+         20 bohr, 8 excitations (precision study; the throughput workload).
+batch  : 64 systems of 50..300 atoms (uniform), box scaled to keep the density of `prec`,
+         grid edge a multiple of 16 in [64, 128], r_c 6, R 20, 4 excitations each.
+scale  : 2000 atoms, 80 bohr, 256^3, 4000 o / 6000 u, r_c 6, truncation 15 bohr
+         (~3 % block fill), 4 excitations; 500- and 1000-atom companions at equal density.
+Small test systems (several grid tiles, ragged tile tails, non-power-of-two FFTs) are
+defined here too.
+
+n_occ / n_vir beyond `tiny` follow n_occ = round(2 * atoms / 3), n_vir = 2 n_occ.
+Seeds: base = 1000 * config_index + system_index.
+"""
+from __future__ import annotations
+
+from .system import Config
+
+
+def tiny(seed: int = 0) -> Config:
+    return Config(name="tiny", n_atoms=12, L=20.0, N=64, r_c=6.0, n_occ=8, n_vir=16,
+                  R_K=None, R_M=None, n_states=3, seed=seed)
+
+
+def prec(seed: int = 1000) -> Config:
+    return Config(name="prec", n_atoms=200, L=40.0, N=128, r_c=7.0, n_occ=133, n_vir=266,
+                  R_K=20.0, R_M=20.0, n_states=8, seed=seed)
+
+
+def _occ(n_atoms: int) -> int:
+    return int(round(2 * n_atoms / 3))
+
+
+def batch_member(i: int, n_atoms: int) -> Config:
+    h = 0.3125
+    L = 40.0 * (n_atoms / 200.0) ** (1.0 / 3.0)
+    N = int(min(128, max(64, 16 * round(L / (16 * h)))))
+    L = N * h
+    return Config(name=f"batch{i}", n_atoms=n_atoms, L=L, N=N, r_c=6.0,
+                  n_occ=_occ(n_atoms), n_vir=2 * _occ(n_atoms), R_K=20.0, R_M=20.0,
+                  n_states=4, seed=2000 + i)
+
+
+def batch(n_systems: int = 64):
+    import numpy as np
+    rng = np.random.default_rng(2000)
+    atoms = rng.integers(50, 301, n_systems)
+    return [batch_member(i, int(a)) for i, a in enumerate(atoms)]
+
+
+def scale(n_atoms: int = 2000) -> Config:
+    table = {500: (50.0, 160), 1000: (62.5, 200), 2000: (80.0, 256)}
+    L, N = table[n_atoms]
+    return Config(name=f"scale{n_atoms}", n_atoms=n_atoms, L=L, N=N, r_c=6.0,
+                  n_occ=_occ(n_atoms), n_vir=2 * _occ(n_atoms), R_K=15.0, R_M=15.0,
+                  n_states=4, seed=4000 + n_atoms)
+
+
+# ---- small cases for parity tests ----------------------------------------------------
+
+def small_dense(seed: int = 11) -> Config:
+    """6 atoms in a 14 bohr cube, 40^3 (radix 2 and 5 FFT), dense."""
+    return Config(name="small_dense", n_atoms=6, L=14.0, N=40, r_c=4.5, n_occ=4, n_vir=8,
+                  R_K=None, R_M=None, n_states=3, seed=seed)
+
+
+def small_trunc(seed: int = 12) -> Config:
+    """24 atoms in a 22 bohr cube, 70^3 (radix 2, 5, 7; ragged 4^3 tiles), truncated."""
+    return Config(name="small_trunc", n_atoms=24, L=22.0, N=70, r_c=4.5, n_occ=16,
+                  n_vir=32, R_K=10.0, R_M=9.0, n_states=4, seed=seed)
+
+
+def small_odd(seed: int = 13) -> Config:
+    """8 atoms in a 15 bohr cube, 45^3 (radix 3 and 5, ragged tiles), truncated M only."""
+    return Config(name="small_odd", n_atoms=8, L=15.0, N=45, r_c=4.0, n_occ=5, n_vir=10,
+                  R_K=None, R_M=8.0, n_states=2, seed=seed)
+
+
+BY_NAME = {"tiny": tiny, "prec": prec, "small_dense": small_dense,
+           "small_trunc": small_trunc, "small_odd": small_odd}

@@ -1,0 +1,107 @@
+"""Pins for the oracle PCG eigensolver: brute force, closed forms and invariants."""
+import numpy as np
+import pytest
+
+from oracle.apply import Operator
+from oracle.casida import Casida
+from oracle.pcg import Options, Solver
+
+
+@pytest.fixture(scope="module")
+def dense(small_dense):
+    return small_dense, Operator(small_dense), Casida(small_dense)
+
+
+@pytest.mark.parametrize("precond", ["cg", "none"])
+def test_pcg_matches_brute_force(dense, precond):
+    s, op, cs = dense
+    n = s.cfg.n_states
+    r = Solver(op, Options(n_states=n, precond=precond, tol_omega=1e-10, max_iter=300)).solve(
+        s.guess())
+    assert r.converged
+    assert np.max(np.abs(r.omega - cs.omega_hermitian()[:n])) < 1e-9
+
+
+def test_pcg_closed_form_without_coupling(small_dense):
+    s = small_dense
+    op = Operator(s, xc=False, hartree=False)
+    cs = Casida(s, xc=False, hartree=False)
+    r = Solver(op, Options(n_states=3, tol_omega=1e-11)).solve(s.guess())
+    assert np.max(np.abs(r.omega - np.sort(cs.D)[:3])) < 1e-9
+
+
+def test_pcg_strong_coupling_differs_from_tda(small_dense):
+    s = small_dense
+    op = Operator(s, coupling_scale=25.0)
+    cs = Casida(s, coupling_scale=25.0)
+    n = 3
+    r = Solver(op, Options(n_states=n, tol_omega=1e-10, max_iter=300)).solve(s.guess())
+    wf = cs.omega_hermitian()[:n]
+    assert np.max(np.abs(r.omega - wf)) < 1e-9
+    assert np.max(np.abs(cs.omega_tda()[:n] - wf)) > 1e-3     # the test is not vacuous
+
+
+def test_final_vectors_orthonormal_and_eigen(dense):
+    s, op, cs = dense
+    sol = Solver(op, Options(n_states=3, tol_omega=1e-11))
+    r = sol.solve(s.guess())
+    C = sol.pq_gram(r.P)
+    assert np.max(np.abs(0.5 * (C + C.T) - np.eye(3))) < 1e-10
+    Nm = sol.n_matrix(r.P, r.F)
+    assert np.max(np.abs(Nm - np.diag(r.omega))) < 1e-8
+
+
+def test_gradient_orthogonal_to_all_trial_vectors(dense):
+    """sum_s <P^s_k, g^s_i> = 0 for all i, k (Sec. III.C)."""
+    s, op, cs = dense
+    sol = Solver(op, Options(n_states=3))
+    p = sol.project(s.guess())
+    P = np.stack([p, 0.7 * p + 0.1 * np.roll(p, 1, axis=0)])
+    Tp, Tq = sol.orthonormalise(sol.pq_gram(P))
+    P = sol.transform(P, Tp, Tq)
+    F = sol.apply(P)
+    Nm = sol.n_matrix(P, F)
+    g = F - np.stack([np.einsum("ij,jkl->ikl", Nm, P[1]), np.einsum("ij,jkl->ikl", Nm, P[0])])
+    dots = sol.gram(g[0], sol.cov(P[0])) + sol.gram(g[1], sol.cov(P[1]))
+    assert np.max(np.abs(dots)) < 1e-12 * np.max(np.abs(F))
+
+
+def test_sign_rule_and_gram_schmidt():
+    """A forced negative <p_i, q_i> is flipped, then Eq. ortho holds."""
+    rng = np.random.default_rng(3)
+    A = rng.standard_normal((4, 4))
+    C = A @ A.T + 4 * np.eye(4)
+    C[2, :] *= -1.0                       # q_2 enters with the wrong sign
+    C = C.T.copy()                        # C_ij = <p_i, q_j>: flip column 2 (q_2)
+    assert C[2, 2] < 0
+    Tp, Tq = Solver.orthonormalise(C)
+    Cp = Tp @ C @ Tq.T
+    assert np.max(np.abs(0.5 * (Cp + Cp.T) - np.eye(4))) < 1e-12
+    assert Tq[2, 2] < 0 < Tp[2, 2]
+
+
+def test_preconditioner_tight_is_inverse_ks_difference(dense):
+    """Solving Eq. precond tightly gives G = sum a_c g_cv / (eps_c - eps_v) b_v^T."""
+    s, op, cs = dense
+    rng = np.random.default_rng(5)
+    x = rng.standard_normal((2, len(cs.eps_c), len(cs.eps_v)))
+    g = cs.to_ngwf(x)
+    sol = Solver(op, Options(n_states=2, eps_tol=1e-13, max_inner=200))
+    G, it = sol.precondition(g)
+    ref = cs.to_ngwf(x / cs.D.reshape(x.shape[1:]))
+    assert np.max(np.abs(G - ref)) < 1e-9 * np.max(np.abs(ref))
+    assert it > 1
+
+
+def test_line_search_minimises_trace_functional(dense):
+    s, op, cs = dense
+    sol = Solver(op, Options(n_states=2))
+    rng = np.random.default_rng(6)
+    Nc = [np.diag([0.2, 0.3]), 0.01 * rng.standard_normal((2, 2)), np.diag([0.5, 0.4])]
+    Nc = [0.5 * (m + m.T) for m in Nc]
+    Bc = [np.eye(2), np.zeros((2, 2)), np.eye(2)]
+    Nc[1] = Nc[1] - 0.3 * np.eye(2)
+    lam = sol.line_search(Nc, Bc, 1.0)
+    grid = np.linspace(0, 3, 30001)
+    vals = [sol.phi(x, Nc, Bc) for x in grid]
+    assert abs(sol.phi(lam, Nc, Bc) - min(vals)) < 1e-9
