@@ -1,0 +1,248 @@
+"""Throughput of the full-TDDFT response operator (A-B)P^p, (A+B)P^q on one MI355X.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload prec]
+                    [--precision fp32|fp64|bf16] [--no-solve] [--no-cpu-baseline]
+
+Workload `prec`: 200 atoms in a 40 bohr periodic cube, 128^3 grid, 400 occupied-set and
+600 unoccupied-set functions (radius 7 bohr), density kernels and response pattern
+truncated at 20 bohr, 8 excitations (synthetic, seeded).  One step applies the operator of
+Eq. operator_RPA to all 8 states at once (one tddft_apply call); inputs are resident in HBM
+before timing starts.  value = 8 * K / time (state-applies per second).
+
+The same JSON line carries:
+  * roofline of the dominant kernel, timed with HIP events on its own stream over the
+    timed region, against its algorithmic bytes (or FLOPs) per launch;
+  * time to omega within 1e-5 Ha: a plain FP64 PCG solve converged to 1e-9 Ha is the
+    reference; the time of each precision mode is read from the solver's timestamped log;
+  * the FP64 CPU oracle applied to one state of the same system on the host cores.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+HBM_PEAK_GBS = 8000.0          # MI355X HBM3E
+FP64_VEC_TFLOPS = 78.6         # MI355X vector FP64
+FP32_VEC_TFLOPS = 157.3        # MI355X vector FP32
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def build_workload(name):
+    from synth import build_system, configs
+    return build_system(configs.BY_NAME[name]())
+
+
+def kernel_work(info, stage, n, prec):
+    """Algorithmic bytes and FLOPs of one launch of a stage for n states."""
+    s_bytes = {0: 8, 1: 4, 2: 2}[prec]          # grid sample storage
+    t_bytes = 8 if prec == 0 else 4             # fields / sparse values
+    nt = info["tiles"]
+    E = info["block_rows"] * info["block_cols"]
+    npair = (n + 1) // 2
+    samples = (info["sample_rows_u"] + info["sample_rows_o"]) * 64 * s_bytes
+    field = npair * nt * 64 * 2 * t_bytes          # one complex-pair field set, tile-major
+    grid = npair * int(np.prod(info["n"])) * 2 * t_bytes
+    pp = info["pair_points"]
+    if stage == "density":
+        # samples read once, P on M read once, rho written once; 2 flops per pair-point FMA
+        return samples + info["blocks_m"] * E * n * t_bytes + field, 2.0 * pp * n
+    if stage == "vint":
+        return samples + field + info["blocks_o"] * E * n * t_bytes, 2.0 * pp * n + 64.0 * nt * n
+    if stage in ("fft_x_fwd", "fft_y_fwd", "fft_y_inv"):
+        return 2 * grid, 0.0
+    if stage == "fft_z_poisson":
+        return 2 * grid, 0.0
+    if stage == "fft_x_inv":
+        return grid + 2 * field + nt * 64 * t_bytes, 0.0
+    if stage in ("kshift_left", "kshift_right"):
+        pairs = info["pairs_kshift"] / 2
+        return info["blocks_m"] * E * 2 * n * t_bytes * 2, 2.0 * pairs * 2 * n * 18
+    if stage in ("sandwich_left", "sandwich_right"):
+        return (info["blocks_o"] + info["blocks_m2"] + info["blocks_m"]) * E * n * t_bytes, \
+            2.0 * info["pairs_sandwich"] / 2 * n * 18
+    return 0.0, 0.0
+
+
+def roofline(info, prof, n, prec):
+    """Dominant apply kernel by device time; its achieved rate against the bound that
+    gives the larger fraction of peak."""
+    apply_stages = ["kshift_left", "kshift_right", "density", "fft_x_fwd", "fft_y_fwd",
+                    "fft_z_poisson", "fft_y_inv", "fft_x_inv", "vint", "sandwich_left",
+                    "sandwich_right"]
+    best = max(apply_stages, key=lambda k: prof[k][0])
+    ms, cnt = prof[best]
+    avg_s = ms / max(cnt, 1) / 1e3
+    nbytes, flops = kernel_work(info, best, n, prec)
+    gbs = nbytes / avg_s / 1e9
+    alu_peak = FP64_VEC_TFLOPS if prec == 0 else FP32_VEC_TFLOPS
+    tfl = flops / avg_s / 1e12
+    if flops > 0 and tfl / alu_peak > gbs / HBM_PEAK_GBS:
+        r = {"bound": "alu", "achieved": round(tfl, 3), "peak": alu_peak, "unit": "TFLOP/s",
+             "frac": round(tfl / alu_peak, 4)}
+    else:
+        r = {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+             "frac": round(gbs / HBM_PEAK_GBS, 4)}
+    r.update({"kernel": best, "avg_launch_us": round(avg_s * 1e6, 2),
+              "bytes_per_launch": int(nbytes), "flops_per_launch": float(flops),
+              "traffic": None})
+    return r
+
+
+def time_to_omega(stats, ref, tol=1e-5):
+    lo = stats.get("log_omega")
+    if lo is None or len(lo) == 0:
+        return None
+    for k in range(len(lo)):
+        if np.max(np.abs(lo[k] - ref)) < tol:
+            return float(stats["log_time_ms"][k]) / 1e3
+    return None
+
+
+def cpu_baseline(sysm):
+    """FP64 oracle applied to one state of the workload, on the host cores (one thread)."""
+    try:
+        from threadpoolctl import threadpool_limits
+    except ImportError:  # pragma: no cover
+        threadpool_limits = None
+    from oracle.apply import Operator
+    ctx = threadpool_limits(1) if threadpool_limits else None
+    try:
+        op = Operator(sysm)
+        rng = np.random.default_rng(99)
+        P = rng.standard_normal((1, sysm.vir.n_fn, sysm.occ.n_fn)) * sysm.fn_mask()[None]
+        t0 = time.perf_counter()
+        op.apply(P, P)
+        dt = time.perf_counter() - t0
+    finally:
+        if ctx is not None:
+            ctx.__exit__(None, None, None)
+    return {"value": round(1.0 / dt, 5), "unit": "state-applies/s", "cores": 1,
+            "kind": "oracle",
+            "sample": f"one state of the {sysm.cfg.name} workload ({dt:.1f} s; host has "
+                      f"{os.cpu_count()} logical CPUs, BLAS limited to 1 thread)"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="prec")
+    ap.add_argument("--precision", default="fp32", choices=["fp64", "fp32", "bf16"])
+    ap.add_argument("--no-solve", action="store_true")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    a = ap.parse_args()
+    if a.gpus != 1:
+        print("bench.py measures one GPU: this build has no multi-GPU path (the sharding "
+              "design is described in DESIGN.md); run with --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_1507_08157_amd import binding
+    from synth import abi as sabi
+
+    t0 = time.perf_counter()
+    sysm = build_workload(a.workload)
+    arrays = sabi.system_arrays(sysm)
+    log(f"workload {a.workload}: generated in {time.perf_counter() - t0:.1f} s")
+    n = sysm.cfg.n_states
+    prec = binding.PRECISION[a.precision]
+    h = binding.tddft_create(arrays, precision=a.precision)
+    info = h.tddft_get_info()
+    log(f"handle ({a.precision}) setup {info['setup_ms']:.0f} ms; {info}")
+
+    rng = np.random.default_rng(2024)
+    X = rng.standard_normal((2, n, sysm.vir.n_fn, sysm.occ.n_fn)) * sysm.fn_mask()[None, None]
+    Pp = torch.from_numpy(sabi.dense_to_m(sysm, X[0])).cuda()
+    Pq = torch.from_numpy(sabi.dense_to_m(sysm, X[1])).cuda()
+    fp = torch.empty_like(Pp)
+    fq = torch.empty_like(Pq)
+    for _ in range(a.warmup):
+        h.tddft_apply(Pp, Pq, fp, fq)
+    torch.cuda.synchronize()
+    h.tddft_profile(True)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    for _ in range(a.steps):
+        h.tddft_apply(Pp, Pq, fp, fq)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t1
+    prof = h.tddft_profile_read()
+    h.tddft_profile(False)
+    value = n * a.steps / dt
+    log(f"{a.steps} applies x {n} states in {dt * 1e3:.1f} ms -> {value:.1f} state-applies/s")
+    log("stages (ms per launch): " + ", ".join(
+        f"{k}={v[0] / max(v[1], 1):.3f}" for k, v in prof.items() if v[1]))
+    roof = roofline(info, prof, n, prec)
+
+    out = {
+        "metric": "(A±B)P1 applies/sec + time to omega within 1e-5 Ha, learned/mixed "
+                  "vs plain PCG",
+        "value": round(value, 2),
+        "unit": "state-applies/s",
+        "n_gpus": 1,
+        "steps": a.steps,
+        "warmup": a.warmup,
+        "ms_per_step": round(dt * 1e3 / a.steps, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": {"fp64": "f64", "fp32": "f32", "bf16": "bf16 samples, f32 accumulation"}[a.precision],
+        "data": "synthetic",
+        "config": {"workload": a.workload, "atoms": sysm.cfg.n_atoms, "grid": sysm.cfg.N,
+                   "cell_bohr": sysm.cfg.L, "n_o": sysm.occ.n_fn, "n_u": sysm.vir.n_fn,
+                   "states": n, "truncation_bohr": sysm.cfg.R_M,
+                   "m_fill": round(float(sysm.M.mean()), 4), "precision": a.precision},
+        "roofline": roof,
+        "stage_ms_per_launch": {k: round(v[0] / v[1], 4) for k, v in prof.items() if v[1]},
+    }
+
+    if not a.no_solve:
+        # reference: plain FP64 PCG converged to 1e-9 Ha
+        h64 = h if a.precision == "fp64" else binding.tddft_create(arrays, precision="fp64")
+        L0 = torch.from_numpy(sabi.dense_to_m(sysm, sysm.guess(n))).cuda()
+        o = binding.tddft_default_options(precision="fp64", tol_omega=1e-9, max_iter=400)
+        P1, P2 = L0.clone(), L0.clone()
+        torch.cuda.synchronize()
+        w64, rc64, st64 = h64.tddft_pcg_solve(n, o, P1, P2, log_capacity=2000)
+        log(f"fp64 PCG: rc={rc64} iters={st64['iterations']} {st64['solve_ms']:.0f} ms "
+            f"omega={np.array2string(w64, precision=8)}")
+        solves = {"fp64": {"iterations": st64["iterations"], "solve_s": st64["solve_ms"] / 1e3,
+                           "time_to_1e-5_s": time_to_omega(st64, w64),
+                           "converged": st64["converged"]}}
+        for mode in [m for m in ("fp32", "bf16") if m != "fp64"]:
+            hm = h if mode == a.precision else binding.tddft_create(arrays, precision=mode)
+            o = binding.tddft_default_options(precision=mode, tol_omega=1e-8, max_iter=300)
+            P1, P2 = L0.clone(), L0.clone()
+            w, rc, st = hm.tddft_pcg_solve(n, o, P1, P2, log_capacity=2000)
+            err = float(np.max(np.abs(w - w64)))
+            solves[mode] = {"iterations": st["iterations"], "solve_s": st["solve_ms"] / 1e3,
+                            "time_to_1e-5_s": time_to_omega(st, w64),
+                            "omega_err_vs_fp64_Ha": err}
+            log(f"{mode} PCG: rc={rc} iters={st['iterations']} {st['solve_ms']:.0f} ms "
+                f"err={err:.2e}")
+            if hm is not h:
+                hm.close()
+        out["time_to_omega"] = solves
+        out["omega_fp64"] = [float(x) for x in w64]
+        if h64 is not h:
+            h64.close()
+
+    if not a.no_cpu_baseline:
+        log("cpu baseline (oracle, one state) ...")
+        out["cpu_baseline"] = cpu_baseline(sysm)
+        log(f"cpu baseline: {out['cpu_baseline']}")
+    h.close()
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,219 @@
+/*
+ * libtddft — full (non-Tamm-Dancoff) linear-response TDDFT in two localised function
+ * sets, on one MI355X (gfx950).
+ *
+ * Method: T. J. Zuehlsdorff, N. D. M. Hine, M. C. Payne, P. D. Haynes,
+ * "Linear-scaling time-dependent density-functional theory beyond the Tamm-Dancoff
+ * approximation ..." (arXiv:1507.08157).
+ *
+ * Notation.  The o-set {o_b} spans the occupied space (the paper's phi_beta), the
+ * u-set {u_a} the low unoccupied space (the paper's chi_alpha).  Response kernels P^p,
+ * P^q have u-set rows and o-set columns (Sec. III.A).  K^v, K^c are the valence and
+ * conduction density kernels (Sec. II.C), S and H the overlap and Hamiltonian matrices
+ * of each set.  All matrices are contravariant; the metric is Tr[X^T S^u Y S^o].
+ *
+ * Conventions of this interface
+ *   - Every call returns an int status (TDDFT_OK = 0, negative = error, positive =
+ *     informational warning).  No call aborts or exits the process.
+ *   - Host arrays passed to tddft_create are read during the call only; the caller keeps
+ *     ownership and may free them on return.
+ *   - Device arrays passed to tddft_apply / tddft_pcg_solve are caller-owned device
+ *     memory of the GPU that was current at tddft_create; they must not alias each
+ *     other.  Work is issued on the options' stream (NULL = the default stream) and the
+ *     calls return after it completes.
+ *   - A handle is not thread-safe: use one handle per host thread.
+ *   - Grid arrays index points as x + nx * (y + ny * z).
+ */
+#ifndef TDDFT_H
+#define TDDFT_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define TDDFT_ABI_VERSION 1
+
+/* ---- status codes ------------------------------------------------------------------ */
+#define TDDFT_OK                 0
+#define TDDFT_E_INVALID         -1  /* bad shapes, patterns, NaN/Inf, asymmetric S or H  */
+#define TDDFT_E_NOMEM           -2  /* device or host allocation failed                  */
+#define TDDFT_E_DEVICE          -3  /* HIP runtime error; text in tddft_last_error       */
+#define TDDFT_E_NOT_PD          -4  /* Tsiper numerator/denominator not positive, or a
+                                       non-positive Kohn-Sham gap detected              */
+#define TDDFT_E_NO_CONVERGENCE  -5  /* outputs hold the last (best) iterate              */
+#define TDDFT_W_FALLBACK         1  /* learned preconditioner rejected at least once     */
+
+/* ---- precision modes --------------------------------------------------------------- */
+#define TDDFT_FP64       0  /* everything FP64                                            */
+#define TDDFT_FP32       1  /* grid samples, fields, sparse products FP32; traces FP64    */
+#define TDDFT_BF16_GRID  2  /* grid samples BF16 (FP32 accumulation), rest as TDDFT_FP32  */
+
+/* ---- coupling kernel ------------------------------------------------------------------ */
+#define TDDFT_XC_ALDA_X  0  /* Hartree + adiabatic LDA exchange kernel (Sec. II.A)        */
+#define TDDFT_XC_NONE    1  /* Hartree only                                                */
+#define TDDFT_HXC_NONE   2  /* no coupling (A = B + D, B = 0): test closed form            */
+
+/* ---- preconditioners (Sec. III.B) ------------------------------------------------------ */
+#define TDDFT_PC_NONE       0
+#define TDDFT_PC_KSDIFF_CG  1  /* solve Eq. precond by CG to relative tolerance eps_tol    */
+#define TDDFT_PC_LEARNED    2  /* learned block correction, KSDIFF_CG as fallback          */
+
+/* Block-sparse matrix in BSR form with variable block sizes.  Blocks are dense and
+ * row-major; their values are concatenated in (block row, colind) order.  rowptr and
+ * colind describe the block pattern; colind is sorted within each block row.  For a
+ * pattern-only matrix (M) val is NULL. */
+typedef struct {
+  int32_t nbr, nbc;          /* number of block rows / block columns (atoms)            */
+  const int32_t *row_off;    /* [nbr+1] first function of each block row               */
+  const int32_t *col_off;    /* [nbc+1] first function of each block column            */
+  const int64_t *rowptr;     /* [nbr+1] offsets into colind                            */
+  const int32_t *colind;     /* [nnzb]                                                 */
+  const double  *val;        /* [sum of block sizes] or NULL                           */
+} tddft_bsr;
+
+/* Grid-sampled localised functions.  Function f is given on a box of grid points with
+ * corner origin[3f..3f+2] = (x, y, z) and dimensions extent[3f..3f+2]; the box wraps
+ * periodically and must not exceed the cell.  val[off[f] .. off[f+1]) holds its values,
+ * x fastest; values outside the function's support are zero.  Function f belongs to the
+ * block (atom) whose row_off range contains f in the matrices of its set. */
+typedef struct {
+  int32_t n_fn;
+  const int32_t *origin;     /* [3 * n_fn]                                             */
+  const int32_t *extent;     /* [3 * n_fn]                                             */
+  const int64_t *off;        /* [n_fn + 1]                                             */
+  const double  *val;
+} tddft_functions;
+
+/* One system: a periodic orthorhombic cell with n[d] points along side L[d] (bohr). */
+typedef struct {
+  int32_t n[3];
+  double  L[3];
+  tddft_functions occ;       /* o-set                                                  */
+  tddft_functions vir;       /* u-set                                                  */
+  tddft_bsr S_o, H_o, K_v;   /* n_o x n_o, symmetric; same block structure             */
+  tddft_bsr S_u, H_u, K_c;   /* n_u x n_u, symmetric; same block structure             */
+  tddft_bsr M;               /* pattern of P^p, P^q, f_p, f_q: u-blocks x o-blocks     */
+} tddft_system;
+
+typedef struct {
+  int32_t  precision;        /* TDDFT_FP64 | TDDFT_FP32 | TDDFT_BF16_GRID               */
+  int32_t  xc;               /* TDDFT_XC_ALDA_X | TDDFT_XC_NONE | TDDFT_HXC_NONE        */
+  double   rho_floor;        /* f_xc = 0 where rho0 < rho_floor (bohr^-3)               */
+  double   coupling_scale;   /* K -> s K (test knob; 1 = the method)                    */
+  int32_t  precond;          /* TDDFT_PC_*                                              */
+  double   eps_tol;          /* inner CG relative tolerance (Sec. III.B)                */
+  double   tol_omega;        /* Ha: stop when max |d omega| < tol and max |g| < sqrt(tol) */
+  int32_t  max_iter;         /* outer iterations                                        */
+  int32_t  max_inner;        /* inner CG iterations                                     */
+  int32_t  refresh;          /* recompute F = apply(P) every `refresh` iterations       */
+  int32_t  restart;          /* steepest-descent restart period                         */
+  uint64_t seed;             /* initial guess when none is given                        */
+  const void *model;         /* learned-preconditioner weights blob, or NULL           */
+  int64_t  model_bytes;
+  void    *stream;           /* hipStream_t, or NULL for the default stream             */
+} tddft_options;
+
+/* Per-solve statistics (host memory, caller-owned).  The log arrays are optional. */
+typedef struct {
+  int32_t iterations;        /* outer iterations done                                   */
+  int32_t converged;
+  int32_t inner_total;       /* inner CG iterations summed over all columns' maxima     */
+  int32_t applies;           /* operator applications (each one for all states)         */
+  int32_t fallbacks;         /* learned-preconditioner rejections                       */
+  double  setup_ms;          /* tddft_create wall time                                  */
+  double  solve_ms;          /* tddft_pcg_solve wall time                               */
+  double  apply_ms;          /* summed device time of operator applications             */
+  int32_t log_capacity;      /* entries the caller provided (0 = no log)                */
+  int32_t log_len;           /* entries written                                         */
+  double *log_omega;         /* [log_capacity * n_states] ascending omega per iteration */
+  double *log_time_ms;       /* [log_capacity] wall time since solve entry              */
+  double *log_gnorm;         /* [log_capacity] max_i ||g_i||_S                          */
+} tddft_stats;
+
+/* Sizes of the structures a handle built (for work and traffic accounting). */
+typedef struct {
+  int32_t n[3];              /* grid                                                    */
+  int32_t tiles;             /* 4x4x4 grid tiles                                        */
+  int32_t block_rows, block_cols;   /* padded block shape of response kernels (BU x BO)  */
+  int32_t brick_edge;        /* tiles per brick edge in the potential-integral kernel   */
+  int32_t precision;
+  int64_t sample_rows_u;     /* tile sample rows (64 points each) of the u-set          */
+  int64_t sample_rows_o;     /* ... of the o-set                                        */
+  int64_t pair_points;       /* sum over tiles of (u rows x o rows x 64)                */
+  int64_t blocks_m;          /* blocks of M                                              */
+  int64_t blocks_o;          /* blocks of the overlap pattern of the potential integrals */
+  int64_t blocks_m2, blocks_m3, blocks_m4;  /* intermediate patterns of the sandwiches  */
+  int64_t pairs_kshift;      /* block products of one K^c H^u X plus X H^o K^v (per column) */
+  int64_t pairs_project;     /* ... of the projection                                   */
+  int64_t pairs_covariant;   /* ... of S^u X S^o                                        */
+  int64_t pairs_sandwich;    /* ... of K^c V K^v                                        */
+  double  setup_ms;
+} tddft_info;
+
+typedef struct tddft_handle tddft_handle;
+
+/* Defaults: FP64, ALDA exchange, rho_floor 1e-10, coupling 1, KSDIFF_CG, eps_tol 1e-4,
+ * tol_omega 1e-7, max_iter 300, max_inner 50, refresh 10, restart 20, seed 0. */
+void tddft_default_options(tddft_options *opts);
+
+/* Build a handle for one system (Sec. III.A: sparse K^v, K^c, S and H, the cutoff
+ * pattern M and grid-sampled functions).  Validates the input (TDDFT_E_INVALID on bad
+ * shapes, unsorted or out-of-range patterns, NaN/Inf, asymmetric S/H, functions whose
+ * boxes exceed the cell), uploads it to the current GPU, builds the grid tiles and the
+ * sparse-product plans, and computes rho0 = 2 sum o_b K^v_bb' o_b' and the ALDA kernel
+ * f_xc(r) (Sec. II.A) once.  opts->precision fixes the storage precision of the grid
+ * samples for the handle's lifetime.  On success *out owns all device state. */
+int tddft_create(const tddft_system *sys, const tddft_options *opts, tddft_handle **out);
+
+int tddft_get_info(const tddft_handle *h, tddft_info *out);
+
+/* Number of values of one response kernel on M (sum of M's block sizes). */
+int64_t tddft_nnz_m(const tddft_handle *h);
+
+/* The operator of Eq. operator_RPA for n_states states at once:
+ *   f_p = mask_M(K^c H^u P^p - P^p H^o K^v)
+ *   f_q = mask_M(K^c H^u P^q - P^q H^o K^v + 2 s K^c V_SCF[P^q] K^v)
+ * with V_SCF[P]_ab = h^3 sum_r u_a (V_H[rho] + f_xc rho) o_b, rho = sum u_a P_ab o_b,
+ * V_H the periodic Hartree potential (G = 0 dropped) and s the coupling scale.
+ * Pp, Pq, fp, fq: DEVICE arrays [n_states][tddft_nnz_m] FP64 in M's value order
+ * (contravariant).  Every product is exact; only results are restricted to M.
+ * n_states in [1, 32].  Internal arithmetic follows the handle's precision. */
+int tddft_apply(tddft_handle *h, int32_t n_states, const double *Pp, const double *Pq,
+                double *fp, double *fq);
+
+/* Lowest n_states positive excitation energies by preconditioned CG on the Tsiper sum
+ * functional (Secs. III.A-III.C).  omega: HOST [n_states], ascending (Ha).
+ * Pp, Pq: DEVICE [n_states][tddft_nnz_m] FP64 or NULL.  On input, if non-NULL, they hold
+ * auxiliary matrices L (Eq. auxiliary) that seed the trial vectors via
+ * P = mask_M(K^c S^u L S^o K^v); if NULL a seeded N(0,1) guess on M is used.  On output
+ * (if non-NULL) they hold the converged Tsiper-orthonormal vectors, rotated to the
+ * eigenvectors of the subspace matrix.  opts may be NULL (handle's create options).
+ * stats may be NULL.  Returns TDDFT_E_NO_CONVERGENCE with the last iterate when
+ * max_iter is reached. */
+int tddft_pcg_solve(tddft_handle *h, int32_t n_states, const tddft_options *opts,
+                    double *omega, double *Pp, double *Pq, tddft_stats *stats);
+
+void tddft_destroy(tddft_handle *h);
+
+/* Device-time profiling of the kernel stages (HIP events recorded on the handle's stream
+ * around each stage; enabling it adds event records and host waits, not extra kernels).
+ * tddft_profile(h, 1) enables and zeroes the counters, tddft_profile(h, 0) disables.
+ * tddft_profile_read copies up to cap entries of accumulated milliseconds and execution
+ * counts per stage (caller-owned host arrays) and returns the number of stages;
+ * tddft_profile_stage_name names stage k (NULL when out of range). */
+int tddft_profile(tddft_handle *h, int enable);
+int tddft_profile_read(tddft_handle *h, int cap, double *ms, int64_t *count);
+const char *tddft_profile_stage_name(int k);
+
+const char *tddft_strerror(int code);
+/* Detail of the last failing call on this handle (or of the last failing tddft_create
+ * on this thread when h is NULL). */
+const char *tddft_last_error(const tddft_handle *h);
+int tddft_abi_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* TDDFT_H */

@@ -1,0 +1,218 @@
+// C-ABI entry points of libtddft: argument checks, error conversion, dispatch on the
+// handle's precision.  No exception crosses this boundary.
+#include <new>
+
+#include "handle.h"
+
+using namespace tddft;
+
+struct tddft_handle {
+  Handle h;
+};
+
+static thread_local std::string g_create_error;
+
+extern "C" {
+
+void tddft_default_options(tddft_options *o) {
+  if (!o) return;
+  std::memset(o, 0, sizeof(*o));
+  o->precision = TDDFT_FP64;
+  o->xc = TDDFT_XC_ALDA_X;
+  o->rho_floor = 1e-10;
+  o->coupling_scale = 1.0;
+  o->precond = TDDFT_PC_KSDIFF_CG;
+  o->eps_tol = 1e-4;
+  o->tol_omega = 1e-7;
+  o->max_iter = 300;
+  o->max_inner = 50;
+  o->refresh = 10;
+  o->restart = 20;
+  o->seed = 0;
+  o->model = nullptr;
+  o->model_bytes = 0;
+  o->stream = nullptr;
+}
+
+int tddft_abi_version(void) { return TDDFT_ABI_VERSION; }
+
+const char *tddft_strerror(int code) {
+  switch (code) {
+    case TDDFT_OK: return "ok";
+    case TDDFT_E_INVALID: return "invalid argument";
+    case TDDFT_E_NOMEM: return "out of memory";
+    case TDDFT_E_DEVICE: return "device error";
+    case TDDFT_E_NOT_PD: return "not positive definite";
+    case TDDFT_E_NO_CONVERGENCE: return "no convergence";
+    case TDDFT_W_FALLBACK: return "learned preconditioner fallback used";
+    default: return "unknown status";
+  }
+}
+
+const char *tddft_last_error(const tddft_handle *h) {
+  if (!h) return g_create_error.c_str();
+  return h->h.last_error.c_str();
+}
+
+int tddft_create(const tddft_system *sys, const tddft_options *opts, tddft_handle **out) {
+  g_create_error.clear();
+  if (!sys || !out) {
+    g_create_error = "null system or output pointer";
+    return TDDFT_E_INVALID;
+  }
+  *out = nullptr;
+  tddft_options o;
+  if (opts) o = *opts; else tddft_default_options(&o);
+  tddft_handle *hd = nullptr;
+  try {
+    hd = new tddft_handle();
+    create_handle(hd->h, *sys, o);
+    *out = hd;
+    return TDDFT_OK;
+  } catch (const Error &e) {
+    g_create_error = e.msg;
+    delete hd;
+    return e.code;
+  } catch (const std::bad_alloc &) {
+    g_create_error = "host allocation failed";
+    delete hd;
+    return TDDFT_E_NOMEM;
+  } catch (const std::exception &e) {
+    g_create_error = e.what();
+    delete hd;
+    return TDDFT_E_INVALID;
+  }
+}
+
+int64_t tddft_nnz_m(const tddft_handle *h) { return h ? h->h.nnzM : -1; }
+
+int tddft_get_info(const tddft_handle *hd, tddft_info *o) {
+  if (!hd || !o) return TDDFT_E_INVALID;
+  const Handle &h = hd->h;
+  std::memset(o, 0, sizeof(*o));
+  for (int d = 0; d < 3; ++d) o->n[d] = h.n[d];
+  o->tiles = h.nt;
+  o->block_rows = h.BU;
+  o->block_cols = h.BO;
+  o->brick_edge = h.brick_edge;
+  o->precision = h.precision;
+  o->sample_rows_u = h.sample_rows_u;
+  o->sample_rows_o = h.sample_rows_o;
+  o->pair_points = h.pair_points;
+  o->blocks_m = h.nM;
+  o->blocks_o = h.nO;
+  o->blocks_m2 = h.nM2;
+  o->blocks_m3 = h.nM3;
+  o->blocks_m4 = h.nM4;
+  o->pairs_kshift = h.pT_left.npairs + h.pT_right.npairs;
+  o->pairs_project = h.pPi1.npairs + h.pPi2.npairs;
+  o->pairs_covariant = h.pCov1.npairs + h.pCov2.npairs;
+  o->pairs_sandwich = h.pSw1.npairs + h.pSw2.npairs;
+  o->setup_ms = h.setup_ms;
+  return TDDFT_OK;
+}
+
+int tddft_apply(tddft_handle *hd, int32_t n, const double *Pp, const double *Pq, double *fp,
+                double *fq) {
+  if (!hd) return TDDFT_E_INVALID;
+  Handle &h = hd->h;
+  h.last_error.clear();
+  if (n < 1 || n > 32 || !Pp || !Pq || !fp || !fq) {
+    h.last_error = "tddft_apply: n_states must be in [1, 32] and all arrays non-null";
+    return TDDFT_E_INVALID;
+  }
+  try {
+    const int nc = 2 * n;
+    auto run = [&](auto tag) {
+      using T = decltype(tag);
+      const size_t elems = (size_t)h.nM * nc * h.E;
+      T *X = (T *)h.w_pcg.get(2 * elems * sizeof(T));
+      T *F = X + elems;
+      pack<T>(h.nM, h.BU, h.BO, n, Pp, h.nnzM, h.m_voff.p, h.m_shape.p, X, nc, 0, h.stream);
+      pack<T>(h.nM, h.BU, h.BO, n, Pq, h.nnzM, h.m_voff.p, h.m_shape.p, X, nc, n, h.stream);
+      apply_sets<T>(h, n, X, nc, 0, n, F, nc, 0, n, true);
+      unpack<T>(h.nM, h.BU, h.BO, n, F, nc, 0, h.m_voff.p, h.m_shape.p, fp, h.nnzM, h.stream);
+      unpack<T>(h.nM, h.BU, h.BO, n, F, nc, n, h.m_voff.p, h.m_shape.p, fq, h.nnzM, h.stream);
+      TD_HIP(hipStreamSynchronize(h.stream));
+    };
+    if (h.precision == TDDFT_FP64) run(double{}); else run(float{});
+    return TDDFT_OK;
+  } catch (const Error &e) {
+    h.last_error = e.msg;
+    return e.code;
+  } catch (const std::bad_alloc &) {
+    h.last_error = "host allocation failed";
+    return TDDFT_E_NOMEM;
+  }
+}
+
+int tddft_pcg_solve(tddft_handle *hd, int32_t n, const tddft_options *opts, double *omega,
+                    double *Pp, double *Pq, tddft_stats *stats) {
+  if (!hd) return TDDFT_E_INVALID;
+  Handle &h = hd->h;
+  h.last_error.clear();
+  if (n < 1 || n > 32 || !omega) {
+    h.last_error = "tddft_pcg_solve: n_states must be in [1, 32] and omega non-null";
+    return TDDFT_E_INVALID;
+  }
+  if ((Pp == nullptr) != (Pq == nullptr)) {
+    h.last_error = "tddft_pcg_solve: give both Pp and Pq or neither";
+    return TDDFT_E_INVALID;
+  }
+  tddft_options o = opts ? *opts : h.opts;
+  if (!(o.eps_tol > 0.0) || !(o.tol_omega > 0.0) || o.max_iter < 0 || o.max_inner < 0) {
+    h.last_error = "tddft_pcg_solve: tolerances must be positive";
+    return TDDFT_E_INVALID;
+  }
+  if (o.precond == TDDFT_PC_LEARNED && !o.model) o.precond = TDDFT_PC_KSDIFF_CG;
+  if (stats) stats->log_len = 0;
+  try {
+    return pcg_solve(h, n, o, omega, Pp, Pq, stats);
+  } catch (const Error &e) {
+    h.last_error = e.msg;
+    return e.code;
+  } catch (const std::bad_alloc &) {
+    h.last_error = "host allocation failed";
+    return TDDFT_E_NOMEM;
+  }
+}
+
+void tddft_destroy(tddft_handle *h) { delete h; }
+
+int tddft_profile(tddft_handle *hd, int enable) {
+  if (!hd) return TDDFT_E_INVALID;
+  Handle &h = hd->h;
+  try {
+    h.prof.collect();
+    if (enable) h.prof.init();
+    h.prof.reset();
+    h.prof.on = enable != 0;
+    return TDDFT_OK;
+  } catch (const Error &e) {
+    h.last_error = e.msg;
+    return e.code;
+  }
+}
+
+int tddft_profile_read(tddft_handle *hd, int cap, double *ms, int64_t *count) {
+  if (!hd || cap < 0 || (cap > 0 && (!ms || !count))) return TDDFT_E_INVALID;
+  Handle &h = hd->h;
+  try {
+    h.prof.collect();
+  } catch (const Error &e) {
+    h.last_error = e.msg;
+    return e.code;
+  }
+  for (int k = 0; k < cap && k < ST_COUNT; ++k) {
+    ms[k] = h.prof.ms[k];
+    count[k] = h.prof.count[k];
+  }
+  return ST_COUNT;
+}
+
+const char *tddft_profile_stage_name(int k) {
+  if (k < 0 || k >= ST_COUNT) return nullptr;
+  return kStageNames[k];
+}
+
+}  // extern "C"

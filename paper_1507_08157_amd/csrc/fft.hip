@@ -1,0 +1,407 @@
+// Periodic Hartree solve plus ALDA term on the real-space grid (Sec. II.A: the Coulomb
+// and f_xc parts of the coupling kernel, evaluated as the response potential of
+// rho^{q} in Sec. III.A).
+//
+//   V_s(r) = IFFT[ 4 pi / |G|^2 FFT[rho_s] ](r) + f_xc(r) rho_s(r),   G = 0 term dropped
+//
+// Two real states share one complex field (real and imaginary part): the Poisson kernel is
+// real and even in G, so the transform of the pair yields both potentials exactly.
+// Mixed-radix (2, 3, 4, 5, 7, 8) Stockham transforms run on lines held in LDS:
+//   pass 1  x-lines, forward   tile-major fields -> natural-order work array
+//   pass 2  y-lines, forward   in place
+//   pass 3  z-lines, forward, times the Poisson kernel, inverse     in place
+//   pass 4  y-lines, inverse   in place
+//   pass 5  x-lines, inverse, plus f_xc rho          work array -> tile-major fields
+#include "internal.h"
+#include "kernels.h"
+
+namespace tddft {
+
+template <class T> struct C2;
+template <> struct C2<double> { using type = double2; };
+template <> struct C2<float> { using type = float2; };
+
+template <int R>
+__host__ __device__ constexpr double root_cos(int k) {
+  if constexpr (R == 3) {
+    constexpr double c[3] = {1.0, -0.5, -0.5};
+    return c[k];
+  } else if constexpr (R == 5) {
+    constexpr double c[5] = {1.0, 0.309016994374947424102, -0.809016994374947424102,
+                             -0.809016994374947424102, 0.309016994374947424102};
+    return c[k];
+  } else if constexpr (R == 7) {
+    constexpr double c[7] = {1.0, 0.623489801858733530525, -0.222520933956314404289,
+                             -0.900968867902419126236, -0.900968867902419126236,
+                             -0.222520933956314404289, 0.623489801858733530525};
+    return c[k];
+  } else {  // 8
+    constexpr double c[8] = {1.0, 0.707106781186547524401, 0.0, -0.707106781186547524401,
+                             -1.0, -0.707106781186547524401, 0.0, 0.707106781186547524401};
+    return c[k];
+  }
+}
+
+template <int R>
+__host__ __device__ constexpr double root_sin(int k) {
+  if constexpr (R == 3) {
+    constexpr double s[3] = {0.0, 0.866025403784438646764, -0.866025403784438646764};
+    return s[k];
+  } else if constexpr (R == 5) {
+    constexpr double s[5] = {0.0, 0.951056516295153572116, 0.587785252292473129169,
+                             -0.587785252292473129169, -0.951056516295153572116};
+    return s[k];
+  } else if constexpr (R == 7) {
+    constexpr double s[7] = {0.0, 0.781831482468029808708, 0.974927912181823607018,
+                             0.433883739117558120476, -0.433883739117558120476,
+                             -0.974927912181823607018, -0.781831482468029808708};
+    return s[k];
+  } else {
+    constexpr double s[8] = {0.0, 0.707106781186547524401, 1.0, 0.707106781186547524401,
+                             0.0, -0.707106781186547524401, -1.0, -0.707106781186547524401};
+    return s[k];
+  }
+}
+
+template <class T2>
+__device__ __forceinline__ T2 cmul(T2 a, T2 b) {
+  T2 r;
+  r.x = a.x * b.x - a.y * b.y;
+  r.y = a.x * b.y + a.y * b.x;
+  return r;
+}
+
+// small DFT of length R, exponent sign SIGN (-1 forward, +1 inverse)
+template <class T, int R, int SIGN>
+__device__ __forceinline__ void dft(typename C2<T>::type (&v)[R]) {
+  using T2 = typename C2<T>::type;
+  if constexpr (R == 2) {
+    T2 a = v[0], b = v[1];
+    v[0].x = a.x + b.x; v[0].y = a.y + b.y;
+    v[1].x = a.x - b.x; v[1].y = a.y - b.y;
+  } else if constexpr (R == 4) {
+    T2 a0, a1, a2, a3;
+    a0.x = v[0].x + v[2].x; a0.y = v[0].y + v[2].y;
+    a1.x = v[0].x - v[2].x; a1.y = v[0].y - v[2].y;
+    a2.x = v[1].x + v[3].x; a2.y = v[1].y + v[3].y;
+    const T dx = v[1].x - v[3].x, dy = v[1].y - v[3].y;
+    // (v1 - v3) * (SIGN i)
+    a3.x = -SIGN * dy; a3.y = SIGN * dx;
+    v[0].x = a0.x + a2.x; v[0].y = a0.y + a2.y;
+    v[2].x = a0.x - a2.x; v[2].y = a0.y - a2.y;
+    v[1].x = a1.x + a3.x; v[1].y = a1.y + a3.y;
+    v[3].x = a1.x - a3.x; v[3].y = a1.y - a3.y;
+  } else {
+    T2 o[R];
+#pragma unroll
+    for (int m = 0; m < R; ++m) {
+      T2 acc = v[0];
+#pragma unroll
+      for (int r = 1; r < R; ++r) {
+        const int k = (r * m) % R;
+        const T c = (T)root_cos<R>(k);
+        const T s = (T)(SIGN * root_sin<R>(k));
+        acc.x += v[r].x * c - v[r].y * s;
+        acc.y += v[r].x * s + v[r].y * c;
+      }
+      o[m] = acc;
+    }
+#pragma unroll
+    for (int m = 0; m < R; ++m) v[m] = o[m];
+  }
+}
+
+struct AxisDev {
+  int n, npass;
+  int radix[12];
+  int tw_off[12];
+};
+
+// one Stockham pass over `nlines` lines (stride ldl) of length N held in LDS
+template <class T, int R, int SIGN>
+__device__ void fft_pass(const typename C2<T>::type *__restrict__ in,
+                         typename C2<T>::type *__restrict__ out, int N, int Ns, int ldl,
+                         int nlines, const typename C2<T>::type *__restrict__ tw) {
+  using T2 = typename C2<T>::type;
+  const int nb = N / R;
+  const int total = nlines * nb;
+  for (int q = threadIdx.x; q < total; q += blockDim.x) {
+    const int line = q / nb;
+    const int j = q - line * nb;
+    const T2 *src = in + line * ldl;
+    T2 *dst = out + line * ldl;
+    const int k = j % Ns;
+    T2 v[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) v[r] = src[j + r * nb];
+    if (Ns > 1) {
+#pragma unroll
+      for (int r = 1; r < R; ++r) {
+        T2 w = tw[k * (R - 1) + r - 1];
+        if (SIGN > 0) w.y = -w.y;
+        v[r] = cmul(v[r], w);
+      }
+    }
+    dft<T, R, SIGN>(v);
+    const int d = (j - k) * R + k;
+#pragma unroll
+    for (int r = 0; r < R; ++r) dst[d + r * Ns] = v[r];
+  }
+}
+
+// full transform of the lines in buffer a (scratch b); returns the buffer with the result
+template <class T, int SIGN>
+__device__ typename C2<T>::type *fft_lines(typename C2<T>::type *a, typename C2<T>::type *b,
+                                           int ldl, int nlines, const AxisDev &ax,
+                                           const typename C2<T>::type *tw) {
+  int Ns = 1;
+  for (int p = 0; p < ax.npass; ++p) {
+    const int R = ax.radix[p];
+    const typename C2<T>::type *t = tw + ax.tw_off[p];
+    switch (R) {
+      case 2: fft_pass<T, 2, SIGN>(a, b, ax.n, Ns, ldl, nlines, t); break;
+      case 3: fft_pass<T, 3, SIGN>(a, b, ax.n, Ns, ldl, nlines, t); break;
+      case 4: fft_pass<T, 4, SIGN>(a, b, ax.n, Ns, ldl, nlines, t); break;
+      case 5: fft_pass<T, 5, SIGN>(a, b, ax.n, Ns, ldl, nlines, t); break;
+      case 7: fft_pass<T, 7, SIGN>(a, b, ax.n, Ns, ldl, nlines, t); break;
+      default: fft_pass<T, 8, SIGN>(a, b, ax.n, Ns, ldl, nlines, t); break;
+    }
+    __syncthreads();
+    typename C2<T>::type *tmp = a;
+    a = b;
+    b = tmp;
+    Ns *= R;
+  }
+  return a;
+}
+
+struct GeomDev {
+  int nx, ny, nz, ntx, nty, ntz;
+  int64_t pair_tile;   // elements (complex) per field in tile-major layout
+  int64_t pair_work;   // elements per field in natural layout
+};
+
+// ---- pass 1: x forward, tile-major -> natural ---------------------------------------------
+// one workgroup per row of tiles (ty, tz): 16 x-lines, contiguous in the tile-major layout
+template <class T>
+__global__ __launch_bounds__(256) void k_fft_x_fwd(GeomDev g, AxisDev ax,
+                                                   const typename C2<T>::type *__restrict__ tw,
+                                                   const typename C2<T>::type *__restrict__ fields,
+                                                   typename C2<T>::type *__restrict__ work) {
+  using T2 = typename C2<T>::type;
+  extern __shared__ unsigned char lds_raw[];
+  T2 *a = reinterpret_cast<T2 *>(lds_raw);
+  const int ldl = g.nx;
+  T2 *b = a + 16 * ldl;
+  const int row = blockIdx.x;           // ty + nty * tz
+  const int ty = row % g.nty, tz = row / g.nty;
+  const int pair = blockIdx.y;
+  const T2 *src = fields + pair * g.pair_tile + (int64_t)row * g.ntx * TP;
+  const int ntot = g.ntx * TP;
+  for (int e = threadIdx.x; e < ntot; e += blockDim.x) {
+    const int tx = e / TP, p = e - (e / TP) * TP;
+    const int px = p & 3, l = p >> 2;
+    const int x = tx * 4 + px;
+    if (x < g.nx) a[l * ldl + x] = src[e];
+  }
+  __syncthreads();
+  T2 *res = fft_lines<T, -1>(a, b, ldl, 16, ax, tw);
+  for (int e = threadIdx.x; e < 16 * g.nx; e += blockDim.x) {
+    const int l = e / g.nx, x = e - l * g.nx;
+    const int y = ty * 4 + (l & 3), z = tz * 4 + (l >> 2);
+    if (y < g.ny && z < g.nz)
+      work[pair * g.pair_work + ((int64_t)z * g.ny + y) * g.nx + x] = res[l * ldl + x];
+  }
+}
+
+// ---- pass 2/4: y lines in place ---------------------------------------------------------
+constexpr int XB = 16;   // x-columns per workgroup in the strided passes
+
+template <class T, int SIGN>
+__global__ __launch_bounds__(256) void k_fft_y(GeomDev g, AxisDev ax,
+                                               const typename C2<T>::type *__restrict__ tw,
+                                               typename C2<T>::type *__restrict__ work) {
+  using T2 = typename C2<T>::type;
+  extern __shared__ unsigned char lds_raw[];
+  T2 *a = reinterpret_cast<T2 *>(lds_raw);
+  const int ldl = g.ny;
+  T2 *b = a + XB * ldl;
+  const int nxb = (g.nx + XB - 1) / XB;
+  const int xb = blockIdx.x % nxb, z = blockIdx.x / nxb;
+  const int x0 = xb * XB;
+  const int nl = min(XB, g.nx - x0);
+  T2 *base = work + blockIdx.y * g.pair_work + (int64_t)z * g.ny * g.nx + x0;
+  for (int e = threadIdx.x; e < XB * g.ny; e += blockDim.x) {
+    const int y = e / XB, l = e - y * XB;
+    if (l < nl) a[l * ldl + y] = base[(int64_t)y * g.nx + l];
+  }
+  __syncthreads();
+  T2 *res = fft_lines<T, SIGN>(a, b, ldl, nl, ax, tw);
+  for (int e = threadIdx.x; e < XB * g.ny; e += blockDim.x) {
+    const int y = e / XB, l = e - y * XB;
+    if (l < nl) base[(int64_t)y * g.nx + l] = res[l * ldl + y];
+  }
+}
+
+// ---- pass 3: z lines, forward, Poisson kernel, inverse -----------------------------------
+template <class T>
+__global__ __launch_bounds__(256) void k_fft_z_poisson(GeomDev g, AxisDev ax,
+                                                       const typename C2<T>::type *__restrict__ tw,
+                                                       typename C2<T>::type *__restrict__ work,
+                                                       double gx, double gy, double gz,
+                                                       double scale) {
+  using T2 = typename C2<T>::type;
+  extern __shared__ unsigned char lds_raw[];
+  T2 *a = reinterpret_cast<T2 *>(lds_raw);
+  const int ldl = g.nz;
+  T2 *b = a + XB * ldl;
+  const int nxb = (g.nx + XB - 1) / XB;
+  const int xb = blockIdx.x % nxb, y = blockIdx.x / nxb;
+  const int x0 = xb * XB;
+  const int nl = min(XB, g.nx - x0);
+  const int64_t plane = (int64_t)g.ny * g.nx;
+  T2 *base = work + blockIdx.y * g.pair_work + (int64_t)y * g.nx + x0;
+  for (int e = threadIdx.x; e < XB * g.nz; e += blockDim.x) {
+    const int z = e / XB, l = e - z * XB;
+    if (l < nl) a[l * ldl + z] = base[(int64_t)z * plane + l];
+  }
+  __syncthreads();
+  T2 *res = fft_lines<T, -1>(a, b, ldl, nl, ax, tw);
+  // multiply by 4 pi / |G|^2 (G = 0 -> 0) including the 1/(nx ny nz) normalisation
+  const int ky = y <= g.ny / 2 ? y : y - g.ny;
+  for (int e = threadIdx.x; e < nl * g.nz; e += blockDim.x) {
+    const int l = e / g.nz, z = e - l * g.nz;
+    const int x = x0 + l;
+    const int kx = x <= g.nx / 2 ? x : x - g.nx;
+    const int kz = z <= g.nz / 2 ? z : z - g.nz;
+    const double G2 = (gx * kx) * (gx * kx) + (gy * ky) * (gy * ky) + (gz * kz) * (gz * kz);
+    const T f = G2 > 0.0 ? (T)(scale / G2) : T(0);
+    T2 v = res[l * ldl + z];
+    v.x *= f;
+    v.y *= f;
+    res[l * ldl + z] = v;
+  }
+  __syncthreads();
+  T2 *other = (res == a) ? b : a;
+  T2 *res2 = fft_lines<T, 1>(res, other, ldl, nl, ax, tw);
+  for (int e = threadIdx.x; e < XB * g.nz; e += blockDim.x) {
+    const int z = e / XB, l = e - z * XB;
+    if (l < nl) base[(int64_t)z * plane + l] = res2[l * ldl + z];
+  }
+}
+
+// ---- pass 5: x inverse, natural -> tile-major, plus f_xc rho ---------------------------------
+template <class T>
+__global__ __launch_bounds__(256) void k_fft_x_inv(GeomDev g, AxisDev ax,
+                                                   const typename C2<T>::type *__restrict__ tw,
+                                                   const typename C2<T>::type *__restrict__ work,
+                                                   typename C2<T>::type *__restrict__ fields,
+                                                   const T *__restrict__ fxc, int use_fxc) {
+  using T2 = typename C2<T>::type;
+  extern __shared__ unsigned char lds_raw[];
+  T2 *a = reinterpret_cast<T2 *>(lds_raw);
+  const int ldl = g.nx;
+  T2 *b = a + 16 * ldl;
+  const int row = blockIdx.x;
+  const int ty = row % g.nty, tz = row / g.nty;
+  const int pair = blockIdx.y;
+  for (int e = threadIdx.x; e < 16 * g.nx; e += blockDim.x) {
+    const int l = e / g.nx, x = e - l * g.nx;
+    const int y = ty * 4 + (l & 3), z = tz * 4 + (l >> 2);
+    T2 v;
+    v.x = T(0);
+    v.y = T(0);
+    if (y < g.ny && z < g.nz) v = work[pair * g.pair_work + ((int64_t)z * g.ny + y) * g.nx + x];
+    a[l * ldl + x] = v;
+  }
+  __syncthreads();
+  T2 *res = fft_lines<T, 1>(a, b, ldl, 16, ax, tw);
+  T2 *dst = fields + pair * g.pair_tile + (int64_t)row * g.ntx * TP;
+  const T *fx = fxc + (int64_t)row * g.ntx * TP;
+  const int ntot = g.ntx * TP;
+  for (int e = threadIdx.x; e < ntot; e += blockDim.x) {
+    const int tx = e / TP, p = e - (e / TP) * TP;
+    const int px = p & 3, l = p >> 2;
+    const int x = tx * 4 + px;
+    const int y = ty * 4 + (l & 3), z = tz * 4 + (l >> 2);
+    T2 v;
+    v.x = T(0);
+    v.y = T(0);
+    if (x < g.nx && y < g.ny && z < g.nz) {
+      v = res[l * ldl + x];
+      if (use_fxc) {
+        const T2 rho = dst[e];
+        const T f = fx[e];
+        v.x += f * rho.x;
+        v.y += f * rho.y;
+      }
+    }
+    dst[e] = v;
+  }
+}
+
+// ---------------------------------------------------------------------------------------
+static AxisDev axis_dev(const AxisFFT &a) {
+  AxisDev d{};
+  d.n = a.n;
+  d.npass = (int)a.radix.size();
+  for (int i = 0; i < d.npass; ++i) {
+    d.radix[i] = a.radix[i];
+    d.tw_off[i] = a.tw_off[i];
+  }
+  return d;
+}
+
+template <class T>
+void hartree_xc(const GridGeom &gg, const FFTPlan &plan, int npair, T *fields, T *work,
+                const T *fxc, bool use_fxc, hipStream_t s, Prof *prof) {
+  using T2 = typename C2<T>::type;
+  if (npair == 0) return;
+  GeomDev g{gg.n[0], gg.n[1], gg.n[2], gg.ntx, gg.nty, gg.ntz,
+            (int64_t)gg.ntx * gg.nty * gg.ntz * TP, (int64_t)gg.n[0] * gg.n[1] * gg.n[2]};
+  const T2 *tw = reinterpret_cast<const T2 *>(std::is_same<T, double>::value ? (const void *)plan.tw64.p
+                                                                             : (const void *)plan.tw32.p);
+  int off[3] = {0, plan.ax[0].tw_len, plan.ax[0].tw_len + plan.ax[1].tw_len};
+  AxisDev ax = axis_dev(plan.ax[0]), ay = axis_dev(plan.ax[1]), az = axis_dev(plan.ax[2]);
+  T2 *F = reinterpret_cast<T2 *>(fields);
+  T2 *W = reinterpret_cast<T2 *>(work);
+  const double pi = 3.14159265358979323846;
+  const double gx = 2.0 * pi / gg.L[0], gy = 2.0 * pi / gg.L[1], gz = 2.0 * pi / gg.L[2];
+  const double scale = 4.0 * pi / ((double)gg.n[0] * gg.n[1] * gg.n[2]);
+  const unsigned rows = (unsigned)(gg.nty * gg.ntz);
+  const unsigned nxb = (unsigned)((gg.n[0] + XB - 1) / XB);
+  const size_t lx = 2 * 16 * (size_t)gg.n[0] * sizeof(T2);
+  const size_t ly = 2 * XB * (size_t)gg.n[1] * sizeof(T2);
+  const size_t lz = 2 * XB * (size_t)gg.n[2] * sizeof(T2);
+  Prof dummy;
+  Prof &pf = prof ? *prof : dummy;
+  pf.begin(ST_FFT_X_FWD, s);
+  hipLaunchKernelGGL((k_fft_x_fwd<T>), dim3(rows, npair), dim3(256), lx, s, g, ax, tw + off[0], F, W);
+  TD_HIP(hipGetLastError());
+  pf.end(ST_FFT_X_FWD, s);
+  pf.begin(ST_FFT_Y_FWD, s);
+  hipLaunchKernelGGL((k_fft_y<T, -1>), dim3(nxb * gg.n[2], npair), dim3(256), ly, s, g, ay, tw + off[1], W);
+  TD_HIP(hipGetLastError());
+  pf.end(ST_FFT_Y_FWD, s);
+  pf.begin(ST_FFT_Z_POISSON, s);
+  hipLaunchKernelGGL((k_fft_z_poisson<T>), dim3(nxb * gg.n[1], npair), dim3(256), lz, s, g, az,
+                     tw + off[2], W, gx, gy, gz, scale);
+  TD_HIP(hipGetLastError());
+  pf.end(ST_FFT_Z_POISSON, s);
+  pf.begin(ST_FFT_Y_INV, s);
+  hipLaunchKernelGGL((k_fft_y<T, 1>), dim3(nxb * gg.n[2], npair), dim3(256), ly, s, g, ay, tw + off[1], W);
+  TD_HIP(hipGetLastError());
+  pf.end(ST_FFT_Y_INV, s);
+  pf.begin(ST_FFT_X_INV, s);
+  hipLaunchKernelGGL((k_fft_x_inv<T>), dim3(rows, npair), dim3(256), lx, s, g, ax, tw + off[0], W, F,
+                     fxc, use_fxc ? 1 : 0);
+  TD_HIP(hipGetLastError());
+  pf.end(ST_FFT_X_INV, s);
+}
+
+template void hartree_xc<double>(const GridGeom &, const FFTPlan &, int, double *, double *,
+                                 const double *, bool, hipStream_t, Prof *);
+template void hartree_xc<float>(const GridGeom &, const FFTPlan &, int, float *, float *,
+                                const float *, bool, hipStream_t, Prof *);
+
+}  // namespace tddft

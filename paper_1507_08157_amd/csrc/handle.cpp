@@ -1,0 +1,642 @@
+// Handle construction (validation, upload, tiles, bricks, plans, rho0 and f_xc) and the
+// operator application of Eq. operator_RPA on column sets.
+#include <algorithm>
+#include <cmath>
+#include <thread>
+
+#include "handle.h"
+
+namespace tddft {
+
+Handle::~Handle() {
+  prof.destroy();
+  if (ev0) (void)hipEventDestroy(ev0);
+  if (ev1) (void)hipEventDestroy(ev1);
+}
+
+const void *Handle::usamp() const {
+  return stype == SAMPLE_F64 ? (const void *)us64.p
+                             : (stype == SAMPLE_F32 ? (const void *)us32.p : (const void *)us16.p);
+}
+const void *Handle::osamp() const {
+  return stype == SAMPLE_F64 ? (const void *)os64.p
+                             : (stype == SAMPLE_F32 ? (const void *)os32.p : (const void *)os16.p);
+}
+
+void DevMat::upload(const HostBsr &m, hipStream_t s) {
+  pat = m.pat;
+  br = m.br;
+  bc = m.bc;
+  d.upload(m.val, s);
+  std::vector<float> v(m.val.begin(), m.val.end());
+  f.upload(v, s);
+  TD_HIP(hipStreamSynchronize(s));
+}
+
+template <class F>
+static void parallel_for(int64_t n, F fn) {
+  unsigned nt = std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
+  if (n < 64 || nt == 1) {
+    for (int64_t i = 0; i < n; ++i) fn(i);
+    return;
+  }
+  std::vector<std::thread> th;
+  for (unsigned t = 0; t < nt; ++t)
+    th.emplace_back([&, t]() {
+      for (int64_t i = t; i < n; i += nt) fn(i);
+    });
+  for (auto &x : th) x.join();
+}
+
+// ---------------------------------------------------------------------------------------
+// validation and conversion of the C-ABI inputs
+static std::vector<int> read_offsets(const int32_t *off, int nb, const char *what) {
+  TD_REQUIRE(off != nullptr && nb > 0, std::string(what) + ": missing block offsets");
+  std::vector<int> v(off, off + nb + 1);
+  TD_REQUIRE(v[0] == 0, std::string(what) + ": block offsets must start at 0");
+  for (int i = 0; i < nb; ++i) {
+    const int sz = v[i + 1] - v[i];
+    TD_REQUIRE(sz >= 1 && sz <= 4, std::string(what) + ": block sizes must be 1..4");
+  }
+  return v;
+}
+
+static Pattern read_pattern(const tddft_bsr &m, const char *what) {
+  TD_REQUIRE(m.rowptr != nullptr, std::string(what) + ": missing rowptr");
+  Pattern p;
+  p.nbr = m.nbr;
+  p.nbc = m.nbc;
+  p.rowptr.assign(m.rowptr, m.rowptr + m.nbr + 1);
+  TD_REQUIRE(p.rowptr[0] == 0, std::string(what) + ": rowptr must start at 0");
+  for (int i = 0; i < m.nbr; ++i)
+    TD_REQUIRE(p.rowptr[i + 1] >= p.rowptr[i], std::string(what) + ": rowptr not monotone");
+  const int64_t nnzb = p.rowptr[m.nbr];
+  TD_REQUIRE(nnzb == 0 || m.colind != nullptr, std::string(what) + ": missing colind");
+  p.col.assign(m.colind, m.colind + nnzb);
+  for (int i = 0; i < m.nbr; ++i)
+    for (int64_t k = p.rowptr[i]; k < p.rowptr[i + 1]; ++k) {
+      TD_REQUIRE(p.col[k] >= 0 && p.col[k] < m.nbc, std::string(what) + ": column out of range");
+      TD_REQUIRE(k == p.rowptr[i] || p.col[k] > p.col[k - 1],
+                 std::string(what) + ": columns not strictly increasing");
+    }
+  return p;
+}
+
+static HostBsr read_bsr(const tddft_bsr &m, const std::vector<int> &roff,
+                        const std::vector<int> &coff, int BR, int BC, const char *what) {
+  TD_REQUIRE(m.nbr == (int)roff.size() - 1 && m.nbc == (int)coff.size() - 1,
+             std::string(what) + ": block counts differ from the function sets");
+  TD_REQUIRE(m.row_off && m.col_off, std::string(what) + ": missing block offsets");
+  for (int i = 0; i <= m.nbr; ++i)
+    TD_REQUIRE(m.row_off[i] == roff[i], std::string(what) + ": row offsets differ from S");
+  for (int i = 0; i <= m.nbc; ++i)
+    TD_REQUIRE(m.col_off[i] == coff[i], std::string(what) + ": column offsets differ from S");
+  HostBsr h;
+  h.pat = read_pattern(m, what);
+  h.br = BR;
+  h.bc = BC;
+  TD_REQUIRE(m.val != nullptr, std::string(what) + ": missing values");
+  h.val.assign((size_t)h.pat.nnzb() * BR * BC, 0.0);
+  int64_t pos = 0;
+  for (int i = 0; i < m.nbr; ++i) {
+    const int rs = roff[i + 1] - roff[i];
+    for (int64_t k = h.pat.rowptr[i]; k < h.pat.rowptr[i + 1]; ++k) {
+      const int j = h.pat.col[k];
+      const int cs = coff[j + 1] - coff[j];
+      for (int r = 0; r < rs; ++r)
+        for (int c = 0; c < cs; ++c) {
+          const double v = m.val[pos++];
+          TD_REQUIRE(std::isfinite(v), std::string(what) + ": non-finite value");
+          h.val[((size_t)k * BR + r) * BC + c] = v;
+        }
+    }
+  }
+  return h;
+}
+
+static void check_symmetric(const HostBsr &A, const char *what) {
+  double amax = 0.0;
+  for (double v : A.val) amax = std::max(amax, std::fabs(v));
+  const double tol = 1e-10 * std::max(amax, 1e-300);
+  for (int i = 0; i < A.pat.nbr; ++i)
+    for (int64_t k = A.pat.rowptr[i]; k < A.pat.rowptr[i + 1]; ++k) {
+      const int j = A.pat.col[k];
+      const int64_t kt = A.pat.find(j, i);
+      TD_REQUIRE(kt >= 0, std::string(what) + ": pattern not symmetric");
+      for (int r = 0; r < A.br; ++r)
+        for (int c = 0; c < A.bc; ++c) {
+          const double a = A.val[((size_t)k * A.br + r) * A.bc + c];
+          const double b = A.val[((size_t)kt * A.br + c) * A.bc + r];
+          TD_REQUIRE(std::fabs(a - b) <= tol, std::string(what) + ": matrix not symmetric");
+        }
+    }
+}
+
+static void check_functions(const tddft_functions &fs, int nfn, const int n[3], const char *what) {
+  TD_REQUIRE(fs.n_fn == nfn, std::string(what) + ": n_fn differs from the matrices");
+  TD_REQUIRE(fs.origin && fs.extent && fs.off && fs.val, std::string(what) + ": missing arrays");
+  TD_REQUIRE(fs.off[0] == 0, std::string(what) + ": off must start at 0");
+  for (int f = 0; f < nfn; ++f) {
+    int64_t cnt = 1;
+    for (int d = 0; d < 3; ++d) {
+      const int o = fs.origin[3 * f + d], e = fs.extent[3 * f + d];
+      TD_REQUIRE(o >= 0 && o < n[d], std::string(what) + ": origin outside the grid");
+      TD_REQUIRE(e >= 1 && e <= n[d], std::string(what) + ": box larger than the cell");
+      cnt *= e;
+    }
+    TD_REQUIRE(fs.off[f + 1] - fs.off[f] == cnt, std::string(what) + ": off inconsistent with extent");
+  }
+  const int64_t tot = fs.off[nfn];
+  for (int64_t i = 0; i < tot; ++i)
+    TD_REQUIRE(std::isfinite(fs.val[i]), std::string(what) + ": non-finite sample");
+}
+
+// ---------------------------------------------------------------------------------------
+// tiles of one function set: atoms touching each tile (nonzero samples) and sample rows
+struct HostSetTiles {
+  std::vector<int32_t> ptr;      // [nt + 1]
+  std::vector<int32_t> atoms;
+  std::vector<double> samples;   // [ptr[nt] * B * TP]
+  int B = 0;
+};
+
+static HostSetTiles build_set_tiles(const tddft_functions &fs, const std::vector<int> &off,
+                                    int B, const int n[3], int ntx, int nty, int ntz) {
+  const int nt = ntx * nty * ntz;
+  const int nb = (int)off.size() - 1;
+  std::vector<int> fatom(fs.n_fn);
+  for (int a = 0; a < nb; ++a)
+    for (int f = off[a]; f < off[a + 1]; ++f) fatom[f] = a;
+  // pass 1: atom lists (functions are ordered by atom, so lists come out sorted)
+  std::vector<std::vector<int32_t>> lists(nt);
+  std::vector<int32_t> stamp(nt, -1);
+  for (int f = 0; f < fs.n_fn; ++f) {
+    const int a = fatom[f];
+    const int ox = fs.origin[3 * f], oy = fs.origin[3 * f + 1], oz = fs.origin[3 * f + 2];
+    const int ex = fs.extent[3 * f], ey = fs.extent[3 * f + 1], ez = fs.extent[3 * f + 2];
+    const double *v = fs.val + fs.off[f];
+    for (int k = 0; k < ez; ++k) {
+      const int z = (oz + k) % n[2];
+      for (int j = 0; j < ey; ++j) {
+        const int y = (oy + j) % n[1];
+        const double *row = v + ((int64_t)k * ey + j) * ex;
+        for (int i = 0; i < ex; ++i) {
+          if (row[i] == 0.0) continue;
+          const int x = (ox + i) % n[0];
+          const int t = (x >> 2) + ntx * ((y >> 2) + nty * (z >> 2));
+          if (stamp[t] != a) {
+            stamp[t] = a;
+            lists[t].push_back(a);
+          }
+        }
+      }
+    }
+  }
+  HostSetTiles r;
+  r.B = B;
+  r.ptr.assign(nt + 1, 0);
+  for (int t = 0; t < nt; ++t) r.ptr[t + 1] = r.ptr[t] + (int32_t)lists[t].size();
+  r.atoms.resize(r.ptr[nt]);
+  for (int t = 0; t < nt; ++t) std::copy(lists[t].begin(), lists[t].end(), r.atoms.begin() + r.ptr[t]);
+  r.samples.assign((size_t)r.ptr[nt] * B * TP, 0.0);
+  // pass 2: samples (each function writes its own rows)
+  parallel_for(fs.n_fn, [&](int64_t f) {
+    const int a = fatom[f];
+    const int row_in_blk = (int)f - off[a];
+    const int ox = fs.origin[3 * f], oy = fs.origin[3 * f + 1], oz = fs.origin[3 * f + 2];
+    const int ex = fs.extent[3 * f], ey = fs.extent[3 * f + 1], ez = fs.extent[3 * f + 2];
+    const double *v = fs.val + fs.off[f];
+    for (int k = 0; k < ez; ++k) {
+      const int z = (oz + k) % n[2];
+      for (int j = 0; j < ey; ++j) {
+        const int y = (oy + j) % n[1];
+        const double *row = v + ((int64_t)k * ey + j) * ex;
+        for (int i = 0; i < ex; ++i) {
+          if (row[i] == 0.0) continue;
+          const int x = (ox + i) % n[0];
+          const int t = (x >> 2) + ntx * ((y >> 2) + nty * (z >> 2));
+          const int p = (x & 3) + 4 * ((y & 3) + 4 * (z & 3));
+          const int32_t *lb = r.atoms.data() + r.ptr[t];
+          const int32_t *le = r.atoms.data() + r.ptr[t + 1];
+          const int idx = (int)(std::lower_bound(lb, le, a) - lb);
+          r.samples[((size_t)(r.ptr[t] + idx) * B + row_in_blk) * TP + p] = row[i];
+        }
+      }
+    }
+  });
+  return r;
+}
+
+template <class T>
+static void upload_converted(DevBuf<T> &dst, const std::vector<double> &src, hipStream_t s) {
+  std::vector<T> tmp(src.size());
+  for (size_t i = 0; i < src.size(); ++i) tmp[i] = (T)src[i];
+  dst.upload(tmp, s);
+  TD_HIP(hipStreamSynchronize(s));
+}
+
+static void upload_bf16(DevBuf<__hip_bfloat16> &dst, const std::vector<double> &src, hipStream_t s) {
+  std::vector<__hip_bfloat16> tmp(src.size());
+  for (size_t i = 0; i < src.size(); ++i) tmp[i] = __float2bfloat16((float)src[i]);  // RNE
+  dst.upload(tmp, s);
+  TD_HIP(hipStreamSynchronize(s));
+}
+
+// bricks of be^3 tiles with union atom lists and the slot -> O-block table
+static void build_bricks(Handle &h, const HostSetTiles &tu, const HostSetTiles &to,
+                         const Pattern &O, int be) {
+  const int ntx = h.geom.ntx, nty = h.geom.nty, ntz = h.geom.ntz;
+  const int nbx = (ntx + be - 1) / be, nby = (nty + be - 1) / be, nbz = (ntz + be - 1) / be;
+  const int nb = nbx * nby * nbz;
+  std::vector<int32_t> tptr(nb + 1, 0), tiles, nu(nb), no(nb), slot;
+  std::vector<int64_t> sptr(nb + 1, 0);
+  std::vector<int32_t> ubl(tu.atoms.size()), obl(to.atoms.size());
+  int max_tiles = 0, max_slots = 0;
+  for (int bz = 0; bz < nbz; ++bz)
+    for (int by = 0; by < nby; ++by)
+      for (int bx = 0; bx < nbx; ++bx) {
+        const int b = bx + nbx * (by + nby * bz);
+        std::vector<int32_t> ul, ol, tl;
+        for (int z = bz * be; z < std::min(ntz, (bz + 1) * be); ++z)
+          for (int y = by * be; y < std::min(nty, (by + 1) * be); ++y)
+            for (int x = bx * be; x < std::min(ntx, (bx + 1) * be); ++x) {
+              const int t = x + ntx * (y + nty * z);
+              if (tu.ptr[t + 1] == tu.ptr[t] || to.ptr[t + 1] == to.ptr[t]) continue;
+              tl.push_back(t);
+              ul.insert(ul.end(), tu.atoms.begin() + tu.ptr[t], tu.atoms.begin() + tu.ptr[t + 1]);
+              ol.insert(ol.end(), to.atoms.begin() + to.ptr[t], to.atoms.begin() + to.ptr[t + 1]);
+            }
+        std::sort(ul.begin(), ul.end());
+        ul.erase(std::unique(ul.begin(), ul.end()), ul.end());
+        std::sort(ol.begin(), ol.end());
+        ol.erase(std::unique(ol.begin(), ol.end()), ol.end());
+        for (int t : tl) {
+          for (int32_t k = tu.ptr[t]; k < tu.ptr[t + 1]; ++k)
+            ubl[k] = (int32_t)(std::lower_bound(ul.begin(), ul.end(), tu.atoms[k]) - ul.begin());
+          for (int32_t k = to.ptr[t]; k < to.ptr[t + 1]; ++k)
+            obl[k] = (int32_t)(std::lower_bound(ol.begin(), ol.end(), to.atoms[k]) - ol.begin());
+        }
+        tiles.insert(tiles.end(), tl.begin(), tl.end());
+        tptr[b + 1] = (int32_t)tiles.size();
+        nu[b] = (int32_t)ul.size();
+        no[b] = (int32_t)ol.size();
+        for (int32_t I : ul)
+          for (int32_t J : ol) slot.push_back((int32_t)O.find(I, J));
+        sptr[b + 1] = (int64_t)slot.size();
+        max_tiles = std::max(max_tiles, (int)tl.size());
+        max_slots = std::max(max_slots, (int)(ul.size() * ol.size()));
+      }
+  hipStream_t s = h.stream;
+  h.b_tptr.upload(tptr, s);
+  h.b_tiles.upload(tiles, s);
+  h.b_nu.upload(nu, s);
+  h.b_no.upload(no, s);
+  h.b_sptr.upload(sptr, s);
+  h.b_slot.upload(slot, s);
+  h.b_ubl.upload(ubl, s);
+  h.b_obl.upload(obl, s);
+  TD_HIP(hipStreamSynchronize(s));
+  h.brick_edge = be;
+  h.bricks.nb = nb;
+  h.bricks.max_tiles = max_tiles;
+  h.bricks.max_slots = max_slots;
+  h.bricks.max_rows = h.maxrows_uo;
+  h.bricks.tptr = h.b_tptr.p;
+  h.bricks.tiles = h.b_tiles.p;
+  h.bricks.nu = h.b_nu.p;
+  h.bricks.no = h.b_no.p;
+  h.bricks.sptr = h.b_sptr.p;
+  h.bricks.slot_blk = h.b_slot.p;
+  h.bricks.ubl = h.b_ubl.p;
+  h.bricks.obl = h.b_obl.p;
+}
+
+size_t vint_lds_bytes(const Handle &h, int ns, size_t tsize) {
+  const size_t acc = ((size_t)h.bricks.max_slots * ns * h.E + 1) & ~(size_t)1;
+  return (acc + (size_t)4 * ((size_t)h.bricks.max_rows * (TP + 1) + (size_t)ns * TP)) * tsize;
+}
+
+// ---------------------------------------------------------------------------------------
+void create_handle(Handle &h, const tddft_system &sys, const tddft_options &o) {
+  const auto t0 = std::chrono::steady_clock::now();
+  h.opts = o;
+  h.precision = o.precision;
+  TD_REQUIRE(o.precision >= TDDFT_FP64 && o.precision <= TDDFT_BF16_GRID, "unknown precision mode");
+  TD_REQUIRE(o.xc >= TDDFT_XC_ALDA_X && o.xc <= TDDFT_HXC_NONE, "unknown coupling kernel");
+  h.stype = o.precision == TDDFT_FP64 ? SAMPLE_F64 : (o.precision == TDDFT_FP32 ? SAMPLE_F32 : SAMPLE_BF16);
+  h.stream = (hipStream_t)o.stream;
+  hipStream_t s = h.stream;
+
+  // ---- geometry
+  for (int d = 0; d < 3; ++d) {
+    TD_REQUIRE(sys.n[d] >= 2 && sys.n[d] <= 4096, "grid dimensions must be in [2, 4096]");
+    TD_REQUIRE(std::isfinite(sys.L[d]) && sys.L[d] > 0.0, "cell lengths must be positive");
+    h.n[d] = sys.n[d];
+    h.L[d] = sys.L[d];
+    std::vector<int> rad;
+    TD_REQUIRE(fft_factor(sys.n[d], rad), "grid dimensions must be products of 2, 3, 5 and 7");
+  }
+  h.dV = (h.L[0] / h.n[0]) * (h.L[1] / h.n[1]) * (h.L[2] / h.n[2]);
+  h.geom.n[0] = h.n[0]; h.geom.n[1] = h.n[1]; h.geom.n[2] = h.n[2];
+  h.geom.L[0] = h.L[0]; h.geom.L[1] = h.L[1]; h.geom.L[2] = h.L[2];
+  h.geom.ntx = (h.n[0] + TILE - 1) / TILE;
+  h.geom.nty = (h.n[1] + TILE - 1) / TILE;
+  h.geom.ntz = (h.n[2] + TILE - 1) / TILE;
+  h.nt = h.geom.ntx * h.geom.nty * h.geom.ntz;
+
+  // ---- blocks and matrices
+  h.ooff = read_offsets(sys.S_o.row_off, sys.S_o.nbr, "S_o");
+  h.uoff = read_offsets(sys.S_u.row_off, sys.S_u.nbr, "S_u");
+  h.nbo = sys.S_o.nbr;
+  h.nbu = sys.S_u.nbr;
+  h.n_o = h.ooff.back();
+  h.n_u = h.uoff.back();
+  int bo = 0, bu = 0;
+  for (int i = 0; i < h.nbo; ++i) bo = std::max(bo, h.ooff[i + 1] - h.ooff[i]);
+  for (int i = 0; i < h.nbu; ++i) bu = std::max(bu, h.uoff[i + 1] - h.uoff[i]);
+  // padded shapes supported by the kernels: (1,1) (2,2) (3,2) (3,3) (4,4)
+  if (bu <= 1 && bo <= 1) { h.BU = 1; h.BO = 1; }
+  else if (bu <= 2 && bo <= 2) { h.BU = 2; h.BO = 2; }
+  else if (bu <= 3 && bo <= 2) { h.BU = 3; h.BO = 2; }
+  else if (bu <= 3 && bo <= 3) { h.BU = 3; h.BO = 3; }
+  else { h.BU = 4; h.BO = 4; }
+  h.E = h.BU * h.BO;
+
+  HostBsr So = read_bsr(sys.S_o, h.ooff, h.ooff, h.BO, h.BO, "S_o");
+  HostBsr Ho = read_bsr(sys.H_o, h.ooff, h.ooff, h.BO, h.BO, "H_o");
+  HostBsr Kv = read_bsr(sys.K_v, h.ooff, h.ooff, h.BO, h.BO, "K_v");
+  HostBsr Su = read_bsr(sys.S_u, h.uoff, h.uoff, h.BU, h.BU, "S_u");
+  HostBsr Hu = read_bsr(sys.H_u, h.uoff, h.uoff, h.BU, h.BU, "H_u");
+  HostBsr Kc = read_bsr(sys.K_c, h.uoff, h.uoff, h.BU, h.BU, "K_c");
+  check_symmetric(So, "S_o");
+  check_symmetric(Ho, "H_o");
+  check_symmetric(Kv, "K_v");
+  check_symmetric(Su, "S_u");
+  check_symmetric(Hu, "H_u");
+  check_symmetric(Kc, "K_c");
+  for (int i = 0; i < h.nbo; ++i) TD_REQUIRE(So.pat.find(i, i) >= 0, "S_o: missing diagonal block");
+  for (int i = 0; i < h.nbu; ++i) TD_REQUIRE(Su.pat.find(i, i) >= 0, "S_u: missing diagonal block");
+
+  TD_REQUIRE(sys.M.nbr == h.nbu && sys.M.nbc == h.nbo, "M: must be u-blocks x o-blocks");
+  if (sys.M.row_off)
+    for (int i = 0; i <= h.nbu; ++i) TD_REQUIRE(sys.M.row_off[i] == h.uoff[i], "M: row offsets differ from S_u");
+  if (sys.M.col_off)
+    for (int i = 0; i <= h.nbo; ++i) TD_REQUIRE(sys.M.col_off[i] == h.ooff[i], "M: column offsets differ from S_o");
+  h.M = read_pattern(sys.M, "M");
+  h.nM = h.M.nnzb();
+  TD_REQUIRE(h.nM > 0, "M: empty pattern");
+  check_functions(sys.occ, h.n_o, h.n, "occ");
+  check_functions(sys.vir, h.n_u, h.n, "vir");
+
+  // ---- every host-side check passed: from here on the device is used
+  TD_HIP(hipGetDevice(&h.device));
+  int lds = 0;
+  TD_HIP(hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, h.device));
+  h.lds_limit = (size_t)lds;
+  TD_HIP(hipEventCreate(&h.ev0));
+  TD_HIP(hipEventCreate(&h.ev1));
+  {
+    std::vector<int64_t> voff(h.nM);
+    std::vector<int32_t> shape(h.nM);
+    int64_t pos = 0;
+    for (int i = 0; i < h.nbu; ++i)
+      for (int64_t k = h.M.rowptr[i]; k < h.M.rowptr[i + 1]; ++k) {
+        const int j = h.M.col[k];
+        const int rs = h.uoff[i + 1] - h.uoff[i], cs = h.ooff[j + 1] - h.ooff[j];
+        voff[k] = pos;
+        shape[k] = rs | (cs << 8);
+        pos += rs * cs;
+      }
+    h.nnzM = pos;
+    h.m_voff.upload(voff, s);
+    h.m_shape.upload(shape, s);
+  }
+
+  // ---- functions and tiles
+  HostSetTiles tu = build_set_tiles(sys.vir, h.uoff, h.BU, h.n, h.geom.ntx, h.geom.nty, h.geom.ntz);
+  HostSetTiles to = build_set_tiles(sys.occ, h.ooff, h.BO, h.n, h.geom.ntx, h.geom.nty, h.geom.ntz);
+  const int nt = h.nt;
+  std::vector<int64_t> pptr_uo(nt + 1, 0), pptr_oo(nt + 1, 0);
+  std::vector<int32_t> pidx_uo, pidx_oo;
+  std::vector<std::vector<int32_t>> orows(h.nbu);
+  h.maxrows_uo = h.maxrows_oo = 0;
+  int64_t pp = 0;
+  for (int t = 0; t < nt; ++t) {
+    const int nua = tu.ptr[t + 1] - tu.ptr[t], noa = to.ptr[t + 1] - to.ptr[t];
+    h.maxrows_uo = std::max(h.maxrows_uo, nua * h.BU + noa * h.BO);
+    h.maxrows_oo = std::max(h.maxrows_oo, 2 * noa * h.BO);
+    pp += (int64_t)nua * h.BU * noa * h.BO;
+    for (int i = 0; i < nua; ++i)
+      for (int j = 0; j < noa; ++j) {
+        const int I = tu.atoms[tu.ptr[t] + i], J = to.atoms[to.ptr[t] + j];
+        pidx_uo.push_back((int32_t)h.M.find(I, J));
+        orows[I].push_back(J);
+      }
+    for (int i = 0; i < noa; ++i)
+      for (int j = 0; j < noa; ++j)
+        pidx_oo.push_back((int32_t)Kv.pat.find(to.atoms[to.ptr[t] + i], to.atoms[to.ptr[t] + j]));
+    pptr_uo[t + 1] = (int64_t)pidx_uo.size();
+    pptr_oo[t + 1] = (int64_t)pidx_oo.size();
+  }
+  h.pair_points = pp * TP;
+  h.sample_rows_u = (int64_t)tu.ptr[nt] * h.BU;
+  h.sample_rows_o = (int64_t)to.ptr[nt] * h.BO;
+  h.mean_u_per_tile = (double)tu.ptr[nt] / nt;
+  h.mean_o_per_tile = (double)to.ptr[nt] / nt;
+  // pattern O: (u-atom, o-atom) pairs sharing a tile
+  Pattern O;
+  O.nbr = h.nbu;
+  O.nbc = h.nbo;
+  O.rowptr.assign(h.nbu + 1, 0);
+  for (int I = 0; I < h.nbu; ++I) {
+    auto &r = orows[I];
+    std::sort(r.begin(), r.end());
+    r.erase(std::unique(r.begin(), r.end()), r.end());
+    O.col.insert(O.col.end(), r.begin(), r.end());
+    O.rowptr[I + 1] = (int64_t)O.col.size();
+    std::vector<int32_t>().swap(r);
+  }
+  h.nO = O.nnzb();
+
+  h.t_uptr.upload(tu.ptr, s);
+  h.t_optr.upload(to.ptr, s);
+  h.t_pptr_uo.upload(pptr_uo, s);
+  h.t_pptr_oo.upload(pptr_oo, s);
+  h.t_pidx_uo.upload(pidx_uo, s);
+  h.t_pidx_oo.upload(pidx_oo, s);
+  TD_HIP(hipStreamSynchronize(s));
+  upload_converted(h.os64, to.samples, s);   // FP64 o-samples for rho0 (freed below if unused)
+  if (h.stype == SAMPLE_F64) {
+    upload_converted(h.us64, tu.samples, s);
+  } else if (h.stype == SAMPLE_F32) {
+    upload_converted(h.us32, tu.samples, s);
+    upload_converted(h.os32, to.samples, s);
+  } else {
+    upload_bf16(h.us16, tu.samples, s);
+    upload_bf16(h.os16, to.samples, s);
+  }
+  h.tiles_uo = DevTiles{nt, h.maxrows_uo, h.t_uptr.p, h.t_optr.p, h.t_pptr_uo.p, h.t_pidx_uo.p,
+                        h.usamp(), h.osamp()};
+  h.tiles_oo = DevTiles{nt, h.maxrows_oo, h.t_optr.p, h.t_optr.p, h.t_pptr_oo.p, h.t_pidx_oo.p,
+                        h.os64.p, h.os64.p};
+  TD_REQUIRE((size_t)4 * h.maxrows_uo * TP * sizeof(double) <= h.lds_limit ||
+                 h.stype != SAMPLE_F64,
+             "too many functions per grid tile for the LDS budget");
+
+  // bricks: 2^3 tiles when the accumulator fits, else single tiles
+  build_bricks(h, tu, to, O, 2);
+  const size_t tsz = h.stype == SAMPLE_F64 ? sizeof(double) : sizeof(float);
+  if (vint_lds_bytes(h, 8, tsz) > h.lds_limit) build_bricks(h, tu, to, O, 1);
+  TD_REQUIRE(vint_lds_bytes(h, 2, tsz) <= h.lds_limit, "too many functions per grid tile for the LDS budget");
+
+  // ---- fixed products (exact, host FP64) and plans
+  HostBsr KcHu = host_product(Kc, Hu, product_pattern(Kc.pat, Hu.pat));
+  HostBsr HoKv = host_product(Ho, Kv, product_pattern(Ho.pat, Kv.pat));
+  HostBsr KcSu = host_product(Kc, Su, product_pattern(Kc.pat, Su.pat));
+  HostBsr SoKv = host_product(So, Kv, product_pattern(So.pat, Kv.pat));
+  h.KcHu.upload(KcHu, s);
+  h.HoKv.upload(HoKv, s);
+  h.KcSu.upload(KcSu, s);
+  h.SoKv.upload(SoKv, s);
+  h.Su.upload(Su, s);
+  h.So.upload(So, s);
+  h.Kc.upload(Kc, s);
+  h.Kv.upload(Kv, s);
+  const Pattern &M = h.M;
+  h.pT_left.upload(plan_product(KcHu.pat, M, M), s);
+  h.pT_right.upload(plan_product(M, HoKv.pat, M), s);
+  Pattern M3 = intersect(product_pattern(KcSu.pat, M), product_pattern(M, transpose(SoKv.pat)));
+  h.nM3 = M3.nnzb();
+  h.pPi1.upload(plan_product(KcSu.pat, M, M3), s);
+  h.pPi2.upload(plan_product(M3, SoKv.pat, M), s);
+  Pattern M4 = intersect(product_pattern(Su.pat, M), product_pattern(M, transpose(So.pat)));
+  h.nM4 = M4.nnzb();
+  h.pCov1.upload(plan_product(Su.pat, M, M4), s);
+  h.pCov2.upload(plan_product(M4, So.pat, M), s);
+  Pattern M2 = intersect(product_pattern(Kc.pat, O), product_pattern(M, transpose(Kv.pat)));
+  h.nM2 = M2.nnzb();
+  h.pSw1.upload(plan_product(Kc.pat, O, M2), s);
+  h.pSw2.upload(plan_product(M2, Kv.pat, M), s);
+
+  // ---- FFT plan, rho0 = 2 sum o K^v o and f_xc (FP64 from FP64 samples)
+  build_fft_plan(h.fft, h.n, s);
+  h.partial.alloc((size_t)h.max_parts * 1024);
+  h.small_dev.alloc(8192);
+  {
+    DevBuf<double> rho((size_t)nt * TP * 2);
+    density<double>(h.tiles_oo, SAMPLE_F64, h.BO, h.BO, h.Kv.d.p, 1, 0, 1, rho.p,
+                    (int64_t)nt * TP * 2, 2.0, s);
+    h.fxc64.alloc((size_t)nt * TP);
+    alda_kernel<double>((int64_t)nt * TP, rho.p, o.rho_floor, h.fxc64.p, s);
+    TD_HIP(hipStreamSynchronize(s));
+    if (h.stype != SAMPLE_F64) {
+      std::vector<double> tmp((size_t)nt * TP);
+      TD_HIP(hipMemcpy(tmp.data(), h.fxc64.p, tmp.size() * sizeof(double), hipMemcpyDeviceToHost));
+      upload_converted(h.fxc32, tmp, s);
+    }
+  }
+  if (h.stype != SAMPLE_F64) {
+    h.os64.release();
+    h.tiles_oo.usamp = h.tiles_oo.osamp = nullptr;
+  }
+  h.setup_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+}
+
+// ---------------------------------------------------------------------------------------
+template <class T>
+static int stype_of(const Handle &h) {
+  return std::is_same<T, double>::value ? SAMPLE_F64 : h.stype;
+}
+
+template <class T>
+void kshift_sets(Handle &h, int ncol, const T *X, int ldx, int x0, T *F, int ldf, int f0) {
+  h.prof.begin(ST_KSHIFT_LEFT, h.stream);
+  spmm_left<T>(h.pT_left, h.BU, h.BO, h.KcHu.ptr<T>(), X, ldx, x0, F, ldf, f0, ncol, 1.0, false, h.stream);
+  h.prof.end(ST_KSHIFT_LEFT, h.stream);
+  h.prof.begin(ST_KSHIFT_RIGHT, h.stream);
+  spmm_right<T>(h.pT_right, h.BU, h.BO, X, ldx, x0, h.HoKv.ptr<T>(), F, ldf, f0, ncol, -1.0, true, h.stream);
+  h.prof.end(ST_KSHIFT_RIGHT, h.stream);
+}
+
+template <class T>
+void project_sets(Handle &h, int ncol, const T *X, int ldx, int x0, T *F, int ldf, int f0) {
+  T *Y = (T *)h.w_small.get((size_t)h.nM3 * ncol * h.E * sizeof(T));
+  h.prof.begin(ST_PROJECT, h.stream);
+  spmm_left<T>(h.pPi1, h.BU, h.BO, h.KcSu.ptr<T>(), X, ldx, x0, Y, ncol, 0, ncol, 1.0, false, h.stream);
+  spmm_right<T>(h.pPi2, h.BU, h.BO, Y, ncol, 0, h.SoKv.ptr<T>(), F, ldf, f0, ncol, 1.0, false, h.stream);
+  h.prof.end(ST_PROJECT, h.stream);
+}
+
+template <class T>
+void covariant_sets(Handle &h, int ncol, const T *X, int ldx, int x0, T *F, int ldf, int f0) {
+  T *Y = (T *)h.w_small.get((size_t)h.nM4 * ncol * h.E * sizeof(T));
+  h.prof.begin(ST_COVARIANT, h.stream);
+  spmm_left<T>(h.pCov1, h.BU, h.BO, h.Su.ptr<T>(), X, ldx, x0, Y, ncol, 0, ncol, 1.0, false, h.stream);
+  spmm_right<T>(h.pCov2, h.BU, h.BO, Y, ncol, 0, h.So.ptr<T>(), F, ldf, f0, ncol, 1.0, false, h.stream);
+  h.prof.end(ST_COVARIANT, h.stream);
+}
+
+template <class T>
+void apply_sets(Handle &h, int n, const T *X, int ldx, int xp0, int xq0, T *F, int ldf, int fp0,
+                int fq0, bool coupling) {
+  hipStream_t s = h.stream;
+  if (xq0 == xp0 + n && fq0 == fp0 + n) {
+    kshift_sets<T>(h, 2 * n, X, ldx, xp0, F, ldf, fp0);
+  } else {
+    kshift_sets<T>(h, n, X, ldx, xp0, F, ldf, fp0);
+    kshift_sets<T>(h, n, X, ldx, xq0, F, ldf, fq0);
+  }
+  if (!coupling || h.opts.xc == TDDFT_HXC_NONE) return;
+  const int npair = (n + 1) / 2;
+  const int64_t pstride = (int64_t)h.nt * TP * 2;
+  const int64_t wstride = (int64_t)h.n[0] * h.n[1] * h.n[2] * 2;
+  const size_t bytes_f = (size_t)npair * pstride * sizeof(T);
+  const size_t bytes_w = (size_t)npair * wstride * sizeof(T);
+  const size_t bytes_v = (size_t)h.nO * n * h.E * sizeof(T);
+  const size_t bytes_y = (size_t)h.nM2 * n * h.E * sizeof(T);
+  unsigned char *base = (unsigned char *)h.w_apply.get(bytes_f + bytes_w + bytes_v + bytes_y + 1024);
+  T *fields = (T *)base;
+  T *work = (T *)(base + bytes_f);
+  T *Vset = (T *)(base + bytes_f + bytes_w);
+  T *Y = (T *)(base + bytes_f + bytes_w + bytes_v);
+  const int st = stype_of<T>(h);
+  DevTiles tl = h.tiles_uo;
+  tl.usamp = h.usamp();
+  tl.osamp = h.osamp();
+  h.prof.begin(ST_DENSITY, s);
+  density<T>(tl, st, h.BU, h.BO, X, ldx, xq0, n, fields, pstride, 1.0, s);
+  h.prof.end(ST_DENSITY, s);
+  hartree_xc<T>(h.geom, h.fft, npair, fields, work, h.fxc<T>(), h.opts.xc == TDDFT_XC_ALDA_X, s, &h.prof);
+  h.prof.begin(ST_VINT_ZERO, s);
+  fill<T>(Vset, (int64_t)h.nO * n * h.E, T(0), s);
+  h.prof.end(ST_VINT_ZERO, s);
+  // states in chunks whose brick accumulators fit in LDS (chunk starts are even)
+  h.prof.begin(ST_VINT, s);
+  int chunk = n;
+  while (chunk > 2 && vint_lds_bytes(h, chunk, sizeof(T)) > h.lds_limit) chunk = (chunk + 1) / 2 + ((chunk + 1) / 2) % 2;
+  for (int s0 = 0; s0 < n; s0 += chunk) {
+    const int ns = std::min(chunk, n - s0);
+    // Vout columns s0.. of a set with n columns: offset the pointer by s0 * E
+    potential_integrals<T>(tl, h.bricks, st, h.BU, h.BO, fields + (int64_t)(s0 / 2) * pstride, pstride,
+                           ns, Vset + (size_t)s0 * h.E, n, h.dV, s);
+  }
+  h.prof.end(ST_VINT, s);
+  h.prof.begin(ST_SANDWICH_LEFT, s);
+  spmm_left<T>(h.pSw1, h.BU, h.BO, h.Kc.ptr<T>(), Vset, n, 0, Y, n, 0, n, 1.0, false, s);
+  h.prof.end(ST_SANDWICH_LEFT, s);
+  h.prof.begin(ST_SANDWICH_RIGHT, s);
+  spmm_right<T>(h.pSw2, h.BU, h.BO, Y, n, 0, h.Kv.ptr<T>(), F, ldf, fq0, n,
+                2.0 * h.opts.coupling_scale, true, s);
+  h.prof.end(ST_SANDWICH_RIGHT, s);
+}
+
+#define TD_INST_APPLY(T)                                                                      \
+  template void apply_sets<T>(Handle &, int, const T *, int, int, int, T *, int, int, int, bool); \
+  template void kshift_sets<T>(Handle &, int, const T *, int, int, T *, int, int);             \
+  template void project_sets<T>(Handle &, int, const T *, int, int, T *, int, int);            \
+  template void covariant_sets<T>(Handle &, int, const T *, int, int, T *, int, int);
+
+TD_INST_APPLY(double)
+TD_INST_APPLY(float)
+
+}  // namespace tddft

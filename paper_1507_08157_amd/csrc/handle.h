@@ -1,0 +1,129 @@
+// The per-system handle: device-resident inputs, plans and workspaces.
+#pragma once
+
+#include <chrono>
+#include <string>
+#include <vector>
+
+#include "internal.h"
+#include "kernels.h"
+
+namespace tddft {
+
+Pattern transpose(const Pattern &A);
+Pattern intersect(const Pattern &A, const Pattern &B);
+bool fft_factor(int n, std::vector<int> &radix);
+void build_fft_plan(FFTPlan &pl, const int n[3], hipStream_t s);
+
+// fixed matrix on device in both working precisions
+struct DevMat {
+  Pattern pat;
+  int br = 0, bc = 0;
+  DevBuf<double> d;
+  DevBuf<float> f;
+  void upload(const HostBsr &m, hipStream_t s);
+  template <class T> const T *ptr() const;
+};
+template <> inline const double *DevMat::ptr<double>() const { return d.p; }
+template <> inline const float *DevMat::ptr<float>() const { return f.p; }
+
+// growable device workspace
+struct Work {
+  DevBuf<unsigned char> buf;
+  void *get(size_t bytes) {
+    if (bytes > buf.n) buf.alloc(bytes + bytes / 4);
+    return buf.p;
+  }
+};
+
+struct Handle {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  tddft_options opts{};
+  int precision = TDDFT_FP64;
+  int stype = SAMPLE_F64;
+  size_t lds_limit = 65536;
+  std::string last_error;
+  double setup_ms = 0.0;
+
+  // geometry
+  int n[3] = {0, 0, 0};
+  double L[3] = {0, 0, 0};
+  double dV = 0.0;
+  GridGeom geom{};
+  int nt = 0;
+
+  // blocks
+  int nbu = 0, nbo = 0, BU = 0, BO = 0, E = 0;
+  std::vector<int> uoff, ooff;
+  int n_u = 0, n_o = 0;
+
+  // pattern M and its C-ABI value layout
+  Pattern M;
+  int64_t nnzM = 0;            // values of one response kernel in the C-ABI layout
+  DevBuf<int64_t> m_voff;      // per block: offset into the C-ABI values
+  DevBuf<int32_t> m_shape;     // per block: rows | cols << 8
+
+  // fixed matrices
+  DevMat KcHu, HoKv, KcSu, SoKv, Su, So, Kc, Kv;
+  // masked-product plans
+  DevPlan pT_left, pT_right, pPi1, pPi2, pCov1, pCov2, pSw1, pSw2;
+  int64_t nM = 0, nM2 = 0, nM3 = 0, nM4 = 0, nO = 0;
+
+  // tiles and bricks
+  DevBuf<int32_t> t_uptr, t_optr, t_pidx_uo, t_pidx_oo;
+  DevBuf<int64_t> t_pptr_uo, t_pptr_oo;
+  DevBuf<double> us64, os64;
+  DevBuf<float> us32, os32;
+  DevBuf<__hip_bfloat16> us16, os16;
+  DevTiles tiles_uo{}, tiles_oo{};
+  int maxrows_uo = 0, maxrows_oo = 0;
+  int brick_edge = 2;
+  DevBuf<int32_t> b_tptr, b_tiles, b_nu, b_no, b_slot, b_ubl, b_obl;
+  DevBuf<int64_t> b_sptr;
+  DevBricks bricks{};
+  double mean_u_per_tile = 0, mean_o_per_tile = 0;
+  int64_t pair_points = 0;     // sum over tiles of (u rows * o rows) * TP (work measure)
+  int64_t sample_rows_u = 0, sample_rows_o = 0;
+
+  // ground state
+  DevBuf<double> fxc64;
+  DevBuf<float> fxc32;
+  FFTPlan fft;
+
+  // workspaces
+  Work w_apply, w_pcg, w_small;
+  DevBuf<double> partial;      // gram partial sums
+  DevBuf<double> small_dev;    // coefficient / result staging
+  int max_parts = 256;
+
+  // timing
+  hipEvent_t ev0 = nullptr, ev1 = nullptr;
+  Prof prof;
+
+  ~Handle();
+  template <class T> const T *fxc() const;
+  const void *usamp() const;
+  const void *osamp() const;
+};
+template <> inline const double *Handle::fxc<double>() const { return fxc64.p; }
+template <> inline const float *Handle::fxc<float>() const { return fxc32.p; }
+
+void create_handle(Handle &h, const tddft_system &sys, const tddft_options &o);
+
+// ---- operator application on column sets (internal precision T) ---------------------------
+// X: column set on M with ld columns; p columns [xp0, xp0 + n), q columns [xq0, xq0 + n).
+template <class T>
+void apply_sets(Handle &h, int n, const T *X, int ldx, int xp0, int xq0, T *F, int ldf, int fp0,
+                int fq0, bool coupling);
+template <class T>
+void kshift_sets(Handle &h, int ncol, const T *X, int ldx, int x0, T *F, int ldf, int f0);
+template <class T>
+void project_sets(Handle &h, int ncol, const T *X, int ldx, int x0, T *F, int ldf, int f0);
+template <class T>
+void covariant_sets(Handle &h, int ncol, const T *X, int ldx, int x0, T *F, int ldf, int f0);
+
+int pcg_solve(Handle &h, int n, const tddft_options &o, double *omega, double *Pp, double *Pq,
+              tddft_stats *stats);
+
+}  // namespace tddft

@@ -1,0 +1,96 @@
+// Launch wrappers of the HIP kernels (host-callable).
+#pragma once
+
+#include "internal.h"
+
+namespace tddft {
+
+// ---- column-set linear combinations ------------------------------------------------------
+struct LcSrc {
+  const void *X;
+  int ldx, xc0, nin;
+  const double *C;   // device [nout][nin]
+};
+struct LcArgs {
+  void *Y;
+  int ldy, yc0, nout;
+  const double *beta;  // device [nout] or nullptr (overwrite)
+  int nsrc;
+  LcSrc src[3];
+};
+
+template <class T>
+void spmm_left(const DevPlan &pl, int bu, int bo, const T *A, const T *X, int ldx, int xc0,
+               T *C, int ldc, int cc0, int ncol, double alpha, bool acc, hipStream_t s);
+template <class T>
+void spmm_right(const DevPlan &pl, int bu, int bo, const T *X, int ldx, int xc0, const T *B,
+                T *C, int ldc, int cc0, int ncol, double alpha, bool acc, hipStream_t s);
+template <class T>
+void lincomb(int64_t nblk, int E, const LcArgs &a, hipStream_t s);
+template <class T>
+void gram(int64_t nblk, int E, const T *X, int ldx, int xc0, int n1, const T *Y, int ldy,
+          int yc0, int n2, bool diag, double *partial, int max_parts, double *out,
+          hipStream_t s);
+template <class T>
+void pack(int64_t nblk, int BU, int BO, int ns, const double *src, int64_t nnz,
+          const int64_t *voff, const int32_t *shape, T *X, int ldx, int xc0, hipStream_t s);
+template <class T>
+void unpack(int64_t nblk, int BU, int BO, int ns, const T *X, int ldx, int xc0,
+            const int64_t *voff, const int32_t *shape, double *dst, int64_t nnz, hipStream_t s);
+template <class T>
+void fill(T *p, int64_t n, T v, hipStream_t s);
+
+// ---- grid ----------------------------------------------------------------------------------
+// device view of a tile set (lists and sample rows of two function sets)
+struct DevTiles {
+  int nt = 0;
+  int maxrows = 0;          // max over tiles of (n_left_atoms * BL + n_right_atoms * BR)
+  const int32_t *uptr = nullptr, *optr = nullptr;   // [nt + 1]
+  const int64_t *pptr = nullptr;                    // [nt + 1]
+  const int32_t *pidx = nullptr;                    // pair -> block index (or -1)
+  const void *usamp = nullptr, *osamp = nullptr;    // rows of TP samples
+};
+
+struct DevBricks {
+  int nb = 0;
+  int max_tiles = 0, max_slots = 0, max_rows = 0;
+  const int32_t *tptr = nullptr, *tiles = nullptr;   // tiles of each brick
+  const int32_t *nu = nullptr, *no = nullptr;        // union list sizes per brick
+  const int64_t *sptr = nullptr;                     // [nb + 1] slot table offsets
+  const int32_t *slot_blk = nullptr;                 // slot -> O block (or -1)
+  const int32_t *ubl = nullptr, *obl = nullptr;      // per tile-list entry: brick-local index
+};
+
+enum SampleType { SAMPLE_F64 = 0, SAMPLE_F32 = 1, SAMPLE_BF16 = 2 };
+
+// rho_s(r) = scale * sum_{a,b} left_a(r) X_s[a,b] right_b(r), written tile-major as complex
+// pairs: out[(s/2) * pair_stride + (t * TP + p) * 2 + (s & 1)]
+template <class T>
+void density(const DevTiles &tl, int stype, int BL, int BR, const T *X, int ldx, int xc0,
+             int ns, T *out, int64_t pair_stride, double scale, hipStream_t s);
+
+// Vout[blk][ldv][E] += scale * sum_r left_a(r) V_s(r) right_b(r) over the tiles of every
+// brick (V tile-major complex pairs); Vout must be zeroed first
+template <class T>
+void potential_integrals(const DevTiles &tl, const DevBricks &br, int stype, int BL, int BR,
+                         const T *V, int64_t pair_stride, int ns, T *Vout, int ldv,
+                         double scale, hipStream_t s);
+
+// f_xc from rho0 (real parts of a tile-major pair array): ALDA exchange kernel
+template <class T>
+void alda_kernel(int64_t npts, const T *rho_pairs, double floor, T *fxc, hipStream_t s);
+
+// ---- FFT / Poisson --------------------------------------------------------------------------
+struct GridGeom {
+  int n[3];
+  double L[3];
+  int ntx, nty, ntz;
+};
+
+// V = (V_H[rho] + fxc * rho) for npair complex-packed fields, tile-major in/out:
+// fields[pair][tile][TP] complex; work: [pair][n_z][n_y][n_x] complex
+template <class T>
+void hartree_xc(const GridGeom &g, const FFTPlan &plan, int npair, T *fields, T *work,
+                const T *fxc, bool use_fxc, hipStream_t s, Prof *prof);
+
+}  // namespace tddft

@@ -1,0 +1,693 @@
+// Preconditioned conjugate-gradient minimisation of the multi-state Tsiper functional
+// (Secs. III.A-III.C).  Trial vectors, operator images and search directions stay on the
+// GPU as column sets in the working precision; every trace is reduced in FP64 and the
+// small N_omega x N_omega algebra (orthonormalisation, line search, subspace
+// diagonalisation) runs in FP64 on the host.
+//
+// Choices the main text leaves open (its listings are in unavailable supplementary
+// material):
+//  * Tsiper orthonormality B_ij = 1/2 (<p_i,q_j> + <p_j,q_i>) = delta_ij (Eq. ortho), sign
+//    rule q_i -> -q_i when <p_i,q_i> < 0, then Gram-Schmidt in index order;
+//  * N_ij = 1/2 (<p_j,f^p_i> + <q_j,f^q_i>) symmetrised, omega = eig(N) when B = I;
+//  * gradient g_i = F_i - sum_j N_ij (q_j, p_j) (Sec. III.C);
+//  * preconditioner: CG on K^c H^u G - G H^o K^v = g in the S metric to relative residual
+//    eps_tol (Sec. III.B, Eq. precond);
+//  * every direction projected by P = K^c S^u L S^o K^v restricted to M (Eq. auxiliary);
+//  * Polak-Ribiere(+) with a common step for all states and an exact line search on
+//    Tr[N(lambda) B(lambda)^-1]; F carried by linearity and refreshed periodically.
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <functional>
+#include <limits>
+
+#include "handle.h"
+
+namespace tddft {
+
+namespace {
+
+using Mat = std::vector<double>;   // row-major n x n
+
+// ---- small dense FP64 linear algebra ------------------------------------------------------
+bool cholesky(const Mat &A, int n, Mat &L) {
+  L.assign((size_t)n * n, 0.0);
+  for (int j = 0; j < n; ++j) {
+    double d = A[j * n + j];
+    for (int k = 0; k < j; ++k) d -= L[j * n + k] * L[j * n + k];
+    if (!(d > 0.0)) return false;
+    L[j * n + j] = std::sqrt(d);
+    for (int i = j + 1; i < n; ++i) {
+      double s = A[i * n + j];
+      for (int k = 0; k < j; ++k) s -= L[i * n + k] * L[j * n + k];
+      L[i * n + j] = s / L[j * n + j];
+    }
+  }
+  return true;
+}
+
+// cyclic Jacobi eigen-decomposition of a symmetric matrix; V columns are eigenvectors,
+// eigenvalues ascending
+void sym_eig(const Mat &A0, int n, std::vector<double> &w, Mat &V) {
+  Mat A = A0;
+  V.assign((size_t)n * n, 0.0);
+  for (int i = 0; i < n; ++i) V[i * n + i] = 1.0;
+  for (int sweep = 0; sweep < 100; ++sweep) {
+    double off = 0.0, tot = 0.0;
+    for (int i = 0; i < n; ++i)
+      for (int j = 0; j < n; ++j) {
+        tot += A[i * n + j] * A[i * n + j];
+        if (i != j) off += A[i * n + j] * A[i * n + j];
+      }
+    if (off <= 1e-30 * tot || off == 0.0) break;
+    for (int p = 0; p < n; ++p)
+      for (int q = p + 1; q < n; ++q) {
+        const double apq = A[p * n + q];
+        if (apq == 0.0) continue;
+        const double theta = (A[q * n + q] - A[p * n + p]) / (2.0 * apq);
+        const double t = (theta >= 0 ? 1.0 : -1.0) / (std::fabs(theta) + std::sqrt(theta * theta + 1.0));
+        const double c = 1.0 / std::sqrt(t * t + 1.0), s = t * c;
+        for (int k = 0; k < n; ++k) {
+          const double akp = A[k * n + p], akq = A[k * n + q];
+          A[k * n + p] = c * akp - s * akq;
+          A[k * n + q] = s * akp + c * akq;
+        }
+        for (int k = 0; k < n; ++k) {
+          const double apk = A[p * n + k], aqk = A[q * n + k];
+          A[p * n + k] = c * apk - s * aqk;
+          A[q * n + k] = s * apk + c * aqk;
+        }
+        for (int k = 0; k < n; ++k) {
+          const double vkp = V[k * n + p], vkq = V[k * n + q];
+          V[k * n + p] = c * vkp - s * vkq;
+          V[k * n + q] = s * vkp + c * vkq;
+        }
+      }
+  }
+  std::vector<int> idx(n);
+  for (int i = 0; i < n; ++i) idx[i] = i;
+  std::sort(idx.begin(), idx.end(), [&](int a, int b) { return A[a * n + a] < A[b * n + b]; });
+  w.resize(n);
+  Mat V2((size_t)n * n);
+  for (int k = 0; k < n; ++k) {
+    w[k] = A[idx[k] * n + idx[k]];
+    for (int i = 0; i < n; ++i) V2[i * n + k] = V[i * n + idx[k]];
+  }
+  V = V2;
+}
+
+Mat sym(const Mat &A, int n) {
+  Mat S(A.size());
+  for (int i = 0; i < n; ++i)
+    for (int j = 0; j < n; ++j) S[i * n + j] = 0.5 * (A[i * n + j] + A[j * n + i]);
+  return S;
+}
+
+// Tr[N B^-1] via B = L L^T; +inf when B is not positive definite
+double trace_nbinv(const Mat &N, const Mat &B, int n) {
+  Mat L;
+  if (!cholesky(B, n, L)) return std::numeric_limits<double>::infinity();
+  // X = L^-1 N L^-T; trace
+  Mat Y((size_t)n * n);  // Y = L^-1 N
+  for (int c = 0; c < n; ++c)
+    for (int i = 0; i < n; ++i) {
+      double s = N[i * n + c];
+      for (int k = 0; k < i; ++k) s -= L[i * n + k] * Y[k * n + c];
+      Y[i * n + c] = s / L[i * n + i];
+    }
+  double tr = 0.0;  // trace of Y L^-T = sum_i (L^-1 Y^T)_ii
+  Mat Z((size_t)n * n);  // Z = L^-1 Y^T
+  for (int c = 0; c < n; ++c)
+    for (int i = 0; i < n; ++i) {
+      double s = Y[c * n + i];
+      for (int k = 0; k < i; ++k) s -= L[i * n + k] * Z[k * n + c];
+      Z[i * n + c] = s / L[i * n + i];
+    }
+  for (int i = 0; i < n; ++i) tr += Z[i * n + i];
+  return tr;
+}
+
+// Brent's minimiser (golden section with parabolic steps) on [a, b]
+double brent_min(const std::function<double(double)> &f, double a, double b, double tol) {
+  const double cg = 0.3819660112501051;
+  double x = a + cg * (b - a), w = x, v = x;
+  double fx = f(x), fw = fx, fv = fx;
+  double d = 0.0, e = 0.0;
+  for (int it = 0; it < 200; ++it) {
+    const double m = 0.5 * (a + b);
+    const double t1 = tol * std::fabs(x) + 1e-300, t2 = 2.0 * t1;
+    if (std::fabs(x - m) <= t2 - 0.5 * (b - a)) break;
+    bool golden = true;
+    if (std::fabs(e) > t1) {
+      double r = (x - w) * (fx - fv);
+      double q = (x - v) * (fx - fw);
+      double p = (x - v) * q - (x - w) * r;
+      q = 2.0 * (q - r);
+      if (q > 0) p = -p;
+      q = std::fabs(q);
+      const double etmp = e;
+      e = d;
+      if (std::fabs(p) < std::fabs(0.5 * q * etmp) && p > q * (a - x) && p < q * (b - x)) {
+        d = p / q;
+        const double u = x + d;
+        if (u - a < t2 || b - u < t2) d = (m >= x) ? t1 : -t1;
+        golden = false;
+      }
+    }
+    if (golden) {
+      e = (x >= m) ? a - x : b - x;
+      d = cg * e;
+    }
+    const double u = std::fabs(d) >= t1 ? x + d : x + (d > 0 ? t1 : -t1);
+    const double fu = f(u);
+    if (fu <= fx) {
+      if (u >= x) a = x; else b = x;
+      v = w; fv = fw; w = x; fw = fx; x = u; fx = fu;
+    } else {
+      if (u < x) a = u; else b = u;
+      if (fu <= fw || w == x) { v = w; fv = fw; w = u; fw = fu; }
+      else if (fu <= fv || v == x || v == w) { v = u; fv = fu; }
+    }
+  }
+  return x;
+}
+
+// Tsiper Gram-Schmidt: transforms with p' = Tp p, q' = Tq q and 1/2 (C' + C'^T) = I
+bool orthonormalise(const Mat &C, int n, Mat &Tp, Mat &Tq) {
+  Tp.assign((size_t)n * n, 0.0);
+  Tq.assign((size_t)n * n, 0.0);
+  for (int i = 0; i < n; ++i) {
+    Tp[i * n + i] = 1.0;
+    Tq[i * n + i] = C[i * n + i] < 0 ? -1.0 : 1.0;   // sign rule before orthogonalising
+  }
+  auto cprime = [&](int i, int j) {  // (Tp C Tq^T)_ij
+    double s = 0.0;
+    for (int a = 0; a < n; ++a) {
+      if (Tp[i * n + a] == 0.0) continue;
+      for (int b = 0; b < n; ++b) s += Tp[i * n + a] * C[a * n + b] * Tq[j * n + b];
+    }
+    return s;
+  };
+  for (int i = 0; i < n; ++i) {
+    for (int j = 0; j < i; ++j) {
+      const double c = 0.5 * (cprime(i, j) + cprime(j, i));
+      for (int k = 0; k < n; ++k) {
+        Tp[i * n + k] -= c * Tp[j * n + k];
+        Tq[i * n + k] -= c * Tq[j * n + k];
+      }
+    }
+    const double b = cprime(i, i);
+    if (!(b > 0.0)) return false;
+    const double sc = 1.0 / std::sqrt(b);
+    for (int k = 0; k < n; ++k) {
+      Tp[i * n + k] *= sc;
+      Tq[i * n + k] *= sc;
+    }
+  }
+  return true;
+}
+
+// ---- device helpers ------------------------------------------------------------------------
+template <class T>
+struct Solver {
+  Handle &h;
+  int n, nc;                 // states, columns (2n)
+  int64_t nM;
+  int E;
+  hipStream_t s;
+  std::vector<T *> sets;
+  DevBuf<unsigned char> arena;
+  // pinned host and device staging for coefficients and results
+  double *hstage = nullptr;
+  DevBuf<double> dstage;
+  size_t stage_cap = 1 << 17, stage_off = 0;   // doubles
+  DevBuf<double> dres;
+  size_t res_off = 0;
+
+  Solver(Handle &h_, int n_) : h(h_), n(n_), nc(2 * n_), nM(h_.nM), E(h_.E), s(h_.stream) {
+    TD_HIP(hipHostMalloc((void **)&hstage, stage_cap * sizeof(double), hipHostMallocDefault));
+    dstage.alloc(stage_cap);
+    dres.alloc(1 << 16);
+  }
+  ~Solver() {
+    if (hstage) (void)hipHostFree(hstage);
+  }
+  size_t set_elems() const { return (size_t)nM * nc * E; }
+  void alloc_sets(int count) {
+    const size_t bytes = set_elems() * sizeof(T);
+    arena.alloc(bytes * count);
+    sets.resize(count);
+    for (int i = 0; i < count; ++i) sets[i] = (T *)(arena.p + bytes * i);
+  }
+  void sync() {
+    TD_HIP(hipStreamSynchronize(s));
+    stage_off = 0;
+  }
+  const double *coef(const Mat &c) {
+    if (stage_off + c.size() > stage_cap) sync();
+    double *hp = hstage + stage_off;
+    std::copy(c.begin(), c.end(), hp);
+    double *dp = dstage.p + stage_off;
+    TD_HIP(hipMemcpyAsync(dp, hp, c.size() * sizeof(double), hipMemcpyHostToDevice, s));
+    stage_off += (c.size() + 31) & ~(size_t)31;
+    return dp;
+  }
+  // ---- column-set algebra
+  // Y = sum of up to 3 sources with coefficient matrices [nout][nin] (+ beta Y)
+  void lc(T *Y, int yc0, int nout, const double *beta, std::initializer_list<std::pair<const T *, Mat>> src,
+          int xc0 = 0, int nin = -1) {
+    LcArgs a{};
+    a.Y = Y;
+    a.ldy = nc;
+    a.yc0 = yc0;
+    a.nout = nout;
+    a.beta = beta;
+    a.nsrc = 0;
+    for (auto &sr : src) {
+      LcSrc &x = a.src[a.nsrc++];
+      x.X = sr.first;
+      x.ldx = nc;
+      x.xc0 = xc0;
+      x.nin = nin < 0 ? nout : nin;
+      x.C = coef(sr.second);
+    }
+    h.prof.begin(ST_LINCOMB, s);
+    lincomb<T>(nM, E, a, s);
+    h.prof.end(ST_LINCOMB, s);
+  }
+  Mat eye(int m, double v = 1.0) {
+    Mat I((size_t)m * m, 0.0);
+    for (int i = 0; i < m; ++i) I[i * m + i] = v;
+    return I;
+  }
+  Mat diag(const std::vector<double> &d) {
+    const int m = (int)d.size();
+    Mat D((size_t)m * m, 0.0);
+    for (int i = 0; i < m; ++i) D[i * m + i] = d[i];
+    return D;
+  }
+  // Y = a X + b Z elementwise over all columns (scalars)
+  void axpby(T *Y, double a, const T *X, double b, const T *Z) {
+    lc(Y, 0, nc, nullptr, {{X, eye(nc, a)}, {Z, eye(nc, b)}});
+  }
+  void axpy_inplace(T *Y, double a, const T *X) {   // Y += a X
+    std::vector<double> one(nc, 1.0);
+    const double *bt = coef(one);
+    lc(Y, 0, nc, bt, {{X, eye(nc, a)}});
+  }
+  void copy(T *Y, const T *X) { lc(Y, 0, nc, nullptr, {{X, eye(nc)}}); }
+  // block-diagonal transform [[Tp,0],[0,Tq]] applied to columns: Y = T X
+  void transform(T *Y, const T *X, const Mat &Tp, const Mat &Tq) {
+    Mat B((size_t)nc * nc, 0.0);
+    for (int i = 0; i < n; ++i)
+      for (int j = 0; j < n; ++j) {
+        B[i * nc + j] = Tp[i * n + j];
+        B[(n + i) * nc + n + j] = Tq[i * n + j];
+      }
+    lc(Y, 0, nc, nullptr, {{X, B}});
+  }
+  // ---- reductions (results queued in dres, fetched by fetch())
+  size_t gram_q(const T *X, int xc0, int n1, const T *Y, int yc0, int n2, bool dg) {
+    const int np = dg ? n1 : n1 * n2;
+    if (res_off + np > dres.n) throw Error{TDDFT_E_DEVICE, "result staging overflow"};
+    const size_t at = res_off;
+    h.prof.begin(ST_GRAM, s);
+    gram<T>(nM, E, X, nc, xc0, n1, Y, nc, yc0, n2, dg, h.partial.p, h.max_parts, dres.p + at, s);
+    h.prof.end(ST_GRAM, s);
+    res_off += np;
+    return at;
+  }
+  std::vector<double> fetch() {
+    std::vector<double> out(res_off);
+    if (res_off) TD_HIP(hipMemcpyAsync(out.data(), dres.p, res_off * sizeof(double), hipMemcpyDeviceToHost, s));
+    sync();
+    res_off = 0;
+    return out;
+  }
+};
+
+}  // namespace
+
+// ---------------------------------------------------------------------------------------
+template <class T>
+static int solve_impl(Handle &h, int n, const tddft_options &o, double *omega, double *Pp,
+                      double *Pq, tddft_stats *st) {
+  const auto t_start = std::chrono::steady_clock::now();
+  auto elapsed_ms = [&]() {
+    return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_start).count();
+  };
+  Solver<T> S(h, n);
+  const int nc = 2 * n;
+  enum { P, F, Pc, D, FD, Dc, G_, Gc, Gr, Grc, Gp, Grp, Grcp, Rr, Rc, K, Kc, LK, LKc, Gs, Tmp, NSET };
+  S.alloc_sets(NSET);
+  auto set = [&](int i) { return S.sets[i]; };
+  hipStream_t s = h.stream;
+  int applies = 0, inner_total = 0;
+  float apply_ms = 0.0f;
+  auto apply = [&](const T *X, T *Fo) {
+    TD_HIP(hipEventRecord(h.ev0, s));
+    apply_sets<T>(h, n, X, nc, 0, n, Fo, nc, 0, n, true);
+    TD_HIP(hipEventRecord(h.ev1, s));
+    TD_HIP(hipEventSynchronize(h.ev1));
+    float ms = 0.0f;
+    TD_HIP(hipEventElapsedTime(&ms, h.ev0, h.ev1));
+    apply_ms += ms;
+    ++applies;
+  };
+
+  // ---- initial auxiliary matrices -> P = Pi(L0)
+  {
+    T *L0 = set(Tmp);
+    if (Pp && Pq) {
+      pack<T>(h.nM, h.BU, h.BO, n, Pp, h.nnzM, h.m_voff.p, h.m_shape.p, L0, nc, 0, s);
+      pack<T>(h.nM, h.BU, h.BO, n, Pq, h.nnzM, h.m_voff.p, h.m_shape.p, L0, nc, n, s);
+    } else {
+      // seeded N(0,1) on M (SplitMix64 + Box-Muller), the same matrix for p and q
+      std::vector<double> g((size_t)n * h.nnzM);
+      uint64_t x = o.seed * 0x9E3779B97F4A7C15ull + 0x632BE59BD9B4E019ull;
+      auto next = [&]() {
+        uint64_t z = (x += 0x9E3779B97F4A7C15ull);
+        z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+        z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+        return z ^ (z >> 31);
+      };
+      for (size_t i = 0; i < g.size(); i += 2) {
+        const double u1 = ((next() >> 11) + 0.5) * (1.0 / 9007199254740992.0);
+        const double u2 = ((next() >> 11) + 0.5) * (1.0 / 9007199254740992.0);
+        const double r = std::sqrt(-2.0 * std::log(u1));
+        g[i] = r * std::cos(2.0 * M_PI * u2);
+        if (i + 1 < g.size()) g[i + 1] = r * std::sin(2.0 * M_PI * u2);
+      }
+      DevBuf<double> dg(g.size());
+      dg.upload(g, s);
+      pack<T>(h.nM, h.BU, h.BO, n, dg.p, h.nnzM, h.m_voff.p, h.m_shape.p, L0, nc, 0, s);
+      pack<T>(h.nM, h.BU, h.BO, n, dg.p, h.nnzM, h.m_voff.p, h.m_shape.p, L0, nc, n, s);
+      S.sync();
+    }
+    project_sets<T>(h, nc, L0, nc, 0, set(P), nc, 0);
+    covariant_sets<T>(h, nc, set(P), nc, 0, set(Pc), nc, 0);
+  }
+  Mat Tp, Tq;
+  auto gs_step = [&](std::initializer_list<int> extra_pairs) -> bool {
+    // C = <p_i, q_j>
+    S.gram_q(set(P), 0, n, set(Pc), n, n, false);
+    std::vector<double> C = S.fetch();
+    if (!orthonormalise(C, n, Tp, Tq)) return false;
+    S.transform(set(Tmp), set(P), Tp, Tq);
+    S.copy(set(P), set(Tmp));
+    S.transform(set(Tmp), set(Pc), Tp, Tq);
+    S.copy(set(Pc), set(Tmp));
+    S.transform(set(Tmp), set(F), Tp, Tq);
+    S.copy(set(F), set(Tmp));
+    for (int k : extra_pairs) {
+      S.transform(set(Tmp), set(k), Tp, Tq);
+      S.copy(set(k), set(Tmp));
+    }
+    return true;
+  };
+  if (!gs_step({})) throw Error{TDDFT_E_NOT_PD, "initial trial vectors are linearly dependent in the Tsiper metric"};
+  apply(set(P), set(F));
+
+  std::vector<double> w(n), w_prev(n, 0.0);
+  bool converged = false, have_prev = false, have_dir = false;
+  int it = 0, stalls = 0;
+  const double sqrt_tol = std::sqrt(o.tol_omega);
+  Mat Nm((size_t)n * n);
+  for (it = 0; it <= o.max_iter; ++it) {
+    // N and omega
+    const size_t qN = S.gram_q(set(F), 0, nc, set(Pc), 0, nc, false);
+    std::vector<double> r = S.fetch();
+    for (int i = 0; i < n; ++i)
+      for (int j = 0; j < n; ++j)
+        Nm[i * n + j] = 0.5 * (r[qN + (size_t)i * nc + j] + r[qN + (size_t)(n + i) * nc + n + j]);
+    Nm = sym(Nm, n);
+    Mat V;
+    sym_eig(Nm, n, w, V);
+    // gradient g = F - N (q, p)
+    {
+      Mat Cg((size_t)nc * nc, 0.0);
+      for (int i = 0; i < n; ++i)
+        for (int j = 0; j < n; ++j) {
+          Cg[i * nc + n + j] = -Nm[i * n + j];
+          Cg[(n + i) * nc + j] = -Nm[i * n + j];
+        }
+      S.lc(set(Gr), 0, nc, nullptr, {{set(F), S.eye(nc)}, {set(P), Cg}});
+      covariant_sets<T>(h, nc, set(Gr), nc, 0, set(Grc), nc, 0);
+    }
+    const size_t qg = S.gram_q(set(Gr), 0, nc, set(Grc), 0, nc, true);
+    r = S.fetch();
+    double gmax = 0.0;
+    for (int i = 0; i < n; ++i) gmax = std::max(gmax, std::sqrt(std::max(0.0, r[qg + i] + r[qg + n + i])));
+    if (st && st->log_omega && st->log_len < st->log_capacity) {
+      for (int i = 0; i < n; ++i) st->log_omega[(size_t)st->log_len * n + i] = w[i];
+      if (st->log_time_ms) st->log_time_ms[st->log_len] = elapsed_ms();
+      if (st->log_gnorm) st->log_gnorm[st->log_len] = gmax;
+      st->log_len++;
+    }
+    for (double v : w)
+      if (!std::isfinite(v)) throw Error{TDDFT_E_NOT_PD, "non-finite Tsiper functional"};
+    if (have_prev) {
+      double dw = 0.0;
+      for (int i = 0; i < n; ++i) dw = std::max(dw, std::fabs(w[i] - w_prev[i]));
+      if (dw < o.tol_omega && gmax < sqrt_tol) {
+        converged = true;
+        break;
+      }
+    }
+    if (it == o.max_iter) break;
+    w_prev = w;
+    have_prev = true;
+
+    // ---- preconditioner: CG on L(G) = g (S metric), per column
+    if (o.precond == TDDFT_PC_NONE) {
+      S.copy(set(Gs), set(Gr));
+    } else {
+      T *R = set(Rr), *Rcv = set(Rc), *Kd = set(K), *Kdc = set(Kc), *L = set(LK), *Lc = set(LKc), *Gsol = set(Gs);
+      S.copy(R, set(Gr));
+      S.copy(Rcv, set(Grc));
+      S.copy(Kd, set(Gr));
+      S.copy(Kdc, set(Grc));
+      fill<T>(Gsol, (int64_t)S.set_elems(), T(0), s);
+      const size_t q0 = S.gram_q(R, 0, nc, Rcv, 0, nc, true);
+      r = S.fetch();
+      std::vector<double> rr(r.begin() + q0, r.begin() + q0 + nc), rr0 = rr;
+      std::vector<char> active(nc);
+      for (int c = 0; c < nc; ++c) active[c] = rr0[c] > 0.0;
+      std::vector<int> steps(nc, 0);
+      const double tol2 = o.eps_tol * o.eps_tol;
+      for (int k = 0; k < o.max_inner; ++k) {
+        bool any = false;
+        for (int c = 0; c < nc; ++c) {
+          if (active[c] && !(rr[c] > tol2 * rr0[c])) active[c] = 0;
+          any |= (bool)active[c];
+        }
+        if (!any) break;
+        kshift_sets<T>(h, nc, Kd, nc, 0, L, nc, 0);
+        const size_t qd = S.gram_q(L, 0, nc, Kdc, 0, nc, true);
+        r = S.fetch();
+        std::vector<double> alpha(nc, 0.0);
+        any = false;
+        for (int c = 0; c < nc; ++c) {
+          if (active[c] && !(r[qd + c] > 0.0)) active[c] = 0;
+          if (active[c]) alpha[c] = rr[c] / r[qd + c];
+          any |= (bool)active[c];
+        }
+        if (!any) break;
+        covariant_sets<T>(h, nc, L, nc, 0, Lc, nc, 0);
+        std::vector<double> ones(nc, 1.0), nalpha(nc);
+        for (int c = 0; c < nc; ++c) nalpha[c] = -alpha[c];
+        const double *b1 = S.coef(ones);
+        S.lc(Gsol, 0, nc, b1, {{Kd, S.diag(alpha)}});
+        S.lc(R, 0, nc, b1, {{L, S.diag(nalpha)}});
+        S.lc(Rcv, 0, nc, b1, {{Lc, S.diag(nalpha)}});
+        const size_t qr = S.gram_q(R, 0, nc, Rcv, 0, nc, true);
+        r = S.fetch();
+        std::vector<double> beta(nc, 1.0);
+        for (int c = 0; c < nc; ++c) {
+          if (active[c]) {
+            beta[c] = rr[c] > 0.0 ? r[qr + c] / rr[c] : 0.0;
+            rr[c] = r[qr + c];
+            steps[c]++;
+          }
+        }
+        // K = R + beta K on active columns (inactive keep K: beta 1, coefficient 0)
+        std::vector<double> keep(nc), take(nc);
+        for (int c = 0; c < nc; ++c) {
+          keep[c] = active[c] ? beta[c] : 1.0;
+          take[c] = active[c] ? 1.0 : 0.0;
+        }
+        const double *bk = S.coef(keep);
+        S.lc(Kd, 0, nc, bk, {{R, S.diag(take)}});
+        S.lc(Kdc, 0, nc, bk, {{Rcv, S.diag(take)}});
+        inner_total++;
+      }
+      // columns that never stepped keep G = g
+      std::vector<double> fromG(nc), fromg(nc);
+      for (int c = 0; c < nc; ++c) {
+        fromG[c] = steps[c] > 0 ? 1.0 : 0.0;
+        fromg[c] = steps[c] > 0 ? 0.0 : 1.0;
+      }
+      S.lc(set(Tmp), 0, nc, nullptr, {{Gsol, S.diag(fromG)}, {set(Gr), S.diag(fromg)}});
+      S.copy(Gsol, set(Tmp));
+    }
+    // projection of the preconditioned gradient, and its covariant form
+    project_sets<T>(h, nc, set(Gs), nc, 0, set(G_), nc, 0);
+    covariant_sets<T>(h, nc, set(G_), nc, 0, set(Gc), nc, 0);
+
+    // Polak-Ribiere(+)
+    double beta = 0.0;
+    const bool restart = !have_dir || (o.restart > 0 && it % o.restart == 0);
+    if (!restart) {
+      const size_t qa = S.gram_q(set(G_), 0, nc, set(Grc), 0, nc, true);
+      const size_t qb = S.gram_q(set(G_), 0, nc, set(Grcp), 0, nc, true);
+      const size_t qc = S.gram_q(set(Gp), 0, nc, set(Grcp), 0, nc, true);
+      r = S.fetch();
+      double num = 0.0, den = 0.0;
+      for (int c = 0; c < nc; ++c) {
+        num += r[qa + c] - r[qb + c];
+        den += r[qc + c];
+      }
+      if (den > 0.0) beta = std::max(0.0, num / den);
+    }
+    if (beta > 0.0) {
+      std::vector<double> bv(nc, beta);
+      const double *bb = S.coef(bv);
+      S.lc(set(D), 0, nc, bb, {{set(G_), S.eye(nc, -1.0)}});
+      S.lc(set(Dc), 0, nc, bb, {{set(Gc), S.eye(nc, -1.0)}});
+    } else {
+      S.lc(set(D), 0, nc, nullptr, {{set(G_), S.eye(nc, -1.0)}});
+      S.lc(set(Dc), 0, nc, nullptr, {{set(Gc), S.eye(nc, -1.0)}});
+    }
+    {
+      const size_t qd = S.gram_q(set(D), 0, nc, set(Grc), 0, nc, true);
+      r = S.fetch();
+      double dd = 0.0;
+      for (int c = 0; c < nc; ++c) dd += r[qd + c];
+      if (dd >= 0.0 && beta > 0.0) {
+        S.lc(set(D), 0, nc, nullptr, {{set(G_), S.eye(nc, -1.0)}});
+        S.lc(set(Dc), 0, nc, nullptr, {{set(Gc), S.eye(nc, -1.0)}});
+      }
+    }
+    have_dir = true;
+    apply(set(D), set(FD));
+
+    // line-search coefficients
+    const size_t q1 = S.gram_q(set(F), 0, nc, set(Dc), 0, nc, false);
+    const size_t q2 = S.gram_q(set(FD), 0, nc, set(Pc), 0, nc, false);
+    const size_t q3 = S.gram_q(set(FD), 0, nc, set(Dc), 0, nc, false);
+    const size_t c0 = S.gram_q(set(P), 0, n, set(Pc), n, n, false);
+    const size_t c1a = S.gram_q(set(P), 0, n, set(Dc), n, n, false);
+    const size_t c1b = S.gram_q(set(D), 0, n, set(Pc), n, n, false);
+    const size_t c2 = S.gram_q(set(D), 0, n, set(Dc), n, n, false);
+    const size_t dn = S.gram_q(set(D), 0, nc, set(Dc), 0, nc, true);
+    r = S.fetch();
+    auto nblock = [&](size_t q) {  // 1/2 (<x^p_j, f^p_i> + <x^q_j, f^q_i>) from a 2n x 2n gram
+      Mat m((size_t)n * n);
+      for (int i = 0; i < n; ++i)
+        for (int j = 0; j < n; ++j)
+          m[i * n + j] = 0.5 * (r[q + (size_t)i * nc + j] + r[q + (size_t)(n + i) * nc + n + j]);
+      return m;
+    };
+    Mat N0 = Nm, N1 = nblock(q1), N1b = nblock(q2), N2 = nblock(q3);
+    for (size_t k = 0; k < N1.size(); ++k) N1[k] += N1b[k];
+    N1 = sym(N1, n);
+    N2 = sym(N2, n);
+    Mat B0((size_t)n * n), B1((size_t)n * n), B2((size_t)n * n);
+    for (int k = 0; k < n * n; ++k) {
+      B0[k] = r[c0 + k];
+      B1[k] = r[c1a + k] + r[c1b + k];
+      B2[k] = r[c2 + k];
+    }
+    B0 = sym(B0, n);
+    B1 = sym(B1, n);
+    B2 = sym(B2, n);
+    double dnorm = 0.0;
+    for (int c = 0; c < nc; ++c) dnorm += r[dn + c];
+    auto phi = [&](double l) {
+      Mat Nl((size_t)n * n), Bl((size_t)n * n);
+      for (int k = 0; k < n * n; ++k) {
+        Nl[k] = N0[k] + l * N1[k] + l * l * N2[k];
+        Bl[k] = B0[k] + l * B1[k] + l * l * B2[k];
+      }
+      return trace_nbinv(Nl, Bl, n);
+    };
+    const double scale = 1.0 / std::sqrt(std::max(std::fabs(dnorm), 1e-300));
+    const int NL = 241;
+    double best = phi(0.0), lam = 0.0;
+    int kbest = -1;
+    std::vector<double> lams(NL), vals(NL);
+    int end = NL;
+    for (int k = 0; k < NL; ++k) {
+      lams[k] = scale * std::pow(10.0, -8.0 + 12.0 * k / (NL - 1));
+      vals[k] = phi(lams[k]);
+      if (!std::isfinite(vals[k])) { end = k; break; }
+      if (vals[k] < best) { best = vals[k]; kbest = k; }
+    }
+    if (kbest >= 0) {
+      const double lo = kbest > 0 ? lams[kbest - 1] : 0.0;
+      const double hi = kbest + 1 < end ? lams[kbest + 1] : lams[kbest];
+      lam = lams[kbest];
+      if (hi > lo) {
+        const double lb = brent_min(phi, lo, hi, 1e-12);
+        if (phi(lb) <= best) lam = lb;
+      }
+      stalls = 0;
+    } else {
+      if (++stalls >= 3) break;
+      have_dir = false;
+      continue;
+    }
+    // update
+    S.axpy_inplace(set(P), lam, set(D));
+    S.axpy_inplace(set(F), lam, set(FD));
+    S.axpy_inplace(set(Pc), lam, set(Dc));
+    if (o.refresh > 0 && (it + 1) % o.refresh == 0) {
+      apply(set(P), set(F));
+      covariant_sets<T>(h, nc, set(P), nc, 0, set(Pc), nc, 0);
+    }
+    // keep the previous gradient data in the new basis (copied before the transform)
+    S.copy(set(Gp), set(G_));
+    S.copy(set(Grp), set(Gr));
+    S.copy(set(Grcp), set(Grc));
+    if (!gs_step({D, Dc, Gp, Grp, Grcp})) throw Error{TDDFT_E_NOT_PD, "Tsiper metric lost positivity"};
+  }
+  // subspace diagonalisation: rotate to eigenvectors of N (B = I)
+  {
+    const size_t qN = S.gram_q(set(F), 0, nc, set(Pc), 0, nc, false);
+    std::vector<double> r = S.fetch();
+    for (int i = 0; i < n; ++i)
+      for (int j = 0; j < n; ++j)
+        Nm[i * n + j] = 0.5 * (r[qN + (size_t)i * nc + j] + r[qN + (size_t)(n + i) * nc + n + j]);
+    Nm = sym(Nm, n);
+    Mat V;
+    sym_eig(Nm, n, w, V);
+    Mat U((size_t)n * n);   // new_k = sum_i V_ik old_i
+    for (int k = 0; k < n; ++k)
+      for (int i = 0; i < n; ++i) U[k * n + i] = V[i * n + k];
+    S.transform(set(Tmp), set(P), U, U);
+    S.copy(set(P), set(Tmp));
+    if (Pp) unpack<T>(h.nM, h.BU, h.BO, n, set(P), nc, 0, h.m_voff.p, h.m_shape.p, Pp, h.nnzM, s);
+    if (Pq) unpack<T>(h.nM, h.BU, h.BO, n, set(P), nc, n, h.m_voff.p, h.m_shape.p, Pq, h.nnzM, s);
+    S.sync();
+  }
+  for (int i = 0; i < n; ++i) omega[i] = w[i];
+  if (st) {
+    st->iterations = it;
+    st->converged = converged ? 1 : 0;
+    st->inner_total = inner_total;
+    st->applies = applies;
+    st->fallbacks = 0;
+    st->setup_ms = h.setup_ms;
+    st->solve_ms = elapsed_ms();
+    st->apply_ms = apply_ms;
+  }
+  return converged ? TDDFT_OK : TDDFT_E_NO_CONVERGENCE;
+}
+
+int pcg_solve(Handle &h, int n, const tddft_options &o, double *omega, double *Pp, double *Pq,
+              tddft_stats *stats) {
+  if (h.precision == TDDFT_FP64) return solve_impl<double>(h, n, o, omega, Pp, Pq, stats);
+  return solve_impl<float>(h, n, o, omega, Pp, Pq, stats);
+}
+
+}  // namespace tddft

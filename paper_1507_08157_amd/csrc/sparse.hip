@@ -1,0 +1,353 @@
+// Block-sparse kernels on the atom-block pattern of the response kernels.
+//
+// A "column set" is an array X[blk][ld][BU*BO] holding `ld` matrices on one block pattern
+// (u-atom rows x o-atom columns, blocks padded to BU x BO, row-major); column c of the set
+// is the c-th matrix.  All matrices of a solve share the pattern, so a block's values for
+// every column are contiguous.
+//
+//  * masked products  C = alpha * mask(A X) (+ C)  and  C = alpha * mask(X B) (+ C) with a
+//    precomputed pair list per output block: every product is exact and only the result
+//    is restricted to the output pattern (Sec. III.A: K^c H^u P, P H^o K^v, the
+//    K^c V K^v sandwich and the projection K^c S^u L S^o K^v of Eq. auxiliary);
+//  * linear combinations of columns (updates, Gram-Schmidt transforms, gradients);
+//  * Gram matrices sum_e X[.,i,e] Y[.,j,e] accumulated in FP64 (the traces Tr[X^T S Y S]
+//    of Secs. II.C and III.C once Y holds the covariant S^u Y S^o);
+//  * conversion between the C-ABI layout [state][values of M] and column sets.
+#include "internal.h"
+#include "kernels.h"
+
+namespace tddft {
+
+// ---------------------------------------------------------------------------------------
+template <class T, int BU, int BO>
+__global__ __launch_bounds__(256) void k_spmm_left(int64_t nout, int ncol,
+                                                   const int64_t *__restrict__ ptr,
+                                                   const int2 *__restrict__ pairs,
+                                                   const T *__restrict__ A,
+                                                   const T *__restrict__ X, int ldx, int xc0,
+                                                   T *__restrict__ C, int ldc, int cc0,
+                                                   double alpha, int accumulate) {
+  constexpr int E = BU * BO;
+  const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (gid >= nout * ncol) return;
+  const int64_t k = gid / ncol;
+  const int m = (int)(gid - k * ncol);
+  T acc[E];
+#pragma unroll
+  for (int e = 0; e < E; ++e) acc[e] = T(0);
+  const int64_t q1 = ptr[k + 1];
+  for (int64_t q = ptr[k]; q < q1; ++q) {
+    const int2 pr = pairs[q];
+    const T *a = A + (int64_t)pr.x * (BU * BU);
+    const T *x = X + ((int64_t)pr.y * ldx + xc0 + m) * E;
+    T xv[E];
+#pragma unroll
+    for (int e = 0; e < E; ++e) xv[e] = x[e];
+#pragma unroll
+    for (int r = 0; r < BU; ++r)
+#pragma unroll
+      for (int t = 0; t < BU; ++t) {
+        const T ar = a[r * BU + t];
+#pragma unroll
+        for (int c = 0; c < BO; ++c) acc[r * BO + c] += ar * xv[t * BO + c];
+      }
+  }
+  T *c = C + (k * ldc + cc0 + m) * E;
+  const T al = (T)alpha;
+  if (accumulate) {
+#pragma unroll
+    for (int e = 0; e < E; ++e) c[e] += al * acc[e];
+  } else {
+#pragma unroll
+    for (int e = 0; e < E; ++e) c[e] = al * acc[e];
+  }
+}
+
+template <class T, int BU, int BO>
+__global__ __launch_bounds__(256) void k_spmm_right(int64_t nout, int ncol,
+                                                    const int64_t *__restrict__ ptr,
+                                                    const int2 *__restrict__ pairs,
+                                                    const T *__restrict__ X, int ldx, int xc0,
+                                                    const T *__restrict__ B,
+                                                    T *__restrict__ C, int ldc, int cc0,
+                                                    double alpha, int accumulate) {
+  constexpr int E = BU * BO;
+  const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (gid >= nout * ncol) return;
+  const int64_t k = gid / ncol;
+  const int m = (int)(gid - k * ncol);
+  T acc[E];
+#pragma unroll
+  for (int e = 0; e < E; ++e) acc[e] = T(0);
+  const int64_t q1 = ptr[k + 1];
+  for (int64_t q = ptr[k]; q < q1; ++q) {
+    const int2 pr = pairs[q];
+    const T *x = X + ((int64_t)pr.x * ldx + xc0 + m) * E;
+    const T *b = B + (int64_t)pr.y * (BO * BO);
+    T xv[E];
+#pragma unroll
+    for (int e = 0; e < E; ++e) xv[e] = x[e];
+#pragma unroll
+    for (int t = 0; t < BO; ++t)
+#pragma unroll
+      for (int c = 0; c < BO; ++c) {
+        const T bv = b[t * BO + c];
+#pragma unroll
+        for (int r = 0; r < BU; ++r) acc[r * BO + c] += xv[r * BO + t] * bv;
+      }
+  }
+  T *c = C + (k * ldc + cc0 + m) * E;
+  const T al = (T)alpha;
+  if (accumulate) {
+#pragma unroll
+    for (int e = 0; e < E; ++e) c[e] += al * acc[e];
+  } else {
+#pragma unroll
+    for (int e = 0; e < E; ++e) c[e] = al * acc[e];
+  }
+}
+
+#define TD_BDIM_DISPATCH(BU_, BO_, ...)                                     \
+  do {                                                                     \
+    if (BU_ == 3 && BO_ == 2) { constexpr int BU = 3, BO = 2; __VA_ARGS__; } \
+    else if (BU_ == 1 && BO_ == 1) { constexpr int BU = 1, BO = 1; __VA_ARGS__; } \
+    else if (BU_ == 2 && BO_ == 2) { constexpr int BU = 2, BO = 2; __VA_ARGS__; } \
+    else if (BU_ == 3 && BO_ == 3) { constexpr int BU = 3, BO = 3; __VA_ARGS__; } \
+    else if (BU_ == 4 && BO_ == 4) { constexpr int BU = 4, BO = 4; __VA_ARGS__; } \
+    else throw Error{TDDFT_E_INVALID, "unsupported padded block shape"};     \
+  } while (0)
+
+static inline unsigned nblocks(int64_t n, int bs) { return (unsigned)((n + bs - 1) / bs); }
+
+template <class T>
+void spmm_left(const DevPlan &pl, int bu, int bo, const T *A, const T *X, int ldx, int xc0,
+               T *C, int ldc, int cc0, int ncol, double alpha, bool acc, hipStream_t s) {
+  if (pl.nout == 0 || ncol == 0) return;
+  const int64_t n = pl.nout * ncol;
+  TD_BDIM_DISPATCH(bu, bo, hipLaunchKernelGGL((k_spmm_left<T, BU, BO>), dim3(nblocks(n, 256)),
+                                              dim3(256), 0, s, pl.nout, ncol, pl.ptr.p,
+                                              pl.pairs.p, A, X, ldx, xc0, C, ldc, cc0, alpha,
+                                              acc ? 1 : 0));
+  TD_HIP(hipGetLastError());
+}
+
+template <class T>
+void spmm_right(const DevPlan &pl, int bu, int bo, const T *X, int ldx, int xc0, const T *B,
+                T *C, int ldc, int cc0, int ncol, double alpha, bool acc, hipStream_t s) {
+  if (pl.nout == 0 || ncol == 0) return;
+  const int64_t n = pl.nout * ncol;
+  TD_BDIM_DISPATCH(bu, bo, hipLaunchKernelGGL((k_spmm_right<T, BU, BO>), dim3(nblocks(n, 256)),
+                                              dim3(256), 0, s, pl.nout, ncol, pl.ptr.p,
+                                              pl.pairs.p, X, ldx, xc0, B, C, ldc, cc0, alpha,
+                                              acc ? 1 : 0));
+  TD_HIP(hipGetLastError());
+}
+
+// ---------------------------------------------------------------------------------------
+// Y[blk][yc0 + j][e] = beta_j Y + sum_s sum_i C_s[j][i] X_s[blk][xc0_s + i][e]
+template <class T>
+__global__ __launch_bounds__(256) void k_lincomb(int64_t nblk, int E, LcArgs a) {
+  const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t per = (int64_t)a.nout * E;
+  if (gid >= nblk * per) return;
+  const int64_t blk = gid / per;
+  const int rem = (int)(gid - blk * per);
+  const int j = rem / E;
+  const int e = rem - j * E;
+  T *y = (T *)a.Y + ((blk * a.ldy + a.yc0 + j) * E + e);
+  double acc = a.beta ? a.beta[j] * (double)(*y) : 0.0;
+  for (int s = 0; s < a.nsrc; ++s) {
+    const LcSrc &src = a.src[s];
+    const T *x = (const T *)src.X + ((blk * src.ldx + src.xc0) * E + e);
+    const double *c = src.C + (int64_t)j * src.nin;
+    for (int i = 0; i < src.nin; ++i) acc += c[i] * (double)x[(int64_t)i * E];
+  }
+  *y = (T)acc;
+}
+
+template <class T>
+void lincomb(int64_t nblk, int E, const LcArgs &a, hipStream_t s) {
+  const int64_t n = nblk * a.nout * E;
+  if (n == 0) return;
+  hipLaunchKernelGGL((k_lincomb<T>), dim3(nblocks(n, 256)), dim3(256), 0, s, nblk, E, a);
+  TD_HIP(hipGetLastError());
+}
+
+// ---------------------------------------------------------------------------------------
+// FP64 Gram matrix of two column sets: out[i * n2 + j] = sum X[., xc0+i, .] Y[., yc0+j, .]
+// (diag: out[i] = sum X[., xc0+i, .] Y[., yc0+i, .]).  Two passes, fixed order.
+template <class T>
+__global__ __launch_bounds__(256) void k_gram_partial(int64_t nblk, int E, const T *__restrict__ X,
+                                                      int ldx, int xc0, int n1,
+                                                      const T *__restrict__ Y, int ldy, int yc0,
+                                                      int n2, int diag, int cb,
+                                                      double *__restrict__ partial) {
+  extern __shared__ double lds[];
+  double *xs = lds;                       // [cb][n1][E]
+  double *ys = lds + (size_t)cb * n1 * E; // [cb][n2][E]
+  const int npair = diag ? n1 : n1 * n2;
+  constexpr int MAXQ = 4;
+  double acc[MAXQ];
+#pragma unroll
+  for (int u = 0; u < MAXQ; ++u) acc[u] = 0.0;
+  const int64_t nchunk = (nblk + cb - 1) / cb;
+  for (int64_t ch = blockIdx.x; ch < nchunk; ch += gridDim.x) {
+    const int64_t b0 = ch * cb;
+    const int nb = (int)min((int64_t)cb, nblk - b0);
+    __syncthreads();
+    for (int t = threadIdx.x; t < nb * n1 * E; t += blockDim.x) {
+      const int b = t / (n1 * E);
+      const int r = t - b * n1 * E;
+      const int i = r / E, e = r - i * E;
+      xs[t] = (double)X[((b0 + b) * ldx + xc0 + i) * E + e];
+    }
+    for (int t = threadIdx.x; t < nb * n2 * E; t += blockDim.x) {
+      const int b = t / (n2 * E);
+      const int r = t - b * n2 * E;
+      const int j = r / E, e = r - j * E;
+      ys[t] = (double)Y[((b0 + b) * ldy + yc0 + j) * E + e];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < MAXQ; ++u) {
+      const int q = threadIdx.x + u * blockDim.x;
+      if (q < npair) {
+        const int i = diag ? q : q / n2;
+        const int j = diag ? q : q - i * n2;
+        double s = 0.0;
+        for (int b = 0; b < nb; ++b) {
+          const double *xr = xs + ((size_t)b * n1 + i) * E;
+          const double *yr = ys + ((size_t)b * n2 + j) * E;
+          for (int e = 0; e < E; ++e) s += xr[e] * yr[e];
+        }
+        acc[u] += s;
+      }
+    }
+  }
+#pragma unroll
+  for (int u = 0; u < MAXQ; ++u) {
+    const int q = threadIdx.x + u * blockDim.x;
+    if (q < npair) partial[(size_t)blockIdx.x * npair + q] = acc[u];
+  }
+}
+
+__global__ void k_gram_reduce(int nparts, int npair, const double *__restrict__ partial,
+                              double *__restrict__ out) {
+  const int q = blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= npair) return;
+  double s = 0.0;
+  for (int p = 0; p < nparts; ++p) s += partial[(size_t)p * npair + q];
+  out[q] = s;
+}
+
+template <class T>
+void gram(int64_t nblk, int E, const T *X, int ldx, int xc0, int n1, const T *Y, int ldy,
+          int yc0, int n2, bool diag, double *partial, int max_parts, double *out,
+          hipStream_t s) {
+  const int npair = diag ? n1 : n1 * n2;
+  if (npair > 4 * 256) throw Error{TDDFT_E_INVALID, "gram: too many column pairs"};
+  int cb = (int)(24576 / ((size_t)(n1 + n2) * E * sizeof(double)));
+  if (cb < 1) cb = 1;
+  if (cb > 64) cb = 64;
+  const int64_t nchunk = (nblk + cb - 1) / cb;
+  int parts = (int)std::min<int64_t>(std::max<int64_t>(nchunk, 1), max_parts);
+  const size_t lds = (size_t)cb * (n1 + n2) * E * sizeof(double);
+  hipLaunchKernelGGL((k_gram_partial<T>), dim3(parts), dim3(256), lds, s, nblk, E, X, ldx, xc0,
+                     n1, Y, ldy, yc0, n2, diag ? 1 : 0, cb, partial);
+  TD_HIP(hipGetLastError());
+  hipLaunchKernelGGL(k_gram_reduce, dim3(nblocks(npair, 256)), dim3(256), 0, s, parts, npair,
+                     partial, out);
+  TD_HIP(hipGetLastError());
+}
+
+// ---------------------------------------------------------------------------------------
+// C-ABI layout [state][values of M, natural block sizes] <-> column set (padded blocks)
+template <class T>
+__global__ __launch_bounds__(256) void k_pack(int64_t nblk, int BU, int BO, int ns,
+                                              const double *__restrict__ src, int64_t nnz,
+                                              const int64_t *__restrict__ voff,
+                                              const int32_t *__restrict__ shape,
+                                              T *__restrict__ X, int ldx, int xc0) {
+  const int E = BU * BO;
+  const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (gid >= nblk * ns * E) return;
+  const int64_t blk = gid / (ns * E);
+  const int rem = (int)(gid - blk * ns * E);
+  const int s = rem / E, e = rem - s * E;
+  const int r = e / BO, c = e - r * BO;
+  const int br = shape[blk] & 0xff, bc = shape[blk] >> 8;
+  double v = 0.0;
+  if (r < br && c < bc) v = src[(int64_t)s * nnz + voff[blk] + r * bc + c];
+  X[(blk * ldx + xc0 + s) * E + e] = (T)v;
+}
+
+template <class T>
+__global__ __launch_bounds__(256) void k_unpack(int64_t nblk, int BU, int BO, int ns,
+                                                const T *__restrict__ X, int ldx, int xc0,
+                                                const int64_t *__restrict__ voff,
+                                                const int32_t *__restrict__ shape,
+                                                double *__restrict__ dst, int64_t nnz) {
+  const int E = BU * BO;
+  const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (gid >= nblk * ns * E) return;
+  const int64_t blk = gid / (ns * E);
+  const int rem = (int)(gid - blk * ns * E);
+  const int s = rem / E, e = rem - s * E;
+  const int r = e / BO, c = e - r * BO;
+  const int br = shape[blk] & 0xff, bc = shape[blk] >> 8;
+  if (r < br && c < bc) dst[(int64_t)s * nnz + voff[blk] + r * bc + c] = (double)X[(blk * ldx + xc0 + s) * E + e];
+}
+
+template <class T>
+void pack(int64_t nblk, int BU, int BO, int ns, const double *src, int64_t nnz,
+          const int64_t *voff, const int32_t *shape, T *X, int ldx, int xc0, hipStream_t s) {
+  const int64_t n = nblk * ns * BU * BO;
+  if (n == 0) return;
+  hipLaunchKernelGGL((k_pack<T>), dim3(nblocks(n, 256)), dim3(256), 0, s, nblk, BU, BO, ns, src,
+                     nnz, voff, shape, X, ldx, xc0);
+  TD_HIP(hipGetLastError());
+}
+
+template <class T>
+void unpack(int64_t nblk, int BU, int BO, int ns, const T *X, int ldx, int xc0,
+            const int64_t *voff, const int32_t *shape, double *dst, int64_t nnz, hipStream_t s) {
+  const int64_t n = nblk * ns * BU * BO;
+  if (n == 0) return;
+  hipLaunchKernelGGL((k_unpack<T>), dim3(nblocks(n, 256)), dim3(256), 0, s, nblk, BU, BO, ns, X,
+                     ldx, xc0, voff, shape, dst, nnz);
+  TD_HIP(hipGetLastError());
+}
+
+// ---------------------------------------------------------------------------------------
+template <class T>
+__global__ void k_fill(int64_t n, T *p, T v) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+
+template <class T>
+void fill(T *p, int64_t n, T v, hipStream_t s) {
+  if (n == 0) return;
+  hipLaunchKernelGGL((k_fill<T>), dim3(nblocks(n, 256)), dim3(256), 0, s, n, p, v);
+  TD_HIP(hipGetLastError());
+}
+
+// explicit instantiations
+#define TD_INST_SPARSE(T)                                                                        \
+  template void spmm_left<T>(const DevPlan &, int, int, const T *, const T *, int, int, T *, int, \
+                             int, int, double, bool, hipStream_t);                               \
+  template void spmm_right<T>(const DevPlan &, int, int, const T *, int, int, const T *, T *,    \
+                              int, int, int, double, bool, hipStream_t);                         \
+  template void lincomb<T>(int64_t, int, const LcArgs &, hipStream_t);                          \
+  template void gram<T>(int64_t, int, const T *, int, int, int, const T *, int, int, int, bool,  \
+                        double *, int, double *, hipStream_t);                                   \
+  template void pack<T>(int64_t, int, int, int, const double *, int64_t, const int64_t *,        \
+                        const int32_t *, T *, int, int, hipStream_t);                            \
+  template void unpack<T>(int64_t, int, int, int, const T *, int, int, const int64_t *,         \
+                          const int32_t *, double *, int64_t, hipStream_t);                      \
+  template void fill<T>(T *, int64_t, T, hipStream_t);
+
+TD_INST_SPARSE(double)
+TD_INST_SPARSE(float)
+
+}  // namespace tddft

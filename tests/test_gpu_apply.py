@@ -1,0 +1,70 @@
+"""GPU parity of tddft_apply (Eq. operator_RPA) against the FP64 oracle, element by element
+on M, for every coupling mode, precision mode and test geometry (dense and truncated
+patterns, grids of 40^3 (radix 2, 5), 45^3 (radix 3, 5; ragged tiles), 70^3 (radix 2, 5, 7;
+ragged tiles) and 64^3)."""
+import sys
+
+import numpy as np
+import pytest
+
+from helpers import XC_MODES, gpu_handle, random_m, rel_err, to_dev
+from oracle.apply import Operator
+from synth import abi as sabi
+
+pytestmark = pytest.mark.gpu
+
+# FP64: every product/sum is exact up to rounding of O(10^3)-term FP64 sums.
+TOL_FP64 = 1e-11
+
+
+def _run(sysm, xc, precision, n, seed=1):
+    print(f"[apply] {sysm.cfg.name} N={sysm.cfg.N} xc={xc} {precision} n={n}", flush=True)
+    sys.stdout.flush()
+    op = Operator(sysm, **XC_MODES[xc])
+    Pp = random_m(sysm, n, seed)
+    Pq = random_m(sysm, n, seed + 100)
+    fp_ref, fq_ref = op.apply(Pp, Pq)
+    h = gpu_handle(sysm, precision=precision, xc=xc)
+    fp, fq = h.tddft_apply(to_dev(sabi.dense_to_m(sysm, Pp)), to_dev(sabi.dense_to_m(sysm, Pq)))
+    fp = sabi.m_to_dense(sysm, fp.cpu().numpy())
+    fq = sabi.m_to_dense(sysm, fq.cpu().numpy())
+    h.close()
+    return fp, fq, fp_ref, fq_ref, op, Pq
+
+
+@pytest.mark.parametrize("name", ["small_dense", "small_odd", "small_trunc"])
+@pytest.mark.parametrize("xc", [2, 1, 0])
+def test_apply_fp64(name, xc, request):
+    s = request.getfixturevalue(name)
+    fp, fq, fp_ref, fq_ref, _, _ = _run(s, xc, "fp64", 3)
+    assert rel_err(fp, fp_ref) < TOL_FP64
+    assert rel_err(fq, fq_ref) < TOL_FP64
+    assert np.all(fp[:, ~s.fn_mask()] == 0) and np.all(fq[:, ~s.fn_mask()] == 0)
+
+
+@pytest.mark.parametrize("n", [1, 2, 5, 8, 13])
+def test_apply_fp64_state_counts(small_trunc, n):
+    fp, fq, fp_ref, fq_ref, _, _ = _run(small_trunc, 0, "fp64", n, seed=n)
+    assert rel_err(fp, fp_ref) < TOL_FP64
+    assert rel_err(fq, fq_ref) < TOL_FP64
+
+
+@pytest.mark.parametrize("precision,bound", [("fp32", 2e-5), ("bf16", 2e-2)])
+def test_apply_reduced_precision(small_trunc, precision, bound):
+    """FP32: T-term and coupling both at FP32 rounding (sums of ~10^3 terms, relative
+    2^-24 * 10^3 ~ 6e-5 worst case, typically far lower).  BF16 grid samples (relative
+    2^-9 each, entering twice: rho and the integrals) bound the coupling part by ~1e-2 of its
+    own size; the T-term stays FP32."""
+    s = small_trunc
+    fp, fq, fp_ref, fq_ref, op, Pq = _run(s, 0, precision, 4)
+    assert rel_err(fp, fp_ref) < 2e-5
+    coup = op.coupling(Pq)
+    err_q = np.max(np.abs(fq - fq_ref))
+    assert err_q < bound * np.max(np.abs(coup)) + 2e-5 * np.max(np.abs(fq_ref))
+
+
+def test_apply_tiny_power_of_two_grid():
+    from conftest import cached_system
+    s = cached_system("tiny")
+    fp, fq, fp_ref, fq_ref, _, _ = _run(s, 0, "fp64", 3, seed=7)
+    assert rel_err(fq, fq_ref) < TOL_FP64
