@@ -161,8 +161,8 @@ def main():
 
     rng = np.random.default_rng(2024)
     X = rng.standard_normal((2, n, sysm.vir.n_fn, sysm.occ.n_fn)) * sysm.fn_mask()[None, None]
-    Pp = torch.from_numpy(sabi.dense_to_m(sysm, X[0])).cuda()
-    Pq = torch.from_numpy(sabi.dense_to_m(sysm, X[1])).cuda()
+    Pp = torch.from_numpy(sabi.dense_to_p(sysm, X[0])).cuda()
+    Pq = torch.from_numpy(sabi.dense_to_p(sysm, X[1])).cuda()
     fp = torch.empty_like(Pp)
     fq = torch.empty_like(Pq)
     for _ in range(a.warmup):
@@ -208,7 +208,7 @@ def main():
     if not a.no_solve:
         # reference: plain FP64 PCG converged to 1e-9 Ha
         h64 = h if a.precision == "fp64" else binding.tddft_create(arrays, precision="fp64")
-        L0 = torch.from_numpy(sabi.dense_to_m(sysm, sysm.guess(n))).cuda()
+        L0 = torch.from_numpy(sabi.dense_to_p(sysm, sysm.guess(n))).cuda()
         o = binding.tddft_default_options(precision="fp64", tol_omega=1e-9, max_iter=400)
         P1, P2 = L0.clone(), L0.clone()
         torch.cuda.synchronize()

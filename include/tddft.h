@@ -12,6 +12,12 @@
  * conduction density kernels (Sec. II.C), S and H the overlap and Hamiltonian matrices
  * of each set.  All matrices are contravariant; the metric is Tr[X^T S^u Y S^o].
  *
+ * Patterns.  M is the cutoff pattern of the auxiliary matrices L (Sec. III.A, Eq.
+ * auxiliary); the response kernels are P = K^c S^u L S^o K^v and live on the response
+ * pattern R: the blocks that product reaches from M (computed by tddft_create, exported by
+ * tddft_response_pattern).  Response-kernel arrays at this interface hold the values of R's
+ * blocks in (block row, block column) order, each block dense row-major.
+ *
  * Conventions of this interface
  *   - Every call returns an int status (TDDFT_OK = 0, negative = error, positive =
  *     informational warning).  No call aborts or exits the process.
@@ -94,7 +100,7 @@ typedef struct {
   tddft_functions vir;       /* u-set                                                  */
   tddft_bsr S_o, H_o, K_v;   /* n_o x n_o, symmetric; same block structure             */
   tddft_bsr S_u, H_u, K_c;   /* n_u x n_u, symmetric; same block structure             */
-  tddft_bsr M;               /* pattern of P^p, P^q, f_p, f_q: u-blocks x o-blocks     */
+  tddft_bsr M;               /* cutoff pattern of the auxiliary matrices L (u x o blocks) */
 } tddft_system;
 
 typedef struct {
@@ -143,10 +149,12 @@ typedef struct {
   int64_t sample_rows_o;     /* ... of the o-set                                        */
   int64_t pair_points;       /* sum over tiles of (u rows x o rows x 64)                */
   int64_t blocks_m;          /* blocks of M                                              */
+  int64_t blocks_r;          /* blocks of the response pattern R                         */
   int64_t blocks_o;          /* blocks of the overlap pattern of the potential integrals */
   int64_t blocks_m2, blocks_m3, blocks_m4;  /* intermediate patterns of the sandwiches  */
   int64_t pairs_kshift;      /* block products of one K^c H^u X plus X H^o K^v (per column) */
   int64_t pairs_project;     /* ... of the projection                                   */
+  int64_t pairs_project_t;   /* ... of its adjoint                                       */
   int64_t pairs_covariant;   /* ... of S^u X S^o                                        */
   int64_t pairs_sandwich;    /* ... of K^c V K^v                                        */
   double  setup_ms;
@@ -169,29 +177,36 @@ int tddft_create(const tddft_system *sys, const tddft_options *opts, tddft_handl
 
 int tddft_get_info(const tddft_handle *h, tddft_info *out);
 
-/* Number of values of one response kernel on M (sum of M's block sizes). */
-int64_t tddft_nnz_m(const tddft_handle *h);
+/* Number of values of one response kernel (sum of the block sizes of R). */
+int64_t tddft_nnz_p(const tddft_handle *h);
+
+/* The response pattern R: rowptr [n_u blocks + 1] and colind [nnzb] (host arrays, either
+ * may be NULL to query only).  Returns the number of blocks of R. */
+int64_t tddft_response_pattern(const tddft_handle *h, int64_t *rowptr, int32_t *colind);
 
 /* The operator of Eq. operator_RPA for n_states states at once:
  *   f_p = mask_M(K^c H^u P^p - P^p H^o K^v)
  *   f_q = mask_M(K^c H^u P^q - P^q H^o K^v + 2 s K^c V_SCF[P^q] K^v)
  * with V_SCF[P]_ab = h^3 sum_r u_a (V_H[rho] + f_xc rho) o_b, rho = sum u_a P_ab o_b,
  * V_H the periodic Hartree potential (G = 0 dropped) and s the coupling scale.
- * Pp, Pq, fp, fq: DEVICE arrays [n_states][tddft_nnz_m] FP64 in M's value order
- * (contravariant).  Every product is exact; only results are restricted to M.
+ * Pp, Pq, fp, fq: DEVICE arrays [n_states][tddft_nnz_p] FP64 in R's value order
+ * (contravariant).  Every product is exact; only results are restricted to R.
  * n_states in [1, 32].  Internal arithmetic follows the handle's precision. */
 int tddft_apply(tddft_handle *h, int32_t n_states, const double *Pp, const double *Pq,
                 double *fp, double *fq);
 
 /* Lowest n_states positive excitation energies by preconditioned CG on the Tsiper sum
  * functional (Secs. III.A-III.C).  omega: HOST [n_states], ascending (Ha).
- * Pp, Pq: DEVICE [n_states][tddft_nnz_m] FP64 or NULL.  On input, if non-NULL, they hold
- * auxiliary matrices L (Eq. auxiliary) that seed the trial vectors via
- * P = mask_M(K^c S^u L S^o K^v); if NULL a seeded N(0,1) guess on M is used.  On output
- * (if non-NULL) they hold the converged Tsiper-orthonormal vectors, rotated to the
- * eigenvectors of the subspace matrix.  opts may be NULL (handle's create options).
- * stats may be NULL.  Returns TDDFT_E_NO_CONVERGENCE with the last iterate when
- * max_iter is reached. */
+ * Pp, Pq: DEVICE [n_states][tddft_nnz_p] FP64 (R's layout) or NULL.  On input, if
+ * non-NULL, their blocks on M are the initial auxiliary matrices L (Eq. auxiliary; other
+ * blocks are ignored) and the trial vectors start at P = K^c S^u L S^o K^v; if NULL a seeded
+ * N(0,1) guess on M is used.  On output (if non-NULL) they hold the converged
+ * Tsiper-orthonormal vectors, rotated to the eigenvectors of the subspace matrix.
+ * The optimisation variable is L on M: the gradient with respect to L is preconditioned by
+ * the Kohn-Sham-difference operator of Eq. precond expressed on L and solved by inner CG.  opts may be NULL (handle's create options).
+ * stats may be NULL.  precision, xc, rho_floor and coupling_scale belong to the handle:
+ * solve options that differ in them are rejected with TDDFT_E_INVALID.  Returns
+ * TDDFT_E_NO_CONVERGENCE with the last iterate when max_iter is reached. */
 int tddft_pcg_solve(tddft_handle *h, int32_t n_states, const tddft_options *opts,
                     double *omega, double *Pp, double *Pq, tddft_stats *stats);
 

@@ -8,9 +8,12 @@ o-set)
 
 where V_SCF[P]_ab = h^3 sum_r u_a(r) (V_H[rho] + f_xc rho)(r) o_b(r) and
 rho(r) = sum_ab u_a(r) P_ab o_b(r) (Sec. III.A, response densities).  The factor 2 is
-A + B = D + 2K (Sec. II.A).  Every product is exact; only the results are restricted to
-the block pattern M of the response kernels (the paper truncates P^p, P^q, P^v and P^c,
-Sec. IV.C).  Contravariant quantities; the metric is <X, Y> = Tr[X^T S^u Y S^o] (Sec. II.C).
+A + B = D + 2K (Sec. II.A).  Contravariant quantities; the metric is
+<X, Y> = Tr[X^T S^u Y S^o] (Sec. II.C).
+
+Truncation (Sec. III.A, Eq. auxiliary): the auxiliary matrices L are truncated to the
+block pattern M; the response kernels are P = K^c S^u L S^o K^v, whose block pattern Mp is
+that of the product (wider than M).  Every product is exact; results are restricted to Mp.
 """
 from __future__ import annotations
 
@@ -31,7 +34,9 @@ class Operator:
         self.h = sysm.cfg.h
         self.Su, self.Hu, self.Kc = sysm.S_u, sysm.H_u, sysm.K_c
         self.So, self.Ho, self.Kv = sysm.S_o, sysm.H_o, sysm.K_v
-        self.mask = np.kron(sysm.M, np.ones((sysm.cfg.n_u, sysm.cfg.n_o)))
+        nb = (sysm.cfg.n_u, sysm.cfg.n_o)
+        self.mask_L = np.kron(sysm.M, np.ones(nb))
+        self.mask = np.kron(response_pattern(sysm), np.ones(nb))
         self.xc = xc
         self.hartree = hartree
         self.coupling_scale = coupling_scale
@@ -85,7 +90,23 @@ class Operator:
         """<X, Y> = Tr[X^T S^u Y S^o] (contravariant X, Y; Sec. II.C)."""
         return float(np.sum(X * (self.Su @ Y @ self.So)))
 
+    def truncate(self, X: np.ndarray) -> np.ndarray:
+        """Restriction of an auxiliary matrix to the truncation pattern M."""
+        return self.mask_L * X
+
     def project(self, X: np.ndarray) -> np.ndarray:
-        """Pi(X) = mask_M(K^c S^u X S^o K^v): the invariance projection applied to auxiliary
-        matrices (Sec. III.A, Eqs. invariance and auxiliary)."""
-        return self.mask * (self.KcSu @ X @ self.SoKv)
+        """Pi(L) = K^c S^u L S^o K^v for L on M (Sec. III.A, Eqs. invariance and
+        auxiliary); exact, on Mp."""
+        return self.mask * (self.KcSu @ self.truncate(X) @ self.SoKv)
+
+
+def response_pattern(sysm) -> np.ndarray:
+    """Atom-block pattern of K^c S^u L S^o K^v for L on M (boolean products of the block
+    patterns of the factors)."""
+    nA = sysm.cfg.n_atoms
+
+    def blocks(A, b):
+        return (np.abs(A.reshape(nA, b, nA, b)).max(axis=(1, 3)) > 0).astype(np.int64)
+    pu = blocks(sysm.K_c, sysm.cfg.n_u) @ blocks(sysm.S_u, sysm.cfg.n_u)
+    po = blocks(sysm.S_o, sysm.cfg.n_o) @ blocks(sysm.K_v, sysm.cfg.n_o)
+    return ((pu > 0).astype(np.int64) @ sysm.M.astype(np.int64) @ (po > 0).astype(np.int64)) > 0

@@ -5,7 +5,7 @@ The paper's own listings (its supplementary algorithms 1 and 2) are not availabl
 steps below follow the equations of the main text, and every choice the text leaves open
 is one of the documented readings:
 
-  * trial vectors P_i = (p_i, q_i) on the pattern M, Tsiper orthonormality
+  * trial vectors P_i = (p_i, q_i) on the response pattern Mp, Tsiper orthonormality
     B_ij = 1/2 (<p_i, q_j> + <p_j, q_i>) = delta_ij (Eq. ortho), sign rule
     q_i -> -q_i when <p_i, q_i> < 0 before orthonormalising (Sec. III.C), Gram-Schmidt in
     index order;
@@ -13,10 +13,16 @@ is one of the documented readings:
     subspace matrix Q of Sec. III.C);
   * gradient g_i = F_i - sum_j N_ij (q_j, p_j) (Sec. III.C, multi-state gradient; with
     B_jj = 1 its coefficient carries the factor 1/2 of the functional);
-  * preconditioner: approximate solve of K^c H^u G - G H^o K^v = g by CG in the S metric to
-    a relative residual eps_tol (Sec. III.B, Eq. precond); none -> G = g;
-  * projection of every new direction by Pi(X) = mask_M(K^c S^u X S^o K^v) (Sec. III.A,
-    Eq. auxiliary: P = K^c S L S K^v with L arbitrary); P itself is never re-projected;
+  * the optimisation variable is the auxiliary matrix L on the truncation pattern M; trial
+    vectors are P = Pi(L) = K^c S^u L S^o K^v, exact (Sec. III.A, Eq. auxiliary), so P never
+    leaves the invariant space and P itself is never re-projected;
+  * M complete (no truncation): Eq. precond, K^c H^u G - G H^o K^v = g, is solved by CG in
+    the S metric to a relative residual eps_tol (Sec. III.B) and the direction is
+    d = -Pi(G) + beta d_prev (Pi(G) = G for invariant G); none -> G = g;
+  * M truncated: the gradient with respect to L is r = mask_M(Pi^T(S^u g S^o)) (chain rule
+    through Pi) and Eq. precond is expressed on L, H_L(X) = mask_M(Pi^T S^u T(Pi X) S^o);
+    H_L z = r is solved by CG (Euclidean inner product on M) to relative residual eps_tol
+    and d = -Pi(z) + beta d_prev, a descent direction by construction; none -> z = r;
   * Polak-Ribiere(+) conjugation, common step lambda for all states, exact line search on
     Tr[N(lambda) B(lambda)^-1] (the sum functional, Eq. Tsiper_multiple, invariant under
     re-orthonormalisation), F carried by linearity F += lambda F(d) and refreshed every
@@ -59,11 +65,12 @@ class Solver:
     def __init__(self, op, opts: Options):
         self.op = op
         self.o = opts
+        self.complete = bool(np.all(op.mask_L == 1))
 
     # -- metric helpers -------------------------------------------------------------------
     def cov(self, X):
         """S^u X S^o for a stack [k, nu, no] (then <X, Y> = sum X * cov(Y))."""
-        return np.einsum("ij,kjl,lm->kim", self.op.Su, X, self.op.So)
+        return self.op.Su @ X @ self.op.So
 
     @staticmethod
     def gram(X, Yc):
@@ -78,10 +85,22 @@ class Solver:
     def project(self, X):
         return np.stack([self.op.project(x) for x in X])
 
-    def precondition(self, g):
-        """Columns of g: [k, nu, no].  CG on L(G) = mask_M(K^c H^u G - G H^o K^v) = g,
-        S metric, G0 = 0, stop at ||r|| <= eps_tol ||g||, after max_inner steps, or on
-        non-positive curvature."""
+    def pi_t(self, Y):
+        """Pi^T(Y) = mask_M(S^u K^c Y K^v S^o): the adjoint of the projection, onto M."""
+        return self.op.mask_L[None] * (self.op.KcSu.T @ Y @ self.op.SoKv.T)
+
+    def grad_L(self, g):
+        """Gradient with respect to L of the functional whose P-gradient is g."""
+        return self.pi_t(self.cov(g))
+
+    def hess_L(self, X):
+        """H_L(X) = mask_M(Pi^T(S^u T(Pi X) S^o)) for X on M."""
+        P = self.project(X)
+        return self.pi_t(self.cov(np.stack([self.op.T(x) for x in P])))
+
+    def precondition_p(self, g):
+        """Columns of g: [k, nu, no].  CG on T(G) = g in the S metric, G0 = 0, stop at
+        ||res|| <= eps_tol ||g||, after max_inner steps or on non-positive curvature."""
         if self.o.precond == "none":
             return g.copy(), 0
         G = np.zeros_like(g)
@@ -91,8 +110,7 @@ class Solver:
         rr0 = rr.copy()
         active = rr0 > 0
         steps = np.zeros(len(g), dtype=int)
-        it = 0
-        for it in range(self.o.max_inner):
+        for _ in range(self.o.max_inner):
             active &= rr > (self.o.eps_tol ** 2) * rr0
             if not np.any(active):
                 break
@@ -111,6 +129,39 @@ class Solver:
             steps += active
         G = np.where((steps > 0)[:, None, None], G, g)
         return G, int(steps.max()) if len(steps) else 0
+
+    def precondition(self, r):
+        """Columns of r: [k, nu, no] on M.  CG on H_L z = r (Euclidean inner product on
+        M), z0 = 0, stop at ||res|| <= eps_tol ||r||, after max_inner steps, or on
+        non-positive curvature; none -> z = r."""
+        if self.o.precond == "none":
+            return r.copy(), 0
+        z = np.zeros_like(r)
+        res = r.copy()
+        d = res.copy()
+        rr = np.einsum("kij,kij->k", res, res)
+        rr0 = rr.copy()
+        active = rr0 > 0
+        steps = np.zeros(len(r), dtype=int)
+        for _ in range(self.o.max_inner):
+            active &= rr > (self.o.eps_tol ** 2) * rr0
+            if not np.any(active):
+                break
+            Hd = self.hess_L(d)
+            dHd = np.einsum("kij,kij->k", d, Hd)
+            active &= dHd > 0
+            if not np.any(active):
+                break
+            alpha = np.where(active, rr / np.where(active, dHd, 1.0), 0.0)
+            z += alpha[:, None, None] * d
+            res -= alpha[:, None, None] * Hd
+            rr_new = np.einsum("kij,kij->k", res, res)
+            beta = np.where(active, rr_new / np.where(rr > 0, rr, 1.0), 0.0)
+            d = np.where(active[:, None, None], res + beta[:, None, None] * d, d)
+            rr = np.where(active, rr_new, rr)
+            steps += active
+        z = np.where((steps > 0)[:, None, None], z, r)
+        return z, int(steps.max()) if len(steps) else 0
 
     # -- subspace algebra ------------------------------------------------------------------
     def pq_gram(self, P):
@@ -196,6 +247,8 @@ class Solver:
         if end == 0:
             return 0.0
         k = int(np.argmin(vals[:end]))
+        if not vals[k] < self.phi(0.0, Nc, Bc):
+            return 0.0
         lo = lams[k - 1] if k > 0 else 0.0
         hi = lams[k + 1] if k + 1 < end else lams[k]
         if hi <= lo:
@@ -217,7 +270,9 @@ class Solver:
         hist = []
         inner = []
         omega_prev = None
-        d_prev = g_prev = G_prev = None
+        D = z_prev = r_prev = None
+        restart_next = False
+        stalls = 0
         converged = False
         it = 0
         for it in range(self.o.max_iter + 1):
@@ -235,21 +290,44 @@ class Solver:
             if it == self.o.max_iter:
                 break
             omega_prev = omega
-            G, ninner = self.precondition(g.reshape(2 * n, *g.shape[2:]))
+            shape = g.shape
+            if self.complete:
+                # r, z in the S metric on the trial-vector space (M complete)
+                r = g.reshape(2 * n, *shape[2:])
+                z, ninner = self.precondition_p(r)
+                Dz = -self.project(z).reshape(shape)
+                num_fn = lambda a, b: float(np.sum(a * self.cov(b)))  # noqa: E731
+            else:
+                r = self.grad_L(g.reshape(2 * n, *shape[2:]))
+                z, ninner = self.precondition(r)
+                Dz = -self.project(z).reshape(shape)
+                num_fn = lambda a, b: float(np.sum(a * b))  # noqa: E731
             inner.append(ninner)
-            G = self.project(G).reshape(g.shape)
-            if d_prev is None or it % self.o.restart == 0:
+            if D is None or restart_next or it % self.o.restart == 0:
                 beta = 0.0
             else:
-                beta = max(0.0, (self.combined_dot(G, g) - self.combined_dot(G, g_prev))
-                           / self.combined_dot(G_prev, g_prev))
-            D = -G + beta * d_prev if beta > 0 else -G
+                num = num_fn(z, r) - num_fn(z, r_prev)
+                den = num_fn(z_prev, r_prev)
+                beta = max(0.0, num / den) if den > 0 else 0.0
+            D = Dz + beta * D if beta > 0 else Dz
             if self.combined_dot(D, g) >= 0:
-                D = -G
+                D = Dz
             FD = self.apply(D)
             Nc, Bc = self.line_coeffs(P, F, D, FD)
             scale = 1.0 / np.sqrt(max(self.combined_dot(D, D), 1e-300))
             lam = self.line_search(Nc, Bc, scale)
+            if lam == 0.0:          # no decrease along d: restart without a step
+                D = None
+                stalls += 1
+                if stalls >= 3:
+                    break
+                continue
+            stalls = 0
+            # a step longer than the trial vectors themselves, or one that does not lower
+            # the functional, invalidates the conjugation history
+            phi0 = self.phi(0.0, Nc, Bc)
+            restart_next = (lam * np.sqrt(self.combined_dot(D, D)) > np.sqrt(self.combined_dot(P, P))
+                            or not self.phi(lam, Nc, Bc) < phi0 - 1e-14 * abs(phi0))
             P = P + lam * D
             F = F + lam * FD
             if (it + 1) % self.o.refresh == 0:
@@ -257,9 +335,9 @@ class Solver:
             Tp, Tq = self.orthonormalise(self.pq_gram(P))
             P = self.transform(P, Tp, Tq)
             F = self.transform(F, Tp, Tq)
-            d_prev = self.transform(D, Tp, Tq)
-            g_prev = self.transform(g, Tp, Tq)
-            G_prev = self.transform(G, Tp, Tq)
+            D = self.transform(D, Tp, Tq)
+            z_prev = self.transform(z.reshape(shape), Tp, Tq).reshape(z.shape)
+            r_prev = self.transform(r.reshape(shape), Tp, Tq).reshape(r.shape)
         # subspace diagonalisation (B = I after Gram-Schmidt)
         Nm = self.n_matrix(P, F)
         w, U = np.linalg.eigh(Nm)

@@ -60,9 +60,11 @@ class tddft_info(C.Structure):
     _fields_ = [("n", C.c_int32 * 3), ("tiles", C.c_int32), ("block_rows", C.c_int32),
                 ("block_cols", C.c_int32), ("brick_edge", C.c_int32), ("precision", C.c_int32),
                 ("sample_rows_u", C.c_int64), ("sample_rows_o", C.c_int64),
-                ("pair_points", C.c_int64), ("blocks_m", C.c_int64), ("blocks_o", C.c_int64),
+                ("pair_points", C.c_int64), ("blocks_m", C.c_int64), ("blocks_r", C.c_int64),
+                ("blocks_o", C.c_int64),
                 ("blocks_m2", C.c_int64), ("blocks_m3", C.c_int64), ("blocks_m4", C.c_int64),
                 ("pairs_kshift", C.c_int64), ("pairs_project", C.c_int64),
+                ("pairs_project_t", C.c_int64),
                 ("pairs_covariant", C.c_int64), ("pairs_sandwich", C.c_int64),
                 ("setup_ms", C.c_double)]
 
@@ -77,7 +79,8 @@ class tddft_stats(C.Structure):
 
 _LIB = None
 
-EXPORTS = ("tddft_default_options", "tddft_create", "tddft_nnz_m", "tddft_apply",
+EXPORTS = ("tddft_default_options", "tddft_create", "tddft_nnz_p", "tddft_response_pattern",
+           "tddft_apply",
            "tddft_pcg_solve", "tddft_destroy", "tddft_strerror", "tddft_last_error",
            "tddft_abi_version", "tddft_get_info", "tddft_profile", "tddft_profile_read",
            "tddft_profile_stage_name")
@@ -90,14 +93,19 @@ def lib():
         if not os.path.exists(LIB_PATH):
             raise RuntimeError(f"libtddft.so not built ({LIB_PATH}); run "
                                "python -m paper_1507_08157_amd.build")
+        # PyTorch's HIP runtime must be the process's only one: load it first so the
+        # library binds to the same libamdhip64 / libhsa-runtime64
+        import torch  # noqa: F401
         L = C.CDLL(LIB_PATH)
         L.tddft_default_options.argtypes = [C.POINTER(tddft_options)]
         L.tddft_default_options.restype = None
         L.tddft_create.argtypes = [C.POINTER(tddft_system), C.POINTER(tddft_options),
                                    C.POINTER(C.c_void_p)]
         L.tddft_create.restype = C.c_int
-        L.tddft_nnz_m.argtypes = [C.c_void_p]
-        L.tddft_nnz_m.restype = C.c_int64
+        L.tddft_nnz_p.argtypes = [C.c_void_p]
+        L.tddft_nnz_p.restype = C.c_int64
+        L.tddft_response_pattern.argtypes = [C.c_void_p, _i64p, _i32p]
+        L.tddft_response_pattern.restype = C.c_int64
         L.tddft_apply.argtypes = [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p,
                                   C.c_void_p]
         L.tddft_apply.restype = C.c_int
@@ -198,10 +206,11 @@ class Handle:
         self.options = options if options is not None else tddft_default_options(**kw)
         keep: list = []
         sysc = _system(arrays, keep)
+        self._nbu = int(arrays["S_u"]["nbr"])
         rc = lib().tddft_create(C.byref(sysc), C.byref(self.options), C.byref(self._h))
         if rc != TDDFT_OK:
             raise TddftError(rc, lib().tddft_last_error(None).decode())
-        self.nnz_m = int(lib().tddft_nnz_m(self._h))
+        self.nnz_p = int(lib().tddft_nnz_p(self._h))
 
     def close(self):
         if self._h:
@@ -218,7 +227,7 @@ class Handle:
         return TddftError(rc, lib().tddft_last_error(self._h).decode())
 
     def tddft_apply(self, Pp, Pq, fp=None, fq=None):
-        """(f_p, f_q) for device tensors [n_states, nnz_m] FP64."""
+        """(f_p, f_q) for device tensors [n_states, nnz_p] FP64 (response-pattern layout)."""
         import torch
         n = Pp.shape[0]
         fp = torch.empty_like(Pp) if fp is None else fp
@@ -228,6 +237,14 @@ class Handle:
         if rc != TDDFT_OK:
             raise self._err(rc)
         return fp, fq
+
+    def tddft_response_pattern(self):
+        """(rowptr, colind) of the response pattern R (numpy arrays)."""
+        nb = int(lib().tddft_response_pattern(self._h, None, None))
+        rowptr = np.zeros(self._nbu + 1, dtype=np.int64)
+        colind = np.zeros(nb, dtype=np.int32)
+        lib().tddft_response_pattern(self._h, _ptr(rowptr, C.c_int64), _ptr(colind, C.c_int32))
+        return rowptr, colind
 
     def tddft_get_info(self) -> dict:
         inf = tddft_info()

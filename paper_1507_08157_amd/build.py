@@ -35,6 +35,18 @@ def hipcc() -> str:
     raise RuntimeError("hipcc not found")
 
 
+def torch_lib_dir():
+    """Directory of the HIP runtime bundled with PyTorch.  The library is linked with an
+    RPATH to it so that one process never holds two HIP/HSA runtimes (PyTorch's and the
+    system's), which cannot share one GPU."""
+    import importlib.util
+    spec = importlib.util.find_spec("torch")
+    if spec is None or not spec.submodule_search_locations:
+        return None
+    d = os.path.join(list(spec.submodule_search_locations)[0], "lib")
+    return d if os.path.exists(os.path.join(d, "libamdhip64.so")) else None
+
+
 def sources():
     return sorted(os.path.join(CSRC, f) for f in os.listdir(CSRC)
                   if f.endswith((".hip", ".cpp")))
@@ -57,6 +69,9 @@ def build(jobs: int | None = None, verbose: bool = False) -> str:
         objs = list(ex.map(_compile, srcs))
     tmp = LIB + ".tmp"
     cmd = [hipcc(), "-shared", f"--offload-arch={ARCH}", "-o", tmp, *objs]
+    tl = torch_lib_dir()
+    if tl:
+        cmd += [f"-Wl,--disable-new-dtags,-rpath,{tl}"]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"link failed: {' '.join(cmd)}\n{r.stdout}\n{r.stderr}")

@@ -84,7 +84,15 @@ int tddft_create(const tddft_system *sys, const tddft_options *opts, tddft_handl
   }
 }
 
-int64_t tddft_nnz_m(const tddft_handle *h) { return h ? h->h.nnzM : -1; }
+int64_t tddft_nnz_p(const tddft_handle *h) { return h ? h->h.nnzR : -1; }
+
+int64_t tddft_response_pattern(const tddft_handle *hd, int64_t *rowptr, int32_t *colind) {
+  if (!hd) return TDDFT_E_INVALID;
+  const Handle &h = hd->h;
+  if (rowptr) std::copy(h.R.rowptr.begin(), h.R.rowptr.end(), rowptr);
+  if (colind) std::copy(h.R.col.begin(), h.R.col.end(), colind);
+  return h.R.nnzb();
+}
 
 int tddft_get_info(const tddft_handle *hd, tddft_info *o) {
   if (!hd || !o) return TDDFT_E_INVALID;
@@ -100,12 +108,14 @@ int tddft_get_info(const tddft_handle *hd, tddft_info *o) {
   o->sample_rows_o = h.sample_rows_o;
   o->pair_points = h.pair_points;
   o->blocks_m = h.nM;
+  o->blocks_r = h.nR;
   o->blocks_o = h.nO;
   o->blocks_m2 = h.nM2;
   o->blocks_m3 = h.nM3;
   o->blocks_m4 = h.nM4;
   o->pairs_kshift = h.pT_left.npairs + h.pT_right.npairs;
   o->pairs_project = h.pPi1.npairs + h.pPi2.npairs;
+  o->pairs_project_t = h.pPt1.npairs + h.pPt2.npairs;
   o->pairs_covariant = h.pCov1.npairs + h.pCov2.npairs;
   o->pairs_sandwich = h.pSw1.npairs + h.pSw2.npairs;
   o->setup_ms = h.setup_ms;
@@ -125,14 +135,14 @@ int tddft_apply(tddft_handle *hd, int32_t n, const double *Pp, const double *Pq,
     const int nc = 2 * n;
     auto run = [&](auto tag) {
       using T = decltype(tag);
-      const size_t elems = (size_t)h.nM * nc * h.E;
+      const size_t elems = (size_t)h.nR * nc * h.E;
       T *X = (T *)h.w_pcg.get(2 * elems * sizeof(T));
       T *F = X + elems;
-      pack<T>(h.nM, h.BU, h.BO, n, Pp, h.nnzM, h.m_voff.p, h.m_shape.p, X, nc, 0, h.stream);
-      pack<T>(h.nM, h.BU, h.BO, n, Pq, h.nnzM, h.m_voff.p, h.m_shape.p, X, nc, n, h.stream);
+      pack<T>(h.nR, h.BU, h.BO, n, Pp, h.nnzR, h.r_voff.p, h.r_shape.p, X, nc, 0, h.stream);
+      pack<T>(h.nR, h.BU, h.BO, n, Pq, h.nnzR, h.r_voff.p, h.r_shape.p, X, nc, n, h.stream);
       apply_sets<T>(h, n, X, nc, 0, n, F, nc, 0, n, true);
-      unpack<T>(h.nM, h.BU, h.BO, n, F, nc, 0, h.m_voff.p, h.m_shape.p, fp, h.nnzM, h.stream);
-      unpack<T>(h.nM, h.BU, h.BO, n, F, nc, n, h.m_voff.p, h.m_shape.p, fq, h.nnzM, h.stream);
+      unpack<T>(h.nR, h.BU, h.BO, n, F, nc, 0, h.r_voff.p, h.r_shape.p, fp, h.nnzR, h.stream);
+      unpack<T>(h.nR, h.BU, h.BO, n, F, nc, n, h.r_voff.p, h.r_shape.p, fq, h.nnzR, h.stream);
       TD_HIP(hipStreamSynchronize(h.stream));
     };
     if (h.precision == TDDFT_FP64) run(double{}); else run(float{});
@@ -160,6 +170,12 @@ int tddft_pcg_solve(tddft_handle *hd, int32_t n, const tddft_options *opts, doub
     return TDDFT_E_INVALID;
   }
   tddft_options o = opts ? *opts : h.opts;
+  if (o.precision != h.opts.precision || o.xc != h.opts.xc || o.rho_floor != h.opts.rho_floor ||
+      o.coupling_scale != h.opts.coupling_scale) {
+    h.last_error = "tddft_pcg_solve: precision, xc, rho_floor and coupling_scale are fixed at "
+                   "tddft_create and must match the handle's";
+    return TDDFT_E_INVALID;
+  }
   if (!(o.eps_tol > 0.0) || !(o.tol_omega > 0.0) || o.max_iter < 0 || o.max_inner < 0) {
     h.last_error = "tddft_pcg_solve: tolerances must be positive";
     return TDDFT_E_INVALID;

@@ -14,6 +14,8 @@
 //  * ALDA exchange kernel f_xc = -(1/3)(3/pi)^{1/3} rho0^{-2/3} (Sec. II.A, xc part).
 // Grid fields are tile-major complex pairs: state 2k in the real part, 2k+1 in the
 // imaginary part of field k, so the Hartree FFT transforms two states at once.
+#include <algorithm>
+
 #include "internal.h"
 #include "kernels.h"
 
@@ -44,7 +46,7 @@ __global__ __launch_bounds__(256) void k_density(DevTiles tl, const T *__restric
   constexpr int E = BL * BR;
   const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int p = threadIdx.x & 63;
-  const int t = blockIdx.x * 4 + w;
+  const int t = blockIdx.x * (blockDim.x >> 6) + w;
   T *lu = lds + (size_t)w * tl.maxrows * TP;
   int nua = 0, noa = 0, u0 = 0, o0 = 0;
   if (t < tl.nt) {
@@ -130,7 +132,8 @@ __global__ __launch_bounds__(256) void k_vint(DevTiles tl, DevBricks br, const T
   for (int i = threadIdx.x; i < nslots * ns * E; i += blockDim.x) acc[i] = T(0);
   const int t0 = br.tptr[b];
   const int ntile = br.tptr[b + 1] - t0;
-  for (int round = 0; round < ntile; round += 4) {
+  const int nw = blockDim.x >> 6;
+  for (int round = 0; round < ntile; round += nw) {
     __syncthreads();
     const int k = round + w;
     int t = -1, nua = 0, noa = 0, u0 = 0, o0 = 0;
@@ -236,9 +239,12 @@ template <class T>
 void density(const DevTiles &tl, int stype, int BL, int BR, const T *X, int ldx, int xc0, int ns,
              T *out, int64_t pair_stride, double scale, hipStream_t s) {
   if (tl.nt == 0 || ns == 0) return;
-  const size_t lds = (size_t)4 * tl.maxrows * TP * sizeof(T);
-  const unsigned grid = (unsigned)((tl.nt + 3) / 4);
-  TD_SAMPLE(T, stype, TD_GRID_BDIM(BL, BR, hipLaunchKernelGGL((k_density<T, S, BL, BR>), dim3(grid), dim3(256), lds, s, tl, X, ldx, xc0, ns, out, pair_stride, (T)scale)));
+  const size_t per_wave = (size_t)tl.maxrows * TP * sizeof(T);
+  const int waves = (int)std::max<size_t>(1, std::min<size_t>(4, tl.lds_limit / std::max<size_t>(per_wave, 1)));
+  if (per_wave > tl.lds_limit) throw Error{TDDFT_E_INVALID, "too many functions per grid tile for the LDS budget"};
+  const size_t lds = (size_t)waves * per_wave;
+  const unsigned grid = (unsigned)((tl.nt + waves - 1) / waves);
+  TD_SAMPLE(T, stype, TD_GRID_BDIM(BL, BR, hipLaunchKernelGGL((k_density<T, S, BL, BR>), dim3(grid), dim3(64 * waves), lds, s, tl, X, ldx, xc0, ns, out, pair_stride, (T)scale)));
   TD_HIP(hipGetLastError());
 }
 
@@ -249,8 +255,12 @@ void potential_integrals(const DevTiles &tl, const DevBricks &br, int stype, int
   if (br.nb == 0 || ns == 0) return;
   const int E = BL * BR;
   const size_t acc_len = ((size_t)br.max_slots * ns * E + 1) & ~(size_t)1;
-  const size_t lds = (acc_len + (size_t)4 * ((size_t)br.max_rows * (TP + 1) + (size_t)ns * TP)) * sizeof(T);
-  TD_SAMPLE(T, stype, TD_GRID_BDIM(BL, BR, hipLaunchKernelGGL((k_vint<T, S, BL, BR>), dim3(br.nb), dim3(256), lds, s, tl, br, V, pair_stride, ns, Vout, ldv, (T)scale)));
+  const size_t per_wave = ((size_t)br.max_rows * (TP + 1) + (size_t)ns * TP) * sizeof(T);
+  int waves = 4;
+  while (waves > 1 && acc_len * sizeof(T) + waves * per_wave > tl.lds_limit) --waves;
+  const size_t lds = acc_len * sizeof(T) + (size_t)waves * per_wave;
+  if (lds > tl.lds_limit) throw Error{TDDFT_E_INVALID, "potential-integral accumulator exceeds the LDS budget"};
+  TD_SAMPLE(T, stype, TD_GRID_BDIM(BL, BR, hipLaunchKernelGGL((k_vint<T, S, BL, BR>), dim3(br.nb), dim3(64 * waves), lds, s, tl, br, V, pair_stride, ns, Vout, ldv, (T)scale)));
   TD_HIP(hipGetLastError());
 }
 

@@ -311,9 +311,10 @@ static void build_bricks(Handle &h, const HostSetTiles &tu, const HostSetTiles &
   h.bricks.obl = h.b_obl.p;
 }
 
+// LDS of the potential-integral kernel with one wave per workgroup (the minimum it needs)
 size_t vint_lds_bytes(const Handle &h, int ns, size_t tsize) {
   const size_t acc = ((size_t)h.bricks.max_slots * ns * h.E + 1) & ~(size_t)1;
-  return (acc + (size_t)4 * ((size_t)h.bricks.max_rows * (TP + 1) + (size_t)ns * TP)) * tsize;
+  return (acc + ((size_t)h.bricks.max_rows * (TP + 1) + (size_t)ns * TP)) * tsize;
 }
 
 // ---------------------------------------------------------------------------------------
@@ -395,21 +396,39 @@ void create_handle(Handle &h, const tddft_system &sys, const tddft_options &o) {
   h.lds_limit = (size_t)lds;
   TD_HIP(hipEventCreate(&h.ev0));
   TD_HIP(hipEventCreate(&h.ev1));
+
+  // ---- fixed products (exact, host FP64) and the response pattern R of K^c S^u L S^o K^v
+  HostBsr KcHu = host_product(Kc, Hu, product_pattern(Kc.pat, Hu.pat));
+  HostBsr HoKv = host_product(Ho, Kv, product_pattern(Ho.pat, Kv.pat));
+  HostBsr KcSu = host_product(Kc, Su, product_pattern(Kc.pat, Su.pat));
+  HostBsr SoKv = host_product(So, Kv, product_pattern(So.pat, Kv.pat));
+  h.R = product_pattern(product_pattern(KcSu.pat, h.M), SoKv.pat);
+  h.nR = h.R.nnzb();
   {
-    std::vector<int64_t> voff(h.nM);
-    std::vector<int32_t> shape(h.nM);
+    std::vector<int64_t> voff(h.nR);
+    std::vector<int32_t> shape(h.nR);
     int64_t pos = 0;
     for (int i = 0; i < h.nbu; ++i)
-      for (int64_t k = h.M.rowptr[i]; k < h.M.rowptr[i + 1]; ++k) {
-        const int j = h.M.col[k];
+      for (int64_t k = h.R.rowptr[i]; k < h.R.rowptr[i + 1]; ++k) {
+        const int j = h.R.col[k];
         const int rs = h.uoff[i + 1] - h.uoff[i], cs = h.ooff[j + 1] - h.ooff[j];
         voff[k] = pos;
         shape[k] = rs | (cs << 8);
         pos += rs * cs;
       }
-    h.nnzM = pos;
-    h.m_voff.upload(voff, s);
-    h.m_shape.upload(shape, s);
+    h.nnzR = pos;
+    h.r_voff.upload(voff, s);
+    h.r_shape.upload(shape, s);
+    std::vector<int32_t> mir(h.nM);
+    for (int i = 0; i < h.nbu; ++i)
+      for (int64_t k = h.M.rowptr[i]; k < h.M.rowptr[i + 1]; ++k) {
+        const int64_t r = h.R.find(i, h.M.col[k]);
+        TD_REQUIRE(r >= 0, "M is not contained in the response pattern (missing diagonal blocks)");
+        mir[k] = (int32_t)r;
+      }
+    h.m_in_r.upload(mir, s);
+    h.m_complete = h.nM == (int64_t)h.nbu * h.nbo;
+    if (h.m_complete) TD_REQUIRE(h.R.col == h.M.col && h.nR == h.nM, "complete M must equal R");
   }
 
   // ---- functions and tiles
@@ -429,7 +448,7 @@ void create_handle(Handle &h, const tddft_system &sys, const tddft_options &o) {
     for (int i = 0; i < nua; ++i)
       for (int j = 0; j < noa; ++j) {
         const int I = tu.atoms[tu.ptr[t] + i], J = to.atoms[to.ptr[t] + j];
-        pidx_uo.push_back((int32_t)h.M.find(I, J));
+        pidx_uo.push_back((int32_t)h.R.find(I, J));
         orows[I].push_back(J);
       }
     for (int i = 0; i < noa; ++i)
@@ -476,47 +495,51 @@ void create_handle(Handle &h, const tddft_system &sys, const tddft_options &o) {
     upload_bf16(h.os16, to.samples, s);
   }
   h.tiles_uo = DevTiles{nt, h.maxrows_uo, h.t_uptr.p, h.t_optr.p, h.t_pptr_uo.p, h.t_pidx_uo.p,
-                        h.usamp(), h.osamp()};
+                        h.usamp(), h.osamp(), h.lds_limit};
   h.tiles_oo = DevTiles{nt, h.maxrows_oo, h.t_optr.p, h.t_optr.p, h.t_pptr_oo.p, h.t_pidx_oo.p,
-                        h.os64.p, h.os64.p};
-  TD_REQUIRE((size_t)4 * h.maxrows_uo * TP * sizeof(double) <= h.lds_limit ||
-                 h.stype != SAMPLE_F64,
+                        h.os64.p, h.os64.p, h.lds_limit};
+  TD_REQUIRE((size_t)h.maxrows_uo * TP * sizeof(double) <= h.lds_limit,
              "too many functions per grid tile for the LDS budget");
 
   // bricks: 2^3 tiles when the accumulator fits, else single tiles
   build_bricks(h, tu, to, O, 2);
   const size_t tsz = h.stype == SAMPLE_F64 ? sizeof(double) : sizeof(float);
-  if (vint_lds_bytes(h, 8, tsz) > h.lds_limit) build_bricks(h, tu, to, O, 1);
+  if (vint_lds_bytes(h, 8, tsz) > h.lds_limit / 2) build_bricks(h, tu, to, O, 1);
   TD_REQUIRE(vint_lds_bytes(h, 2, tsz) <= h.lds_limit, "too many functions per grid tile for the LDS budget");
 
-  // ---- fixed products (exact, host FP64) and plans
-  HostBsr KcHu = host_product(Kc, Hu, product_pattern(Kc.pat, Hu.pat));
-  HostBsr HoKv = host_product(Ho, Kv, product_pattern(Ho.pat, Kv.pat));
-  HostBsr KcSu = host_product(Kc, Su, product_pattern(Kc.pat, Su.pat));
-  HostBsr SoKv = host_product(So, Kv, product_pattern(So.pat, Kv.pat));
+  // ---- plans
+  HostBsr KcSuT = host_transpose(KcSu);
+  HostBsr SoKvT = host_transpose(SoKv);
   h.KcHu.upload(KcHu, s);
   h.HoKv.upload(HoKv, s);
   h.KcSu.upload(KcSu, s);
   h.SoKv.upload(SoKv, s);
+  h.KcSuT.upload(KcSuT, s);
+  h.SoKvT.upload(SoKvT, s);
   h.Su.upload(Su, s);
   h.So.upload(So, s);
   h.Kc.upload(Kc, s);
   h.Kv.upload(Kv, s);
   const Pattern &M = h.M;
-  h.pT_left.upload(plan_product(KcHu.pat, M, M), s);
-  h.pT_right.upload(plan_product(M, HoKv.pat, M), s);
-  Pattern M3 = intersect(product_pattern(KcSu.pat, M), product_pattern(M, transpose(SoKv.pat)));
+  const Pattern &R = h.R;
+  h.pT_left.upload(plan_product(KcHu.pat, R, R), s);
+  h.pT_right.upload(plan_product(R, HoKv.pat, R), s);
+  Pattern M3 = intersect(product_pattern(KcSu.pat, M), product_pattern(R, transpose(SoKv.pat)));
   h.nM3 = M3.nnzb();
   h.pPi1.upload(plan_product(KcSu.pat, M, M3), s);
-  h.pPi2.upload(plan_product(M3, SoKv.pat, M), s);
-  Pattern M4 = intersect(product_pattern(Su.pat, M), product_pattern(M, transpose(So.pat)));
+  h.pPi2.upload(plan_product(M3, SoKv.pat, R), s);
+  Pattern M5 = intersect(product_pattern(KcSuT.pat, R), product_pattern(M, transpose(SoKvT.pat)));
+  h.nM5 = M5.nnzb();
+  h.pPt1.upload(plan_product(KcSuT.pat, R, M5), s);
+  h.pPt2.upload(plan_product(M5, SoKvT.pat, M), s);
+  Pattern M4 = intersect(product_pattern(Su.pat, R), product_pattern(R, transpose(So.pat)));
   h.nM4 = M4.nnzb();
-  h.pCov1.upload(plan_product(Su.pat, M, M4), s);
-  h.pCov2.upload(plan_product(M4, So.pat, M), s);
-  Pattern M2 = intersect(product_pattern(Kc.pat, O), product_pattern(M, transpose(Kv.pat)));
+  h.pCov1.upload(plan_product(Su.pat, R, M4), s);
+  h.pCov2.upload(plan_product(M4, So.pat, R), s);
+  Pattern M2 = intersect(product_pattern(Kc.pat, O), product_pattern(R, transpose(Kv.pat)));
   h.nM2 = M2.nnzb();
   h.pSw1.upload(plan_product(Kc.pat, O, M2), s);
-  h.pSw2.upload(plan_product(M2, Kv.pat, M), s);
+  h.pSw2.upload(plan_product(M2, Kv.pat, R), s);
 
   // ---- FFT plan, rho0 = 2 sum o K^v o and f_xc (FP64 from FP64 samples)
   build_fft_plan(h.fft, h.n, s);
@@ -565,6 +588,15 @@ void project_sets(Handle &h, int ncol, const T *X, int ldx, int x0, T *F, int ld
   spmm_left<T>(h.pPi1, h.BU, h.BO, h.KcSu.ptr<T>(), X, ldx, x0, Y, ncol, 0, ncol, 1.0, false, h.stream);
   spmm_right<T>(h.pPi2, h.BU, h.BO, Y, ncol, 0, h.SoKv.ptr<T>(), F, ldf, f0, ncol, 1.0, false, h.stream);
   h.prof.end(ST_PROJECT, h.stream);
+}
+
+template <class T>
+void project_t_sets(Handle &h, int ncol, const T *X, int ldx, int x0, T *F, int ldf, int f0) {
+  T *Y = (T *)h.w_small.get((size_t)h.nM5 * ncol * h.E * sizeof(T));
+  h.prof.begin(ST_PROJECT_T, h.stream);
+  spmm_left<T>(h.pPt1, h.BU, h.BO, h.KcSuT.ptr<T>(), X, ldx, x0, Y, ncol, 0, ncol, 1.0, false, h.stream);
+  spmm_right<T>(h.pPt2, h.BU, h.BO, Y, ncol, 0, h.SoKvT.ptr<T>(), F, ldf, f0, ncol, 1.0, false, h.stream);
+  h.prof.end(ST_PROJECT_T, h.stream);
 }
 
 template <class T>
@@ -634,6 +666,7 @@ void apply_sets(Handle &h, int n, const T *X, int ldx, int xp0, int xq0, T *F, i
   template void apply_sets<T>(Handle &, int, const T *, int, int, int, T *, int, int, int, bool); \
   template void kshift_sets<T>(Handle &, int, const T *, int, int, T *, int, int);             \
   template void project_sets<T>(Handle &, int, const T *, int, int, T *, int, int);            \
+  template void project_t_sets<T>(Handle &, int, const T *, int, int, T *, int, int);          \
   template void covariant_sets<T>(Handle &, int, const T *, int, int, T *, int, int);
 
 TD_INST_APPLY(double)

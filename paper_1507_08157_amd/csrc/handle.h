@@ -58,17 +58,19 @@ struct Handle {
   std::vector<int> uoff, ooff;
   int n_u = 0, n_o = 0;
 
-  // pattern M and its C-ABI value layout
-  Pattern M;
-  int64_t nnzM = 0;            // values of one response kernel in the C-ABI layout
-  DevBuf<int64_t> m_voff;      // per block: offset into the C-ABI values
-  DevBuf<int32_t> m_shape;     // per block: rows | cols << 8
+  // truncation pattern M of the auxiliary matrices L, response pattern R of P, f
+  Pattern M, R;
+  int64_t nnzR = 0;            // values of one response kernel in the C-ABI layout
+  DevBuf<int64_t> r_voff;      // per R block: offset into the C-ABI values
+  DevBuf<int32_t> r_shape;     // per R block: rows | cols << 8
+  DevBuf<int32_t> m_in_r;      // per M block: its index in R
 
   // fixed matrices
-  DevMat KcHu, HoKv, KcSu, SoKv, Su, So, Kc, Kv;
+  DevMat KcHu, HoKv, KcSu, SoKv, KcSuT, SoKvT, Su, So, Kc, Kv;
   // masked-product plans
-  DevPlan pT_left, pT_right, pPi1, pPi2, pCov1, pCov2, pSw1, pSw2;
-  int64_t nM = 0, nM2 = 0, nM3 = 0, nM4 = 0, nO = 0;
+  DevPlan pT_left, pT_right, pPi1, pPi2, pPt1, pPt2, pCov1, pCov2, pSw1, pSw2;
+  int64_t nM = 0, nR = 0, nM2 = 0, nM3 = 0, nM4 = 0, nM5 = 0, nO = 0;
+  bool m_complete = false;     // M holds every (u-block, o-block) pair (then R == M)
 
   // tiles and bricks
   DevBuf<int32_t> t_uptr, t_optr, t_pidx_uo, t_pidx_oo;
@@ -112,16 +114,20 @@ template <> inline const float *Handle::fxc<float>() const { return fxc32.p; }
 void create_handle(Handle &h, const tddft_system &sys, const tddft_options &o);
 
 // ---- operator application on column sets (internal precision T) ---------------------------
-// X: column set on M with ld columns; p columns [xp0, xp0 + n), q columns [xq0, xq0 + n).
+// X: column set on R with ld columns; p columns [xp0, xp0 + n), q columns [xq0, xq0 + n).
 template <class T>
 void apply_sets(Handle &h, int n, const T *X, int ldx, int xp0, int xq0, T *F, int ldf, int fp0,
                 int fq0, bool coupling);
 template <class T>
 void kshift_sets(Handle &h, int ncol, const T *X, int ldx, int x0, T *F, int ldf, int f0);
+// Pi(L) = K^c S^u L S^o K^v: L on M, result on R
 template <class T>
 void project_sets(Handle &h, int ncol, const T *X, int ldx, int x0, T *F, int ldf, int f0);
 template <class T>
 void covariant_sets(Handle &h, int ncol, const T *X, int ldx, int x0, T *F, int ldf, int f0);
+// Pi^T(Y) = mask_M(S^u K^c Y K^v S^o): Y on R, result on M
+template <class T>
+void project_t_sets(Handle &h, int ncol, const T *X, int ldx, int x0, T *F, int ldf, int f0);
 
 int pcg_solve(Handle &h, int n, const tddft_options &o, double *omega, double *Pp, double *Pq,
               tddft_stats *stats);

@@ -102,6 +102,8 @@ Plan plan_product(const Pattern &A, const Pattern &B, const Pattern &out);
 HostBsr host_product(const HostBsr &A, const HostBsr &B, const Pattern &out);
 // pattern of the full product A * B
 Pattern product_pattern(const Pattern &A, const Pattern &B);
+// block transpose (pattern and values)
+HostBsr host_transpose(const HostBsr &A);
 
 struct DevPlan {
   int64_t nout = 0, npairs = 0;
@@ -144,7 +146,7 @@ struct FFTPlan {
 enum Stage {
   ST_KSHIFT_LEFT = 0, ST_KSHIFT_RIGHT, ST_DENSITY, ST_FFT_X_FWD, ST_FFT_Y_FWD, ST_FFT_Z_POISSON,
   ST_FFT_Y_INV, ST_FFT_X_INV, ST_VINT_ZERO, ST_VINT, ST_SANDWICH_LEFT, ST_SANDWICH_RIGHT,
-  ST_PROJECT, ST_COVARIANT, ST_GRAM, ST_LINCOMB, ST_COUNT
+  ST_PROJECT, ST_COVARIANT, ST_GRAM, ST_LINCOMB, ST_PROJECT_T, ST_GATHER, ST_COUNT
 };
 extern const char *const kStageNames[ST_COUNT];
 

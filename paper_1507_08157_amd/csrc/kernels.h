@@ -39,6 +39,8 @@ void unpack(int64_t nblk, int BU, int BO, int ns, const T *X, int ldx, int xc0,
             const int64_t *voff, const int32_t *shape, double *dst, int64_t nnz, hipStream_t s);
 template <class T>
 void fill(T *p, int64_t n, T v, hipStream_t s);
+template <class T>
+void gather_blocks(int64_t nout, int blk_elems, const int32_t *map, const T *X, T *Y, hipStream_t s);
 
 // ---- grid ----------------------------------------------------------------------------------
 // device view of a tile set (lists and sample rows of two function sets)
@@ -49,6 +51,7 @@ struct DevTiles {
   const int64_t *pptr = nullptr;                    // [nt + 1]
   const int32_t *pidx = nullptr;                    // pair -> block index (or -1)
   const void *usamp = nullptr, *osamp = nullptr;    // rows of TP samples
+  size_t lds_limit = 65536;                          // device LDS bytes per workgroup
 };
 
 struct DevBricks {

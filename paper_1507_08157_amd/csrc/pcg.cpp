@@ -10,11 +10,16 @@
 //    rule q_i -> -q_i when <p_i,q_i> < 0, then Gram-Schmidt in index order;
 //  * N_ij = 1/2 (<p_j,f^p_i> + <q_j,f^q_i>) symmetrised, omega = eig(N) when B = I;
 //  * gradient g_i = F_i - sum_j N_ij (q_j, p_j) (Sec. III.C);
-//  * preconditioner: CG on K^c H^u G - G H^o K^v = g in the S metric to relative residual
-//    eps_tol (Sec. III.B, Eq. precond);
-//  * every direction projected by P = K^c S^u L S^o K^v restricted to M (Eq. auxiliary);
-//  * Polak-Ribiere(+) with a common step for all states and an exact line search on
-//    Tr[N(lambda) B(lambda)^-1]; F carried by linearity and refreshed periodically.
+//  * the optimisation variable is the auxiliary matrix L on the truncation pattern M and the
+//    trial vectors are P = K^c S^u L S^o K^v, exact (Eq. auxiliary), so P stays in the
+//    invariant space; the gradient with respect to L is r = mask_M(Pi^T(S^u g S^o));
+//  * preconditioner: the KS-difference operator of Eq. precond expressed on L,
+//    H_L(X) = mask_M(Pi^T(S^u T(Pi X) S^o)), H_L z = r solved by CG to relative residual
+//    eps_tol (Sec. III.B); without truncation Pi z solves Eq. precond itself;
+//  * direction d = -Pi(z) + beta d_prev (Polak-Ribiere(+) in L), a common step for all states
+//    from an exact line search on Tr[N(lambda) B(lambda)^-1]; history dropped after a step
+//    longer than the trial vectors or one without decrease; F carried by linearity and
+//    refreshed periodically.
 #include <algorithm>
 #include <chrono>
 #include <cmath>
@@ -208,23 +213,24 @@ bool orthonormalise(const Mat &C, int n, Mat &Tp, Mat &Tq) {
 }
 
 // ---- device helpers ------------------------------------------------------------------------
+// Column sets live on two block patterns: R (trial vectors, operator images, search
+// directions) and M (auxiliary matrices L and their gradients).
 template <class T>
 struct Solver {
   Handle &h;
   int n, nc;                 // states, columns (2n)
-  int64_t nM;
+  int64_t nR, nM;
   int E;
   hipStream_t s;
   std::vector<T *> sets;
   DevBuf<unsigned char> arena;
-  // pinned host and device staging for coefficients and results
-  double *hstage = nullptr;
+  double *hstage = nullptr;  // pinned staging of coefficients
   DevBuf<double> dstage;
   size_t stage_cap = 1 << 17, stage_off = 0;   // doubles
   DevBuf<double> dres;
   size_t res_off = 0;
 
-  Solver(Handle &h_, int n_) : h(h_), n(n_), nc(2 * n_), nM(h_.nM), E(h_.E), s(h_.stream) {
+  Solver(Handle &h_, int n_) : h(h_), n(n_), nc(2 * n_), nR(h_.nR), nM(h_.nM), E(h_.E), s(h_.stream) {
     TD_HIP(hipHostMalloc((void **)&hstage, stage_cap * sizeof(double), hipHostMallocDefault));
     dstage.alloc(stage_cap);
     dres.alloc(1 << 16);
@@ -232,12 +238,14 @@ struct Solver {
   ~Solver() {
     if (hstage) (void)hipHostFree(hstage);
   }
-  size_t set_elems() const { return (size_t)nM * nc * E; }
-  void alloc_sets(int count) {
-    const size_t bytes = set_elems() * sizeof(T);
-    arena.alloc(bytes * count);
-    sets.resize(count);
-    for (int i = 0; i < count; ++i) sets[i] = (T *)(arena.p + bytes * i);
+  size_t elems(int64_t nblk) const { return (size_t)nblk * nc * E; }
+  // sets [0, nr) on R, [nr, nr + nm) on M
+  void alloc_sets(int nr, int nm) {
+    const size_t br = elems(nR) * sizeof(T), bm = elems(nM) * sizeof(T);
+    arena.alloc(br * nr + bm * nm);
+    sets.resize(nr + nm);
+    for (int i = 0; i < nr; ++i) sets[i] = (T *)(arena.p + br * i);
+    for (int i = 0; i < nm; ++i) sets[nr + i] = (T *)(arena.p + br * nr + bm * i);
   }
   void sync() {
     TD_HIP(hipStreamSynchronize(s));
@@ -252,67 +260,60 @@ struct Solver {
     stage_off += (c.size() + 31) & ~(size_t)31;
     return dp;
   }
-  // ---- column-set algebra
-  // Y = sum of up to 3 sources with coefficient matrices [nout][nin] (+ beta Y)
-  void lc(T *Y, int yc0, int nout, const double *beta, std::initializer_list<std::pair<const T *, Mat>> src,
-          int xc0 = 0, int nin = -1) {
+  // Y = sum of up to 3 sources with coefficient matrices [nc][nc] (+ beta Y), all on nblk blocks
+  void lc(int64_t nblk, T *Y, const double *beta, std::initializer_list<std::pair<const T *, Mat>> src) {
     LcArgs a{};
     a.Y = Y;
     a.ldy = nc;
-    a.yc0 = yc0;
-    a.nout = nout;
+    a.yc0 = 0;
+    a.nout = nc;
     a.beta = beta;
     a.nsrc = 0;
     for (auto &sr : src) {
       LcSrc &x = a.src[a.nsrc++];
       x.X = sr.first;
       x.ldx = nc;
-      x.xc0 = xc0;
-      x.nin = nin < 0 ? nout : nin;
+      x.xc0 = 0;
+      x.nin = nc;
       x.C = coef(sr.second);
     }
     h.prof.begin(ST_LINCOMB, s);
-    lincomb<T>(nM, E, a, s);
+    lincomb<T>(nblk, E, a, s);
     h.prof.end(ST_LINCOMB, s);
   }
-  Mat eye(int m, double v = 1.0) {
-    Mat I((size_t)m * m, 0.0);
-    for (int i = 0; i < m; ++i) I[i * m + i] = v;
+  Mat eye(double v = 1.0) {
+    Mat I((size_t)nc * nc, 0.0);
+    for (int i = 0; i < nc; ++i) I[i * nc + i] = v;
     return I;
   }
   Mat diag(const std::vector<double> &d) {
-    const int m = (int)d.size();
-    Mat D((size_t)m * m, 0.0);
-    for (int i = 0; i < m; ++i) D[i * m + i] = d[i];
+    Mat D((size_t)nc * nc, 0.0);
+    for (int i = 0; i < nc; ++i) D[i * nc + i] = d[i];
     return D;
   }
-  // Y = a X + b Z elementwise over all columns (scalars)
-  void axpby(T *Y, double a, const T *X, double b, const T *Z) {
-    lc(Y, 0, nc, nullptr, {{X, eye(nc, a)}, {Z, eye(nc, b)}});
-  }
-  void axpy_inplace(T *Y, double a, const T *X) {   // Y += a X
+  void copy(int64_t nblk, T *Y, const T *X) { lc(nblk, Y, nullptr, {{X, eye()}}); }
+  void axpy(int64_t nblk, T *Y, double a, const T *X) {   // Y += a X
     std::vector<double> one(nc, 1.0);
-    const double *bt = coef(one);
-    lc(Y, 0, nc, bt, {{X, eye(nc, a)}});
+    lc(nblk, Y, coef(one), {{X, eye(a)}});
   }
-  void copy(T *Y, const T *X) { lc(Y, 0, nc, nullptr, {{X, eye(nc)}}); }
-  // block-diagonal transform [[Tp,0],[0,Tq]] applied to columns: Y = T X
-  void transform(T *Y, const T *X, const Mat &Tp, const Mat &Tq) {
+  // block-diagonal transform [[Tp,0],[0,Tq]] of the columns, in place (via tmp)
+  void transform(int64_t nblk, T *X, T *tmp, const Mat &Tp, const Mat &Tq) {
     Mat B((size_t)nc * nc, 0.0);
     for (int i = 0; i < n; ++i)
       for (int j = 0; j < n; ++j) {
         B[i * nc + j] = Tp[i * n + j];
         B[(n + i) * nc + n + j] = Tq[i * n + j];
       }
-    lc(Y, 0, nc, nullptr, {{X, B}});
+    lc(nblk, tmp, nullptr, {{X, B}});
+    copy(nblk, X, tmp);
   }
-  // ---- reductions (results queued in dres, fetched by fetch())
-  size_t gram_q(const T *X, int xc0, int n1, const T *Y, int yc0, int n2, bool dg) {
+  // FP64 reductions, queued into dres and fetched together
+  size_t gram_q(int64_t nblk, const T *X, int xc0, int n1, const T *Y, int yc0, int n2, bool dg) {
     const int np = dg ? n1 : n1 * n2;
     if (res_off + np > dres.n) throw Error{TDDFT_E_DEVICE, "result staging overflow"};
     const size_t at = res_off;
     h.prof.begin(ST_GRAM, s);
-    gram<T>(nM, E, X, nc, xc0, n1, Y, nc, yc0, n2, dg, h.partial.p, h.max_parts, dres.p + at, s);
+    gram<T>(nblk, E, X, nc, xc0, n1, Y, nc, yc0, n2, dg, h.partial.p, h.max_parts, dres.p + at, s);
     h.prof.end(ST_GRAM, s);
     res_off += np;
     return at;
@@ -338,9 +339,16 @@ static int solve_impl(Handle &h, int n, const tddft_options &o, double *omega, d
   };
   Solver<T> S(h, n);
   const int nc = 2 * n;
-  enum { P, F, Pc, D, FD, Dc, G_, Gc, Gr, Grc, Gp, Grp, Grcp, Rr, Rc, K, Kc, LK, LKc, Gs, Tmp, NSET };
-  S.alloc_sets(NSET);
+  // sets on R: trial vectors P, images F, covariant Pc, direction D, FD, Dc, gradient g, gc,
+  // two scratch sets; sets on M: L-gradient r, preconditioned z, their previous values, the
+  // inner-CG residual, direction and operator image, scratch
+  enum { P, F, Pc, D, FD, Dc, G, Gc, T1, T2, NR_SETS };
+  enum { Lr = NR_SETS, Lz, Lrp, Lzp, Lres, Ld, LHd, Ltmp, Lresc, Ldc, LHdc, NSETS };
+  S.alloc_sets(NR_SETS, NSETS - NR_SETS);
   auto set = [&](int i) { return S.sets[i]; };
+  const int64_t nR = h.nR, nM = h.nM;
+  // M complete: the auxiliary matrices and the trial vectors share one full pattern
+  const bool complete = h.m_complete;
   hipStream_t s = h.stream;
   int applies = 0, inner_total = 0;
   float apply_ms = 0.0f;
@@ -354,16 +362,19 @@ static int solve_impl(Handle &h, int n, const tddft_options &o, double *omega, d
     apply_ms += ms;
     ++applies;
   };
+  auto cov = [&](const T *X, T *Y) { covariant_sets<T>(h, nc, X, nc, 0, Y, nc, 0); };
+  auto proj = [&](const T *Lm, T *Y) { project_sets<T>(h, nc, Lm, nc, 0, Y, nc, 0); };
+  auto proj_t = [&](const T *Y, T *Lm) { project_t_sets<T>(h, nc, Y, nc, 0, Lm, nc, 0); };
 
-  // ---- initial auxiliary matrices -> P = Pi(L0)
+  // ---- initial auxiliary matrices L0 on M -> P = Pi(L0)
   {
-    T *L0 = set(Tmp);
+    T *tmpR = set(T1);
     if (Pp && Pq) {
-      pack<T>(h.nM, h.BU, h.BO, n, Pp, h.nnzM, h.m_voff.p, h.m_shape.p, L0, nc, 0, s);
-      pack<T>(h.nM, h.BU, h.BO, n, Pq, h.nnzM, h.m_voff.p, h.m_shape.p, L0, nc, n, s);
+      pack<T>(nR, h.BU, h.BO, n, Pp, h.nnzR, h.r_voff.p, h.r_shape.p, tmpR, nc, 0, s);
+      pack<T>(nR, h.BU, h.BO, n, Pq, h.nnzR, h.r_voff.p, h.r_shape.p, tmpR, nc, n, s);
     } else {
-      // seeded N(0,1) on M (SplitMix64 + Box-Muller), the same matrix for p and q
-      std::vector<double> g((size_t)n * h.nnzM);
+      // seeded N(0,1) (SplitMix64 + Box-Muller), the same matrix for p and q
+      std::vector<double> g((size_t)n * h.nnzR);
       uint64_t x = o.seed * 0x9E3779B97F4A7C15ull + 0x632BE59BD9B4E019ull;
       auto next = [&]() {
         uint64_t z = (x += 0x9E3779B97F4A7C15ull);
@@ -380,42 +391,44 @@ static int solve_impl(Handle &h, int n, const tddft_options &o, double *omega, d
       }
       DevBuf<double> dg(g.size());
       dg.upload(g, s);
-      pack<T>(h.nM, h.BU, h.BO, n, dg.p, h.nnzM, h.m_voff.p, h.m_shape.p, L0, nc, 0, s);
-      pack<T>(h.nM, h.BU, h.BO, n, dg.p, h.nnzM, h.m_voff.p, h.m_shape.p, L0, nc, n, s);
+      pack<T>(nR, h.BU, h.BO, n, dg.p, h.nnzR, h.r_voff.p, h.r_shape.p, tmpR, nc, 0, s);
+      pack<T>(nR, h.BU, h.BO, n, dg.p, h.nnzR, h.r_voff.p, h.r_shape.p, tmpR, nc, n, s);
       S.sync();
     }
-    project_sets<T>(h, nc, L0, nc, 0, set(P), nc, 0);
-    covariant_sets<T>(h, nc, set(P), nc, 0, set(Pc), nc, 0);
+    h.prof.begin(ST_GATHER, s);
+    gather_blocks<T>(nM, nc * h.E, h.m_in_r.p, tmpR, set(Ltmp), s);
+    h.prof.end(ST_GATHER, s);
+    proj(set(Ltmp), set(P));
+    cov(set(P), set(Pc));
   }
   Mat Tp, Tq;
-  auto gs_step = [&](std::initializer_list<int> extra_pairs) -> bool {
-    // C = <p_i, q_j>
-    S.gram_q(set(P), 0, n, set(Pc), n, n, false);
+  // Tsiper Gram-Schmidt of P (and the same transform of F, Pc and the carried history)
+  auto gs_step = [&](bool with_history) -> bool {
+    S.gram_q(nR, set(P), 0, n, set(Pc), n, n, false);
     std::vector<double> C = S.fetch();
     if (!orthonormalise(C, n, Tp, Tq)) return false;
-    S.transform(set(Tmp), set(P), Tp, Tq);
-    S.copy(set(P), set(Tmp));
-    S.transform(set(Tmp), set(Pc), Tp, Tq);
-    S.copy(set(Pc), set(Tmp));
-    S.transform(set(Tmp), set(F), Tp, Tq);
-    S.copy(set(F), set(Tmp));
-    for (int k : extra_pairs) {
-      S.transform(set(Tmp), set(k), Tp, Tq);
-      S.copy(set(k), set(Tmp));
+    S.transform(nR, set(P), set(T1), Tp, Tq);
+    S.transform(nR, set(Pc), set(T1), Tp, Tq);
+    S.transform(nR, set(F), set(T1), Tp, Tq);
+    if (with_history) {
+      S.transform(nR, set(D), set(T1), Tp, Tq);
+      S.transform(nR, set(Dc), set(T1), Tp, Tq);
+      S.transform(nM, set(Lrp), set(Ltmp), Tp, Tq);
+      S.transform(nM, set(Lzp), set(Ltmp), Tp, Tq);
     }
     return true;
   };
-  if (!gs_step({})) throw Error{TDDFT_E_NOT_PD, "initial trial vectors are linearly dependent in the Tsiper metric"};
+  if (!gs_step(false)) throw Error{TDDFT_E_NOT_PD, "initial trial vectors are linearly dependent in the Tsiper metric"};
   apply(set(P), set(F));
 
   std::vector<double> w(n), w_prev(n, 0.0);
-  bool converged = false, have_prev = false, have_dir = false;
+  bool converged = false, have_prev = false, have_dir = false, restart_next = false;
   int it = 0, stalls = 0;
   const double sqrt_tol = std::sqrt(o.tol_omega);
   Mat Nm((size_t)n * n);
   for (it = 0; it <= o.max_iter; ++it) {
-    // N and omega
-    const size_t qN = S.gram_q(set(F), 0, nc, set(Pc), 0, nc, false);
+    // N, omega, gradient g = F - N (q, p), its covariant form and norms
+    const size_t qN = S.gram_q(nR, set(F), 0, nc, set(Pc), 0, nc, false);
     std::vector<double> r = S.fetch();
     for (int i = 0; i < n; ++i)
       for (int j = 0; j < n; ++j)
@@ -423,7 +436,6 @@ static int solve_impl(Handle &h, int n, const tddft_options &o, double *omega, d
     Nm = sym(Nm, n);
     Mat V;
     sym_eig(Nm, n, w, V);
-    // gradient g = F - N (q, p)
     {
       Mat Cg((size_t)nc * nc, 0.0);
       for (int i = 0; i < n; ++i)
@@ -431,10 +443,10 @@ static int solve_impl(Handle &h, int n, const tddft_options &o, double *omega, d
           Cg[i * nc + n + j] = -Nm[i * n + j];
           Cg[(n + i) * nc + j] = -Nm[i * n + j];
         }
-      S.lc(set(Gr), 0, nc, nullptr, {{set(F), S.eye(nc)}, {set(P), Cg}});
-      covariant_sets<T>(h, nc, set(Gr), nc, 0, set(Grc), nc, 0);
+      S.lc(nR, set(G), nullptr, {{set(F), S.eye()}, {set(P), Cg}});
+      cov(set(G), set(Gc));
     }
-    const size_t qg = S.gram_q(set(Gr), 0, nc, set(Grc), 0, nc, true);
+    const size_t qg = S.gram_q(nR, set(G), 0, nc, set(Gc), 0, nc, true);
     r = S.fetch();
     double gmax = 0.0;
     for (int i = 0; i < n; ++i) gmax = std::max(gmax, std::sqrt(std::max(0.0, r[qg + i] + r[qg + n + i])));
@@ -458,17 +470,93 @@ static int solve_impl(Handle &h, int n, const tddft_options &o, double *omega, d
     w_prev = w;
     have_prev = true;
 
-    // ---- preconditioner: CG on L(G) = g (S metric), per column
-    if (o.precond == TDDFT_PC_NONE) {
-      S.copy(set(Gs), set(Gr));
+    if (complete) {
+      // ---- M complete: CG on Eq. precond T(z) = g in the S metric (vectors on R = M);
+      //      the conjugation uses r = S^u g S^o with Euclidean dots, i.e. S-metric dots of g
+      S.copy(nM, set(Lr), set(Gc));
+      if (o.precond == TDDFT_PC_NONE) {
+        S.copy(nM, set(Lz), set(G));
+      } else {
+        T *res = set(Lres), *resc = set(Lresc), *dk = set(Ld), *dkc = set(Ldc);
+        T *Lk = set(LHd), *Lkc = set(LHdc), *zk = set(Lz);
+        S.copy(nM, res, set(G));
+        S.copy(nM, resc, set(Gc));
+        S.copy(nM, dk, set(G));
+        S.copy(nM, dkc, set(Gc));
+        fill<T>(zk, (int64_t)S.elems(nM), T(0), s);
+        const size_t q0 = S.gram_q(nM, res, 0, nc, resc, 0, nc, true);
+        r = S.fetch();
+        std::vector<double> rr(r.begin() + q0, r.begin() + q0 + nc), rr0 = rr;
+        std::vector<char> active(nc);
+        for (int c = 0; c < nc; ++c) active[c] = rr0[c] > 0.0;
+        std::vector<int> steps(nc, 0);
+        const double tol2 = o.eps_tol * o.eps_tol;
+        for (int k = 0; k < o.max_inner; ++k) {
+          bool any = false;
+          for (int c = 0; c < nc; ++c) {
+            if (active[c] && !(rr[c] > tol2 * rr0[c])) active[c] = 0;
+            any |= (bool)active[c];
+          }
+          if (!any) break;
+          kshift_sets<T>(h, nc, dk, nc, 0, Lk, nc, 0);
+          const size_t qd = S.gram_q(nM, Lk, 0, nc, dkc, 0, nc, true);
+          r = S.fetch();
+          std::vector<double> alpha(nc, 0.0), nalpha(nc, 0.0);
+          any = false;
+          for (int c = 0; c < nc; ++c) {
+            if (active[c] && !(r[qd + c] > 0.0)) active[c] = 0;
+            if (active[c]) {
+              alpha[c] = rr[c] / r[qd + c];
+              nalpha[c] = -alpha[c];
+            }
+            any |= (bool)active[c];
+          }
+          if (!any) break;
+          cov(Lk, Lkc);
+          std::vector<double> ones(nc, 1.0);
+          const double *b1 = S.coef(ones);
+          S.lc(nM, zk, b1, {{dk, S.diag(alpha)}});
+          S.lc(nM, res, b1, {{Lk, S.diag(nalpha)}});
+          S.lc(nM, resc, b1, {{Lkc, S.diag(nalpha)}});
+          const size_t qr = S.gram_q(nM, res, 0, nc, resc, 0, nc, true);
+          r = S.fetch();
+          std::vector<double> keep(nc), take(nc);
+          for (int c = 0; c < nc; ++c) {
+            double beta = 1.0;
+            if (active[c]) {
+              beta = rr[c] > 0.0 ? r[qr + c] / rr[c] : 0.0;
+              rr[c] = r[qr + c];
+              steps[c]++;
+            }
+            keep[c] = active[c] ? beta : 1.0;
+            take[c] = active[c] ? 1.0 : 0.0;
+          }
+          const double *bk = S.coef(keep);
+          S.lc(nM, dk, bk, {{res, S.diag(take)}});
+          S.lc(nM, dkc, bk, {{resc, S.diag(take)}});
+          inner_total++;
+        }
+        std::vector<double> fromz(nc), fromr(nc);
+        for (int c = 0; c < nc; ++c) {
+          fromz[c] = steps[c] > 0 ? 1.0 : 0.0;
+          fromr[c] = steps[c] > 0 ? 0.0 : 1.0;
+        }
+        S.lc(nM, set(Ltmp), nullptr, {{zk, S.diag(fromz)}, {set(G), S.diag(fromr)}});
+        S.copy(nM, zk, set(Ltmp));
+      }
     } else {
-      T *R = set(Rr), *Rcv = set(Rc), *Kd = set(K), *Kdc = set(Kc), *L = set(LK), *Lc = set(LKc), *Gsol = set(Gs);
-      S.copy(R, set(Gr));
-      S.copy(Rcv, set(Grc));
-      S.copy(Kd, set(Gr));
-      S.copy(Kdc, set(Grc));
-      fill<T>(Gsol, (int64_t)S.set_elems(), T(0), s);
-      const size_t q0 = S.gram_q(R, 0, nc, Rcv, 0, nc, true);
+    // ---- gradient with respect to L: r = mask_M(Pi^T(S^u g S^o))
+    proj_t(set(Gc), set(Lr));
+    // ---- preconditioner: CG on H_L z = r, H_L(X) = mask_M(Pi^T(S^u T(Pi X) S^o)),
+    //      Euclidean inner product on M, per column
+    if (o.precond == TDDFT_PC_NONE) {
+      S.copy(nM, set(Lz), set(Lr));
+    } else {
+      T *res = set(Lres), *dk = set(Ld), *Hd = set(LHd), *zk = set(Lz);
+      S.copy(nM, res, set(Lr));
+      S.copy(nM, dk, set(Lr));
+      fill<T>(zk, (int64_t)S.elems(nM), T(0), s);
+      const size_t q0 = S.gram_q(nM, res, 0, nc, res, 0, nc, true);
       r = S.fetch();
       std::vector<double> rr(r.begin() + q0, r.begin() + q0 + nc), rr0 = rr;
       std::vector<char> active(nc);
@@ -482,65 +570,60 @@ static int solve_impl(Handle &h, int n, const tddft_options &o, double *omega, d
           any |= (bool)active[c];
         }
         if (!any) break;
-        kshift_sets<T>(h, nc, Kd, nc, 0, L, nc, 0);
-        const size_t qd = S.gram_q(L, 0, nc, Kdc, 0, nc, true);
+        proj(dk, set(T1));
+        kshift_sets<T>(h, nc, set(T1), nc, 0, set(T2), nc, 0);
+        cov(set(T2), set(T1));
+        proj_t(set(T1), Hd);
+        const size_t qd = S.gram_q(nM, dk, 0, nc, Hd, 0, nc, true);
         r = S.fetch();
-        std::vector<double> alpha(nc, 0.0);
+        std::vector<double> alpha(nc, 0.0), nalpha(nc, 0.0);
         any = false;
         for (int c = 0; c < nc; ++c) {
           if (active[c] && !(r[qd + c] > 0.0)) active[c] = 0;
-          if (active[c]) alpha[c] = rr[c] / r[qd + c];
+          if (active[c]) {
+            alpha[c] = rr[c] / r[qd + c];
+            nalpha[c] = -alpha[c];
+          }
           any |= (bool)active[c];
         }
         if (!any) break;
-        covariant_sets<T>(h, nc, L, nc, 0, Lc, nc, 0);
-        std::vector<double> ones(nc, 1.0), nalpha(nc);
-        for (int c = 0; c < nc; ++c) nalpha[c] = -alpha[c];
+        std::vector<double> ones(nc, 1.0);
         const double *b1 = S.coef(ones);
-        S.lc(Gsol, 0, nc, b1, {{Kd, S.diag(alpha)}});
-        S.lc(R, 0, nc, b1, {{L, S.diag(nalpha)}});
-        S.lc(Rcv, 0, nc, b1, {{Lc, S.diag(nalpha)}});
-        const size_t qr = S.gram_q(R, 0, nc, Rcv, 0, nc, true);
+        S.lc(nM, zk, b1, {{dk, S.diag(alpha)}});
+        S.lc(nM, res, b1, {{Hd, S.diag(nalpha)}});
+        const size_t qr = S.gram_q(nM, res, 0, nc, res, 0, nc, true);
         r = S.fetch();
-        std::vector<double> beta(nc, 1.0);
+        std::vector<double> keep(nc), take(nc);
         for (int c = 0; c < nc; ++c) {
+          double beta = 1.0;
           if (active[c]) {
-            beta[c] = rr[c] > 0.0 ? r[qr + c] / rr[c] : 0.0;
+            beta = rr[c] > 0.0 ? r[qr + c] / rr[c] : 0.0;
             rr[c] = r[qr + c];
             steps[c]++;
           }
-        }
-        // K = R + beta K on active columns (inactive keep K: beta 1, coefficient 0)
-        std::vector<double> keep(nc), take(nc);
-        for (int c = 0; c < nc; ++c) {
-          keep[c] = active[c] ? beta[c] : 1.0;
+          keep[c] = active[c] ? beta : 1.0;
           take[c] = active[c] ? 1.0 : 0.0;
         }
-        const double *bk = S.coef(keep);
-        S.lc(Kd, 0, nc, bk, {{R, S.diag(take)}});
-        S.lc(Kdc, 0, nc, bk, {{Rcv, S.diag(take)}});
+        S.lc(nM, dk, S.coef(keep), {{res, S.diag(take)}});
         inner_total++;
       }
-      // columns that never stepped keep G = g
-      std::vector<double> fromG(nc), fromg(nc);
+      // columns that never stepped keep z = r
+      std::vector<double> fromz(nc), fromr(nc);
       for (int c = 0; c < nc; ++c) {
-        fromG[c] = steps[c] > 0 ? 1.0 : 0.0;
-        fromg[c] = steps[c] > 0 ? 0.0 : 1.0;
+        fromz[c] = steps[c] > 0 ? 1.0 : 0.0;
+        fromr[c] = steps[c] > 0 ? 0.0 : 1.0;
       }
-      S.lc(set(Tmp), 0, nc, nullptr, {{Gsol, S.diag(fromG)}, {set(Gr), S.diag(fromg)}});
-      S.copy(Gsol, set(Tmp));
+      S.lc(nM, set(Ltmp), nullptr, {{zk, S.diag(fromz)}, {set(Lr), S.diag(fromr)}});
+      S.copy(nM, zk, set(Ltmp));
     }
-    // projection of the preconditioned gradient, and its covariant form
-    project_sets<T>(h, nc, set(Gs), nc, 0, set(G_), nc, 0);
-    covariant_sets<T>(h, nc, set(G_), nc, 0, set(Gc), nc, 0);
-
-    // Polak-Ribiere(+)
+    }
+    // ---- Polak-Ribiere(+) in L: beta = <z, r - r_prev> / <z_prev, r_prev>
     double beta = 0.0;
-    const bool restart = !have_dir || (o.restart > 0 && it % o.restart == 0);
+    const bool restart = !have_dir || restart_next || (o.restart > 0 && it % o.restart == 0);
     if (!restart) {
-      const size_t qa = S.gram_q(set(G_), 0, nc, set(Grc), 0, nc, true);
-      const size_t qb = S.gram_q(set(G_), 0, nc, set(Grcp), 0, nc, true);
-      const size_t qc = S.gram_q(set(Gp), 0, nc, set(Grcp), 0, nc, true);
+      const size_t qa = S.gram_q(nM, set(Lz), 0, nc, set(Lr), 0, nc, true);
+      const size_t qb = S.gram_q(nM, set(Lz), 0, nc, set(Lrp), 0, nc, true);
+      const size_t qc = S.gram_q(nM, set(Lzp), 0, nc, set(Lrp), 0, nc, true);
       r = S.fetch();
       double num = 0.0, den = 0.0;
       for (int c = 0; c < nc; ++c) {
@@ -549,39 +632,41 @@ static int solve_impl(Handle &h, int n, const tddft_options &o, double *omega, d
       }
       if (den > 0.0) beta = std::max(0.0, num / den);
     }
+    // ---- direction D = -Pi(z) + beta D_prev on R and its covariant form
+    proj(set(Lz), set(T2));
+    cov(set(T2), set(T1));
     if (beta > 0.0) {
       std::vector<double> bv(nc, beta);
       const double *bb = S.coef(bv);
-      S.lc(set(D), 0, nc, bb, {{set(G_), S.eye(nc, -1.0)}});
-      S.lc(set(Dc), 0, nc, bb, {{set(Gc), S.eye(nc, -1.0)}});
-    } else {
-      S.lc(set(D), 0, nc, nullptr, {{set(G_), S.eye(nc, -1.0)}});
-      S.lc(set(Dc), 0, nc, nullptr, {{set(Gc), S.eye(nc, -1.0)}});
-    }
-    {
-      const size_t qd = S.gram_q(set(D), 0, nc, set(Grc), 0, nc, true);
+      S.lc(nR, set(D), bb, {{set(T2), S.eye(-1.0)}});
+      S.lc(nR, set(Dc), bb, {{set(T1), S.eye(-1.0)}});
+      const size_t qd = S.gram_q(nR, set(D), 0, nc, set(Gc), 0, nc, true);
       r = S.fetch();
       double dd = 0.0;
       for (int c = 0; c < nc; ++c) dd += r[qd + c];
-      if (dd >= 0.0 && beta > 0.0) {
-        S.lc(set(D), 0, nc, nullptr, {{set(G_), S.eye(nc, -1.0)}});
-        S.lc(set(Dc), 0, nc, nullptr, {{set(Gc), S.eye(nc, -1.0)}});
+      if (dd >= 0.0) {   // not a descent direction: steepest (preconditioned) descent
+        S.lc(nR, set(D), nullptr, {{set(T2), S.eye(-1.0)}});
+        S.lc(nR, set(Dc), nullptr, {{set(T1), S.eye(-1.0)}});
       }
+    } else {
+      S.lc(nR, set(D), nullptr, {{set(T2), S.eye(-1.0)}});
+      S.lc(nR, set(Dc), nullptr, {{set(T1), S.eye(-1.0)}});
     }
     have_dir = true;
     apply(set(D), set(FD));
 
-    // line-search coefficients
-    const size_t q1 = S.gram_q(set(F), 0, nc, set(Dc), 0, nc, false);
-    const size_t q2 = S.gram_q(set(FD), 0, nc, set(Pc), 0, nc, false);
-    const size_t q3 = S.gram_q(set(FD), 0, nc, set(Dc), 0, nc, false);
-    const size_t c0 = S.gram_q(set(P), 0, n, set(Pc), n, n, false);
-    const size_t c1a = S.gram_q(set(P), 0, n, set(Dc), n, n, false);
-    const size_t c1b = S.gram_q(set(D), 0, n, set(Pc), n, n, false);
-    const size_t c2 = S.gram_q(set(D), 0, n, set(Dc), n, n, false);
-    const size_t dn = S.gram_q(set(D), 0, nc, set(Dc), 0, nc, true);
+    // ---- exact line search on Tr[N(lambda) B(lambda)^-1]
+    const size_t q1 = S.gram_q(nR, set(F), 0, nc, set(Dc), 0, nc, false);
+    const size_t q2 = S.gram_q(nR, set(FD), 0, nc, set(Pc), 0, nc, false);
+    const size_t q3 = S.gram_q(nR, set(FD), 0, nc, set(Dc), 0, nc, false);
+    const size_t c0 = S.gram_q(nR, set(P), 0, n, set(Pc), n, n, false);
+    const size_t c1a = S.gram_q(nR, set(P), 0, n, set(Dc), n, n, false);
+    const size_t c1b = S.gram_q(nR, set(D), 0, n, set(Pc), n, n, false);
+    const size_t c2 = S.gram_q(nR, set(D), 0, n, set(Dc), n, n, false);
+    const size_t dn = S.gram_q(nR, set(D), 0, nc, set(Dc), 0, nc, true);
+    const size_t pn = S.gram_q(nR, set(P), 0, nc, set(Pc), 0, nc, true);
     r = S.fetch();
-    auto nblock = [&](size_t q) {  // 1/2 (<x^p_j, f^p_i> + <x^q_j, f^q_i>) from a 2n x 2n gram
+    auto nblock = [&](size_t q) {
       Mat m((size_t)n * n);
       for (int i = 0; i < n; ++i)
         for (int j = 0; j < n; ++j)
@@ -601,8 +686,11 @@ static int solve_impl(Handle &h, int n, const tddft_options &o, double *omega, d
     B0 = sym(B0, n);
     B1 = sym(B1, n);
     B2 = sym(B2, n);
-    double dnorm = 0.0;
-    for (int c = 0; c < nc; ++c) dnorm += r[dn + c];
+    double dnorm = 0.0, pnorm = 0.0;
+    for (int c = 0; c < nc; ++c) {
+      dnorm += r[dn + c];
+      pnorm += r[pn + c];
+    }
     auto phi = [&](double l) {
       Mat Nl((size_t)n * n), Bl((size_t)n * n);
       for (int k = 0; k < n * n; ++k) {
@@ -613,17 +701,23 @@ static int solve_impl(Handle &h, int n, const tddft_options &o, double *omega, d
     };
     const double scale = 1.0 / std::sqrt(std::max(std::fabs(dnorm), 1e-300));
     const int NL = 241;
-    double best = phi(0.0), lam = 0.0;
-    int kbest = -1;
+    const double phi0 = phi(0.0);
+    double best = phi0, lam = 0.0;
+    int kbest = -1, end = NL;
     std::vector<double> lams(NL), vals(NL);
-    int end = NL;
     for (int k = 0; k < NL; ++k) {
       lams[k] = scale * std::pow(10.0, -8.0 + 12.0 * k / (NL - 1));
       vals[k] = phi(lams[k]);
       if (!std::isfinite(vals[k])) { end = k; break; }
       if (vals[k] < best) { best = vals[k]; kbest = k; }
     }
-    if (kbest >= 0) {
+    if (kbest < 0) {
+      if (++stalls >= 3) break;
+      have_dir = false;
+      continue;
+    }
+    stalls = 0;
+    {
       const double lo = kbest > 0 ? lams[kbest - 1] : 0.0;
       const double hi = kbest + 1 < end ? lams[kbest + 1] : lams[kbest];
       lam = lams[kbest];
@@ -631,29 +725,26 @@ static int solve_impl(Handle &h, int n, const tddft_options &o, double *omega, d
         const double lb = brent_min(phi, lo, hi, 1e-12);
         if (phi(lb) <= best) lam = lb;
       }
-      stalls = 0;
-    } else {
-      if (++stalls >= 3) break;
-      have_dir = false;
-      continue;
     }
-    // update
-    S.axpy_inplace(set(P), lam, set(D));
-    S.axpy_inplace(set(F), lam, set(FD));
-    S.axpy_inplace(set(Pc), lam, set(Dc));
+    // a step longer than the trial vectors themselves, or one that does not lower the
+    // functional, invalidates the conjugation history
+    restart_next = lam * std::sqrt(std::max(dnorm, 0.0)) > std::sqrt(std::max(pnorm, 0.0)) ||
+                   !(phi(lam) < phi0 - 1e-14 * std::fabs(phi0));
+    // ---- update, periodic refresh, keep history, orthonormalise
+    S.axpy(nR, set(P), lam, set(D));
+    S.axpy(nR, set(F), lam, set(FD));
+    S.axpy(nR, set(Pc), lam, set(Dc));
     if (o.refresh > 0 && (it + 1) % o.refresh == 0) {
       apply(set(P), set(F));
-      covariant_sets<T>(h, nc, set(P), nc, 0, set(Pc), nc, 0);
+      cov(set(P), set(Pc));
     }
-    // keep the previous gradient data in the new basis (copied before the transform)
-    S.copy(set(Gp), set(G_));
-    S.copy(set(Grp), set(Gr));
-    S.copy(set(Grcp), set(Grc));
-    if (!gs_step({D, Dc, Gp, Grp, Grcp})) throw Error{TDDFT_E_NOT_PD, "Tsiper metric lost positivity"};
+    S.copy(nM, set(Lrp), set(Lr));
+    S.copy(nM, set(Lzp), set(Lz));
+    if (!gs_step(true)) throw Error{TDDFT_E_NOT_PD, "Tsiper metric lost positivity"};
   }
-  // subspace diagonalisation: rotate to eigenvectors of N (B = I)
+  // ---- subspace diagonalisation: rotate to eigenvectors of N (B = I)
   {
-    const size_t qN = S.gram_q(set(F), 0, nc, set(Pc), 0, nc, false);
+    const size_t qN = S.gram_q(nR, set(F), 0, nc, set(Pc), 0, nc, false);
     std::vector<double> r = S.fetch();
     for (int i = 0; i < n; ++i)
       for (int j = 0; j < n; ++j)
@@ -664,10 +755,9 @@ static int solve_impl(Handle &h, int n, const tddft_options &o, double *omega, d
     Mat U((size_t)n * n);   // new_k = sum_i V_ik old_i
     for (int k = 0; k < n; ++k)
       for (int i = 0; i < n; ++i) U[k * n + i] = V[i * n + k];
-    S.transform(set(Tmp), set(P), U, U);
-    S.copy(set(P), set(Tmp));
-    if (Pp) unpack<T>(h.nM, h.BU, h.BO, n, set(P), nc, 0, h.m_voff.p, h.m_shape.p, Pp, h.nnzM, s);
-    if (Pq) unpack<T>(h.nM, h.BU, h.BO, n, set(P), nc, n, h.m_voff.p, h.m_shape.p, Pq, h.nnzM, s);
+    S.transform(nR, set(P), set(T1), U, U);
+    if (Pp) unpack<T>(nR, h.BU, h.BO, n, set(P), nc, 0, h.r_voff.p, h.r_shape.p, Pp, h.nnzR, s);
+    if (Pq) unpack<T>(nR, h.BU, h.BO, n, set(P), nc, n, h.r_voff.p, h.r_shape.p, Pq, h.nnzR, s);
     S.sync();
   }
   for (int i = 0; i < n; ++i) omega[i] = w[i];

@@ -149,6 +149,22 @@ HostBsr host_product(const HostBsr &A, const HostBsr &B, const Pattern &out) {
   return C;
 }
 
+HostBsr host_transpose(const HostBsr &A) {
+  HostBsr T;
+  T.pat = transpose(A.pat);
+  T.br = A.bc;
+  T.bc = A.br;
+  T.val.assign(A.val.size(), 0.0);
+  for (int i = 0; i < A.pat.nbr; ++i)
+    for (int64_t k = A.pat.rowptr[i]; k < A.pat.rowptr[i + 1]; ++k) {
+      const int64_t kt = T.pat.find(A.pat.col[k], i);
+      for (int r = 0; r < A.br; ++r)
+        for (int c = 0; c < A.bc; ++c)
+          T.val[((size_t)kt * T.br + c) * T.bc + r] = A.val[((size_t)k * A.br + r) * A.bc + c];
+    }
+  return T;
+}
+
 void DevPlan::upload(const Plan &p, hipStream_t s) {
   nout = p.out.nnzb();
   npairs = (int64_t)p.pa.size();
@@ -212,7 +228,7 @@ namespace tddft {
 const char *const kStageNames[ST_COUNT] = {
     "kshift_left", "kshift_right", "density", "fft_x_fwd", "fft_y_fwd", "fft_z_poisson",
     "fft_y_inv", "fft_x_inv", "vint_zero", "vint", "sandwich_left", "sandwich_right",
-    "project", "covariant", "gram", "lincomb"};
+    "project", "covariant", "gram", "lincomb", "project_t", "gather"};
 
 void Prof::init() {
   for (int k = 0; k < ST_COUNT; ++k) {

@@ -319,6 +319,29 @@ void unpack(int64_t nblk, int BU, int BO, int ns, const T *X, int ldx, int xc0,
 }
 
 // ---------------------------------------------------------------------------------------
+// Y[k][...] = X[map[k]][...]: blocks of a column set on a sub-pattern (truncation to M)
+template <class T>
+__global__ __launch_bounds__(256) void k_gather_blocks(int64_t nout, int blk_elems,
+                                                       const int32_t *__restrict__ map,
+                                                       const T *__restrict__ X,
+                                                       T *__restrict__ Y) {
+  const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (gid >= nout * blk_elems) return;
+  const int64_t k = gid / blk_elems;
+  const int r = (int)(gid - k * blk_elems);
+  Y[gid] = X[(int64_t)map[k] * blk_elems + r];
+}
+
+template <class T>
+void gather_blocks(int64_t nout, int blk_elems, const int32_t *map, const T *X, T *Y, hipStream_t s) {
+  const int64_t n = nout * blk_elems;
+  if (n == 0) return;
+  hipLaunchKernelGGL((k_gather_blocks<T>), dim3(nblocks(n, 256)), dim3(256), 0, s, nout, blk_elems,
+                     map, X, Y);
+  TD_HIP(hipGetLastError());
+}
+
+// ---------------------------------------------------------------------------------------
 template <class T>
 __global__ void k_fill(int64_t n, T *p, T v) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -345,7 +368,8 @@ void fill(T *p, int64_t n, T v, hipStream_t s) {
                         const int32_t *, T *, int, int, hipStream_t);                            \
   template void unpack<T>(int64_t, int, int, int, const T *, int, int, const int64_t *,         \
                           const int32_t *, double *, int64_t, hipStream_t);                      \
-  template void fill<T>(T *, int64_t, T, hipStream_t);
+  template void fill<T>(T *, int64_t, T, hipStream_t);                                          \
+  template void gather_blocks<T>(int64_t, int, const int32_t *, const T *, T *, hipStream_t);
 
 TD_INST_SPARSE(double)
 TD_INST_SPARSE(float)

@@ -1,7 +1,10 @@
 """Convert a synthetic system to the array layout of the libtddft C-ABI (BSR matrices with
 atom blocks, function boxes with (x, y, z) origins) and move response kernels between dense
-[n_states, n_u, n_o] form and the [n_states, values of M] layout.  Pure layout; no
-arithmetic of the method."""
+[n_states, n_u, n_o] form and the [n_states, values of the response pattern] layout.  Pure layout; no
+arithmetic of the method.
+
+Response kernels P^p, P^q live on the response pattern: the blocks K^c S^u L S^o K^v can
+reach from auxiliary matrices L on the truncation pattern M (Eq. auxiliary)."""
 from __future__ import annotations
 
 import numpy as np
@@ -31,6 +34,14 @@ def dense_to_bsr(A: np.ndarray, bmask: np.ndarray, br: int, bc: int):
 
 def _nonzero_blocks(A, nb, b):
     return np.abs(A.reshape(nb, b, nb, b)).max(axis=(1, 3)) > 0
+
+
+def matrix_blocks(A, nb, b):
+    """Block pattern a symmetric matrix is passed with: nonzero blocks, the diagonal, and
+    the transpose pattern."""
+    mask = _nonzero_blocks(A, nb, b)
+    np.fill_diagonal(mask, True)
+    return mask | mask.T
 
 
 def _functions(fs, N):
@@ -67,10 +78,7 @@ def system_arrays(sysm) -> dict:
     for name, A, b, off in (("S_o", sysm.S_o, no, ooff), ("H_o", sysm.H_o, no, ooff),
                             ("K_v", sysm.K_v, no, ooff), ("S_u", sysm.S_u, nu, uoff),
                             ("H_u", sysm.H_u, nu, uoff), ("K_c", sysm.K_c, nu, uoff)):
-        mask = _nonzero_blocks(A, nA, b)
-        np.fill_diagonal(mask, True)
-        mask = mask | mask.T
-        rowptr, colind, val = dense_to_bsr(A, mask, b, b)
+        rowptr, colind, val = dense_to_bsr(A, matrix_blocks(A, nA, b), b, b)
         out[name] = dict(nbr=nA, nbc=nA, row_off=off, col_off=off, rowptr=rowptr,
                          colind=colind, val=val)
     rowptr, colind, _ = dense_to_bsr(np.zeros((nA * nu, nA * no)), sysm.M, nu, no)
@@ -79,29 +87,49 @@ def system_arrays(sysm) -> dict:
     return out
 
 
-def m_index(sysm) -> np.ndarray:
-    """Flat dense indices (into [n_u, n_o]) of the values of M in C-ABI order."""
+def response_blocks(sysm) -> np.ndarray:
+    """Atom pairs (u-atom, o-atom) of the response pattern: the blocks reachable in
+    K^c S^u L S^o K^v from L on M (graph reachability over the nonzero blocks)."""
+    nA = sysm.cfg.n_atoms
+
+    def nz(A, b):
+        return matrix_blocks(A, nA, b)
+
+    def bmul(X, Y):
+        return (X.astype(np.int32) @ Y.astype(np.int32)) > 0
+    left = bmul(nz(sysm.K_c, sysm.cfg.n_u), nz(sysm.S_u, sysm.cfg.n_u))
+    right = bmul(nz(sysm.S_o, sysm.cfg.n_o), nz(sysm.K_v, sysm.cfg.n_o))
+    return bmul(bmul(left, sysm.M), right)
+
+
+def _index(sysm, blocks) -> np.ndarray:
     cfg = sysm.cfg
     nu, no = cfg.n_u, cfg.n_o
     idx = []
     nofn = sysm.occ.n_fn
     for I in range(cfg.n_atoms):
-        for J in np.nonzero(sysm.M[I])[0]:
+        for J in np.nonzero(blocks[I])[0]:
             r = I * nu + np.arange(nu)
             c = J * no + np.arange(no)
             idx.append((r[:, None] * nofn + c[None, :]).ravel())
     return np.concatenate(idx)
 
 
-def dense_to_m(sysm, X: np.ndarray) -> np.ndarray:
-    """[n, n_u, n_o] -> [n, nnz(M)]"""
-    idx = m_index(sysm)
+def p_index(sysm) -> np.ndarray:
+    """Flat dense indices (into [n_u, n_o]) of the values of a response kernel in C-ABI
+    order (blocks of the response pattern, row-major inside each block)."""
+    return _index(sysm, response_blocks(sysm))
+
+
+def dense_to_p(sysm, X: np.ndarray) -> np.ndarray:
+    """[n, n_u, n_o] -> [n, values of the response pattern]"""
+    idx = p_index(sysm)
     X = np.asarray(X)
     return np.ascontiguousarray(X.reshape(X.shape[0], -1)[:, idx])
 
 
-def m_to_dense(sysm, V: np.ndarray) -> np.ndarray:
-    idx = m_index(sysm)
+def p_to_dense(sysm, V: np.ndarray) -> np.ndarray:
+    idx = p_index(sysm)
     V = np.asarray(V)
     out = np.zeros((V.shape[0], sysm.vir.n_fn * sysm.occ.n_fn))
     out[:, idx] = V

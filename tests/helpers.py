@@ -13,10 +13,16 @@ XC_MODES = {  # C-ABI coupling kernel -> oracle switches
 }
 
 
-def random_m(sysm, n, seed):
+def response_mask(sysm):
+    """Function-level mask of the response pattern (blocks of K^c S^u L S^o K^v, L on M)."""
+    return np.kron(sabi.response_blocks(sysm), np.ones((sysm.cfg.n_u, sysm.cfg.n_o))).astype(bool)
+
+
+def random_p(sysm, n, seed):
+    """Random response kernels on the response pattern, [n, n_u, n_o]."""
     rng = np.random.default_rng(seed)
     X = rng.standard_normal((n, sysm.vir.n_fn, sysm.occ.n_fn))
-    return X * sysm.fn_mask()[None]
+    return X * response_mask(sysm)[None]
 
 
 def gpu_handle(sysm, **opts):

@@ -7,7 +7,7 @@ import sys
 import numpy as np
 import pytest
 
-from helpers import XC_MODES, gpu_handle, random_m, rel_err, to_dev
+from helpers import XC_MODES, gpu_handle, random_p, rel_err, response_mask, to_dev
 from oracle.apply import Operator
 from synth import abi as sabi
 
@@ -21,13 +21,13 @@ def _run(sysm, xc, precision, n, seed=1):
     print(f"[apply] {sysm.cfg.name} N={sysm.cfg.N} xc={xc} {precision} n={n}", flush=True)
     sys.stdout.flush()
     op = Operator(sysm, **XC_MODES[xc])
-    Pp = random_m(sysm, n, seed)
-    Pq = random_m(sysm, n, seed + 100)
+    Pp = random_p(sysm, n, seed)
+    Pq = random_p(sysm, n, seed + 100)
     fp_ref, fq_ref = op.apply(Pp, Pq)
     h = gpu_handle(sysm, precision=precision, xc=xc)
-    fp, fq = h.tddft_apply(to_dev(sabi.dense_to_m(sysm, Pp)), to_dev(sabi.dense_to_m(sysm, Pq)))
-    fp = sabi.m_to_dense(sysm, fp.cpu().numpy())
-    fq = sabi.m_to_dense(sysm, fq.cpu().numpy())
+    fp, fq = h.tddft_apply(to_dev(sabi.dense_to_p(sysm, Pp)), to_dev(sabi.dense_to_p(sysm, Pq)))
+    fp = sabi.p_to_dense(sysm, fp.cpu().numpy())
+    fq = sabi.p_to_dense(sysm, fq.cpu().numpy())
     h.close()
     return fp, fq, fp_ref, fq_ref, op, Pq
 
@@ -39,7 +39,24 @@ def test_apply_fp64(name, xc, request):
     fp, fq, fp_ref, fq_ref, _, _ = _run(s, xc, "fp64", 3)
     assert rel_err(fp, fp_ref) < TOL_FP64
     assert rel_err(fq, fq_ref) < TOL_FP64
-    assert np.all(fp[:, ~s.fn_mask()] == 0) and np.all(fq[:, ~s.fn_mask()] == 0)
+    outside = ~response_mask(s)
+    assert np.all(fp[:, outside] == 0) and np.all(fq[:, outside] == 0)
+
+
+@pytest.mark.parametrize("name", ["small_dense", "small_odd", "small_trunc"])
+def test_response_pattern_matches_independent_constructions(name, request):
+    """The library's response pattern equals the generator's and the oracle's."""
+    from oracle.apply import response_pattern
+    from synth import abi as sabi
+    s = request.getfixturevalue(name)
+    h = gpu_handle(s, precision="fp64")
+    rowptr, colind = h.tddft_response_pattern()
+    h.close()
+    lib = np.zeros((s.cfg.n_atoms, s.cfg.n_atoms), dtype=bool)
+    for i in range(s.cfg.n_atoms):
+        lib[i, colind[rowptr[i]:rowptr[i + 1]]] = True
+    assert np.array_equal(lib, sabi.response_blocks(s))
+    assert np.array_equal(lib, response_pattern(s))
 
 
 @pytest.mark.parametrize("n", [1, 2, 5, 8, 13])

@@ -86,11 +86,15 @@ def test_preconditioner_tight_is_inverse_ks_difference(dense):
     rng = np.random.default_rng(5)
     x = rng.standard_normal((2, len(cs.eps_c), len(cs.eps_v)))
     g = cs.to_ngwf(x)
-    sol = Solver(op, Options(n_states=2, eps_tol=1e-13, max_inner=200))
-    G, it = sol.precondition(g)
     ref = cs.to_ngwf(x / cs.D.reshape(x.shape[1:]))
+    sol = Solver(op, Options(n_states=2, eps_tol=1e-13, max_inner=200))
+    G, it = sol.precondition_p(g)
     assert np.max(np.abs(G - ref)) < 1e-9 * np.max(np.abs(ref))
     assert it > 1
+    # the same operator expressed on the auxiliary matrices: Pi(z) solves Eq. precond
+    sol = Solver(op, Options(n_states=2, eps_tol=1e-14, max_inner=2000))
+    z, it = sol.precondition(sol.grad_L(g))
+    assert np.max(np.abs(sol.project(z) - ref)) < 1e-7 * np.max(np.abs(ref))
 
 
 def test_line_search_minimises_trace_functional(dense):
