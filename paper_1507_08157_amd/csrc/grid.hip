@@ -9,8 +9,8 @@
 //    wave-uniform (scalar) loads; also used once for rho0 = 2 sum o K^v o.
 //  * potential integrals (Sec. II.C, V_SCF^{chi phi}):  V_s,ab = h^3 sum_r u_a V_s o_b
 //    per tile the (u-atom, o-atom) block products are reduced over the 64 points in
-//    registers, summed over a brick of tiles in LDS, and flushed once per brick with
-//    global atomic adds.
+//    registers, summed over a brick of tiles in LDS, written per brick to a partial-sum
+//    buffer and reduced per block in a fixed order (no global atomics, deterministic).
 //  * ALDA exchange kernel f_xc = -(1/3)(3/pi)^{1/3} rho0^{-2/3} (Sec. II.A, xc part).
 // Grid fields are tile-major complex pairs: state 2k in the real part, 2k+1 in the
 // imaginary part of field k, so the Hartree FFT transforms two states at once.
@@ -37,17 +37,23 @@ __device__ __forceinline__ double cvt<double, __hip_bfloat16>(__hip_bfloat16 v) 
 }
 
 // ---------------------------------------------------------------------------------------
+// One wave per tile.  The tile's sample rows are staged in LDS once; for each chunk of NSP
+// states the P blocks of every (u-atom, o-atom) pair of the tile are staged too (coalesced
+// loads, zero for pairs outside R and states beyond ns), so the FMA loop is branch-free and
+// reads P with broadcast LDS loads.
 template <class T, class S, int BL, int BR>
 __global__ __launch_bounds__(256) void k_density(DevTiles tl, const T *__restrict__ X, int ldx,
                                                  int xc0, int ns, T *__restrict__ out,
                                                  int64_t pair_stride, T scale) {
   extern __shared__ unsigned char lds_raw[];
-  T *lds = reinterpret_cast<T *>(lds_raw);
   constexpr int E = BL * BR;
+  constexpr int NSP = 4;
   const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int p = threadIdx.x & 63;
   const int t = blockIdx.x * (blockDim.x >> 6) + w;
-  T *lu = lds + (size_t)w * tl.maxrows * TP;
+  const size_t per_wave = (size_t)tl.maxrows * TP + (size_t)tl.maxpairs * NSP * E;
+  T *lu = reinterpret_cast<T *>(lds_raw) + (size_t)w * per_wave;
+  T *lp = lu + (size_t)tl.maxrows * TP;
   int nua = 0, noa = 0, u0 = 0, o0 = 0;
   if (t < tl.nt) {
     u0 = tl.uptr[t];
@@ -62,43 +68,52 @@ __global__ __launch_bounds__(256) void k_density(DevTiles tl, const T *__restric
     for (int r = 0; r < nua * BL; ++r) lu[r * TP + p] = cvt<T>(us[r * TP + p]);
     for (int r = 0; r < noa * BR; ++r) lo[r * TP + p] = cvt<T>(os[r * TP + p]);
   }
-  __syncthreads();
-  if (t >= tl.nt) return;
-  const int32_t *pid = tl.pidx + tl.pptr[t];
+  const int npair = nua * noa;
+  const int32_t *pid = tl.pidx + (t < tl.nt ? tl.pptr[t] : 0);
   using T2 = typename Vec2<T>::type;
-  for (int s0 = 0; s0 < ns; s0 += 4) {
-    const int nk = min(4, ns - s0);
-    T acc[4] = {T(0), T(0), T(0), T(0)};
-    for (int i = 0; i < nua; ++i) {
-      T tmp[4][BL];
+  for (int s0 = 0; s0 < ns; s0 += NSP) {
+    __syncthreads();
+    for (int idx = p; idx < npair * NSP * E; idx += 64) {
+      const int pr = idx / (NSP * E);
+      const int rem = idx - pr * (NSP * E);
+      const int sk = rem / E;
+      const int pb = pid[pr];
+      T v = T(0);
+      if (pb >= 0 && s0 + sk < ns) v = X[((int64_t)pb * ldx + xc0 + s0) * E + rem];
+      lp[idx] = v;
+    }
+    __syncthreads();
+    if (t >= tl.nt) continue;
+    T acc[NSP];
 #pragma unroll
-      for (int k = 0; k < 4; ++k)
+    for (int k = 0; k < NSP; ++k) acc[k] = T(0);
+    for (int i = 0; i < nua; ++i) {
+      T tmp[NSP][BL];
+#pragma unroll
+      for (int k = 0; k < NSP; ++k)
 #pragma unroll
         for (int r = 0; r < BL; ++r) tmp[k][r] = T(0);
+      const T *Pi = lp + (size_t)i * noa * NSP * E;
       for (int j = 0; j < noa; ++j) {
-        const int pb = pid[i * noa + j];
-        if (pb < 0) continue;
         T o[BR];
 #pragma unroll
         for (int c = 0; c < BR; ++c) o[c] = lo[(j * BR + c) * TP + p];
-        const T *P = X + ((int64_t)pb * ldx + xc0 + s0) * E;
+        const T *Pj = Pi + (size_t)j * NSP * E;
 #pragma unroll
-        for (int k = 0; k < 4; ++k) {
-          if (k < nk) {
+        for (int k = 0; k < NSP; ++k)
 #pragma unroll
-            for (int r = 0; r < BL; ++r)
+          for (int r = 0; r < BL; ++r)
 #pragma unroll
-              for (int c = 0; c < BR; ++c) tmp[k][r] += P[k * E + r * BR + c] * o[c];
-          }
-        }
+            for (int c = 0; c < BR; ++c) tmp[k][r] += Pj[k * E + r * BR + c] * o[c];
       }
 #pragma unroll
       for (int r = 0; r < BL; ++r) {
         const T u = lu[(i * BL + r) * TP + p];
 #pragma unroll
-        for (int k = 0; k < 4; ++k) acc[k] += u * tmp[k][r];
+        for (int k = 0; k < NSP; ++k) acc[k] += u * tmp[k][r];
       }
     }
+    const int nk = min(NSP, ns - s0);
     T2 v0, v1;
     v0.x = scale * acc[0];
     v0.y = nk > 1 ? scale * acc[1] : T(0);
@@ -112,10 +127,14 @@ __global__ __launch_bounds__(256) void k_density(DevTiles tl, const T *__restric
 }
 
 // ---------------------------------------------------------------------------------------
+// One workgroup per brick of tiles.  Per tile the (u-atom, o-atom) block integrals are
+// reduced over the 64 points in registers (one pair per lane) and added into the brick's
+// LDS accumulator; the accumulator is then written, without atomics, to the brick's slots
+// of a partial-sum buffer that k_vint_reduce sums per overlap block in a fixed order.
 template <class T, class S, int BL, int BR>
 __global__ __launch_bounds__(256) void k_vint(DevTiles tl, DevBricks br, const T *__restrict__ V,
                                               int64_t pair_stride, int ns,
-                                              T *__restrict__ Vout, int ldv, T scale) {
+                                              T *__restrict__ partial, T scale) {
   extern __shared__ unsigned char lds_raw[];
   constexpr int E = BL * BR;
   constexpr int LD = TP + 1;   // padded rows: lanes reading different rows hit different banks
@@ -167,21 +186,19 @@ __global__ __launch_bounds__(256) void k_vint(DevTiles tl, DevBricks br, const T
           for (int q = 0; q < SC; ++q)
 #pragma unroll
             for (int e = 0; e < E; ++e) a[q][e] = T(0);
-          for (int p = 0; p < TP; ++p) {
+          for (int pt = 0; pt < TP; ++pt) {
             T uo[E];
 #pragma unroll
             for (int r = 0; r < BL; ++r) {
-              const T u = lu[(i * BL + r) * LD + p];
+              const T u = lu[(i * BL + r) * LD + pt];
 #pragma unroll
-              for (int c = 0; c < BR; ++c) uo[r * BR + c] = u * lo[(j * BR + c) * LD + p];
+              for (int c = 0; c < BR; ++c) uo[r * BR + c] = u * lo[(j * BR + c) * LD + pt];
             }
 #pragma unroll
             for (int q = 0; q < SC; ++q) {
-              if (q < nk) {
-                const T v = lv[(s0 + q) * TP + p];
+              const T v = (q < nk) ? lv[(s0 + q) * TP + pt] : T(0);
 #pragma unroll
-                for (int e = 0; e < E; ++e) a[q][e] += uo[e] * v;
-              }
+              for (int e = 0; e < E; ++e) a[q][e] += uo[e] * v;
             }
           }
 #pragma unroll
@@ -194,16 +211,26 @@ __global__ __launch_bounds__(256) void k_vint(DevTiles tl, DevBricks br, const T
     }
   }
   __syncthreads();
-  const int64_t sb = br.sptr[b];
-  for (int idx = threadIdx.x; idx < nslots * ns * E; idx += blockDim.x) {
-    const int slot = idx / (ns * E);
-    const int ob = br.slot_blk[sb + slot];
-    if (ob < 0) continue;
-    const int rem = idx - slot * ns * E;
-    const int s = rem / E, e = rem - s * E;
-    const T v = acc[idx];
-    if (v != T(0)) atomicAdd(&Vout[((int64_t)ob * ldv + s) * E + e], scale * v);
-  }
+  T *dst = partial + br.sptr[b] * ns * E;
+  for (int idx = threadIdx.x; idx < nslots * ns * E; idx += blockDim.x) dst[idx] = scale * acc[idx];
+}
+
+// Vout[ob][ldv][E] (columns 0..ns) = sum over the (brick, slot) contributions of block ob
+template <class T>
+__global__ __launch_bounds__(256) void k_vint_reduce(int64_t nblk, int ns, int E,
+                                                     const int64_t *__restrict__ cptr,
+                                                     const int64_t *__restrict__ cslot,
+                                                     const T *__restrict__ partial,
+                                                     T *__restrict__ Vout, int ldv) {
+  const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int per = ns * E;
+  if (gid >= nblk * per) return;
+  const int64_t ob = gid / per;
+  const int r = (int)(gid - ob * per);
+  T acc = T(0);
+  for (int64_t q = cptr[ob]; q < cptr[ob + 1]; ++q) acc += partial[cslot[q] * per + r];
+  const int s = r / E, e = r - (r / E) * E;
+  Vout[((int64_t)ob * ldv + s) * E + e] = acc;
 }
 
 // ---------------------------------------------------------------------------------------
@@ -239,9 +266,9 @@ template <class T>
 void density(const DevTiles &tl, int stype, int BL, int BR, const T *X, int ldx, int xc0, int ns,
              T *out, int64_t pair_stride, double scale, hipStream_t s) {
   if (tl.nt == 0 || ns == 0) return;
-  const size_t per_wave = (size_t)tl.maxrows * TP * sizeof(T);
-  const int waves = (int)std::max<size_t>(1, std::min<size_t>(4, tl.lds_limit / std::max<size_t>(per_wave, 1)));
+  const size_t per_wave = ((size_t)tl.maxrows * TP + (size_t)tl.maxpairs * 4 * BL * BR) * sizeof(T);
   if (per_wave > tl.lds_limit) throw Error{TDDFT_E_INVALID, "too many functions per grid tile for the LDS budget"};
+  const int waves = (int)std::max<size_t>(1, std::min<size_t>(4, tl.lds_limit / per_wave));
   const size_t lds = (size_t)waves * per_wave;
   const unsigned grid = (unsigned)((tl.nt + waves - 1) / waves);
   TD_SAMPLE(T, stype, TD_GRID_BDIM(BL, BR, hipLaunchKernelGGL((k_density<T, S, BL, BR>), dim3(grid), dim3(64 * waves), lds, s, tl, X, ldx, xc0, ns, out, pair_stride, (T)scale)));
@@ -250,8 +277,8 @@ void density(const DevTiles &tl, int stype, int BL, int BR, const T *X, int ldx,
 
 template <class T>
 void potential_integrals(const DevTiles &tl, const DevBricks &br, int stype, int BL, int BR,
-                         const T *V, int64_t pair_stride, int ns, T *Vout, int ldv,
-                         double scale, hipStream_t s) {
+                         const T *V, int64_t pair_stride, int ns, T *partial, T *Vout, int ldv,
+                         int64_t nblk_out, double scale, hipStream_t s) {
   if (br.nb == 0 || ns == 0) return;
   const int E = BL * BR;
   const size_t acc_len = ((size_t)br.max_slots * ns * E + 1) & ~(size_t)1;
@@ -260,7 +287,12 @@ void potential_integrals(const DevTiles &tl, const DevBricks &br, int stype, int
   while (waves > 1 && acc_len * sizeof(T) + waves * per_wave > tl.lds_limit) --waves;
   const size_t lds = acc_len * sizeof(T) + (size_t)waves * per_wave;
   if (lds > tl.lds_limit) throw Error{TDDFT_E_INVALID, "potential-integral accumulator exceeds the LDS budget"};
-  TD_SAMPLE(T, stype, TD_GRID_BDIM(BL, BR, hipLaunchKernelGGL((k_vint<T, S, BL, BR>), dim3(br.nb), dim3(64 * waves), lds, s, tl, br, V, pair_stride, ns, Vout, ldv, (T)scale)));
+  TD_SAMPLE(T, stype, TD_GRID_BDIM(BL, BR, hipLaunchKernelGGL((k_vint<T, S, BL, BR>), dim3(br.nb), dim3(64 * waves), lds, s, tl, br, V, pair_stride, ns, partial, (T)scale)));
+  TD_HIP(hipGetLastError());
+  const int64_t n = nblk_out * ns * E;
+  if (n == 0) return;
+  hipLaunchKernelGGL((k_vint_reduce<T>), dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, nblk_out, ns, E,
+                     br.cptr, br.cslot, partial, Vout, ldv);
   TD_HIP(hipGetLastError());
 }
 
@@ -277,11 +309,11 @@ template void density<double>(const DevTiles &, int, int, int, const double *, i
 template void density<float>(const DevTiles &, int, int, int, const float *, int, int, int,
                              float *, int64_t, double, hipStream_t);
 template void potential_integrals<double>(const DevTiles &, const DevBricks &, int, int, int,
-                                          const double *, int64_t, int, double *, int, double,
-                                          hipStream_t);
+                                          const double *, int64_t, int, double *, double *, int,
+                                          int64_t, double, hipStream_t);
 template void potential_integrals<float>(const DevTiles &, const DevBricks &, int, int, int,
-                                         const float *, int64_t, int, float *, int, double,
-                                         hipStream_t);
+                                         const float *, int64_t, int, float *, float *, int,
+                                         int64_t, double, hipStream_t);
 template void alda_kernel<double>(int64_t, const double *, double, double *, hipStream_t);
 template void alda_kernel<float>(int64_t, const float *, double, float *, hipStream_t);
 

@@ -286,7 +286,23 @@ static void build_bricks(Handle &h, const HostSetTiles &tu, const HostSetTiles &
         max_tiles = std::max(max_tiles, (int)tl.size());
         max_slots = std::max(max_slots, (int)(ul.size() * ol.size()));
       }
+  // per overlap block: the global slots (brick base + slot) that hold its partial sums
+  std::vector<int64_t> cptr(O.nnzb() + 1, 0), cslot;
+  for (size_t k = 0; k < slot.size(); ++k)
+    if (slot[k] >= 0) cptr[slot[k] + 1]++;
+  for (int64_t k = 0; k < O.nnzb(); ++k) cptr[k + 1] += cptr[k];
+  cslot.resize(cptr[O.nnzb()]);
+  {
+    std::vector<int64_t> fillp(cptr.begin(), cptr.end() - 1);
+    for (size_t k = 0; k < slot.size(); ++k)
+      if (slot[k] >= 0) cslot[fillp[slot[k]]++] = (int64_t)k;
+  }
   hipStream_t s = h.stream;
+  h.b_cptr.upload(cptr, s);
+  h.b_cslot.upload(cslot, s);
+  h.bricks.nslots_total = (int64_t)slot.size();
+  h.bricks.cptr = h.b_cptr.p;
+  h.bricks.cslot = h.b_cslot.p;
   h.b_tptr.upload(tptr, s);
   h.b_tiles.upload(tiles, s);
   h.b_nu.upload(nu, s);
@@ -439,11 +455,14 @@ void create_handle(Handle &h, const tddft_system &sys, const tddft_options &o) {
   std::vector<int32_t> pidx_uo, pidx_oo;
   std::vector<std::vector<int32_t>> orows(h.nbu);
   h.maxrows_uo = h.maxrows_oo = 0;
+  int maxpairs_uo = 0, maxpairs_oo = 0;
   int64_t pp = 0;
   for (int t = 0; t < nt; ++t) {
     const int nua = tu.ptr[t + 1] - tu.ptr[t], noa = to.ptr[t + 1] - to.ptr[t];
     h.maxrows_uo = std::max(h.maxrows_uo, nua * h.BU + noa * h.BO);
     h.maxrows_oo = std::max(h.maxrows_oo, 2 * noa * h.BO);
+    maxpairs_uo = std::max(maxpairs_uo, nua * noa);
+    maxpairs_oo = std::max(maxpairs_oo, noa * noa);
     pp += (int64_t)nua * h.BU * noa * h.BO;
     for (int i = 0; i < nua; ++i)
       for (int j = 0; j < noa; ++j) {
@@ -494,17 +513,17 @@ void create_handle(Handle &h, const tddft_system &sys, const tddft_options &o) {
     upload_bf16(h.us16, tu.samples, s);
     upload_bf16(h.os16, to.samples, s);
   }
-  h.tiles_uo = DevTiles{nt, h.maxrows_uo, h.t_uptr.p, h.t_optr.p, h.t_pptr_uo.p, h.t_pidx_uo.p,
-                        h.usamp(), h.osamp(), h.lds_limit};
-  h.tiles_oo = DevTiles{nt, h.maxrows_oo, h.t_optr.p, h.t_optr.p, h.t_pptr_oo.p, h.t_pidx_oo.p,
-                        h.os64.p, h.os64.p, h.lds_limit};
-  TD_REQUIRE((size_t)h.maxrows_uo * TP * sizeof(double) <= h.lds_limit,
+  h.tiles_uo = DevTiles{nt, h.maxrows_uo, maxpairs_uo, h.t_uptr.p, h.t_optr.p, h.t_pptr_uo.p,
+                        h.t_pidx_uo.p, h.usamp(), h.osamp(), h.lds_limit};
+  h.tiles_oo = DevTiles{nt, h.maxrows_oo, maxpairs_oo, h.t_optr.p, h.t_optr.p, h.t_pptr_oo.p,
+                        h.t_pidx_oo.p, h.os64.p, h.os64.p, h.lds_limit};
+  TD_REQUIRE(((size_t)h.maxrows_uo * TP + (size_t)maxpairs_uo * 4 * h.E) * sizeof(double) <= h.lds_limit,
              "too many functions per grid tile for the LDS budget");
 
   // bricks: 2^3 tiles when the accumulator fits, else single tiles
   build_bricks(h, tu, to, O, 2);
   const size_t tsz = h.stype == SAMPLE_F64 ? sizeof(double) : sizeof(float);
-  if (vint_lds_bytes(h, 8, tsz) > h.lds_limit / 2) build_bricks(h, tu, to, O, 1);
+  if (vint_lds_bytes(h, 8, tsz) > h.lds_limit) build_bricks(h, tu, to, O, 1);
   TD_REQUIRE(vint_lds_bytes(h, 2, tsz) <= h.lds_limit, "too many functions per grid tile for the LDS budget");
 
   // ---- plans
@@ -626,11 +645,15 @@ void apply_sets(Handle &h, int n, const T *X, int ldx, int xp0, int xq0, T *F, i
   const size_t bytes_w = (size_t)npair * wstride * sizeof(T);
   const size_t bytes_v = (size_t)h.nO * n * h.E * sizeof(T);
   const size_t bytes_y = (size_t)h.nM2 * n * h.E * sizeof(T);
-  unsigned char *base = (unsigned char *)h.w_apply.get(bytes_f + bytes_w + bytes_v + bytes_y + 1024);
+  int chunk = n;
+  while (chunk > 2 && vint_lds_bytes(h, chunk, sizeof(T)) > h.lds_limit) chunk = (chunk + 1) / 2 + ((chunk + 1) / 2) % 2;
+  const size_t bytes_part = (size_t)h.bricks.nslots_total * chunk * h.E * sizeof(T);
+  unsigned char *base = (unsigned char *)h.w_apply.get(bytes_f + bytes_w + bytes_v + bytes_y + bytes_part + 1024);
   T *fields = (T *)base;
   T *work = (T *)(base + bytes_f);
   T *Vset = (T *)(base + bytes_f + bytes_w);
   T *Y = (T *)(base + bytes_f + bytes_w + bytes_v);
+  T *part = (T *)(base + bytes_f + bytes_w + bytes_v + bytes_y);
   const int st = stype_of<T>(h);
   DevTiles tl = h.tiles_uo;
   tl.usamp = h.usamp();
@@ -639,18 +662,13 @@ void apply_sets(Handle &h, int n, const T *X, int ldx, int xp0, int xq0, T *F, i
   density<T>(tl, st, h.BU, h.BO, X, ldx, xq0, n, fields, pstride, 1.0, s);
   h.prof.end(ST_DENSITY, s);
   hartree_xc<T>(h.geom, h.fft, npair, fields, work, h.fxc<T>(), h.opts.xc == TDDFT_XC_ALDA_X, s, &h.prof);
-  h.prof.begin(ST_VINT_ZERO, s);
-  fill<T>(Vset, (int64_t)h.nO * n * h.E, T(0), s);
-  h.prof.end(ST_VINT_ZERO, s);
   // states in chunks whose brick accumulators fit in LDS (chunk starts are even)
   h.prof.begin(ST_VINT, s);
-  int chunk = n;
-  while (chunk > 2 && vint_lds_bytes(h, chunk, sizeof(T)) > h.lds_limit) chunk = (chunk + 1) / 2 + ((chunk + 1) / 2) % 2;
   for (int s0 = 0; s0 < n; s0 += chunk) {
     const int ns = std::min(chunk, n - s0);
     // Vout columns s0.. of a set with n columns: offset the pointer by s0 * E
     potential_integrals<T>(tl, h.bricks, st, h.BU, h.BO, fields + (int64_t)(s0 / 2) * pstride, pstride,
-                           ns, Vset + (size_t)s0 * h.E, n, h.dV, s);
+                           ns, part, Vset + (size_t)s0 * h.E, n, h.nO, h.dV, s);
   }
   h.prof.end(ST_VINT, s);
   h.prof.begin(ST_SANDWICH_LEFT, s);

@@ -82,7 +82,7 @@ struct Handle {
   int maxrows_uo = 0, maxrows_oo = 0;
   int brick_edge = 2;
   DevBuf<int32_t> b_tptr, b_tiles, b_nu, b_no, b_slot, b_ubl, b_obl;
-  DevBuf<int64_t> b_sptr;
+  DevBuf<int64_t> b_sptr, b_cptr, b_cslot;
   DevBricks bricks{};
   double mean_u_per_tile = 0, mean_o_per_tile = 0;
   int64_t pair_points = 0;     // sum over tiles of (u rows * o rows) * TP (work measure)

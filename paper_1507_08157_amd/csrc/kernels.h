@@ -47,6 +47,7 @@ void gather_blocks(int64_t nout, int blk_elems, const int32_t *map, const T *X, 
 struct DevTiles {
   int nt = 0;
   int maxrows = 0;          // max over tiles of (n_left_atoms * BL + n_right_atoms * BR)
+  int maxpairs = 0;         // max over tiles of n_left_atoms * n_right_atoms
   const int32_t *uptr = nullptr, *optr = nullptr;   // [nt + 1]
   const int64_t *pptr = nullptr;                    // [nt + 1]
   const int32_t *pidx = nullptr;                    // pair -> block index (or -1)
@@ -62,6 +63,9 @@ struct DevBricks {
   const int64_t *sptr = nullptr;                     // [nb + 1] slot table offsets
   const int32_t *slot_blk = nullptr;                 // slot -> O block (or -1)
   const int32_t *ubl = nullptr, *obl = nullptr;      // per tile-list entry: brick-local index
+  int64_t nslots_total = 0;                          // sum over bricks of their slots
+  const int64_t *cptr = nullptr;                     // [n_out_blocks + 1] contributions
+  const int64_t *cslot = nullptr;                    // global slot ids (brick base + slot)
 };
 
 enum SampleType { SAMPLE_F64 = 0, SAMPLE_F32 = 1, SAMPLE_BF16 = 2 };
@@ -72,12 +76,12 @@ template <class T>
 void density(const DevTiles &tl, int stype, int BL, int BR, const T *X, int ldx, int xc0,
              int ns, T *out, int64_t pair_stride, double scale, hipStream_t s);
 
-// Vout[blk][ldv][E] += scale * sum_r left_a(r) V_s(r) right_b(r) over the tiles of every
-// brick (V tile-major complex pairs); Vout must be zeroed first
+// Vout[blk][ldv][E] = scale * sum_r left_a(r) V_s(r) right_b(r) for the nblk_out overlap
+// blocks (V tile-major complex pairs); partial: [nslots_total][ns][E] scratch
 template <class T>
 void potential_integrals(const DevTiles &tl, const DevBricks &br, int stype, int BL, int BR,
-                         const T *V, int64_t pair_stride, int ns, T *Vout, int ldv,
-                         double scale, hipStream_t s);
+                         const T *V, int64_t pair_stride, int ns, T *partial, T *Vout, int ldv,
+                         int64_t nblk_out, double scale, hipStream_t s);
 
 // f_xc from rho0 (real parts of a tile-major pair array): ALDA exchange kernel
 template <class T>
