@@ -2,12 +2,17 @@
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload prec]
                     [--precision fp32|fp64|bf16] [--no-solve] [--no-cpu-baseline]
+                    [--copy-calibration MiB]
 
 Workload `prec`: 200 atoms in a 40 bohr periodic cube, 128^3 grid, 400 occupied-set and
-600 unoccupied-set functions (radius 7 bohr), density kernels and response pattern
-truncated at 20 bohr, 8 excitations (synthetic, seeded).  One step applies the operator of
-Eq. operator_RPA to all 8 states at once (one tddft_apply call); inputs are resident in HBM
-before timing starts.  value = 8 * K / time (state-applies per second).
+600 unoccupied-set functions (radius 7 bohr), untruncated density kernels (so the response
+pattern K^c S^u L S^o K^v covers every atom block), 8 excitations (synthetic, seeded).
+One step applies the operator of Eq. operator_RPA to all 8 states at once (one
+tddft_apply call); inputs are resident in HBM before timing starts.
+value = 8 * K / time (state-applies per second).
+
+--copy-calibration runs one plain device-to-device copy of the given size before the
+timed loop, so that hardware byte counters can be scaled against a kernel of known traffic.
 
 The same JSON line carries:
   * roofline of the dominant kernel, timed with HIP events on its own stream over the
@@ -19,6 +24,7 @@ The same JSON line carries:
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -53,9 +59,12 @@ def kernel_work(info, stage, n, prec):
     pp = info["pair_points"]
     if stage == "density":
         # samples read once, P on M read once, rho written once; 2 flops per pair-point FMA
-        return samples + info["blocks_m"] * E * n * t_bytes + field, 2.0 * pp * n
+        return samples + info["blocks_r"] * E * n * t_bytes + field, 2.0 * pp * n
     if stage == "vint":
         return samples + field + info["blocks_o"] * E * n * t_bytes, 2.0 * pp * n + 64.0 * nt * n
+    if stage == "vint_reduce":
+        slots = info["brick_slots"] * E * n * t_bytes
+        return slots + info["blocks_o"] * E * n * t_bytes, float(info["brick_slots"] * E * n)
     if stage in ("fft_x_fwd", "fft_y_fwd", "fft_y_inv"):
         return 2 * grid, 0.0
     if stage == "fft_z_poisson":
@@ -64,20 +73,20 @@ def kernel_work(info, stage, n, prec):
         return grid + 2 * field + nt * 64 * t_bytes, 0.0
     if stage in ("kshift_left", "kshift_right"):
         pairs = info["pairs_kshift"] / 2
-        return info["blocks_m"] * E * 2 * n * t_bytes * 2, 2.0 * pairs * 2 * n * 18
+        return info["blocks_r"] * E * 2 * n * t_bytes * 2, 2.0 * pairs * 2 * n * 18
     if stage in ("sandwich_left", "sandwich_right"):
-        return (info["blocks_o"] + info["blocks_m2"] + info["blocks_m"]) * E * n * t_bytes, \
+        return (info["blocks_o"] + info["blocks_m2"] + info["blocks_r"]) * E * n * t_bytes, \
             2.0 * info["pairs_sandwich"] / 2 * n * 18
     return 0.0, 0.0
 
 
-def roofline(info, prof, n, prec):
+def roofline(info, prof, n, prec, workload, precision):
     """Dominant apply kernel by device time; its achieved rate against the bound that
     gives the larger fraction of peak."""
     apply_stages = ["kshift_left", "kshift_right", "density", "fft_x_fwd", "fft_y_fwd",
-                    "fft_z_poisson", "fft_y_inv", "fft_x_inv", "vint", "sandwich_left",
+                    "fft_z_poisson", "fft_y_inv", "fft_x_inv", "vint", "vint_reduce", "sandwich_left",
                     "sandwich_right"]
-    best = max(apply_stages, key=lambda k: prof[k][0])
+    best = max((k for k in apply_stages if k in prof), key=lambda k: prof[k][0])
     ms, cnt = prof[best]
     avg_s = ms / max(cnt, 1) / 1e3
     nbytes, flops = kernel_work(info, best, n, prec)
@@ -92,8 +101,49 @@ def roofline(info, prof, n, prec):
              "frac": round(gbs / HBM_PEAK_GBS, 4)}
     r.update({"kernel": best, "avg_launch_us": round(avg_s * 1e6, 2),
               "bytes_per_launch": int(nbytes), "flops_per_launch": float(flops),
-              "traffic": None})
+              "traffic": measured_traffic(best, workload, precision)})
     return r
+
+
+KERNEL_SYMBOL = {"vint": "k_vint", "density": "k_density", "vint_reduce": "k_vint_reduce"}
+KERNEL_SOURCE = os.path.join(os.path.dirname(os.path.abspath(__file__)),
+                             "paper_1507_08157_amd", "csrc", "grid.hip")
+TRAFFIC_FILE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "profiles",
+                            "hbm_traffic_{workload}_{precision}.txt")
+
+
+def kernel_source_hash(symbol, path=KERNEL_SOURCE):
+    """sha256 of a kernel's source text: from its template line to the closing brace."""
+    try:
+        lines = open(path).read().split("\n")
+    except OSError:
+        return None
+    for i, ln in enumerate(lines):
+        if f"void {symbol}(" in ln:
+            j = i
+            while j > 0 and not lines[j].startswith("template"):
+                j -= 1
+            k = i
+            while k < len(lines) and lines[k] != "}":
+                k += 1
+            return hashlib.sha256("\n".join(lines[j:k + 1]).encode()).hexdigest()
+    return None
+
+
+def measured_traffic(stage, workload, precision):
+    """HBM bytes per launch from the committed rocprofv3 counter summary, or None when the
+    kernel's source has changed since the counters were taken."""
+    sym = KERNEL_SYMBOL.get(stage)
+    path = TRAFFIC_FILE.format(workload=workload, precision=precision)
+    if sym is None or not os.path.exists(path):
+        return None
+    for ln in open(path):
+        f = ln.split()
+        if len(f) >= 6 and f[0] == "kernel" and f[1] == sym:
+            kv = dict(zip(f[2::2], f[3::2]))
+            if kv.get("source_sha256") == kernel_source_hash(sym):
+                return int(kv["traffic_bytes"])
+    return None
 
 
 def time_to_omega(stats, ref, tol=1e-5):
@@ -107,7 +157,9 @@ def time_to_omega(stats, ref, tol=1e-5):
 
 
 def cpu_baseline(sysm):
-    """FP64 oracle applied to one state of the workload, on the host cores (one thread)."""
+    """FP64 oracle applied to one state of the workload on the host (operator set-up not
+    timed).  The oracle's grid steps are Python loops over atom pairs, so BLAS is held to
+    one thread and the sample runs on one core."""
     try:
         from threadpoolctl import threadpool_limits
     except ImportError:  # pragma: no cover
@@ -126,8 +178,9 @@ def cpu_baseline(sysm):
             ctx.__exit__(None, None, None)
     return {"value": round(1.0 / dt, 5), "unit": "state-applies/s", "cores": 1,
             "kind": "oracle",
-            "sample": f"one state of the {sysm.cfg.name} workload ({dt:.1f} s; host has "
-                      f"{os.cpu_count()} logical CPUs, BLAS limited to 1 thread)"}
+            "sample": f"one state-apply (A-B)p, (A+B)q of the {sysm.cfg.name} workload, "
+                      f"operator set-up excluded ({dt:.1f} s; host has {os.cpu_count()} "
+                      f"logical CPUs, BLAS limited to 1 thread)"}
 
 
 def main():
@@ -139,6 +192,7 @@ def main():
     ap.add_argument("--precision", default="fp32", choices=["fp64", "fp32", "bf16"])
     ap.add_argument("--no-solve", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MiB")
     a = ap.parse_args()
     if a.gpus != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path (the sharding "
@@ -165,6 +219,13 @@ def main():
     Pq = torch.from_numpy(sabi.dense_to_p(sysm, X[1])).cuda()
     fp = torch.empty_like(Pp)
     fq = torch.empty_like(Pq)
+    if a.copy_calibration > 0:
+        src = torch.ones(a.copy_calibration << 18, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        torch.neg(src, out=dst)
+        torch.cuda.synchronize()
+        log(f"copy calibration: negation kernel reads and writes {src.numel() * 4} bytes once")
+        del src, dst
     for _ in range(a.warmup):
         h.tddft_apply(Pp, Pq, fp, fq)
     torch.cuda.synchronize()
@@ -181,7 +242,7 @@ def main():
     log(f"{a.steps} applies x {n} states in {dt * 1e3:.1f} ms -> {value:.1f} state-applies/s")
     log("stages (ms per launch): " + ", ".join(
         f"{k}={v[0] / max(v[1], 1):.3f}" for k, v in prof.items() if v[1]))
-    roof = roofline(info, prof, n, prec)
+    roof = roofline(info, prof, n, prec, a.workload, a.precision)
 
     out = {
         "metric": "(A±B)P1 applies/sec + time to omega within 1e-5 Ha, learned/mixed "

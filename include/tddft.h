@@ -157,6 +157,7 @@ typedef struct {
   int64_t pairs_project_t;   /* ... of its adjoint                                       */
   int64_t pairs_covariant;   /* ... of S^u X S^o                                        */
   int64_t pairs_sandwich;    /* ... of K^c V K^v                                        */
+  int64_t brick_slots;       /* (u-atom, o-atom) partial-sum slots over all bricks        */
   double  setup_ms;
 } tddft_info;
 

@@ -66,7 +66,7 @@ class tddft_info(C.Structure):
                 ("pairs_kshift", C.c_int64), ("pairs_project", C.c_int64),
                 ("pairs_project_t", C.c_int64),
                 ("pairs_covariant", C.c_int64), ("pairs_sandwich", C.c_int64),
-                ("setup_ms", C.c_double)]
+                ("brick_slots", C.c_int64), ("setup_ms", C.c_double)]
 
 
 class tddft_stats(C.Structure):

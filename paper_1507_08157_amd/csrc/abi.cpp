@@ -118,6 +118,7 @@ int tddft_get_info(const tddft_handle *hd, tddft_info *o) {
   o->pairs_project_t = h.pPt1.npairs + h.pPt2.npairs;
   o->pairs_covariant = h.pCov1.npairs + h.pCov2.npairs;
   o->pairs_sandwich = h.pSw1.npairs + h.pSw2.npairs;
+  o->brick_slots = h.bricks.nslots_total;
   o->setup_ms = h.setup_ms;
   return TDDFT_OK;
 }

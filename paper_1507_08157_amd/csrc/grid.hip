@@ -278,7 +278,7 @@ void density(const DevTiles &tl, int stype, int BL, int BR, const T *X, int ldx,
 template <class T>
 void potential_integrals(const DevTiles &tl, const DevBricks &br, int stype, int BL, int BR,
                          const T *V, int64_t pair_stride, int ns, T *partial, T *Vout, int ldv,
-                         int64_t nblk_out, double scale, hipStream_t s) {
+                         int64_t nblk_out, double scale, hipStream_t s, Prof *prof) {
   if (br.nb == 0 || ns == 0) return;
   const int E = BL * BR;
   const size_t acc_len = ((size_t)br.max_slots * ns * E + 1) & ~(size_t)1;
@@ -287,13 +287,17 @@ void potential_integrals(const DevTiles &tl, const DevBricks &br, int stype, int
   while (waves > 1 && acc_len * sizeof(T) + waves * per_wave > tl.lds_limit) --waves;
   const size_t lds = acc_len * sizeof(T) + (size_t)waves * per_wave;
   if (lds > tl.lds_limit) throw Error{TDDFT_E_INVALID, "potential-integral accumulator exceeds the LDS budget"};
+  if (prof) prof->begin(ST_VINT, s);
   TD_SAMPLE(T, stype, TD_GRID_BDIM(BL, BR, hipLaunchKernelGGL((k_vint<T, S, BL, BR>), dim3(br.nb), dim3(64 * waves), lds, s, tl, br, V, pair_stride, ns, partial, (T)scale)));
   TD_HIP(hipGetLastError());
+  if (prof) prof->end(ST_VINT, s);
   const int64_t n = nblk_out * ns * E;
   if (n == 0) return;
+  if (prof) prof->begin(ST_VINT_REDUCE, s);
   hipLaunchKernelGGL((k_vint_reduce<T>), dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, nblk_out, ns, E,
                      br.cptr, br.cslot, partial, Vout, ldv);
   TD_HIP(hipGetLastError());
+  if (prof) prof->end(ST_VINT_REDUCE, s);
 }
 
 template <class T>
@@ -310,10 +314,10 @@ template void density<float>(const DevTiles &, int, int, int, const float *, int
                              float *, int64_t, double, hipStream_t);
 template void potential_integrals<double>(const DevTiles &, const DevBricks &, int, int, int,
                                           const double *, int64_t, int, double *, double *, int,
-                                          int64_t, double, hipStream_t);
+                                          int64_t, double, hipStream_t, Prof *);
 template void potential_integrals<float>(const DevTiles &, const DevBricks &, int, int, int,
                                          const float *, int64_t, int, float *, float *, int,
-                                         int64_t, double, hipStream_t);
+                                         int64_t, double, hipStream_t, Prof *);
 template void alda_kernel<double>(int64_t, const double *, double, double *, hipStream_t);
 template void alda_kernel<float>(int64_t, const float *, double, float *, hipStream_t);
 

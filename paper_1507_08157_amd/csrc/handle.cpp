@@ -663,14 +663,12 @@ void apply_sets(Handle &h, int n, const T *X, int ldx, int xp0, int xq0, T *F, i
   h.prof.end(ST_DENSITY, s);
   hartree_xc<T>(h.geom, h.fft, npair, fields, work, h.fxc<T>(), h.opts.xc == TDDFT_XC_ALDA_X, s, &h.prof);
   // states in chunks whose brick accumulators fit in LDS (chunk starts are even)
-  h.prof.begin(ST_VINT, s);
   for (int s0 = 0; s0 < n; s0 += chunk) {
     const int ns = std::min(chunk, n - s0);
     // Vout columns s0.. of a set with n columns: offset the pointer by s0 * E
     potential_integrals<T>(tl, h.bricks, st, h.BU, h.BO, fields + (int64_t)(s0 / 2) * pstride, pstride,
-                           ns, part, Vset + (size_t)s0 * h.E, n, h.nO, h.dV, s);
+                           ns, part, Vset + (size_t)s0 * h.E, n, h.nO, h.dV, s, &h.prof);
   }
-  h.prof.end(ST_VINT, s);
   h.prof.begin(ST_SANDWICH_LEFT, s);
   spmm_left<T>(h.pSw1, h.BU, h.BO, h.Kc.ptr<T>(), Vset, n, 0, Y, n, 0, n, 1.0, false, s);
   h.prof.end(ST_SANDWICH_LEFT, s);

@@ -145,7 +145,7 @@ struct FFTPlan {
 // optional per-stage device timing with events on the launching stream
 enum Stage {
   ST_KSHIFT_LEFT = 0, ST_KSHIFT_RIGHT, ST_DENSITY, ST_FFT_X_FWD, ST_FFT_Y_FWD, ST_FFT_Z_POISSON,
-  ST_FFT_Y_INV, ST_FFT_X_INV, ST_VINT_ZERO, ST_VINT, ST_SANDWICH_LEFT, ST_SANDWICH_RIGHT,
+  ST_FFT_Y_INV, ST_FFT_X_INV, ST_VINT, ST_VINT_REDUCE, ST_SANDWICH_LEFT, ST_SANDWICH_RIGHT,
   ST_PROJECT, ST_COVARIANT, ST_GRAM, ST_LINCOMB, ST_PROJECT_T, ST_GATHER, ST_COUNT
 };
 extern const char *const kStageNames[ST_COUNT];

@@ -81,7 +81,7 @@ void density(const DevTiles &tl, int stype, int BL, int BR, const T *X, int ldx,
 template <class T>
 void potential_integrals(const DevTiles &tl, const DevBricks &br, int stype, int BL, int BR,
                          const T *V, int64_t pair_stride, int ns, T *partial, T *Vout, int ldv,
-                         int64_t nblk_out, double scale, hipStream_t s);
+                         int64_t nblk_out, double scale, hipStream_t s, Prof *prof);
 
 // f_xc from rho0 (real parts of a tile-major pair array): ALDA exchange kernel
 template <class T>

@@ -227,7 +227,7 @@ namespace tddft {
 
 const char *const kStageNames[ST_COUNT] = {
     "kshift_left", "kshift_right", "density", "fft_x_fwd", "fft_y_fwd", "fft_z_poisson",
-    "fft_y_inv", "fft_x_inv", "vint_zero", "vint", "sandwich_left", "sandwich_right",
+    "fft_y_inv", "fft_x_inv", "vint", "vint_reduce", "sandwich_left", "sandwich_right",
     "project", "covariant", "gram", "lincomb", "project_t", "gather"};
 
 void Prof::init() {
