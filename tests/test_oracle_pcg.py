@@ -109,3 +109,53 @@ def test_line_search_minimises_trace_functional(dense):
     grid = np.linspace(0, 3, 30001)
     vals = [sol.phi(x, Nc, Bc) for x in grid]
     assert abs(sol.phi(lam, Nc, Bc) - min(vals)) < 1e-9
+
+
+def _aux_range(s, cs):
+    """Matrix of the map L (entries on M) -> KS-basis coefficients of K^c S^u L S^o K^v:
+    x = a^T S^u L S^o b for the kernel states a (u-set) and b (o-set)."""
+    Mf = np.kron(s.M, np.ones((s.cfg.n_u, s.cfg.n_o))).astype(bool)
+    ii, jj = np.nonzero(Mf)
+    left = cs.a.T @ s.S_u
+    right = s.S_o @ cs.b
+    return (left[:, ii][:, None, :] * right[jj, :].T[None, :, :]).reshape(-1, len(ii))
+
+
+def test_truncated_auxiliary_of_full_rank_reaches_brute_force(small_odd):
+    """M truncated (the L-space branch of the solver), but the truncated auxiliary matrices
+    still reach every KS pair, so the minimum is the Casida spectrum itself."""
+    s = small_odd
+    op = Operator(s)
+    cs = Casida(s)
+    assert not np.all(op.mask_L == 1)
+    sv = np.linalg.svd(_aux_range(s, cs), compute_uv=False)
+    assert sv[-1] > 1e-3 * sv[0] and len(sv) == len(cs.D)
+    n = s.cfg.n_states
+    solver = Solver(op, Options(n_states=n, tol_omega=1e-10, max_iter=300))
+    assert not solver.complete
+    r = solver.solve(s.guess())
+    assert r.converged
+    assert np.max(np.abs(r.omega - cs.omega_hermitian()[:n])) < 1e-8
+
+
+def test_truncated_iterates_are_variational(small_trunc):
+    """With a rank-deficient auxiliary space every iterate's Tsiper sum lies above the
+    minimum over that subspace (brute force: the Casida pencil restricted to the range of
+    L -> K^c S^u L S^o K^v), which lies above the untruncated minimum; the line search
+    lowers the sum at every step."""
+    s = small_trunc
+    op = Operator(s)
+    cs = Casida(s)
+    n = s.cfg.n_states
+    U, sv, _ = np.linalg.svd(_aux_range(s, cs), full_matrices=False)
+    U = U[:, sv > 0]
+    assert U.shape[1] < len(cs.D)
+    am = U.T @ (cs.A - cs.B) @ U
+    ap = U.T @ (cs.A + cs.B) @ U
+    w_sub = np.sort(np.sqrt(np.linalg.eigvals(am @ ap).real))[:n]
+    w_all = cs.omega_hermitian()[:n]
+    assert np.sum(w_sub) > np.sum(w_all)
+    r = Solver(op, Options(n_states=n, max_iter=8)).solve(s.guess())
+    sums = np.array([np.sum(h) for h in r.history])
+    assert np.all(sums >= np.sum(w_sub) - 1e-10)
+    assert np.all(np.diff(sums) <= 1e-12 * np.abs(sums[:-1]))
