@@ -59,7 +59,7 @@ def test_response_pattern_matches_independent_constructions(name, request):
     assert np.array_equal(lib, response_pattern(s))
 
 
-@pytest.mark.parametrize("n", [1, 2, 5, 8, 13])
+@pytest.mark.parametrize("n", [1, 2, 5, 8, 13, 32])
 def test_apply_fp64_state_counts(small_trunc, n):
     fp, fq, fp_ref, fq_ref, _, _ = _run(small_trunc, 0, "fp64", n, seed=n)
     assert rel_err(fp, fp_ref) < TOL_FP64
@@ -85,3 +85,17 @@ def test_apply_tiny_power_of_two_grid():
     s = cached_system("tiny")
     fp, fq, fp_ref, fq_ref, _, _ = _run(s, 0, "fp64", 3, seed=7)
     assert rel_err(fq, fq_ref) < TOL_FP64
+
+
+@pytest.mark.parametrize("n", [0, 33])
+def test_apply_rejects_state_count_outside_range(small_dense, n):
+    """0 states (empty input) and more than the maximum of 32 are refused on the host."""
+    import torch
+    from paper_1507_08157_amd import binding
+    s = small_dense
+    h = gpu_handle(s, precision="fp64")
+    P = torch.zeros((n, h.nnz_p), dtype=torch.float64, device="cuda")
+    with pytest.raises(binding.TddftError) as e:
+        h.tddft_apply(P, P.clone())
+    h.close()
+    assert e.value.code == binding.TDDFT_E_INVALID
