@@ -61,10 +61,11 @@ def kernel_work(info, stage, n, prec):
         # samples read once, P on M read once, rho written once; 2 flops per pair-point FMA
         return samples + info["blocks_r"] * E * n * t_bytes + field, 2.0 * pp * n
     if stage == "vint":
-        return samples + field + info["blocks_o"] * E * n * t_bytes, 2.0 * pp * n + 64.0 * nt * n
+        # samples and V read once, per-tile partial sums written once
+        return samples + field + info["partial_pairs"] * n * t_bytes, 2.0 * pp * n + 64.0 * nt * n
     if stage == "vint_reduce":
-        slots = info["brick_slots"] * E * n * t_bytes
-        return slots + info["blocks_o"] * E * n * t_bytes, float(info["brick_slots"] * E * n)
+        part = info["partial_pairs"] * n * t_bytes
+        return part + info["blocks_o"] * E * n * t_bytes, float(info["partial_pairs"] * n)
     if stage in ("fft_x_fwd", "fft_y_fwd", "fft_y_inv"):
         return 2 * grid, 0.0
     if stage == "fft_z_poisson":

@@ -143,7 +143,7 @@ typedef struct {
   int32_t n[3];              /* grid                                                    */
   int32_t tiles;             /* 4x4x4 grid tiles                                        */
   int32_t block_rows, block_cols;   /* padded block shape of response kernels (BU x BO)  */
-  int32_t brick_edge;        /* tiles per brick edge in the potential-integral kernel   */
+  int32_t max_rows_o;        /* most o-set sample rows touching one tile                 */
   int32_t precision;
   int64_t sample_rows_u;     /* tile sample rows (64 points each) of the u-set          */
   int64_t sample_rows_o;     /* ... of the o-set                                        */
@@ -157,7 +157,7 @@ typedef struct {
   int64_t pairs_project_t;   /* ... of its adjoint                                       */
   int64_t pairs_covariant;   /* ... of S^u X S^o                                        */
   int64_t pairs_sandwich;    /* ... of K^c V K^v                                        */
-  int64_t brick_slots;       /* (u-atom, o-atom) partial-sum slots over all bricks        */
+  int64_t partial_pairs;     /* function pairs with per-tile partial integral sums       */
   double  setup_ms;
 } tddft_info;
 

@@ -58,7 +58,7 @@ class tddft_options(C.Structure):
 
 class tddft_info(C.Structure):
     _fields_ = [("n", C.c_int32 * 3), ("tiles", C.c_int32), ("block_rows", C.c_int32),
-                ("block_cols", C.c_int32), ("brick_edge", C.c_int32), ("precision", C.c_int32),
+                ("block_cols", C.c_int32), ("max_rows_o", C.c_int32), ("precision", C.c_int32),
                 ("sample_rows_u", C.c_int64), ("sample_rows_o", C.c_int64),
                 ("pair_points", C.c_int64), ("blocks_m", C.c_int64), ("blocks_r", C.c_int64),
                 ("blocks_o", C.c_int64),
@@ -66,7 +66,7 @@ class tddft_info(C.Structure):
                 ("pairs_kshift", C.c_int64), ("pairs_project", C.c_int64),
                 ("pairs_project_t", C.c_int64),
                 ("pairs_covariant", C.c_int64), ("pairs_sandwich", C.c_int64),
-                ("brick_slots", C.c_int64), ("setup_ms", C.c_double)]
+                ("partial_pairs", C.c_int64), ("setup_ms", C.c_double)]
 
 
 class tddft_stats(C.Structure):

@@ -102,7 +102,7 @@ int tddft_get_info(const tddft_handle *hd, tddft_info *o) {
   o->tiles = h.nt;
   o->block_rows = h.BU;
   o->block_cols = h.BO;
-  o->brick_edge = h.brick_edge;
+  o->max_rows_o = h.maxrows_o;
   o->precision = h.precision;
   o->sample_rows_u = h.sample_rows_u;
   o->sample_rows_o = h.sample_rows_o;
@@ -118,7 +118,7 @@ int tddft_get_info(const tddft_handle *hd, tddft_info *o) {
   o->pairs_project_t = h.pPt1.npairs + h.pPt2.npairs;
   o->pairs_covariant = h.pCov1.npairs + h.pCov2.npairs;
   o->pairs_sandwich = h.pSw1.npairs + h.pSw2.npairs;
-  o->brick_slots = h.bricks.nslots_total;
+  o->partial_pairs = h.partials.total;
   o->setup_ms = h.setup_ms;
   return TDDFT_OK;
 }

@@ -1,16 +1,16 @@
 // Real-space grid kernels on 4x4x4 point tiles.
 //
 // Samples of both function sets are stored tile-major: for every tile, the rows (one per
-// function of every atom touching the tile, 64 values each) are contiguous, so each wave
-// streams a tile's samples with fully coalesced loads and keeps them in LDS.
+// function of every atom touching the tile, 64 values each) are contiguous, so a tile's
+// samples are read with fully coalesced vector loads, or, when every lane needs the same
+// row, with scalar loads into SGPRs.
 //
 //  * response density (Sec. III.A):   rho_s(r) = sum_ab u_a(r) P_s,ab o_b(r)
 //    per tile: psi_a = sum_b P_ab o_b, then rho = sum_a u_a psi_a, P blocks read with
 //    wave-uniform (scalar) loads; also used once for rho0 = 2 sum o K^v o.
 //  * potential integrals (Sec. II.C, V_SCF^{chi phi}):  V_s,ab = h^3 sum_r u_a V_s o_b
-//    per tile the (u-atom, o-atom) block products are reduced over the 64 points in
-//    registers, summed over a brick of tiles in LDS, written per brick to a partial-sum
-//    buffer and reduced per block in a fixed order (no global atomics, deterministic).
+//    per tile, one lane per (o-row, state) reduces over the 64 points in registers; the
+//    per-tile sums are added per overlap block in a fixed order (no atomics, reproducible).
 //  * ALDA exchange kernel f_xc = -(1/3)(3/pi)^{1/3} rho0^{-2/3} (Sec. II.A, xc part).
 // Grid fields are tile-major complex pairs: state 2k in the real part, 2k+1 in the
 // imaginary part of field k, so the Hartree FFT transforms two states at once.
@@ -36,24 +36,69 @@ __device__ __forceinline__ double cvt<double, __hip_bfloat16>(__hip_bfloat16 v) 
   return (double)__bfloat162float(v);
 }
 
+// two consecutive samples (q even, p 4-byte aligned); BF16 pairs come in one 32-bit word so
+// that wave-uniform rows are fetched with scalar loads and widened with integer shifts
+template <class T, class S>
+__device__ __forceinline__ void load2(const S *p, int q, T &a, T &b) {
+  a = (T)p[q];
+  b = (T)p[q + 1];
+}
+template <class T>
+__device__ __forceinline__ void load2_bf16(const __hip_bfloat16 *p, int q, T &a, T &b) {
+  const uint32_t w = reinterpret_cast<const uint32_t *>(p)[q >> 1];
+  a = (T)__uint_as_float(w << 16);
+  b = (T)__uint_as_float(w & 0xffff0000u);
+}
+template <>
+__device__ __forceinline__ void load2<float, __hip_bfloat16>(const __hip_bfloat16 *p, int q, float &a, float &b) {
+  load2_bf16<float>(p, q, a, b);
+}
+template <>
+__device__ __forceinline__ void load2<double, __hip_bfloat16>(const __hip_bfloat16 *p, int q, double &a, double &b) {
+  load2_bf16<double>(p, q, a, b);
+}
+
 // ---------------------------------------------------------------------------------------
-// One wave per tile.  The tile's sample rows are staged in LDS once; for each chunk of NSP
-// states the P blocks of every (u-atom, o-atom) pair of the tile are staged too (coalesced
-// loads, zero for pairs outside R and states beyond ns), so the FMA loop is branch-free and
-// reads P with broadcast LDS loads.
-template <class T, class S, int BL, int BR>
-__global__ __launch_bounds__(256) void k_density(DevTiles tl, const T *__restrict__ X, int ldx,
-                                                 int xc0, int ns, T *__restrict__ out,
-                                                 int64_t pair_stride, T scale) {
-  extern __shared__ unsigned char lds_raw[];
+// Response density.  One wave per tile, one lane per grid point.  The tile's right-set rows
+// are staged in LDS as [atom][point][BR] (one wide LDS read per atom); for every left atom
+// i the partial sums psi_s,r = sum_j P_s[(i,r),(j,.)] . o_j are built from wave-uniform P
+// blocks (all NS states of a block are contiguous, so they arrive in SGPRs through a few
+// scalar loads and feed the FMAs as scalar operands), then rho_s += u_(i,r) psi_s,r.
+template <class T, int NS, int BL, int BR, bool FULL>
+__device__ __forceinline__ void density_pairs(const int32_t *__restrict__ pid, int noa,
+                                              const T *__restrict__ X, int64_t xoff, int ldx,
+                                              int nk, const T *lo, int lane, T (&tmp)[NS][BL]) {
   constexpr int E = BL * BR;
-  constexpr int NSP = 4;
+  for (int j = 0; j < noa; ++j) {
+    const int pb = pid[j];
+    if (pb < 0) continue;
+    T o[BR];
+#pragma unroll
+    for (int c = 0; c < BR; ++c) o[c] = lo[(j * TP + lane) * BR + c];
+    const T *Pj = X + ((int64_t)pb * ldx) * E + xoff;
+#pragma unroll
+    for (int k = 0; k < NS; ++k) {
+      if (!FULL && k >= nk) break;
+#pragma unroll
+      for (int r = 0; r < BL; ++r)
+#pragma unroll
+        for (int c = 0; c < BR; ++c) tmp[k][r] += Pj[k * E + r * BR + c] * o[c];
+    }
+  }
+}
+
+template <class T, class S, int BL, int BR>
+__global__ __launch_bounds__(256) void k_density(DevTiles tl, const S *__restrict__ usamp,
+                                                 const S *__restrict__ osamp,
+                                                 const int32_t *__restrict__ pidx,
+                                                 const T *__restrict__ X, int ldx, int xc0, int ns,
+                                                 T *__restrict__ out, int64_t pair_stride, T scale) {
+  extern __shared__ unsigned char lds_raw[];
+  constexpr int NS = sizeof(T) == 8 ? 4 : 8;   // states per pass (P of a block fits in SGPRs)
   const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  const int p = threadIdx.x & 63;
+  const int lane = threadIdx.x & 63;
   const int t = blockIdx.x * (blockDim.x >> 6) + w;
-  const size_t per_wave = (size_t)tl.maxrows * TP + (size_t)tl.maxpairs * NSP * E;
-  T *lu = reinterpret_cast<T *>(lds_raw) + (size_t)w * per_wave;
-  T *lp = lu + (size_t)tl.maxrows * TP;
+  T *lo = reinterpret_cast<T *>(lds_raw) + (size_t)w * tl.maxrows_r * TP;
   int nua = 0, noa = 0, u0 = 0, o0 = 0;
   if (t < tl.nt) {
     u0 = tl.uptr[t];
@@ -61,176 +106,180 @@ __global__ __launch_bounds__(256) void k_density(DevTiles tl, const T *__restric
     o0 = tl.optr[t];
     noa = tl.optr[t + 1] - o0;
   }
-  T *lo = lu + (size_t)nua * BL * TP;
   {
-    const S *us = reinterpret_cast<const S *>(tl.usamp) + (int64_t)u0 * BL * TP;
-    const S *os = reinterpret_cast<const S *>(tl.osamp) + (int64_t)o0 * BR * TP;
-    for (int r = 0; r < nua * BL; ++r) lu[r * TP + p] = cvt<T>(us[r * TP + p]);
-    for (int r = 0; r < noa * BR; ++r) lo[r * TP + p] = cvt<T>(os[r * TP + p]);
+    const S *os = osamp + (int64_t)o0 * BR * TP;
+    for (int j = 0; j < noa; ++j)
+#pragma unroll
+      for (int c = 0; c < BR; ++c) lo[(j * TP + lane) * BR + c] = cvt<T>(os[(j * BR + c) * TP + lane]);
   }
-  const int npair = nua * noa;
-  const int32_t *pid = tl.pidx + (t < tl.nt ? tl.pptr[t] : 0);
+  __syncthreads();
+  if (t >= tl.nt) return;
   using T2 = typename Vec2<T>::type;
-  for (int s0 = 0; s0 < ns; s0 += NSP) {
-    __syncthreads();
-    for (int idx = p; idx < npair * NSP * E; idx += 64) {
-      const int pr = idx / (NSP * E);
-      const int rem = idx - pr * (NSP * E);
-      const int sk = rem / E;
-      const int pb = pid[pr];
-      T v = T(0);
-      if (pb >= 0 && s0 + sk < ns) v = X[((int64_t)pb * ldx + xc0 + s0) * E + rem];
-      lp[idx] = v;
-    }
-    __syncthreads();
-    if (t >= tl.nt) continue;
-    T acc[NSP];
+  const int32_t *pid = pidx + tl.pptr[t];
+  for (int s0 = 0; s0 < ns; s0 += NS) {
+    const int nk = min(NS, ns - s0);
+    T acc[NS];
 #pragma unroll
-    for (int k = 0; k < NSP; ++k) acc[k] = T(0);
+    for (int k = 0; k < NS; ++k) acc[k] = T(0);
     for (int i = 0; i < nua; ++i) {
-      T tmp[NSP][BL];
+      T tmp[NS][BL];
 #pragma unroll
-      for (int k = 0; k < NSP; ++k)
+      for (int k = 0; k < NS; ++k)
 #pragma unroll
         for (int r = 0; r < BL; ++r) tmp[k][r] = T(0);
-      const T *Pi = lp + (size_t)i * noa * NSP * E;
-      for (int j = 0; j < noa; ++j) {
-        T o[BR];
-#pragma unroll
-        for (int c = 0; c < BR; ++c) o[c] = lo[(j * BR + c) * TP + p];
-        const T *Pj = Pi + (size_t)j * NSP * E;
-#pragma unroll
-        for (int k = 0; k < NSP; ++k)
-#pragma unroll
-          for (int r = 0; r < BL; ++r)
-#pragma unroll
-            for (int c = 0; c < BR; ++c) tmp[k][r] += Pj[k * E + r * BR + c] * o[c];
-      }
+      const int64_t xoff = (int64_t)(xc0 + s0) * BL * BR;
+      if (nk == NS)
+        density_pairs<T, NS, BL, BR, true>(pid + i * noa, noa, X, xoff, ldx, nk, lo, lane, tmp);
+      else
+        density_pairs<T, NS, BL, BR, false>(pid + i * noa, noa, X, xoff, ldx, nk, lo, lane, tmp);
+      const S *us = usamp + ((int64_t)(u0 + i) * BL) * TP + lane;
 #pragma unroll
       for (int r = 0; r < BL; ++r) {
-        const T u = lu[(i * BL + r) * TP + p];
+        const T u = cvt<T>(us[r * TP]);
 #pragma unroll
-        for (int k = 0; k < NSP; ++k) acc[k] += u * tmp[k][r];
+        for (int k = 0; k < NS; ++k) acc[k] += u * tmp[k][r];
       }
     }
-    const int nk = min(NSP, ns - s0);
-    T2 v0, v1;
-    v0.x = scale * acc[0];
-    v0.y = nk > 1 ? scale * acc[1] : T(0);
-    *reinterpret_cast<T2 *>(out + (int64_t)(s0 / 2) * pair_stride + ((int64_t)t * TP + p) * 2) = v0;
-    if (nk > 2) {
-      v1.x = scale * acc[2];
-      v1.y = nk > 3 ? scale * acc[3] : T(0);
-      *reinterpret_cast<T2 *>(out + (int64_t)(s0 / 2 + 1) * pair_stride + ((int64_t)t * TP + p) * 2) = v1;
+    T *dst = out + (int64_t)(s0 / 2) * pair_stride + ((int64_t)t * TP + lane) * 2;
+#pragma unroll
+    for (int m = 0; m < NS / 2; ++m) {
+      if (2 * m < nk) {
+        T2 v;
+        v.x = scale * acc[2 * m];
+        v.y = 2 * m + 1 < nk ? scale * acc[2 * m + 1] : T(0);
+        *reinterpret_cast<T2 *>(dst + (int64_t)m * pair_stride) = v;
+      }
     }
   }
 }
 
 // ---------------------------------------------------------------------------------------
-// One workgroup per brick of tiles.  Per tile the (u-atom, o-atom) block integrals are
-// reduced over the 64 points in registers (one pair per lane) and added into the brick's
-// LDS accumulator; the accumulator is then written, without atomics, to the brick's slots
-// of a partial-sum buffer that k_vint_reduce sums per overlap block in a fixed order.
+// Potential integrals.  One wave per tile, one lane per (o-row b of the tile, state s),
+// looping over 64-item chunks when the tile has more.  The lane forms w(r) = V_s(r) o_b(r)
+// for the tile's 64 points in registers (wide loads of the o-row and of the complex-pair
+// field), then for every u-row a of the tile sums u_a(r) w(r); u_a's row is wave-uniform and
+// arrives in SGPRs through scalar loads, so the inner loop is FMAs with one scalar and one
+// vector operand.  Each tile writes its sums, coalesced, to its own range of a partial-sum
+// buffer [function pair][state]; k_vint_reduce adds them per overlap block in a fixed
+// order (no atomics, reproducible).
+template <class T, class S>
+__device__ __forceinline__ void load4(const S *p, T (&o)[4]) {
+  o[0] = cvt<T>(p[0]); o[1] = cvt<T>(p[1]); o[2] = cvt<T>(p[2]); o[3] = cvt<T>(p[3]);
+}
+template <>
+__device__ __forceinline__ void load4<float, float>(const float *p, float (&o)[4]) {
+  const float4 v = *reinterpret_cast<const float4 *>(p);
+  o[0] = v.x; o[1] = v.y; o[2] = v.z; o[3] = v.w;
+}
+template <>
+__device__ __forceinline__ void load4<double, double>(const double *p, double (&o)[4]) {
+  const double2 a = reinterpret_cast<const double2 *>(p)[0];
+  const double2 b = reinterpret_cast<const double2 *>(p)[1];
+  o[0] = a.x; o[1] = a.y; o[2] = b.x; o[3] = b.y;
+}
+template <>
+__device__ __forceinline__ void load4<float, __hip_bfloat16>(const __hip_bfloat16 *p, float (&o)[4]) {
+  const uint2 v = *reinterpret_cast<const uint2 *>(p);
+  o[0] = __uint_as_float(v.x << 16); o[1] = __uint_as_float(v.x & 0xffff0000u);
+  o[2] = __uint_as_float(v.y << 16); o[3] = __uint_as_float(v.y & 0xffff0000u);
+}
+// component c (0 real, 1 imaginary) of two consecutive complex values (p 4-element aligned)
+template <class T>
+__device__ __forceinline__ void load_comp2(const T *p, int c, T &a, T &b) {
+  using T2 = typename Vec2<T>::type;
+  const T2 x = reinterpret_cast<const T2 *>(p)[0];
+  const T2 y = reinterpret_cast<const T2 *>(p)[1];
+  a = c ? x.y : x.x;
+  b = c ? y.y : y.x;
+}
+
 template <class T, class S, int BL, int BR>
-__global__ __launch_bounds__(256) void k_vint(DevTiles tl, DevBricks br, const T *__restrict__ V,
-                                              int64_t pair_stride, int ns,
-                                              T *__restrict__ partial, T scale) {
-  extern __shared__ unsigned char lds_raw[];
-  constexpr int E = BL * BR;
-  constexpr int LD = TP + 1;   // padded rows: lanes reading different rows hit different banks
-  constexpr int SC = 8;        // states per register chunk
-  T *acc = reinterpret_cast<T *>(lds_raw);
-  const size_t acc_len = ((size_t)br.max_slots * ns * E + 1) & ~(size_t)1;
-  T *stage = acc + acc_len;
-  const int b = blockIdx.x;
+__global__ __launch_bounds__(256) void k_vint(DevTiles tl, const int64_t *__restrict__ tbase,
+                                              const S *__restrict__ usamp,
+                                              const S *__restrict__ osamp,
+                                              const T *__restrict__ V, int64_t pair_stride,
+                                              int ns, T *__restrict__ partial, T scale) {
   const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
-  T *my = stage + (size_t)w * ((size_t)br.max_rows * LD + (size_t)ns * TP);
-  const int bno = br.no[b];
-  const int nslots = br.nu[b] * bno;
-  for (int i = threadIdx.x; i < nslots * ns * E; i += blockDim.x) acc[i] = T(0);
-  const int t0 = br.tptr[b];
-  const int ntile = br.tptr[b + 1] - t0;
-  const int nw = blockDim.x >> 6;
-  for (int round = 0; round < ntile; round += nw) {
-    __syncthreads();
-    const int k = round + w;
-    int t = -1, nua = 0, noa = 0, u0 = 0, o0 = 0;
-    if (k < ntile) {
-      t = br.tiles[t0 + k];
-      u0 = tl.uptr[t];
-      nua = tl.uptr[t + 1] - u0;
-      o0 = tl.optr[t];
-      noa = tl.optr[t + 1] - o0;
+  const int t = blockIdx.x * (blockDim.x >> 6) + w;
+  if (t >= tl.nt) return;
+  const int u0 = tl.uptr[t], nua = tl.uptr[t + 1] - u0;
+  const int o0 = tl.optr[t], noa = tl.optr[t + 1] - o0;
+  const int rows_o = noa * BR;
+  const int items = rows_o * ns;
+  T *dst = partial + tbase[t] * ns;
+  const T *vt = V + (int64_t)t * TP * 2;
+  for (int c0 = 0; c0 < items; c0 += 64) {
+    const int item = c0 + lane;
+    const bool active = item < items;
+    const int b = active ? item / ns : 0;
+    const int s = active ? item - (item / ns) * ns : 0;
+    const S *orow = osamp + ((int64_t)o0 * BR + b) * TP;
+    const T *vs = vt + (int64_t)(s >> 1) * pair_stride;
+    T wv[TP];
+#pragma unroll
+    for (int q = 0; q < TP; q += 4) {
+      T o[4], v0, v1, v2, v3;
+      load4<T, S>(orow + q, o);
+      load_comp2<T>(vs + 2 * q, s & 1, v0, v1);
+      load_comp2<T>(vs + 2 * q + 4, s & 1, v2, v3);
+      wv[q] = o[0] * v0;
+      wv[q + 1] = o[1] * v1;
+      wv[q + 2] = o[2] * v2;
+      wv[q + 3] = o[3] * v3;
     }
-    T *lu = my;
-    T *lo = lu + (size_t)nua * BL * LD;
-    T *lv = lo + (size_t)noa * BR * LD;
-    if (t >= 0) {
-      const S *us = reinterpret_cast<const S *>(tl.usamp) + (int64_t)u0 * BL * TP;
-      const S *os = reinterpret_cast<const S *>(tl.osamp) + (int64_t)o0 * BR * TP;
-      for (int r = 0; r < nua * BL; ++r) lu[r * LD + lane] = cvt<T>(us[r * TP + lane]);
-      for (int r = 0; r < noa * BR; ++r) lo[r * LD + lane] = cvt<T>(os[r * TP + lane]);
-      for (int s = 0; s < ns; ++s)
-        lv[s * TP + lane] = V[(int64_t)(s >> 1) * pair_stride + ((int64_t)t * TP + lane) * 2 + (s & 1)];
-    }
-    __syncthreads();
-    if (t >= 0) {
-      for (int item = lane; item < nua * noa; item += 64) {
-        const int i = item / noa, j = item - (item / noa) * noa;
-        const int slot = br.ubl[u0 + i] * bno + br.obl[o0 + j];
-        for (int s0 = 0; s0 < ns; s0 += SC) {
-          const int nk = min(SC, ns - s0);
-          T a[SC][E];
+    for (int i = 0; i < nua; ++i) {
 #pragma unroll
-          for (int q = 0; q < SC; ++q)
+      for (int r = 0; r < BL; ++r) {
+        const S *urow = usamp + ((int64_t)(u0 + i) * BL + r) * TP;
+        T s0 = T(0), s1 = T(0), s2 = T(0), s3 = T(0);
 #pragma unroll
-            for (int e = 0; e < E; ++e) a[q][e] = T(0);
-          for (int pt = 0; pt < TP; ++pt) {
-            T uo[E];
-#pragma unroll
-            for (int r = 0; r < BL; ++r) {
-              const T u = lu[(i * BL + r) * LD + pt];
-#pragma unroll
-              for (int c = 0; c < BR; ++c) uo[r * BR + c] = u * lo[(j * BR + c) * LD + pt];
-            }
-#pragma unroll
-            for (int q = 0; q < SC; ++q) {
-              const T v = (q < nk) ? lv[(s0 + q) * TP + pt] : T(0);
-#pragma unroll
-              for (int e = 0; e < E; ++e) a[q][e] += uo[e] * v;
-            }
-          }
-#pragma unroll
-          for (int q = 0; q < SC; ++q)
-            if (q < nk)
-#pragma unroll
-              for (int e = 0; e < E; ++e) atomicAdd(&acc[((size_t)slot * ns + s0 + q) * E + e], a[q][e]);
+        for (int q = 0; q < TP; q += 4) {
+          T a0, a1, a2, a3;
+          load2<T, S>(urow, q, a0, a1);
+          load2<T, S>(urow, q + 2, a2, a3);
+          s0 += a0 * wv[q];
+          s1 += a1 * wv[q + 1];
+          s2 += a2 * wv[q + 2];
+          s3 += a3 * wv[q + 3];
         }
+        if (active) dst[(int64_t)(i * BL + r) * rows_o * ns + item] = scale * ((s0 + s1) + (s2 + s3));
       }
     }
   }
-  __syncthreads();
-  T *dst = partial + br.sptr[b] * ns * E;
-  for (int idx = threadIdx.x; idx < nslots * ns * E; idx += blockDim.x) dst[idx] = scale * acc[idx];
 }
 
-// Vout[ob][ldv][E] (columns 0..ns) = sum over the (brick, slot) contributions of block ob
+// Vout[ob][ldv][E] (columns 0..ns) = sum over the contributions of block ob.  One wave
+// per overlap block, one lane per (element, state); the contribution offsets are
+// wave-uniform (scalar loads) and four contributions are in flight at a time, summed in a
+// fixed order.
 template <class T>
-__global__ __launch_bounds__(256) void k_vint_reduce(int64_t nblk, int ns, int E,
+__global__ __launch_bounds__(256) void k_vint_reduce(int64_t nblk, int ns, int E, int BR,
                                                      const int64_t *__restrict__ cptr,
-                                                     const int64_t *__restrict__ cslot,
+                                                     const int64_t *__restrict__ cbase,
+                                                     const int32_t *__restrict__ crs,
                                                      const T *__restrict__ partial,
                                                      T *__restrict__ Vout, int ldv) {
-  const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  const int64_t ob = (int64_t)blockIdx.x * (blockDim.x >> 6) + w;
+  if (ob >= nblk) return;
   const int per = ns * E;
-  if (gid >= nblk * per) return;
-  const int64_t ob = gid / per;
-  const int r = (int)(gid - ob * per);
-  T acc = T(0);
-  for (int64_t q = cptr[ob]; q < cptr[ob + 1]; ++q) acc += partial[cslot[q] * per + r];
-  const int s = r / E, e = r - (r / E) * E;
-  Vout[((int64_t)ob * ldv + s) * E + e] = acc;
+  const int64_t q0 = cptr[ob], q1 = cptr[ob + 1];
+  for (int idx = lane; idx < per; idx += 64) {
+    const int e = idx / ns, s = idx - (idx / ns) * ns;
+    const int r = e / BR, c = e - (e / BR) * BR;
+    T a0 = T(0), a1 = T(0), a2 = T(0), a3 = T(0);
+    int64_t q = q0;
+    for (; q + 4 <= q1; q += 4) {
+      a0 += partial[(cbase[q] + (int64_t)r * crs[q] + c) * ns + s];
+      a1 += partial[(cbase[q + 1] + (int64_t)r * crs[q + 1] + c) * ns + s];
+      a2 += partial[(cbase[q + 2] + (int64_t)r * crs[q + 2] + c) * ns + s];
+      a3 += partial[(cbase[q + 3] + (int64_t)r * crs[q + 3] + c) * ns + s];
+    }
+    for (; q < q1; ++q) a0 += partial[(cbase[q] + (int64_t)r * crs[q] + c) * ns + s];
+    Vout[(ob * ldv + s) * E + e] = (a0 + a1) + (a2 + a3);
+  }
 }
 
 // ---------------------------------------------------------------------------------------
@@ -266,36 +315,30 @@ template <class T>
 void density(const DevTiles &tl, int stype, int BL, int BR, const T *X, int ldx, int xc0, int ns,
              T *out, int64_t pair_stride, double scale, hipStream_t s) {
   if (tl.nt == 0 || ns == 0) return;
-  const size_t per_wave = ((size_t)tl.maxrows * TP + (size_t)tl.maxpairs * 4 * BL * BR) * sizeof(T);
+  const size_t per_wave = (size_t)tl.maxrows_r * TP * sizeof(T);
   if (per_wave > tl.lds_limit) throw Error{TDDFT_E_INVALID, "too many functions per grid tile for the LDS budget"};
-  const int waves = (int)std::max<size_t>(1, std::min<size_t>(4, tl.lds_limit / per_wave));
+  const int waves = (int)std::max<size_t>(1, std::min<size_t>(4, tl.lds_limit / std::max<size_t>(per_wave, 1)));
   const size_t lds = (size_t)waves * per_wave;
   const unsigned grid = (unsigned)((tl.nt + waves - 1) / waves);
-  TD_SAMPLE(T, stype, TD_GRID_BDIM(BL, BR, hipLaunchKernelGGL((k_density<T, S, BL, BR>), dim3(grid), dim3(64 * waves), lds, s, tl, X, ldx, xc0, ns, out, pair_stride, (T)scale)));
+  TD_SAMPLE(T, stype, TD_GRID_BDIM(BL, BR, hipLaunchKernelGGL((k_density<T, S, BL, BR>), dim3(grid), dim3(64 * waves), lds, s, tl, reinterpret_cast<const S *>(tl.usamp), reinterpret_cast<const S *>(tl.osamp), tl.pidx, X, ldx, xc0, ns, out, pair_stride, (T)scale)));
   TD_HIP(hipGetLastError());
 }
 
 template <class T>
-void potential_integrals(const DevTiles &tl, const DevBricks &br, int stype, int BL, int BR,
+void potential_integrals(const DevTiles &tl, const DevPartials &pa, int stype, int BL, int BR,
                          const T *V, int64_t pair_stride, int ns, T *partial, T *Vout, int ldv,
                          int64_t nblk_out, double scale, hipStream_t s, Prof *prof) {
-  if (br.nb == 0 || ns == 0) return;
+  if (tl.nt == 0 || ns == 0) return;
   const int E = BL * BR;
-  const size_t acc_len = ((size_t)br.max_slots * ns * E + 1) & ~(size_t)1;
-  const size_t per_wave = ((size_t)br.max_rows * (TP + 1) + (size_t)ns * TP) * sizeof(T);
-  int waves = 4;
-  while (waves > 1 && acc_len * sizeof(T) + waves * per_wave > tl.lds_limit) --waves;
-  const size_t lds = acc_len * sizeof(T) + (size_t)waves * per_wave;
-  if (lds > tl.lds_limit) throw Error{TDDFT_E_INVALID, "potential-integral accumulator exceeds the LDS budget"};
   if (prof) prof->begin(ST_VINT, s);
-  TD_SAMPLE(T, stype, TD_GRID_BDIM(BL, BR, hipLaunchKernelGGL((k_vint<T, S, BL, BR>), dim3(br.nb), dim3(64 * waves), lds, s, tl, br, V, pair_stride, ns, partial, (T)scale)));
+  const unsigned grid = (unsigned)((tl.nt + 3) / 4);
+  TD_SAMPLE(T, stype, TD_GRID_BDIM(BL, BR, hipLaunchKernelGGL((k_vint<T, S, BL, BR>), dim3(grid), dim3(256), 0, s, tl, pa.tbase, reinterpret_cast<const S *>(tl.usamp), reinterpret_cast<const S *>(tl.osamp), V, pair_stride, ns, partial, (T)scale)));
   TD_HIP(hipGetLastError());
   if (prof) prof->end(ST_VINT, s);
-  const int64_t n = nblk_out * ns * E;
-  if (n == 0) return;
+  if (nblk_out == 0) return;
   if (prof) prof->begin(ST_VINT_REDUCE, s);
-  hipLaunchKernelGGL((k_vint_reduce<T>), dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, nblk_out, ns, E,
-                     br.cptr, br.cslot, partial, Vout, ldv);
+  hipLaunchKernelGGL((k_vint_reduce<T>), dim3((unsigned)((nblk_out + 3) / 4)), dim3(256), 0, s, nblk_out, ns, E, BR,
+                     pa.cptr, pa.cbase, pa.crs, partial, Vout, ldv);
   TD_HIP(hipGetLastError());
   if (prof) prof->end(ST_VINT_REDUCE, s);
 }
@@ -312,10 +355,10 @@ template void density<double>(const DevTiles &, int, int, int, const double *, i
                               double *, int64_t, double, hipStream_t);
 template void density<float>(const DevTiles &, int, int, int, const float *, int, int, int,
                              float *, int64_t, double, hipStream_t);
-template void potential_integrals<double>(const DevTiles &, const DevBricks &, int, int, int,
+template void potential_integrals<double>(const DevTiles &, const DevPartials &, int, int, int,
                                           const double *, int64_t, int, double *, double *, int,
                                           int64_t, double, hipStream_t, Prof *);
-template void potential_integrals<float>(const DevTiles &, const DevBricks &, int, int, int,
+template void potential_integrals<float>(const DevTiles &, const DevPartials &, int, int, int,
                                          const float *, int64_t, int, float *, float *, int,
                                          int64_t, double, hipStream_t, Prof *);
 template void alda_kernel<double>(int64_t, const double *, double, double *, hipStream_t);

@@ -1,4 +1,4 @@
-// Handle construction (validation, upload, tiles, bricks, plans, rho0 and f_xc) and the
+// Handle construction (validation, upload, tiles, partial-sum tables, plans, rho0 and f_xc) and the
 // operator application of Eq. operator_RPA on column sets.
 #include <algorithm>
 #include <cmath>
@@ -242,95 +242,50 @@ static void upload_bf16(DevBuf<__hip_bfloat16> &dst, const std::vector<double> &
   TD_HIP(hipStreamSynchronize(s));
 }
 
-// bricks of be^3 tiles with union atom lists and the slot -> O-block table
-static void build_bricks(Handle &h, const HostSetTiles &tu, const HostSetTiles &to,
-                         const Pattern &O, int be) {
-  const int ntx = h.geom.ntx, nty = h.geom.nty, ntz = h.geom.ntz;
-  const int nbx = (ntx + be - 1) / be, nby = (nty + be - 1) / be, nbz = (ntz + be - 1) / be;
-  const int nb = nbx * nby * nbz;
-  std::vector<int32_t> tptr(nb + 1, 0), tiles, nu(nb), no(nb), slot;
-  std::vector<int64_t> sptr(nb + 1, 0);
-  std::vector<int32_t> ubl(tu.atoms.size()), obl(to.atoms.size());
-  int max_tiles = 0, max_slots = 0;
-  for (int bz = 0; bz < nbz; ++bz)
-    for (int by = 0; by < nby; ++by)
-      for (int bx = 0; bx < nbx; ++bx) {
-        const int b = bx + nbx * (by + nby * bz);
-        std::vector<int32_t> ul, ol, tl;
-        for (int z = bz * be; z < std::min(ntz, (bz + 1) * be); ++z)
-          for (int y = by * be; y < std::min(nty, (by + 1) * be); ++y)
-            for (int x = bx * be; x < std::min(ntx, (bx + 1) * be); ++x) {
-              const int t = x + ntx * (y + nty * z);
-              if (tu.ptr[t + 1] == tu.ptr[t] || to.ptr[t + 1] == to.ptr[t]) continue;
-              tl.push_back(t);
-              ul.insert(ul.end(), tu.atoms.begin() + tu.ptr[t], tu.atoms.begin() + tu.ptr[t + 1]);
-              ol.insert(ol.end(), to.atoms.begin() + to.ptr[t], to.atoms.begin() + to.ptr[t + 1]);
-            }
-        std::sort(ul.begin(), ul.end());
-        ul.erase(std::unique(ul.begin(), ul.end()), ul.end());
-        std::sort(ol.begin(), ol.end());
-        ol.erase(std::unique(ol.begin(), ol.end()), ol.end());
-        for (int t : tl) {
-          for (int32_t k = tu.ptr[t]; k < tu.ptr[t + 1]; ++k)
-            ubl[k] = (int32_t)(std::lower_bound(ul.begin(), ul.end(), tu.atoms[k]) - ul.begin());
-          for (int32_t k = to.ptr[t]; k < to.ptr[t + 1]; ++k)
-            obl[k] = (int32_t)(std::lower_bound(ol.begin(), ol.end(), to.atoms[k]) - ol.begin());
-        }
-        tiles.insert(tiles.end(), tl.begin(), tl.end());
-        tptr[b + 1] = (int32_t)tiles.size();
-        nu[b] = (int32_t)ul.size();
-        no[b] = (int32_t)ol.size();
-        for (int32_t I : ul)
-          for (int32_t J : ol) slot.push_back((int32_t)O.find(I, J));
-        sptr[b + 1] = (int64_t)slot.size();
-        max_tiles = std::max(max_tiles, (int)tl.size());
-        max_slots = std::max(max_slots, (int)(ul.size() * ol.size()));
+// Per-tile partial sums of the potential integrals: tile t owns u-rows x o-rows function
+// pairs from tbase[t] on (u-rows outer); every (tile, u-atom i, o-atom j) with its block
+// (I, J) in O is one contribution, listed per O block in tile order (a fixed summation
+// order, so results are reproducible).
+static void build_partials(Handle &h, const HostSetTiles &tu, const HostSetTiles &to,
+                           const Pattern &O) {
+  const int nt = h.nt;
+  std::vector<int64_t> tbase(nt, 0), cptr(O.nnzb() + 1, 0);
+  std::vector<int64_t> cblk;   // per (tile, i, j) in order: the O block (or -1)
+  int64_t total = 0;
+  for (int t = 0; t < nt; ++t) {
+    const int nua = tu.ptr[t + 1] - tu.ptr[t], noa = to.ptr[t + 1] - to.ptr[t];
+    tbase[t] = total;
+    total += (int64_t)nua * h.BU * noa * h.BO;
+    for (int i = 0; i < nua; ++i)
+      for (int j = 0; j < noa; ++j) {
+        const int64_t k = O.find(tu.atoms[tu.ptr[t] + i], to.atoms[to.ptr[t] + j]);
+        cblk.push_back(k);
+        if (k >= 0) cptr[k + 1]++;
       }
-  // per overlap block: the global slots (brick base + slot) that hold its partial sums
-  std::vector<int64_t> cptr(O.nnzb() + 1, 0), cslot;
-  for (size_t k = 0; k < slot.size(); ++k)
-    if (slot[k] >= 0) cptr[slot[k] + 1]++;
+  }
   for (int64_t k = 0; k < O.nnzb(); ++k) cptr[k + 1] += cptr[k];
-  cslot.resize(cptr[O.nnzb()]);
-  {
-    std::vector<int64_t> fillp(cptr.begin(), cptr.end() - 1);
-    for (size_t k = 0; k < slot.size(); ++k)
-      if (slot[k] >= 0) cslot[fillp[slot[k]]++] = (int64_t)k;
+  std::vector<int64_t> cbase(cptr[O.nnzb()]);
+  std::vector<int32_t> crs(cptr[O.nnzb()]);
+  std::vector<int64_t> fillp(cptr.begin(), cptr.end() - 1);
+  size_t q = 0;
+  for (int t = 0; t < nt; ++t) {
+    const int nua = tu.ptr[t + 1] - tu.ptr[t], noa = to.ptr[t + 1] - to.ptr[t];
+    const int rows_o = noa * h.BO;
+    for (int i = 0; i < nua; ++i)
+      for (int j = 0; j < noa; ++j, ++q) {
+        const int64_t k = cblk[q];
+        if (k < 0) continue;
+        cbase[fillp[k]] = tbase[t] + (int64_t)i * h.BU * rows_o + (int64_t)j * h.BO;
+        crs[fillp[k]++] = rows_o;
+      }
   }
   hipStream_t s = h.stream;
-  h.b_cptr.upload(cptr, s);
-  h.b_cslot.upload(cslot, s);
-  h.bricks.nslots_total = (int64_t)slot.size();
-  h.bricks.cptr = h.b_cptr.p;
-  h.bricks.cslot = h.b_cslot.p;
-  h.b_tptr.upload(tptr, s);
-  h.b_tiles.upload(tiles, s);
-  h.b_nu.upload(nu, s);
-  h.b_no.upload(no, s);
-  h.b_sptr.upload(sptr, s);
-  h.b_slot.upload(slot, s);
-  h.b_ubl.upload(ubl, s);
-  h.b_obl.upload(obl, s);
+  h.pa_tbase.upload(tbase, s);
+  h.pa_cptr.upload(cptr, s);
+  h.pa_cbase.upload(cbase, s);
+  h.pa_crs.upload(crs, s);
   TD_HIP(hipStreamSynchronize(s));
-  h.brick_edge = be;
-  h.bricks.nb = nb;
-  h.bricks.max_tiles = max_tiles;
-  h.bricks.max_slots = max_slots;
-  h.bricks.max_rows = h.maxrows_uo;
-  h.bricks.tptr = h.b_tptr.p;
-  h.bricks.tiles = h.b_tiles.p;
-  h.bricks.nu = h.b_nu.p;
-  h.bricks.no = h.b_no.p;
-  h.bricks.sptr = h.b_sptr.p;
-  h.bricks.slot_blk = h.b_slot.p;
-  h.bricks.ubl = h.b_ubl.p;
-  h.bricks.obl = h.b_obl.p;
-}
-
-// LDS of the potential-integral kernel with one wave per workgroup (the minimum it needs)
-size_t vint_lds_bytes(const Handle &h, int ns, size_t tsize) {
-  const size_t acc = ((size_t)h.bricks.max_slots * ns * h.E + 1) & ~(size_t)1;
-  return (acc + ((size_t)h.bricks.max_rows * (TP + 1) + (size_t)ns * TP)) * tsize;
+  h.partials = DevPartials{total, h.pa_tbase.p, h.pa_cptr.p, h.pa_cbase.p, h.pa_crs.p};
 }
 
 // ---------------------------------------------------------------------------------------
@@ -455,7 +410,7 @@ void create_handle(Handle &h, const tddft_system &sys, const tddft_options &o) {
   std::vector<int32_t> pidx_uo, pidx_oo;
   std::vector<std::vector<int32_t>> orows(h.nbu);
   h.maxrows_uo = h.maxrows_oo = 0;
-  int maxpairs_uo = 0, maxpairs_oo = 0;
+  int maxpairs_uo = 0, maxpairs_oo = 0, maxrows_r = 0;
   int64_t pp = 0;
   for (int t = 0; t < nt; ++t) {
     const int nua = tu.ptr[t + 1] - tu.ptr[t], noa = to.ptr[t + 1] - to.ptr[t];
@@ -463,6 +418,7 @@ void create_handle(Handle &h, const tddft_system &sys, const tddft_options &o) {
     h.maxrows_oo = std::max(h.maxrows_oo, 2 * noa * h.BO);
     maxpairs_uo = std::max(maxpairs_uo, nua * noa);
     maxpairs_oo = std::max(maxpairs_oo, noa * noa);
+    maxrows_r = std::max(maxrows_r, noa * h.BO);
     pp += (int64_t)nua * h.BU * noa * h.BO;
     for (int i = 0; i < nua; ++i)
       for (int j = 0; j < noa; ++j) {
@@ -513,18 +469,15 @@ void create_handle(Handle &h, const tddft_system &sys, const tddft_options &o) {
     upload_bf16(h.us16, tu.samples, s);
     upload_bf16(h.os16, to.samples, s);
   }
-  h.tiles_uo = DevTiles{nt, h.maxrows_uo, maxpairs_uo, h.t_uptr.p, h.t_optr.p, h.t_pptr_uo.p,
-                        h.t_pidx_uo.p, h.usamp(), h.osamp(), h.lds_limit};
-  h.tiles_oo = DevTiles{nt, h.maxrows_oo, maxpairs_oo, h.t_optr.p, h.t_optr.p, h.t_pptr_oo.p,
-                        h.t_pidx_oo.p, h.os64.p, h.os64.p, h.lds_limit};
-  TD_REQUIRE(((size_t)h.maxrows_uo * TP + (size_t)maxpairs_uo * 4 * h.E) * sizeof(double) <= h.lds_limit,
+  h.tiles_uo = DevTiles{nt, h.maxrows_uo, maxpairs_uo, maxrows_r, h.t_uptr.p, h.t_optr.p,
+                        h.t_pptr_uo.p, h.t_pidx_uo.p, h.usamp(), h.osamp(), h.lds_limit};
+  h.tiles_oo = DevTiles{nt, h.maxrows_oo, maxpairs_oo, maxrows_r, h.t_optr.p, h.t_optr.p,
+                        h.t_pptr_oo.p, h.t_pidx_oo.p, h.os64.p, h.os64.p, h.lds_limit};
+  TD_REQUIRE((size_t)maxrows_r * TP * sizeof(double) <= h.lds_limit,
              "too many functions per grid tile for the LDS budget");
 
-  // bricks: 2^3 tiles when the accumulator fits, else single tiles
-  build_bricks(h, tu, to, O, 2);
-  const size_t tsz = h.stype == SAMPLE_F64 ? sizeof(double) : sizeof(float);
-  if (vint_lds_bytes(h, 8, tsz) > h.lds_limit) build_bricks(h, tu, to, O, 1);
-  TD_REQUIRE(vint_lds_bytes(h, 2, tsz) <= h.lds_limit, "too many functions per grid tile for the LDS budget");
+  h.maxrows_o = maxrows_r;
+  build_partials(h, tu, to, O);
 
   // ---- plans
   HostBsr KcSuT = host_transpose(KcSu);
@@ -645,9 +598,10 @@ void apply_sets(Handle &h, int n, const T *X, int ldx, int xp0, int xq0, T *F, i
   const size_t bytes_w = (size_t)npair * wstride * sizeof(T);
   const size_t bytes_v = (size_t)h.nO * n * h.E * sizeof(T);
   const size_t bytes_y = (size_t)h.nM2 * n * h.E * sizeof(T);
-  int chunk = n;
-  while (chunk > 2 && vint_lds_bytes(h, chunk, sizeof(T)) > h.lds_limit) chunk = (chunk + 1) / 2 + ((chunk + 1) / 2) % 2;
-  const size_t bytes_part = (size_t)h.bricks.nslots_total * chunk * h.E * sizeof(T);
+  // potential integrals in chunks of at most 8 states (chunk starts stay even), which
+  // bounds the per-tile partial-sum buffer
+  const int chunk = std::min(n, 8);
+  const size_t bytes_part = (size_t)h.partials.total * chunk * sizeof(T);
   unsigned char *base = (unsigned char *)h.w_apply.get(bytes_f + bytes_w + bytes_v + bytes_y + bytes_part + 1024);
   T *fields = (T *)base;
   T *work = (T *)(base + bytes_f);
@@ -662,11 +616,10 @@ void apply_sets(Handle &h, int n, const T *X, int ldx, int xp0, int xq0, T *F, i
   density<T>(tl, st, h.BU, h.BO, X, ldx, xq0, n, fields, pstride, 1.0, s);
   h.prof.end(ST_DENSITY, s);
   hartree_xc<T>(h.geom, h.fft, npair, fields, work, h.fxc<T>(), h.opts.xc == TDDFT_XC_ALDA_X, s, &h.prof);
-  // states in chunks whose brick accumulators fit in LDS (chunk starts are even)
   for (int s0 = 0; s0 < n; s0 += chunk) {
     const int ns = std::min(chunk, n - s0);
     // Vout columns s0.. of a set with n columns: offset the pointer by s0 * E
-    potential_integrals<T>(tl, h.bricks, st, h.BU, h.BO, fields + (int64_t)(s0 / 2) * pstride, pstride,
+    potential_integrals<T>(tl, h.partials, st, h.BU, h.BO, fields + (int64_t)(s0 / 2) * pstride, pstride,
                            ns, part, Vset + (size_t)s0 * h.E, n, h.nO, h.dV, s, &h.prof);
   }
   h.prof.begin(ST_SANDWICH_LEFT, s);

@@ -72,7 +72,7 @@ struct Handle {
   int64_t nM = 0, nR = 0, nM2 = 0, nM3 = 0, nM4 = 0, nM5 = 0, nO = 0;
   bool m_complete = false;     // M holds every (u-block, o-block) pair (then R == M)
 
-  // tiles and bricks
+  // tiles and partial-sum tables
   DevBuf<int32_t> t_uptr, t_optr, t_pidx_uo, t_pidx_oo;
   DevBuf<int64_t> t_pptr_uo, t_pptr_oo;
   DevBuf<double> us64, os64;
@@ -80,10 +80,10 @@ struct Handle {
   DevBuf<__hip_bfloat16> us16, os16;
   DevTiles tiles_uo{}, tiles_oo{};
   int maxrows_uo = 0, maxrows_oo = 0;
-  int brick_edge = 2;
-  DevBuf<int32_t> b_tptr, b_tiles, b_nu, b_no, b_slot, b_ubl, b_obl;
-  DevBuf<int64_t> b_sptr, b_cptr, b_cslot;
-  DevBricks bricks{};
+  int maxrows_o = 0;           // max over tiles of o-rows (o-atoms * BO)
+  DevBuf<int64_t> pa_tbase, pa_cptr, pa_cbase;
+  DevBuf<int32_t> pa_crs;
+  DevPartials partials{};
   double mean_u_per_tile = 0, mean_o_per_tile = 0;
   int64_t pair_points = 0;     // sum over tiles of (u rows * o rows) * TP (work measure)
   int64_t sample_rows_u = 0, sample_rows_o = 0;

@@ -48,6 +48,7 @@ struct DevTiles {
   int nt = 0;
   int maxrows = 0;          // max over tiles of (n_left_atoms * BL + n_right_atoms * BR)
   int maxpairs = 0;         // max over tiles of n_left_atoms * n_right_atoms
+  int maxrows_r = 0;        // max over tiles of n_right_atoms * BR
   const int32_t *uptr = nullptr, *optr = nullptr;   // [nt + 1]
   const int64_t *pptr = nullptr;                    // [nt + 1]
   const int32_t *pidx = nullptr;                    // pair -> block index (or -1)
@@ -55,17 +56,14 @@ struct DevTiles {
   size_t lds_limit = 65536;                          // device LDS bytes per workgroup
 };
 
-struct DevBricks {
-  int nb = 0;
-  int max_tiles = 0, max_slots = 0, max_rows = 0;
-  const int32_t *tptr = nullptr, *tiles = nullptr;   // tiles of each brick
-  const int32_t *nu = nullptr, *no = nullptr;        // union list sizes per brick
-  const int64_t *sptr = nullptr;                     // [nb + 1] slot table offsets
-  const int32_t *slot_blk = nullptr;                 // slot -> O block (or -1)
-  const int32_t *ubl = nullptr, *obl = nullptr;      // per tile-list entry: brick-local index
-  int64_t nslots_total = 0;                          // sum over bricks of their slots
-  const int64_t *cptr = nullptr;                     // [n_out_blocks + 1] contributions
-  const int64_t *cslot = nullptr;                    // global slot ids (brick base + slot)
+// Per-tile partial sums of the potential integrals ([function pair][state], tiles in order,
+// u-rows outer) and the fixed-order table that sums them per overlap block.
+struct DevPartials {
+  int64_t total = 0;                  // function pairs over all tiles (values per state)
+  const int64_t *tbase = nullptr;     // [nt] first function pair of each tile
+  const int64_t *cptr = nullptr;      // [n_out_blocks + 1] contributions per overlap block
+  const int64_t *cbase = nullptr;     // per contribution: function pair of its (0, 0) element
+  const int32_t *crs = nullptr;       // per contribution: function pairs per u-row of its tile
 };
 
 enum SampleType { SAMPLE_F64 = 0, SAMPLE_F32 = 1, SAMPLE_BF16 = 2 };
@@ -77,9 +75,9 @@ void density(const DevTiles &tl, int stype, int BL, int BR, const T *X, int ldx,
              int ns, T *out, int64_t pair_stride, double scale, hipStream_t s);
 
 // Vout[blk][ldv][E] = scale * sum_r left_a(r) V_s(r) right_b(r) for the nblk_out overlap
-// blocks (V tile-major complex pairs); partial: [nslots_total][ns][E] scratch
+// blocks (V tile-major complex pairs); partial: [pa.total][ns] scratch
 template <class T>
-void potential_integrals(const DevTiles &tl, const DevBricks &br, int stype, int BL, int BR,
+void potential_integrals(const DevTiles &tl, const DevPartials &pa, int stype, int BL, int BR,
                          const T *V, int64_t pair_stride, int ns, T *partial, T *Vout, int ldv,
                          int64_t nblk_out, double scale, hipStream_t s, Prof *prof);
 

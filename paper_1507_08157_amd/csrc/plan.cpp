@@ -1,5 +1,5 @@
 // Host-side symbolic work done once per system: block patterns, the pair lists of every
-// masked product, exact host products of the fixed matrices, grid tiles and bricks, and
+// masked product, exact host products of the fixed matrices, grid tiles, and
 // FFT plans.
 #include <algorithm>
 #include <cmath>
