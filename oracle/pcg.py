@@ -16,6 +16,9 @@ is one of the documented readings:
   * the optimisation variable is the auxiliary matrix L on the truncation pattern M; trial
     vectors are P = Pi(L) = K^c S^u L S^o K^v, exact (Sec. III.A, Eq. auxiliary), so P never
     leaves the invariant space and P itself is never re-projected;
+  * learned (optional): G = c * g with a per-block elementwise scaling c predicted from
+    two-atom features (oracle/learned.py), used when it is a descent direction for every
+    state, else the CG preconditioner below;
   * M complete (no truncation): Eq. precond, K^c H^u G - G H^o K^v = g, is solved by CG in
     the S metric to a relative residual eps_tol (Sec. III.B) and the direction is
     d = -Pi(G) + beta d_prev (Pi(G) = G for invariant G); none -> G = g;
@@ -41,7 +44,8 @@ import scipy.optimize
 @dataclass
 class Options:
     n_states: int
-    precond: str = "cg"          # "cg" (Eq. precond solved by CG) or "none"
+    precond: str = "cg"          # "cg" (Eq. precond solved by CG), "none" or "learned"
+    scaling: np.ndarray | None = None   # learned: elementwise gradient scaling [n_u, n_o]
     eps_tol: float = 1e-4
     tol_omega: float = 1e-7
     max_iter: int = 300
@@ -59,6 +63,7 @@ class Result:
     converged: bool
     history: list = field(default_factory=list)
     inner_iters: list = field(default_factory=list)
+    fallbacks: int = 0
 
 
 class Solver:
@@ -66,6 +71,7 @@ class Solver:
         self.op = op
         self.o = opts
         self.complete = bool(np.all(op.mask_L == 1))
+        self.fallbacks = 0
 
     # -- metric helpers -------------------------------------------------------------------
     def cov(self, X):
@@ -103,6 +109,12 @@ class Solver:
         ||res|| <= eps_tol ||g||, after max_inner steps or on non-positive curvature."""
         if self.o.precond == "none":
             return g.copy(), 0
+        if self.o.precond == "learned":
+            # learned block scaling, kept only if it is a descent direction for every column
+            z = self.o.scaling[None] * g
+            if np.all(np.einsum("kij,kij->k", z, self.cov(g)) > 0):
+                return z, 0
+            self.fallbacks += 1
         G = np.zeros_like(g)
         r = g.copy()
         d = r.copy()
@@ -136,6 +148,11 @@ class Solver:
         non-positive curvature; none -> z = r."""
         if self.o.precond == "none":
             return r.copy(), 0
+        if self.o.precond == "learned":
+            z = self.op.truncate(self.o.scaling)[None] * r
+            if np.all(np.einsum("kij,kij->k", z, r) > 0):
+                return z, 0
+            self.fallbacks += 1
         z = np.zeros_like(r)
         res = r.copy()
         d = res.copy()
@@ -344,4 +361,4 @@ class Solver:
         P = self.transform(P, U.T, U.T)
         F = self.transform(F, U.T, U.T)
         return Result(omega=w, P=P, F=F, iterations=it, converged=converged, history=hist,
-                      inner_iters=inner)
+                      inner_iters=inner, fallbacks=self.fallbacks)
