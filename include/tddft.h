@@ -186,8 +186,8 @@ int64_t tddft_nnz_p(const tddft_handle *h);
 int64_t tddft_response_pattern(const tddft_handle *h, int64_t *rowptr, int32_t *colind);
 
 /* The operator of Eq. operator_RPA for n_states states at once:
- *   f_p = mask_M(K^c H^u P^p - P^p H^o K^v)
- *   f_q = mask_M(K^c H^u P^q - P^q H^o K^v + 2 s K^c V_SCF[P^q] K^v)
+ *   f_p = mask_R(K^c H^u P^p - P^p H^o K^v)
+ *   f_q = mask_R(K^c H^u P^q - P^q H^o K^v + 2 s K^c V_SCF[P^q] K^v)
  * with V_SCF[P]_ab = h^3 sum_r u_a (V_H[rho] + f_xc rho) o_b, rho = sum u_a P_ab o_b,
  * V_H the periodic Hartree potential (G = 0 dropped) and s the coupling scale.
  * Pp, Pq, fp, fq: DEVICE arrays [n_states][tddft_nnz_p] FP64 in R's value order
@@ -203,15 +203,83 @@ int tddft_apply(tddft_handle *h, int32_t n_states, const double *Pp, const doubl
  * blocks are ignored) and the trial vectors start at P = K^c S^u L S^o K^v; if NULL a seeded
  * N(0,1) guess on M is used.  On output (if non-NULL) they hold the converged
  * Tsiper-orthonormal vectors, rotated to the eigenvectors of the subspace matrix.
- * The optimisation variable is L on M: the gradient with respect to L is preconditioned by
- * the Kohn-Sham-difference operator of Eq. precond expressed on L and solved by inner CG.  opts may be NULL (handle's create options).
- * stats may be NULL.  precision, xc, rho_floor and coupling_scale belong to the handle:
- * solve options that differ in them are rejected with TDDFT_E_INVALID.  Returns
- * TDDFT_E_NO_CONVERGENCE with the last iterate when max_iter is reached. */
+ * The optimisation variable is L on M.  Preconditioner (opts->precond): KSDIFF_CG solves
+ * the Kohn-Sham-difference equation of Eq. precond by inner CG (on the trial-vector space
+ * when M is complete, expressed on L otherwise); LEARNED scales each gradient block
+ * elementwise by the output of the model blob opts->model (see tddft_mlp_export) evaluated
+ * once per solve on tddft_block_features, falls back to KSDIFF_CG in any iteration where
+ * that is not a descent direction for every state, and, when Pp/Pq are NULL, scales the
+ * random initial L block by block by the model's guess head.  opts may be NULL (handle's
+ * create options).  stats may be NULL.  precision, xc, rho_floor and coupling_scale belong
+ * to the handle: solve options that differ in them are rejected with TDDFT_E_INVALID.
+ * Returns TDDFT_E_NO_CONVERGENCE with the last iterate when max_iter is reached, and
+ * TDDFT_W_FALLBACK (converged) when the learned scaling was rejected at least once. */
 int tddft_pcg_solve(tddft_handle *h, int32_t n_states, const tddft_options *opts,
                     double *omega, double *Pp, double *Pq, tddft_stats *stats);
 
 void tddft_destroy(tddft_handle *h);
+
+/* ---- building blocks of the solver, exposed for training and testing -------------------- */
+
+/* Pi(L) = mask_R(K^c S^u L S^o K^v) (Sec. III.A, Eq. auxiliary) for n_states auxiliary
+ * matrices.  L, P: DEVICE [n_states][tddft_nnz_p] FP64 in R's layout; only L's blocks on M
+ * are read.  n_states in [1, 32]. */
+int tddft_project(tddft_handle *h, int32_t n_states, const double *L, double *P);
+
+/* Eq. precond (Sec. III.B): K^c H^u G - G H^o K^v = g solved by CG in the metric
+ * Tr[X^T S^u Y S^o] from G = 0, per state, to relative residual eps_tol or max_inner steps
+ * (or non-positive curvature).  g, G: DEVICE [n_states][tddft_nnz_p] FP64.  Requires a
+ * complete M (the trial vectors' own space); TDDFT_E_INVALID otherwise. */
+int tddft_precondition(tddft_handle *h, int32_t n_states, const double *g, double *G,
+                       double eps_tol, int32_t max_inner);
+
+/* Two-atom features of every block (I, J) of R, in R's block order, for the learned
+ * preconditioner: the upper triangles (row-major) of S^u_II, H^u_II, S^o_JJ, H^o_JJ; the
+ * generalised eigenvalues of (H^u_II, S^u_II) and (H^o_JJ, S^o_JJ), ascending; their
+ * differences (u index outer); the minimum-image distance (bohr) between the centres of
+ * the two atoms' function boxes.  out: DEVICE [blocks of R][tddft_n_features] FP32. */
+int32_t tddft_n_features(const tddft_handle *h);
+int tddft_block_features(tddft_handle *h, float *out);
+
+/* Guess targets from converged vectors: t_IJ = log10(sum_i ||P^q_i,IJ||^2 /
+ * sum_i ||P^q_i||^2 + 1e-8) per block of R.  Pq: DEVICE [n_states][tddft_nnz_p] FP64;
+ * t: DEVICE [blocks of R] FP32. */
+int tddft_guess_targets(tddft_handle *h, int32_t n_states, const double *Pq, float *t);
+
+/* ---- the learned preconditioner's network ----------------------------------------------
+ * y = W3 a(W2 a(W1 x^ + b1) + b2) + b3 with a(z) = z / (1 + e^-z), x^ = (x - mean) / std,
+ * hidden width `width`; outputs: y[0..E-1] elementwise scaling of a gradient block,
+ * y[E] the guess head.  Master parameters and Adam moments are FP32; the forward and
+ * backward passes use BF16 copies of the weight matrices (round to nearest even) with
+ * FP32 accumulation.  Parameters are packed as W1 [n_in][width], b1, W2 [width][width],
+ * b2, W3 [width][n_out], b3.  All row arrays are DEVICE FP32, row-major.  Work runs on the
+ * stream given at creation.  Not thread-safe. */
+typedef struct tddft_mlp tddft_mlp;
+
+/* Weights ~ N(0, 2 / fan_in) from a seeded generator, zero biases, mean 0, std 1. */
+int tddft_mlp_create(int32_t n_in, int32_t width, int32_t n_out, uint64_t seed, void *stream,
+                     tddft_mlp **out);
+void tddft_mlp_destroy(tddft_mlp *m);
+int64_t tddft_mlp_n_params(const tddft_mlp *m);
+/* host arrays: params [n_params] (packed order above), mean and std [n_in] (either pair
+ * may be NULL to leave it unchanged / not read back) */
+int tddft_mlp_set_params(tddft_mlp *m, const float *params, const float *mean, const float *std);
+int tddft_mlp_get_params(const tddft_mlp *m, float *params, float *mean, float *std);
+/* mean and std of each input column over rows X [rows][n_in] (FP64 sums; std floored at
+ * 1e-6), stored as the network's input normalisation */
+int tddft_mlp_fit_normalisation(tddft_mlp *m, int64_t rows, const float *X);
+int tddft_mlp_forward(tddft_mlp *m, int64_t rows, const float *X, float *Y);
+/* One Adam step (lr, beta1 0.9, beta2 0.999, eps 1e-8) on the loss
+ *   sum_rows [ 1/2 ||y[0..E-1] * g - gstar||^2 / loss_scale + 1/2 (y[E] - t)^2 ]
+ * with g, gstar [rows][E] and t [rows] (E = n_out - 1).  loss: HOST, the loss before the
+ * step; grad: DEVICE [n_params] or NULL, the gradient used. */
+int tddft_mlp_train_step(tddft_mlp *m, int64_t rows, const float *X, const float *g,
+                         const float *gstar, const float *t, double loss_scale, double lr,
+                         double *loss, float *grad);
+/* Model blob for tddft_options.model: *size bytes (query with blob NULL). */
+int tddft_mlp_export(const tddft_mlp *m, void *blob, int64_t cap, int64_t *size);
+int tddft_mlp_import(const void *blob, int64_t size, void *stream, tddft_mlp **out);
+const char *tddft_mlp_last_error(const tddft_mlp *m);
 
 /* Device-time profiling of the kernel stages (HIP events recorded on the handle's stream
  * around each stage; enabling it adds event records and host waits, not extra kernels).

@@ -83,7 +83,12 @@ EXPORTS = ("tddft_default_options", "tddft_create", "tddft_nnz_p", "tddft_respon
            "tddft_apply",
            "tddft_pcg_solve", "tddft_destroy", "tddft_strerror", "tddft_last_error",
            "tddft_abi_version", "tddft_get_info", "tddft_profile", "tddft_profile_read",
-           "tddft_profile_stage_name")
+           "tddft_profile_stage_name", "tddft_project", "tddft_precondition",
+           "tddft_n_features", "tddft_block_features", "tddft_guess_targets",
+           "tddft_mlp_create", "tddft_mlp_destroy", "tddft_mlp_n_params", "tddft_mlp_set_params",
+           "tddft_mlp_get_params", "tddft_mlp_fit_normalisation", "tddft_mlp_forward",
+           "tddft_mlp_train_step", "tddft_mlp_export", "tddft_mlp_import",
+           "tddft_mlp_last_error")
 
 
 def lib():
@@ -128,6 +133,29 @@ def lib():
         L.tddft_profile_read.restype = C.c_int
         L.tddft_profile_stage_name.argtypes = [C.c_int]
         L.tddft_profile_stage_name.restype = C.c_char_p
+        vp = C.c_void_p
+        for name, args, res in (
+                ("tddft_project", [vp, C.c_int32, vp, vp], C.c_int),
+                ("tddft_precondition", [vp, C.c_int32, vp, vp, C.c_double, C.c_int32], C.c_int),
+                ("tddft_n_features", [vp], C.c_int32),
+                ("tddft_block_features", [vp, vp], C.c_int),
+                ("tddft_guess_targets", [vp, C.c_int32, vp, vp], C.c_int),
+                ("tddft_mlp_create", [C.c_int32, C.c_int32, C.c_int32, C.c_uint64, vp,
+                                      C.POINTER(C.c_void_p)], C.c_int),
+                ("tddft_mlp_destroy", [vp], None),
+                ("tddft_mlp_n_params", [vp], C.c_int64),
+                ("tddft_mlp_set_params", [vp, vp, vp, vp], C.c_int),
+                ("tddft_mlp_get_params", [vp, vp, vp, vp], C.c_int),
+                ("tddft_mlp_fit_normalisation", [vp, C.c_int64, vp], C.c_int),
+                ("tddft_mlp_forward", [vp, C.c_int64, vp, vp], C.c_int),
+                ("tddft_mlp_train_step", [vp, C.c_int64, vp, vp, vp, vp, C.c_double,
+                                          C.c_double, C.POINTER(C.c_double), vp], C.c_int),
+                ("tddft_mlp_export", [vp, vp, C.c_int64, C.POINTER(C.c_int64)], C.c_int),
+                ("tddft_mlp_import", [vp, C.c_int64, vp, C.POINTER(C.c_void_p)], C.c_int),
+                ("tddft_mlp_last_error", [vp], C.c_char_p)):
+            f = getattr(L, name)
+            f.argtypes = args
+            f.restype = res
         _LIB = L
     return _LIB
 
@@ -138,12 +166,26 @@ class TddftError(RuntimeError):
         self.code = code
 
 
+PRECOND = {"none": 0, "cg": 1, "learned": 2}
+
+
 def tddft_default_options(**kw) -> tddft_options:
+    """Options with library defaults, then keyword overrides.  precision and precond take
+    names ("fp32", "learned", ...); model takes the bytes of a model blob (kept alive by
+    the returned options object)."""
     o = tddft_options()
     lib().tddft_default_options(C.byref(o))
     for k, v in kw.items():
         if k == "precision" and isinstance(v, str):
             v = PRECISION[v]
+        if k == "precond" and isinstance(v, str):
+            v = PRECOND[v]
+        if k == "model":
+            buf = C.create_string_buffer(bytes(v), len(v))
+            o._model_buf = buf
+            o.model = C.cast(buf, C.c_void_p)
+            o.model_bytes = len(v)
+            continue
         setattr(o, k, v)
     return o
 
@@ -238,6 +280,46 @@ class Handle:
             raise self._err(rc)
         return fp, fq
 
+    def tddft_project(self, L, P=None):
+        """Pi(L) (Eq. auxiliary) for device tensors [n_states, nnz_p] FP64."""
+        import torch
+        P = torch.empty_like(L) if P is None else P
+        rc = lib().tddft_project(self._h, L.shape[0], _dev(L, "L"), _dev(P, "P"))
+        if rc != TDDFT_OK:
+            raise self._err(rc)
+        return P
+
+    def tddft_precondition(self, g, eps_tol=1e-4, max_inner=50, G=None):
+        """Eq. precond solved by CG in the S metric for device tensors [n_states, nnz_p]."""
+        import torch
+        G = torch.empty_like(g) if G is None else G
+        rc = lib().tddft_precondition(self._h, g.shape[0], _dev(g, "g"), _dev(G, "G"),
+                                      float(eps_tol), int(max_inner))
+        if rc != TDDFT_OK:
+            raise self._err(rc)
+        return G
+
+    def tddft_block_features(self):
+        """[blocks of R, n_features] FP32 device tensor."""
+        import torch
+        nf = int(lib().tddft_n_features(self._h))
+        nb = int(lib().tddft_response_pattern(self._h, None, None))
+        out = torch.empty((nb, nf), dtype=torch.float32, device="cuda")
+        rc = lib().tddft_block_features(self._h, C.c_void_p(out.data_ptr()))
+        if rc != TDDFT_OK:
+            raise self._err(rc)
+        return out
+
+    def tddft_guess_targets(self, Pq):
+        import torch
+        nb = int(lib().tddft_response_pattern(self._h, None, None))
+        t = torch.empty(nb, dtype=torch.float32, device="cuda")
+        rc = lib().tddft_guess_targets(self._h, Pq.shape[0], _dev(Pq, "Pq"),
+                                       C.c_void_p(t.data_ptr()))
+        if rc != TDDFT_OK:
+            raise self._err(rc)
+        return t
+
     def tddft_response_pattern(self):
         """(rowptr, colind) of the response pattern R (numpy arrays)."""
         nb = int(lib().tddft_response_pattern(self._h, None, None))
@@ -316,3 +398,85 @@ def tddft_abi_version() -> int:
 
 def tddft_strerror(code: int) -> str:
     return lib().tddft_strerror(code).decode()
+
+
+def _f32dev(t, name):
+    import torch
+    if not (isinstance(t, torch.Tensor) and t.is_cuda and t.dtype == torch.float32
+            and t.is_contiguous()):
+        raise TypeError(f"{name} must be a contiguous float32 CUDA tensor")
+    return C.c_void_p(t.data_ptr())
+
+
+class Mlp:
+    """The learned preconditioner's network (tddft_mlp_*)."""
+
+    def __init__(self, n_in=None, width=128, n_out=None, seed=0, blob: bytes | None = None):
+        self._m = C.c_void_p()
+        if blob is not None:
+            buf = C.create_string_buffer(bytes(blob), len(blob))
+            rc = lib().tddft_mlp_import(buf, len(blob), None, C.byref(self._m))
+        else:
+            rc = lib().tddft_mlp_create(n_in, width, n_out, seed, None, C.byref(self._m))
+        if rc != TDDFT_OK:
+            raise TddftError(rc, lib().tddft_last_error(None).decode())
+        self.n_params = int(lib().tddft_mlp_n_params(self._m))
+
+    def close(self):
+        if self._m:
+            lib().tddft_mlp_destroy(self._m)
+            self._m = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _check(self, rc):
+        if rc != TDDFT_OK:
+            raise TddftError(rc, lib().tddft_mlp_last_error(self._m).decode())
+
+    def set_params(self, params=None, mean=None, std=None):
+        p = None if params is None else np.ascontiguousarray(params, dtype=np.float32)
+        mu = None if mean is None else np.ascontiguousarray(mean, dtype=np.float32)
+        sd = None if std is None else np.ascontiguousarray(std, dtype=np.float32)
+        f = C.POINTER(C.c_float)
+        self._check(lib().tddft_mlp_set_params(
+            self._m, None if p is None else p.ctypes.data_as(f),
+            None if mu is None else mu.ctypes.data_as(f), None if sd is None else sd.ctypes.data_as(f)))
+
+    def get_params(self, n_in):
+        p = np.zeros(self.n_params, dtype=np.float32)
+        mu = np.zeros(n_in, dtype=np.float32)
+        sd = np.zeros(n_in, dtype=np.float32)
+        f = C.POINTER(C.c_float)
+        self._check(lib().tddft_mlp_get_params(self._m, p.ctypes.data_as(f), mu.ctypes.data_as(f),
+                                               sd.ctypes.data_as(f)))
+        return p, mu, sd
+
+    def fit_normalisation(self, X):
+        self._check(lib().tddft_mlp_fit_normalisation(self._m, X.shape[0], _f32dev(X, "X")))
+
+    def forward(self, X, n_out):
+        import torch
+        Y = torch.empty((X.shape[0], n_out), dtype=torch.float32, device="cuda")
+        self._check(lib().tddft_mlp_forward(self._m, X.shape[0], _f32dev(X, "X"), _f32dev(Y, "Y")))
+        return Y
+
+    def train_step(self, X, g, gstar, t, loss_scale=1.0, lr=1e-3, want_grad=False):
+        import torch
+        loss = C.c_double(0.0)
+        grad = torch.empty(self.n_params, dtype=torch.float32, device="cuda") if want_grad else None
+        self._check(lib().tddft_mlp_train_step(
+            self._m, X.shape[0], _f32dev(X, "X"), _f32dev(g, "g"), _f32dev(gstar, "gstar"),
+            _f32dev(t, "t"), float(loss_scale), float(lr), C.byref(loss),
+            _f32dev(grad, "grad") if want_grad else None))
+        return (loss.value, grad) if want_grad else loss.value
+
+    def export(self) -> bytes:
+        size = C.c_int64(0)
+        self._check(lib().tddft_mlp_export(self._m, None, 0, C.byref(size)))
+        buf = C.create_string_buffer(size.value)
+        self._check(lib().tddft_mlp_export(self._m, buf, size.value, C.byref(size)))
+        return buf.raw

@@ -3,12 +3,47 @@
 #include <new>
 
 #include "handle.h"
+#include "learned.h"
 
 using namespace tddft;
 
 struct tddft_handle {
   Handle h;
 };
+
+struct tddft_mlp {
+  Mlp m;
+};
+
+namespace {
+// run f() converting library errors into a status code and the handle's error text
+template <class F>
+int guarded(std::string &err, F &&f) {
+  err.clear();
+  try {
+    f();
+    return TDDFT_OK;
+  } catch (const Error &e) {
+    err = e.msg;
+    return e.code;
+  } catch (const std::bad_alloc &) {
+    err = "host allocation failed";
+    return TDDFT_E_NOMEM;
+  }
+}
+
+template <class T>
+void project_abi(Handle &h, int n, const double *L, double *P) {
+  const size_t eR = (size_t)h.nR * n * h.E, eM = (size_t)h.nM * n * h.E;
+  T *A = (T *)h.w_pcg.get((2 * eR + eM) * sizeof(T));
+  T *Lm = A + eR, *B = Lm + eM;
+  pack<T>(h.nR, h.BU, h.BO, n, L, h.nnzR, h.r_voff.p, h.r_shape.p, A, n, 0, h.stream);
+  gather_blocks<T>(h.nM, n * h.E, h.m_in_r.p, A, Lm, h.stream);
+  project_sets<T>(h, n, Lm, n, 0, B, n, 0);
+  unpack<T>(h.nR, h.BU, h.BO, n, B, n, 0, h.r_voff.p, h.r_shape.p, P, h.nnzR, h.stream);
+  TD_HIP(hipStreamSynchronize(h.stream));
+}
+}  // namespace
 
 static thread_local std::string g_create_error;
 
@@ -195,6 +230,164 @@ int tddft_pcg_solve(tddft_handle *hd, int32_t n, const tddft_options *opts, doub
 }
 
 void tddft_destroy(tddft_handle *h) { delete h; }
+
+int tddft_project(tddft_handle *hd, int32_t n, const double *L, double *P) {
+  if (!hd) return TDDFT_E_INVALID;
+  Handle &h = hd->h;
+  if (n < 1 || n > 32 || !L || !P) {
+    h.last_error = "tddft_project: n_states must be in [1, 32] and arrays non-null";
+    return TDDFT_E_INVALID;
+  }
+  return guarded(h.last_error, [&] {
+    if (h.precision == TDDFT_FP64) project_abi<double>(h, n, L, P);
+    else project_abi<float>(h, n, L, P);
+  });
+}
+
+int tddft_precondition(tddft_handle *hd, int32_t n, const double *g, double *G, double eps_tol,
+                       int32_t max_inner) {
+  if (!hd) return TDDFT_E_INVALID;
+  Handle &h = hd->h;
+  if (n < 1 || n > 32 || !g || !G || !(eps_tol > 0.0) || max_inner < 0) {
+    h.last_error = "tddft_precondition: n_states in [1, 32], non-null arrays, eps_tol > 0";
+    return TDDFT_E_INVALID;
+  }
+  return guarded(h.last_error, [&] { precondition(h, n, g, G, eps_tol, max_inner); });
+}
+
+int32_t tddft_n_features(const tddft_handle *h) { return h ? h->h.nfeat : TDDFT_E_INVALID; }
+
+int tddft_block_features(tddft_handle *hd, float *out) {
+  if (!hd || !out) return TDDFT_E_INVALID;
+  Handle &h = hd->h;
+  return guarded(h.last_error, [&] {
+    TD_HIP(hipMemcpyAsync(out, h.features.p, (size_t)h.nR * h.nfeat * sizeof(float),
+                          hipMemcpyDeviceToDevice, h.stream));
+    TD_HIP(hipStreamSynchronize(h.stream));
+  });
+}
+
+int tddft_guess_targets(tddft_handle *hd, int32_t n, const double *Pq, float *t) {
+  if (!hd) return TDDFT_E_INVALID;
+  Handle &h = hd->h;
+  if (n < 1 || n > 32 || !Pq || !t) {
+    h.last_error = "tddft_guess_targets: n_states in [1, 32] and non-null arrays";
+    return TDDFT_E_INVALID;
+  }
+  return guarded(h.last_error, [&] {
+    DevBuf<double> w(h.nR);
+    block_sqnorm(h.nR, n, h.nnzR, h.r_voff.p, h.r_shape.p, Pq, w.p, h.stream);
+    std::vector<double> hw(h.nR);
+    TD_HIP(hipMemcpyAsync(hw.data(), w.p, h.nR * sizeof(double), hipMemcpyDeviceToHost, h.stream));
+    TD_HIP(hipStreamSynchronize(h.stream));
+    double tot = 0.0;
+    for (double x : hw) tot += x;
+    TD_REQUIRE(tot > 0.0, "tddft_guess_targets: the vectors are zero");
+    guess_from_weights(h.nR, w.p, 1.0 / tot, t, h.stream);
+    TD_HIP(hipStreamSynchronize(h.stream));
+  });
+}
+
+// ---- network ---------------------------------------------------------------------------
+int tddft_mlp_create(int32_t n_in, int32_t width, int32_t n_out, uint64_t seed, void *stream,
+                     tddft_mlp **out) {
+  g_create_error.clear();
+  if (!out) return TDDFT_E_INVALID;
+  *out = nullptr;
+  tddft_mlp *m = nullptr;
+  try {
+    m = new tddft_mlp();
+    m->m.init(n_in, width, n_out, (hipStream_t)stream);
+    m->m.randomize(seed);
+    *out = m;
+    return TDDFT_OK;
+  } catch (const Error &e) {
+    g_create_error = e.msg;
+    delete m;
+    return e.code;
+  } catch (const std::bad_alloc &) {
+    g_create_error = "host allocation failed";
+    delete m;
+    return TDDFT_E_NOMEM;
+  }
+}
+
+void tddft_mlp_destroy(tddft_mlp *m) { delete m; }
+
+int64_t tddft_mlp_n_params(const tddft_mlp *m) { return m ? m->m.nparams : TDDFT_E_INVALID; }
+
+int tddft_mlp_set_params(tddft_mlp *m, const float *params, const float *mean, const float *stdv) {
+  if (!m) return TDDFT_E_INVALID;
+  return guarded(m->m.last_error, [&] { m->m.set(params, mean, stdv); });
+}
+
+int tddft_mlp_get_params(const tddft_mlp *m, float *params, float *mean, float *stdv) {
+  if (!m) return TDDFT_E_INVALID;
+  std::string err;
+  return guarded(err, [&] { m->m.get(params, mean, stdv); });
+}
+
+int tddft_mlp_fit_normalisation(tddft_mlp *m, int64_t rows, const float *X) {
+  if (!m) return TDDFT_E_INVALID;
+  return guarded(m->m.last_error, [&] { m->m.fit_normalisation(rows, X); });
+}
+
+int tddft_mlp_forward(tddft_mlp *m, int64_t rows, const float *X, float *Y) {
+  if (!m) return TDDFT_E_INVALID;
+  return guarded(m->m.last_error, [&] {
+    m->m.forward(rows, X, Y);
+    TD_HIP(hipStreamSynchronize(m->m.s));
+  });
+}
+
+int tddft_mlp_train_step(tddft_mlp *m, int64_t rows, const float *X, const float *g,
+                         const float *gstar, const float *t, double loss_scale, double lr,
+                         double *loss, float *grad) {
+  if (!m) return TDDFT_E_INVALID;
+  return guarded(m->m.last_error, [&] {
+    const double l = m->m.train_step(rows, X, g, gstar, t, loss_scale, lr, grad);
+    if (loss) *loss = l;
+  });
+}
+
+int tddft_mlp_export(const tddft_mlp *m, void *blob, int64_t cap, int64_t *size) {
+  if (!m || !size) return TDDFT_E_INVALID;
+  std::string err;
+  return guarded(err, [&] {
+    const std::vector<unsigned char> b = m->m.blob();
+    *size = (int64_t)b.size();
+    if (blob) {
+      TD_REQUIRE(cap >= (int64_t)b.size(), "tddft_mlp_export: buffer too small");
+      std::memcpy(blob, b.data(), b.size());
+    }
+  });
+}
+
+int tddft_mlp_import(const void *blob, int64_t size, void *stream, tddft_mlp **out) {
+  g_create_error.clear();
+  if (!out) return TDDFT_E_INVALID;
+  *out = nullptr;
+  tddft_mlp *m = nullptr;
+  try {
+    m = new tddft_mlp();
+    m->m.from_blob(blob, size, (hipStream_t)stream);
+    *out = m;
+    return TDDFT_OK;
+  } catch (const Error &e) {
+    g_create_error = e.msg;
+    delete m;
+    return e.code;
+  } catch (const std::bad_alloc &) {
+    g_create_error = "host allocation failed";
+    delete m;
+    return TDDFT_E_NOMEM;
+  }
+}
+
+const char *tddft_mlp_last_error(const tddft_mlp *m) {
+  if (!m) return g_create_error.c_str();
+  return m->m.last_error.c_str();
+}
 
 int tddft_profile(tddft_handle *hd, int enable) {
   if (!hd) return TDDFT_E_INVALID;

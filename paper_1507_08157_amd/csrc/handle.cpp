@@ -5,6 +5,7 @@
 #include <thread>
 
 #include "handle.h"
+#include "learned.h"
 
 namespace tddft {
 
@@ -390,6 +391,8 @@ void create_handle(Handle &h, const tddft_system &sys, const tddft_options &o) {
     h.nnzR = pos;
     h.r_voff.upload(voff, s);
     h.r_shape.upload(shape, s);
+    h.r_voff_host = voff;
+    h.r_shape_host = shape;
     std::vector<int32_t> mir(h.nM);
     for (int i = 0; i < h.nbu; ++i)
       for (int64_t k = h.M.rowptr[i]; k < h.M.rowptr[i + 1]; ++k) {
@@ -401,6 +404,8 @@ void create_handle(Handle &h, const tddft_system &sys, const tddft_options &o) {
     h.m_complete = h.nM == (int64_t)h.nbu * h.nbo;
     if (h.m_complete) TD_REQUIRE(h.R.col == h.M.col && h.nR == h.nM, "complete M must equal R");
   }
+
+  build_features(h, Su, Hu, So, Ho, sys);
 
   // ---- functions and tiles
   HostSetTiles tu = build_set_tiles(sys.vir, h.uoff, h.BU, h.n, h.geom.ntx, h.geom.nty, h.geom.ntz);

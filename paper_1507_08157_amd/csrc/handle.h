@@ -88,6 +88,12 @@ struct Handle {
   int64_t pair_points = 0;     // sum over tiles of (u rows * o rows) * TP (work measure)
   int64_t sample_rows_u = 0, sample_rows_o = 0;
 
+  // learned preconditioner: two-atom features of every R block
+  int nfeat = 0;
+  DevBuf<float> features;      // [nR][nfeat]
+  std::vector<int64_t> r_voff_host;
+  std::vector<int32_t> r_shape_host;
+
   // ground state
   DevBuf<double> fxc64;
   DevBuf<float> fxc32;
@@ -131,5 +137,7 @@ void project_t_sets(Handle &h, int ncol, const T *X, int ldx, int x0, T *F, int 
 
 int pcg_solve(Handle &h, int n, const tddft_options &o, double *omega, double *Pp, double *Pq,
               tddft_stats *stats);
+// Eq. precond by CG in the S metric for n states in the C-ABI layout (complete M)
+void precondition(Handle &h, int n, const double *g, double *G, double eps_tol, int max_inner);
 
 }  // namespace tddft

@@ -27,6 +27,7 @@
 #include <limits>
 
 #include "handle.h"
+#include "learned.h"
 
 namespace tddft {
 
@@ -327,6 +328,84 @@ struct Solver {
   }
 };
 
+// Eq. precond by CG in the S metric, per column, from z = 0 (vectors on R with M complete):
+// T(z) = g with T(X) = K^c H^u X - X H^o K^v.  gc = S^u g S^o.  Stops at relative residual
+// eps_tol, after max_inner steps, or on non-positive curvature; columns that never step keep
+// z = g.  Returns the number of CG steps taken.
+template <class T>
+int ksdiff_cg(Solver<T> &S, Handle &h, const T *g, const T *gc, T *zk, T *res, T *resc, T *dk,
+              T *dkc, T *Lk, T *Lkc, T *tmp, double eps_tol, int max_inner) {
+  const int nc = S.nc;
+  const int64_t nb = S.nR;
+  hipStream_t s = S.s;
+  int iters = 0;
+  S.copy(nb, res, g);
+  S.copy(nb, resc, gc);
+  S.copy(nb, dk, g);
+  S.copy(nb, dkc, gc);
+  fill<T>(zk, (int64_t)S.elems(nb), T(0), s);
+  const size_t q0 = S.gram_q(nb, res, 0, nc, resc, 0, nc, true);
+  std::vector<double> r = S.fetch();
+  std::vector<double> rr(r.begin() + q0, r.begin() + q0 + nc), rr0 = rr;
+  std::vector<char> active(nc);
+  for (int c = 0; c < nc; ++c) active[c] = rr0[c] > 0.0;
+  std::vector<int> steps(nc, 0);
+  const double tol2 = eps_tol * eps_tol;
+  for (int k = 0; k < max_inner; ++k) {
+    bool any = false;
+    for (int c = 0; c < nc; ++c) {
+      if (active[c] && !(rr[c] > tol2 * rr0[c])) active[c] = 0;
+      any |= (bool)active[c];
+    }
+    if (!any) break;
+    kshift_sets<T>(h, nc, dk, nc, 0, Lk, nc, 0);
+    const size_t qd = S.gram_q(nb, Lk, 0, nc, dkc, 0, nc, true);
+    r = S.fetch();
+    std::vector<double> alpha(nc, 0.0), nalpha(nc, 0.0);
+    any = false;
+    for (int c = 0; c < nc; ++c) {
+      if (active[c] && !(r[qd + c] > 0.0)) active[c] = 0;
+      if (active[c]) {
+        alpha[c] = rr[c] / r[qd + c];
+        nalpha[c] = -alpha[c];
+      }
+      any |= (bool)active[c];
+    }
+    if (!any) break;
+    covariant_sets<T>(h, nc, Lk, nc, 0, Lkc, nc, 0);
+    std::vector<double> ones(nc, 1.0);
+    const double *b1 = S.coef(ones);
+    S.lc(nb, zk, b1, {{dk, S.diag(alpha)}});
+    S.lc(nb, res, b1, {{Lk, S.diag(nalpha)}});
+    S.lc(nb, resc, b1, {{Lkc, S.diag(nalpha)}});
+    const size_t qr = S.gram_q(nb, res, 0, nc, resc, 0, nc, true);
+    r = S.fetch();
+    std::vector<double> keep(nc), take(nc);
+    for (int c = 0; c < nc; ++c) {
+      double beta = 1.0;
+      if (active[c]) {
+        beta = rr[c] > 0.0 ? r[qr + c] / rr[c] : 0.0;
+        rr[c] = r[qr + c];
+        steps[c]++;
+      }
+      keep[c] = active[c] ? beta : 1.0;
+      take[c] = active[c] ? 1.0 : 0.0;
+    }
+    const double *bk = S.coef(keep);
+    S.lc(nb, dk, bk, {{res, S.diag(take)}});
+    S.lc(nb, dkc, bk, {{resc, S.diag(take)}});
+    ++iters;
+  }
+  std::vector<double> fromz(nc), fromr(nc);
+  for (int c = 0; c < nc; ++c) {
+    fromz[c] = steps[c] > 0 ? 1.0 : 0.0;
+    fromr[c] = steps[c] > 0 ? 0.0 : 1.0;
+  }
+  S.lc(nb, tmp, nullptr, {{zk, S.diag(fromz)}, {g, S.diag(fromr)}});
+  S.copy(nb, zk, tmp);
+  return iters;
+}
+
 }  // namespace
 
 // ---------------------------------------------------------------------------------------
@@ -350,7 +429,26 @@ static int solve_impl(Handle &h, int n, const tddft_options &o, double *omega, d
   // M complete: the auxiliary matrices and the trial vectors share one full pattern
   const bool complete = h.m_complete;
   hipStream_t s = h.stream;
-  int applies = 0, inner_total = 0;
+  int applies = 0, inner_total = 0, fallbacks = 0;
+  // learned preconditioner: the network evaluated once on the block features gives the
+  // elementwise scaling of every R block (and of M's blocks) and the guess weights
+  DevBuf<T> cscale, cscale_m;
+  std::vector<float> guess_t;
+  if (o.precond == TDDFT_PC_LEARNED) {
+    Mlp net;
+    net.from_blob(o.model, o.model_bytes, s);
+    TD_REQUIRE(net.n_in == h.nfeat && net.n_out == h.E + 1,
+               "learned-preconditioner model does not match this system's feature or block size");
+    DevBuf<float> Y((size_t)nR * (h.E + 1)), tdev(nR);
+    net.forward(nR, h.features.p, Y.p);
+    cscale.alloc((size_t)nR * h.E);
+    split_outputs<T>(nR, h.E, Y.p, cscale.p, tdev.p, s);
+    cscale_m.alloc((size_t)nM * h.E);
+    gather_blocks<T>(nM, h.E, h.m_in_r.p, cscale.p, cscale_m.p, s);
+    guess_t.resize(nR);
+    TD_HIP(hipMemcpyAsync(guess_t.data(), tdev.p, nR * sizeof(float), hipMemcpyDeviceToHost, s));
+    TD_HIP(hipStreamSynchronize(s));
+  }
   float apply_ms = 0.0f;
   auto apply = [&](const T *X, T *Fo) {
     TD_HIP(hipEventRecord(h.ev0, s));
@@ -388,6 +486,16 @@ static int solve_impl(Handle &h, int n, const tddft_options &o, double *omega, d
         const double r = std::sqrt(-2.0 * std::log(u1));
         g[i] = r * std::cos(2.0 * M_PI * u2);
         if (i + 1 < g.size()) g[i + 1] = r * std::sin(2.0 * M_PI * u2);
+      }
+      if (!guess_t.empty()) {   // learned guess: block (I, J) scaled by sqrt(10^t_IJ)
+        for (int64_t b = 0; b < nR; ++b) {
+          const double f = std::sqrt(std::pow(10.0, (double)guess_t[b]));
+          const int sz = (h.r_shape_host[b] & 0xff) * (h.r_shape_host[b] >> 8);
+          for (int i = 0; i < n; ++i) {
+            double *v = g.data() + (size_t)i * h.nnzR + h.r_voff_host[b];
+            for (int e = 0; e < sz; ++e) v[e] *= f;
+          }
+        }
       }
       DevBuf<double> dg(g.size());
       dg.upload(g, s);
@@ -474,82 +582,40 @@ static int solve_impl(Handle &h, int n, const tddft_options &o, double *omega, d
       // ---- M complete: CG on Eq. precond T(z) = g in the S metric (vectors on R = M);
       //      the conjugation uses r = S^u g S^o with Euclidean dots, i.e. S-metric dots of g
       S.copy(nM, set(Lr), set(Gc));
-      if (o.precond == TDDFT_PC_NONE) {
-        S.copy(nM, set(Lz), set(G));
-      } else {
-        T *res = set(Lres), *resc = set(Lresc), *dk = set(Ld), *dkc = set(Ldc);
-        T *Lk = set(LHd), *Lkc = set(LHdc), *zk = set(Lz);
-        S.copy(nM, res, set(G));
-        S.copy(nM, resc, set(Gc));
-        S.copy(nM, dk, set(G));
-        S.copy(nM, dkc, set(Gc));
-        fill<T>(zk, (int64_t)S.elems(nM), T(0), s);
-        const size_t q0 = S.gram_q(nM, res, 0, nc, resc, 0, nc, true);
+      bool done = false;
+      if (o.precond == TDDFT_PC_LEARNED) {
+        // learned block scaling, kept if it is a descent direction for every column
+        block_scale<T>(nM, nc, h.E, cscale.p, set(G), set(Lz), s);
+        const size_t qd = S.gram_q(nM, set(Lz), 0, nc, set(Gc), 0, nc, true);
         r = S.fetch();
-        std::vector<double> rr(r.begin() + q0, r.begin() + q0 + nc), rr0 = rr;
-        std::vector<char> active(nc);
-        for (int c = 0; c < nc; ++c) active[c] = rr0[c] > 0.0;
-        std::vector<int> steps(nc, 0);
-        const double tol2 = o.eps_tol * o.eps_tol;
-        for (int k = 0; k < o.max_inner; ++k) {
-          bool any = false;
-          for (int c = 0; c < nc; ++c) {
-            if (active[c] && !(rr[c] > tol2 * rr0[c])) active[c] = 0;
-            any |= (bool)active[c];
-          }
-          if (!any) break;
-          kshift_sets<T>(h, nc, dk, nc, 0, Lk, nc, 0);
-          const size_t qd = S.gram_q(nM, Lk, 0, nc, dkc, 0, nc, true);
-          r = S.fetch();
-          std::vector<double> alpha(nc, 0.0), nalpha(nc, 0.0);
-          any = false;
-          for (int c = 0; c < nc; ++c) {
-            if (active[c] && !(r[qd + c] > 0.0)) active[c] = 0;
-            if (active[c]) {
-              alpha[c] = rr[c] / r[qd + c];
-              nalpha[c] = -alpha[c];
-            }
-            any |= (bool)active[c];
-          }
-          if (!any) break;
-          cov(Lk, Lkc);
-          std::vector<double> ones(nc, 1.0);
-          const double *b1 = S.coef(ones);
-          S.lc(nM, zk, b1, {{dk, S.diag(alpha)}});
-          S.lc(nM, res, b1, {{Lk, S.diag(nalpha)}});
-          S.lc(nM, resc, b1, {{Lkc, S.diag(nalpha)}});
-          const size_t qr = S.gram_q(nM, res, 0, nc, resc, 0, nc, true);
-          r = S.fetch();
-          std::vector<double> keep(nc), take(nc);
-          for (int c = 0; c < nc; ++c) {
-            double beta = 1.0;
-            if (active[c]) {
-              beta = rr[c] > 0.0 ? r[qr + c] / rr[c] : 0.0;
-              rr[c] = r[qr + c];
-              steps[c]++;
-            }
-            keep[c] = active[c] ? beta : 1.0;
-            take[c] = active[c] ? 1.0 : 0.0;
-          }
-          const double *bk = S.coef(keep);
-          S.lc(nM, dk, bk, {{res, S.diag(take)}});
-          S.lc(nM, dkc, bk, {{resc, S.diag(take)}});
-          inner_total++;
+        done = true;
+        for (int c = 0; c < nc; ++c) done = done && r[qd + c] > 0.0;
+        if (!done) ++fallbacks;
+      }
+      if (!done) {
+        if (o.precond == TDDFT_PC_NONE) {
+          S.copy(nM, set(Lz), set(G));
+        } else {
+          inner_total += ksdiff_cg(S, h, set(G), set(Gc), set(Lz), set(Lres), set(Lresc), set(Ld),
+                                   set(Ldc), set(LHd), set(LHdc), set(Ltmp), o.eps_tol, o.max_inner);
         }
-        std::vector<double> fromz(nc), fromr(nc);
-        for (int c = 0; c < nc; ++c) {
-          fromz[c] = steps[c] > 0 ? 1.0 : 0.0;
-          fromr[c] = steps[c] > 0 ? 0.0 : 1.0;
-        }
-        S.lc(nM, set(Ltmp), nullptr, {{zk, S.diag(fromz)}, {set(G), S.diag(fromr)}});
-        S.copy(nM, zk, set(Ltmp));
       }
     } else {
     // ---- gradient with respect to L: r = mask_M(Pi^T(S^u g S^o))
     proj_t(set(Gc), set(Lr));
     // ---- preconditioner: CG on H_L z = r, H_L(X) = mask_M(Pi^T(S^u T(Pi X) S^o)),
     //      Euclidean inner product on M, per column
-    if (o.precond == TDDFT_PC_NONE) {
+    bool done = false;
+    if (o.precond == TDDFT_PC_LEARNED) {
+      block_scale<T>(nM, nc, h.E, cscale_m.p, set(Lr), set(Lz), s);
+      const size_t qd = S.gram_q(nM, set(Lz), 0, nc, set(Lr), 0, nc, true);
+      r = S.fetch();
+      done = true;
+      for (int c = 0; c < nc; ++c) done = done && r[qd + c] > 0.0;
+      if (!done) ++fallbacks;
+    }
+    if (done) {
+    } else if (o.precond == TDDFT_PC_NONE) {
       S.copy(nM, set(Lz), set(Lr));
     } else {
       T *res = set(Lres), *dk = set(Ld), *Hd = set(LHd), *zk = set(Lz);
@@ -766,12 +832,36 @@ static int solve_impl(Handle &h, int n, const tddft_options &o, double *omega, d
     st->converged = converged ? 1 : 0;
     st->inner_total = inner_total;
     st->applies = applies;
-    st->fallbacks = 0;
+    st->fallbacks = fallbacks;
     st->setup_ms = h.setup_ms;
     st->solve_ms = elapsed_ms();
     st->apply_ms = apply_ms;
   }
-  return converged ? TDDFT_OK : TDDFT_E_NO_CONVERGENCE;
+  if (!converged) return TDDFT_E_NO_CONVERGENCE;
+  return fallbacks > 0 ? TDDFT_W_FALLBACK : TDDFT_OK;
+}
+
+// Eq. precond alone, for n states in the C-ABI layout (complete M only)
+template <class T>
+static void precondition_impl(Handle &h, int n, const double *g, double *G, double eps_tol,
+                              int max_inner) {
+  TD_REQUIRE(h.m_complete, "tddft_precondition needs a complete M");
+  Solver<T> S(h, n);
+  const int nc = 2 * n;
+  enum { X, Xc, Z, RES, RESC, DK, DKC, LK, LKC, TMP, NS };
+  S.alloc_sets(NS, 0);
+  fill<T>(S.sets[X], (int64_t)S.elems(h.nR), T(0), h.stream);
+  pack<T>(h.nR, h.BU, h.BO, n, g, h.nnzR, h.r_voff.p, h.r_shape.p, S.sets[X], nc, 0, h.stream);
+  covariant_sets<T>(h, nc, S.sets[X], nc, 0, S.sets[Xc], nc, 0);
+  ksdiff_cg(S, h, S.sets[X], S.sets[Xc], S.sets[Z], S.sets[RES], S.sets[RESC], S.sets[DK],
+            S.sets[DKC], S.sets[LK], S.sets[LKC], S.sets[TMP], eps_tol, max_inner);
+  unpack<T>(h.nR, h.BU, h.BO, n, S.sets[Z], nc, 0, h.r_voff.p, h.r_shape.p, G, h.nnzR, h.stream);
+  S.sync();
+}
+
+void precondition(Handle &h, int n, const double *g, double *G, double eps_tol, int max_inner) {
+  if (h.precision == TDDFT_FP64) precondition_impl<double>(h, n, g, G, eps_tol, max_inner);
+  else precondition_impl<float>(h, n, g, G, eps_tol, max_inner);
 }
 
 int pcg_solve(Handle &h, int n, const tddft_options &o, double *omega, double *Pp, double *Pq,

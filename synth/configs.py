@@ -57,6 +57,17 @@ def batch(n_systems: int = 64):
     return [batch_member(i, int(a)) for i, a in enumerate(atoms)]
 
 
+def training_member(i: int, n_atoms: int = 100, seed0: int = 300000) -> Config:
+    """Training systems of the learned preconditioner: the density, radius and spacing of
+    `prec` (h = 0.3125 bohr) in a smaller cell, grid edge rounded to a multiple of 4."""
+    h = 0.3125
+    L = 40.0 * (n_atoms / 200.0) ** (1.0 / 3.0)
+    N = int(4 * round(L / (4 * h)))
+    return Config(name=f"train{i}", n_atoms=n_atoms, L=N * h, N=N, r_c=7.0,
+                  n_occ=_occ(n_atoms), n_vir=2 * _occ(n_atoms), R_K=None, R_M=None,
+                  n_states=8, seed=seed0 + i)
+
+
 def scale(n_atoms: int = 2000) -> Config:
     table = {500: (50.0, 160), 1000: (62.5, 200), 2000: (80.0, 256)}
     L, N = table[n_atoms]

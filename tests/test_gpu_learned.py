@@ -1,0 +1,222 @@
+"""GPU parity of the learned-preconditioner pieces against the FP64 oracle: block features,
+the projection of Eq. auxiliary, the CG preconditioner of Eq. precond, guess targets, the
+network's forward pass, gradients and Adam step, and solves with the learned scaling."""
+import numpy as np
+import pytest
+
+from helpers import gpu_handle, random_p, to_dev
+from oracle import learned as olearn
+from oracle.apply import Operator, response_pattern
+from oracle.casida import Casida
+from oracle.mlp import MLP, precond_loss
+from oracle.pcg import Options, Solver
+from synth import abi as sabi
+
+pytestmark = pytest.mark.gpu
+
+
+def _dense(s, t):
+    return sabi.p_to_dense(s, t.cpu().numpy())
+
+
+@pytest.mark.parametrize("name", ["small_dense", "small_odd", "small_trunc"])
+def test_block_features(name, request):
+    s = request.getfixturevalue(name)
+    h = gpu_handle(s, precision="fp64")
+    F = h.tddft_block_features().cpu().numpy().astype(np.float64)
+    h.close()
+    ref = olearn.block_features(s, response_pattern(s))
+    assert F.shape == ref.shape
+    assert np.max(np.abs(F - ref) / np.maximum(np.abs(ref), 1.0)) < 2e-6
+
+
+@pytest.mark.parametrize("name", ["small_dense", "small_trunc"])
+def test_project(name, request):
+    s = request.getfixturevalue(name)
+    op = Operator(s)
+    L = random_p(s, 3, 41)
+    ref = np.stack([op.project(x) for x in L])
+    h = gpu_handle(s, precision="fp64")
+    P = _dense(s, h.tddft_project(to_dev(sabi.dense_to_p(s, L))))
+    h.close()
+    assert np.max(np.abs(P - ref)) < 1e-11 * np.max(np.abs(ref))
+
+
+def test_precondition_matches_oracle_cg(small_dense):
+    """Same CG, same stopping rule: tight solves agree to the tolerance's order."""
+    s = small_dense
+    op = Operator(s)
+    g = np.stack([op.project(x) for x in random_p(s, 2, 43)])
+    solver = Solver(op, Options(n_states=2, eps_tol=1e-10, max_inner=500))
+    ref, _ = solver.precondition_p(g)
+    h = gpu_handle(s, precision="fp64")
+    G = _dense(s, h.tddft_precondition(to_dev(sabi.dense_to_p(s, g)), eps_tol=1e-10, max_inner=500))
+    h.close()
+    assert np.max(np.abs(G - ref)) < 1e-8 * np.max(np.abs(ref))
+
+
+def test_precondition_rejects_truncated_m(small_trunc):
+    from paper_1507_08157_amd import binding
+    h = gpu_handle(small_trunc, precision="fp64")
+    g = to_dev(np.zeros((1, h.nnz_p)))
+    with pytest.raises(binding.TddftError) as e:
+        h.tddft_precondition(g)
+    h.close()
+    assert e.value.code == binding.TDDFT_E_INVALID
+
+
+def test_guess_targets(small_odd):
+    s = small_odd
+    P = random_p(s, 3, 44)
+    h = gpu_handle(s, precision="fp64")
+    t = h.tddft_guess_targets(to_dev(sabi.dense_to_p(s, P))).cpu().numpy()
+    h.close()
+    ref = olearn.guess_target(s, P, response_pattern(s))
+    assert np.max(np.abs(t - ref)) < 1e-5
+
+
+def _oracle_net(params, n_in, width, n_out):
+    """The oracle network with the GPU's parameters, weights rounded to BF16 as the GPU
+    uses them."""
+    net = MLP(n_in, n_out, width=width)
+    sizes = [(n_in, width), (width,), (width, width), (width,), (width, n_out), (n_out,)]
+    out, o = [], 0
+    for k, sh in enumerate(sizes):
+        n = int(np.prod(sh))
+        v = params[o:o + n].astype(np.float64).reshape(sh)
+        out.append(olearn.bf16_round(v) if k % 2 == 0 else v)
+        o += n
+    net.params = out
+    return net
+
+
+def _net_inputs(seed, rows, n_in):
+    rng = np.random.default_rng(seed)
+    X = (rng.standard_normal((rows, n_in)) * rng.uniform(0.1, 5, n_in) + rng.uniform(-2, 2, n_in))
+    return X.astype(np.float32)
+
+
+def test_mlp_normalisation_forward_and_blob():
+    import torch
+    from paper_1507_08157_amd.binding import Mlp
+    n_in, width, n_out, rows = 30, 128, 7, 1000
+    X = _net_inputs(0, rows, n_in)
+    m = Mlp(n_in, width, n_out, seed=3)
+    Xd = torch.from_numpy(X).cuda()
+    m.fit_normalisation(Xd)
+    p, mu, sd = m.get_params(n_in)
+    X64 = X.astype(np.float64)
+    assert np.max(np.abs(mu - X64.mean(0)) / X64.std(0)) < 1e-6
+    assert np.max(np.abs(sd / X64.std(0) - 1)) < 1e-6
+    Y = m.forward(Xd, n_out).cpu().numpy()
+    net = _oracle_net(p, n_in, width, n_out)
+    ref, _ = net.forward((X64 - mu.astype(np.float64)) / sd.astype(np.float64))
+    assert np.max(np.abs(Y - ref)) < 1e-5 * np.max(np.abs(ref))
+    blob = m.export()
+    m2 = Mlp(blob=blob)
+    assert np.array_equal(m2.forward(Xd, n_out).cpu().numpy(), Y)
+    m.close()
+    m2.close()
+
+
+def test_mlp_gradient_and_adam_step():
+    import torch
+    from paper_1507_08157_amd.binding import Mlp
+    n_in, width, n_out, rows = 30, 64, 7, 1500
+    E = n_out - 1
+    rng = np.random.default_rng(7)
+    X = _net_inputs(1, rows, n_in)
+    g = rng.standard_normal((rows, E)).astype(np.float32)
+    gs = rng.standard_normal((rows, E)).astype(np.float32)
+    t = rng.standard_normal(rows).astype(np.float32)
+    m = Mlp(n_in, width, n_out, seed=5)
+    Xd = torch.from_numpy(X).cuda()
+    m.fit_normalisation(Xd)
+    p0, mu, sd = m.get_params(n_in)
+    lr, scale = 1e-3, 4.0
+    loss, grad = m.train_step(Xd, torch.from_numpy(g).cuda(), torch.from_numpy(gs).cuda(),
+                              torch.from_numpy(t).cuda(), loss_scale=scale, lr=lr, want_grad=True)
+    grad = grad.cpu().numpy().astype(np.float64)
+    p1, _, _ = m.get_params(n_in)
+    m.close()
+    net = _oracle_net(p0, n_in, width, n_out)
+    Xn = (X.astype(np.float64) - mu.astype(np.float64)) / sd.astype(np.float64)
+    y, cache = net.forward(Xn)
+    ref_loss, dy = precond_loss(y, g.astype(np.float64), gs.astype(np.float64),
+                                t.astype(np.float64), E, scale)
+    ref_grad = np.concatenate([x.ravel() for x in net.backward(cache, dy)])
+    assert abs(loss - ref_loss) < 1e-5 * abs(ref_loss)
+    assert np.max(np.abs(grad - ref_grad)) < 1e-4 * np.max(np.abs(ref_grad))
+    # first Adam step: m / (1 - b1) = g and v / (1 - b2) = g^2, so p moves by lr g / (|g| + eps)
+    step = lr * grad / (np.abs(grad) + 1e-8)
+    assert np.max(np.abs((p0.astype(np.float64) - p1) - step)) < 1e-3 * lr
+
+
+def _model_blob(s, seed, negate=False):
+    """A network with the system's feature and block sizes; its scaling head made strictly
+    positive (or strictly negative) by a large output bias."""
+    from paper_1507_08157_amd.binding import Mlp
+    h = gpu_handle(s, precision="fp64")
+    F = h.tddft_block_features()
+    h.close()
+    E = s.cfg.n_u * s.cfg.n_o
+    m = Mlp(F.shape[1], 32, E + 1, seed=seed)
+    m.fit_normalisation(F)
+    p, mu, sd = m.get_params(F.shape[1])
+    p[-(E + 1):-1] = -20.0 if negate else 20.0
+    p[-1] = 0.0
+    m.set_params(p)
+    blob = m.export()
+    m.close()
+    return blob
+
+
+@pytest.mark.parametrize("kind", ["positive", "negative"])
+def test_learned_solve_reaches_brute_force(small_dense, kind):
+    from paper_1507_08157_amd import binding
+    s = small_dense
+    n = s.cfg.n_states
+    blob = _model_blob(s, 11, negate=(kind == "negative"))
+    h = gpu_handle(s, precision="fp64")
+    o = binding.tddft_default_options(precond="learned", model=blob, tol_omega=1e-10, max_iter=300)
+    w, rc, st = h.tddft_pcg_solve(n, o)
+    h.close()
+    ref = Casida(s).omega_hermitian()[:n]
+    assert st["converged"] and np.max(np.abs(w - ref)) < 1e-9
+    if kind == "negative":
+        assert rc == binding.TDDFT_W_FALLBACK and st["fallbacks"] == st["iterations"]
+    else:
+        assert rc == binding.TDDFT_OK and st["fallbacks"] == 0
+
+
+def test_learned_solve_truncated_m_is_variational(small_odd):
+    """Truncated M (L-space branch) with a near-constant learned scaling, which is a weak
+    preconditioner there: every iterate stays above the Casida minimum (the truncated
+    auxiliary space of this system spans every KS pair) and the sum decreases."""
+    from paper_1507_08157_amd import binding
+    s = small_odd
+    n = s.cfg.n_states
+    blob = _model_blob(s, 12)
+    h = gpu_handle(s, precision="fp64")
+    o = binding.tddft_default_options(precond="learned", model=blob, tol_omega=1e-10, max_iter=60)
+    w, rc, st = h.tddft_pcg_solve(n, o, log_capacity=100)
+    h.close()
+    assert rc in (binding.TDDFT_OK, binding.TDDFT_E_NO_CONVERGENCE) and st["fallbacks"] == 0
+    sums = st["log_omega"].sum(axis=1)
+    exact = np.sum(Casida(s).omega_hermitian()[:n])
+    assert np.all(sums >= exact - 1e-10)
+    assert sums[-1] < sums[0] and np.all(np.diff(sums) <= 1e-12 * np.abs(sums[:-1]))
+
+
+def test_learned_model_shape_mismatch_is_rejected(small_dense):
+    from paper_1507_08157_amd import binding
+    from paper_1507_08157_amd.binding import Mlp
+    m = Mlp(30, 16, 5, seed=1)        # wrong output count for 3 x 2 blocks
+    blob = m.export()
+    m.close()
+    h = gpu_handle(small_dense, precision="fp64")
+    o = binding.tddft_default_options(precond="learned", model=blob)
+    with pytest.raises(binding.TddftError) as e:
+        h.tddft_pcg_solve(small_dense.cfg.n_states, o)
+    h.close()
+    assert e.value.code == binding.TDDFT_E_INVALID
