@@ -94,6 +94,9 @@ struct Plan {
   Pattern out;
   std::vector<int64_t> ptr;      // [nnzb_out + 1]
   std::vector<int32_t> pa, pb;   // block indices into the two operands
+  // when A, B and the output are all complete block patterns: their block counts
+  // (A: di x dk, B: dk x dj), else 0; the product is then a plain dense one
+  int di = 0, dk = 0, dj = 0;
 };
 
 // C = mask_out(A * B), symbolic only: pairs (iA, iB) with A[i,k], B[k,j], (i,j) in out
@@ -107,6 +110,7 @@ HostBsr host_transpose(const HostBsr &A);
 
 struct DevPlan {
   int64_t nout = 0, npairs = 0;
+  int di = 0, dk = 0, dj = 0;    // complete patterns (see Plan)
   DevBuf<int64_t> ptr;
   DevBuf<int2> pairs;
   void upload(const Plan &p, hipStream_t s);

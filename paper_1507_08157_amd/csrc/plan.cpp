@@ -121,6 +121,13 @@ Plan plan_product(const Pattern &A, const Pattern &B, const Pattern &out) {
       for (int64_t q = out.rowptr[i]; q < out.rowptr[i + 1]; ++q) omap[out.col[q]] = -1;
     }
   }
+  auto complete = [](const Pattern &P) { return P.nnzb() == (int64_t)P.nbr * P.nbc; };
+  if (complete(A) && complete(B) && complete(out) && out.nbr == A.nbr && out.nbc == B.nbc &&
+      A.nbc == B.nbr) {
+    p.di = A.nbr;
+    p.dk = A.nbc;
+    p.dj = B.nbc;
+  }
   return p;
 }
 
@@ -168,6 +175,9 @@ HostBsr host_transpose(const HostBsr &A) {
 void DevPlan::upload(const Plan &p, hipStream_t s) {
   nout = p.out.nnzb();
   npairs = (int64_t)p.pa.size();
+  di = p.di;
+  dk = p.dk;
+  dj = p.dj;
   ptr.upload(p.ptr, s);
   std::vector<int2> pr(npairs);
   for (int64_t i = 0; i < npairs; ++i) pr[i] = make_int2(p.pa[i], p.pb[i]);

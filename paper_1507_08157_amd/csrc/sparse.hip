@@ -13,6 +13,8 @@
 //  * Gram matrices sum_e X[.,i,e] Y[.,j,e] accumulated in FP64 (the traces Tr[X^T S Y S]
 //    of Secs. II.C and III.C once Y holds the covariant S^u Y S^o);
 //  * conversion between the C-ABI layout [state][values of M] and column sets.
+#include <type_traits>
+
 #include "internal.h"
 #include "kernels.h"
 
@@ -107,6 +109,132 @@ __global__ __launch_bounds__(256) void k_spmm_right(int64_t nout, int ncol,
   }
 }
 
+// ---------------------------------------------------------------------------------------
+// Dense path (FP32).  When both operands and the output of a masked product have complete
+// block patterns, the product is a plain dense matrix product; it runs on MFMA
+// (v_mfma_f32_16x16x4f32) with 64 x 64 output tiles per workgroup (4 waves, each 32 x 32
+// as 2 x 2 MFMA blocks) and k-slabs of 32 staged in LDS straight from the padded-block
+// layouts:
+//   left  C = A X:  A [di*BU x dk*BU] in BU x BU blocks, X a column set on dk x dj blocks;
+//                   rows (I, r), columns (J, m, c), k = (K, t)
+//   right C = X B:  X a column set on di x dk blocks, B [dk*BO x dj*BO] in BO x BO blocks;
+//                   rows (I, r, m), columns (J, c), k = (L, t)
+typedef float v4f __attribute__((ext_vector_type(4)));
+constexpr int GM = 64, GN = 64, GK = 32;
+
+template <int BU, int BO, bool LEFT>
+__global__ __launch_bounds__(256) void k_gemm_blocks(int di, int dk, int dj, int ncol,
+                                                     const float *__restrict__ A,
+                                                     const float *__restrict__ B, int ldx, int xc0,
+                                                     float *__restrict__ C, int ldc, int cc0,
+                                                     float alpha, int accumulate) {
+  constexpr int E = BU * BO;
+  __shared__ float As[GK][GM + 1];
+  __shared__ float Bs[GK][GN + 1];
+  const int M = LEFT ? di * BU : di * BU * ncol;
+  const int N = LEFT ? dj * ncol * BO : dj * BO;
+  const int K = LEFT ? dk * BU : dk * BO;
+  const int i0 = blockIdx.y * GM, n0 = blockIdx.x * GN;
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int64_t ldxE = (int64_t)ldx * E, ldcE = (int64_t)ldc * E;
+  // row part of an A address, k part of an A address, column / k parts of a B address
+  auto rowA = [&](int i) -> int64_t {
+    if (LEFT) return (int64_t)(i / BU) * dk * (BU * BU) + (i % BU) * BU;
+    const int I = i / (BU * ncol), rem = i - I * (BU * ncol), r = rem / ncol, m = rem - r * ncol;
+    return ((int64_t)I * dk * ldx + xc0 + m) * E + r * BO;
+  };
+  auto kA = [&](int k) -> int64_t {
+    if (LEFT) return (int64_t)(k / BU) * (BU * BU) + k % BU;
+    return (int64_t)(k / BO) * ldxE + k % BO;
+  };
+  auto colB = [&](int n) -> int64_t {
+    if (LEFT) {
+      const int J = n / (ncol * BO), rem = n - J * (ncol * BO), m = rem / BO, c = rem - m * BO;
+      return ((int64_t)J * ldx + xc0 + m) * E + c;
+    }
+    return (int64_t)(n / BO) * (BO * BO) + n % BO;
+  };
+  auto kB = [&](int k) -> int64_t {
+    if (LEFT) return (int64_t)(k / BU) * dj * ldxE + (k % BU) * BO;
+    return (int64_t)(k / BO) * dj * (BO * BO) + (k % BO) * BO;
+  };
+  // A tile: thread -> k = tid % GK, rows tid / GK + 8 q; B tile: n = tid % GN, k = tid / GN + 4 q
+  const int ak = tid % GK, ar = tid / GK;
+  int64_t arow[8];
+  bool aval[8];
+#pragma unroll
+  for (int q = 0; q < 8; ++q) {
+    const int i = i0 + ar + 8 * q;
+    aval[q] = i < M;
+    arow[q] = aval[q] ? rowA(i) : 0;
+  }
+  const int bnl = tid % GN, bkl = tid / GN;
+  const bool bval = n0 + bnl < N;
+  const int64_t bcol = bval ? colB(n0 + bnl) : 0;
+  const int wm = (w >> 1) * 32, wn = (w & 1) * 32;
+  v4f acc[2][2];
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b) acc[a][b] = v4f{0.f, 0.f, 0.f, 0.f};
+  for (int k0 = 0; k0 < K; k0 += GK) {
+    {
+      const int k = k0 + ak;
+      const bool kv = k < K;
+      const int64_t kp = kv ? kA(k) : 0;
+#pragma unroll
+      for (int q = 0; q < 8; ++q) As[ak][ar + 8 * q] = (kv && aval[q]) ? A[arow[q] + kp] : 0.0f;
+    }
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      const int kl = bkl + 4 * q, k = k0 + kl;
+      Bs[kl][bnl] = (k < K && bval) ? B[bcol + kB(k)] : 0.0f;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int kk = 0; kk < GK; kk += 4) {
+      const int kr = kk + (lane >> 4), c16 = lane & 15;
+      const float a0 = As[kr][wm + c16], a1 = As[kr][wm + 16 + c16];
+      const float b0 = Bs[kr][wn + c16], b1 = Bs[kr][wn + 16 + c16];
+      acc[0][0] = __builtin_amdgcn_mfma_f32_16x16x4f32(a0, b0, acc[0][0], 0, 0, 0);
+      acc[0][1] = __builtin_amdgcn_mfma_f32_16x16x4f32(a0, b1, acc[0][1], 0, 0, 0);
+      acc[1][0] = __builtin_amdgcn_mfma_f32_16x16x4f32(a1, b0, acc[1][0], 0, 0, 0);
+      acc[1][1] = __builtin_amdgcn_mfma_f32_16x16x4f32(a1, b1, acc[1][1], 0, 0, 0);
+    }
+    __syncthreads();
+  }
+  // D of 16x16x4: lane holds column lane % 16, rows 4 (lane / 16) + j
+#pragma unroll
+  for (int nb = 0; nb < 2; ++nb) {
+    const int n = n0 + wn + nb * 16 + (lane & 15);
+    if (n >= N) continue;
+    int64_t ccol;
+    if (LEFT) {
+      const int J = n / (ncol * BO), rem = n - J * (ncol * BO), m = rem / BO, c = rem - m * BO;
+      ccol = ((int64_t)J * ldc + cc0 + m) * E + c;
+    } else {
+      ccol = (int64_t)(n / BO) * ldcE + n % BO;
+    }
+#pragma unroll
+    for (int mb = 0; mb < 2; ++mb)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int i = i0 + wm + mb * 16 + 4 * (lane >> 4) + j;
+        if (i >= M) continue;
+        int64_t crow;
+        if (LEFT) {
+          crow = (int64_t)(i / BU) * dj * ldcE + (i % BU) * BO;
+        } else {
+          const int I = i / (BU * ncol), rem = i - I * (BU * ncol), r = rem / ncol, m = rem - r * ncol;
+          crow = ((int64_t)I * dj * ldc + cc0 + m) * E + r * BO;
+        }
+        float *cp = C + crow + ccol;
+        const float v = alpha * acc[mb][nb][j];
+        *cp = accumulate ? *cp + v : v;
+      }
+  }
+}
+
 #define TD_BDIM_DISPATCH(BU_, BO_, ...)                                     \
   do {                                                                     \
     if (BU_ == 3 && BO_ == 2) { constexpr int BU = 3, BO = 2; __VA_ARGS__; } \
@@ -123,6 +251,16 @@ template <class T>
 void spmm_left(const DevPlan &pl, int bu, int bo, const T *A, const T *X, int ldx, int xc0,
                T *C, int ldc, int cc0, int ncol, double alpha, bool acc, hipStream_t s) {
   if (pl.nout == 0 || ncol == 0) return;
+  if constexpr (std::is_same<T, float>::value) {
+    if (pl.di > 0) {
+      const dim3 grid((unsigned)((pl.dj * ncol * bo + GN - 1) / GN), (unsigned)((pl.di * bu + GM - 1) / GM));
+      TD_BDIM_DISPATCH(bu, bo, hipLaunchKernelGGL((k_gemm_blocks<BU, BO, true>), grid, dim3(256), 0, s,
+                                                  pl.di, pl.dk, pl.dj, ncol, A, X, ldx, xc0, C, ldc,
+                                                  cc0, (float)alpha, acc ? 1 : 0));
+      TD_HIP(hipGetLastError());
+      return;
+    }
+  }
   const int64_t n = pl.nout * ncol;
   TD_BDIM_DISPATCH(bu, bo, hipLaunchKernelGGL((k_spmm_left<T, BU, BO>), dim3(nblocks(n, 256)),
                                               dim3(256), 0, s, pl.nout, ncol, pl.ptr.p,
@@ -135,6 +273,16 @@ template <class T>
 void spmm_right(const DevPlan &pl, int bu, int bo, const T *X, int ldx, int xc0, const T *B,
                 T *C, int ldc, int cc0, int ncol, double alpha, bool acc, hipStream_t s) {
   if (pl.nout == 0 || ncol == 0) return;
+  if constexpr (std::is_same<T, float>::value) {
+    if (pl.di > 0) {
+      const dim3 grid((unsigned)((pl.dj * bo + GN - 1) / GN), (unsigned)((pl.di * bu * ncol + GM - 1) / GM));
+      TD_BDIM_DISPATCH(bu, bo, hipLaunchKernelGGL((k_gemm_blocks<BU, BO, false>), grid, dim3(256), 0, s,
+                                                  pl.di, pl.dk, pl.dj, ncol, X, B, ldx, xc0, C, ldc,
+                                                  cc0, (float)alpha, acc ? 1 : 0));
+      TD_HIP(hipGetLastError());
+      return;
+    }
+  }
   const int64_t n = pl.nout * ncol;
   TD_BDIM_DISPATCH(bu, bo, hipLaunchKernelGGL((k_spmm_right<T, BU, BO>), dim3(nblocks(n, 256)),
                                               dim3(256), 0, s, pl.nout, ncol, pl.ptr.p,
