@@ -184,6 +184,56 @@ def cpu_baseline(sysm):
                       f"logical CPUs, BLAS limited to 1 thread)"}
 
 
+def _gen_batch_member(args):
+    from synth import build_system, configs
+    i, atoms = args
+    s = build_system(configs.batch_member(i, atoms))
+    from synth import abi as sabi
+    return s.cfg.n_atoms, s.cfg.N, s.cfg.n_states, sabi.system_arrays(s)
+
+
+def generate_batch(k):
+    """The first K systems of the batch workload, generated by worker processes.  Called
+    before anything touches the GPU, so the workers are forked from a process without a
+    GPU context."""
+    import concurrent.futures as cf
+    import multiprocessing as mp
+    from synth import configs
+    members = [(i, c.n_atoms) for i, c in enumerate(configs.batch(64))][:k]
+    t0 = time.perf_counter()
+    with cf.ProcessPoolExecutor(max_workers=min(16, os.cpu_count() or 1),
+                                mp_context=mp.get_context("fork")) as ex:
+        systems = list(ex.map(_gen_batch_member, members))
+    log(f"batch: {k} systems generated in {time.perf_counter() - t0:.1f} s")
+    return systems
+
+
+def batch_solves(systems, precision="fp32"):
+    """Sequential plain solves of the given systems against one batched call, handle set-up
+    excluded from both."""
+    import torch
+    from paper_1507_08157_amd import binding
+    k = len(systems)
+    o = binding.tddft_default_options(precision=precision, tol_omega=1e-7, max_iter=300)
+    hs = [binding.tddft_create(arr, precision=precision) for (_, _, _, arr) in systems]
+    ns = [n for (_, _, n, _) in systems]
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    seq = [h.tddft_pcg_solve(n, o) for h, n in zip(hs, ns)]
+    t_seq = time.perf_counter() - t1
+    t2 = time.perf_counter()
+    bat = binding.tddft_pcg_solve_batched(hs, ns, o)
+    t_bat = time.perf_counter() - t2
+    same = all(np.array_equal(a[0], b[0]) for a, b in zip(seq, bat))
+    for h in hs:
+        h.close()
+    return {"systems": k, "atoms": [a for (a, _, _, _) in systems],
+            "grids": [g for (_, g, _, _) in systems], "states": ns[0], "precision": precision,
+            "sequential_s": round(t_seq, 3), "batched_s": round(t_bat, 3),
+            "speedup": round(t_seq / t_bat, 3), "identical_results": bool(same),
+            "converged": int(sum(1 for b in bat if b[2]["converged"]))}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -194,11 +244,16 @@ def main():
     ap.add_argument("--no-solve", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MiB")
+    ap.add_argument("--batch", type=int, default=0, metavar="K",
+                    help="also time K systems of the batch workload solved one after another "
+                         "and through tddft_pcg_solve_batched")
     a = ap.parse_args()
     if a.gpus != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path (the sharding "
               "design is described in DESIGN.md); run with --gpus 1", file=sys.stderr)
         sys.exit(2)
+
+    batch_systems = generate_batch(a.batch) if a.batch > 0 else None
 
     import torch
     from paper_1507_08157_amd import binding
@@ -277,26 +332,45 @@ def main():
         w64, rc64, st64 = h64.tddft_pcg_solve(n, o, P1, P2, log_capacity=2000)
         log(f"fp64 PCG: rc={rc64} iters={st64['iterations']} {st64['solve_ms']:.0f} ms "
             f"omega={np.array2string(w64, precision=8)}")
-        solves = {"fp64": {"iterations": st64["iterations"], "solve_s": st64["solve_ms"] / 1e3,
+        solves = {"fp64_cg": {"iterations": st64["iterations"], "solve_s": st64["solve_ms"] / 1e3,
                            "time_to_1e-5_s": time_to_omega(st64, w64),
                            "converged": st64["converged"]}}
-        for mode in [m for m in ("fp32", "bf16") if m != "fp64"]:
-            hm = h if mode == a.precision else binding.tddft_create(arrays, precision=mode)
-            o = binding.tddft_default_options(precision=mode, tol_omega=1e-8, max_iter=300)
+        model_path = os.path.join(os.path.dirname(os.path.abspath(__file__)),
+                                  "paper_1507_08157_amd", "precond_model.bin")
+        model = open(model_path, "rb").read() if os.path.exists(model_path) else None
+        handles = {}
+        # mixed precision with each preconditioner: Eq. precond by CG, none, learned
+        runs = [("fp32_cg", "fp32", "cg"), ("fp32_none", "fp32", "none"),
+                ("bf16_cg", "bf16", "cg")]
+        if model is not None:
+            runs.insert(2, ("fp32_learned", "fp32", "learned"))
+        for key, mode, pc in runs:
+            if mode not in handles:
+                handles[mode] = h if mode == a.precision else binding.tddft_create(arrays, precision=mode)
+            hm = handles[mode]
+            kw = dict(precision=mode, precond=pc, tol_omega=1e-8, max_iter=300)
+            if pc == "learned":
+                kw["model"] = model
+            o = binding.tddft_default_options(**kw)
             P1, P2 = L0.clone(), L0.clone()
             w, rc, st = hm.tddft_pcg_solve(n, o, P1, P2, log_capacity=2000)
             err = float(np.max(np.abs(w - w64)))
-            solves[mode] = {"iterations": st["iterations"], "solve_s": st["solve_ms"] / 1e3,
-                            "time_to_1e-5_s": time_to_omega(st, w64),
-                            "omega_err_vs_fp64_Ha": err}
-            log(f"{mode} PCG: rc={rc} iters={st['iterations']} {st['solve_ms']:.0f} ms "
+            solves[key] = {"iterations": st["iterations"], "solve_s": st["solve_ms"] / 1e3,
+                           "time_to_1e-5_s": time_to_omega(st, w64),
+                           "omega_err_vs_fp64_Ha": err, "fallbacks": st["fallbacks"]}
+            log(f"{key} PCG: rc={rc} iters={st['iterations']} {st['solve_ms']:.0f} ms "
                 f"err={err:.2e}")
+        for mode, hm in handles.items():
             if hm is not h:
                 hm.close()
         out["time_to_omega"] = solves
         out["omega_fp64"] = [float(x) for x in w64]
         if h64 is not h:
             h64.close()
+
+    if a.batch > 0:
+        out["batch"] = batch_solves(batch_systems)
+        log(f"batch: {out['batch']}")
 
     if not a.no_cpu_baseline:
         log("cpu baseline (oracle, one state) ...")

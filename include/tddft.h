@@ -217,6 +217,23 @@ int tddft_apply(tddft_handle *h, int32_t n_states, const double *Pp, const doubl
 int tddft_pcg_solve(tddft_handle *h, int32_t n_states, const tddft_options *opts,
                     double *omega, double *Pp, double *Pq, tddft_stats *stats);
 
+/* Solves of several systems at once (a work queue over systems): up to max_workers host
+ * threads (0 = one per system, at most 16) each take the next unsolved system and run
+ * tddft_pcg_solve on it on a private non-blocking stream of the handle's GPU, so the
+ * kernels and host round trips of different systems overlap.  hs[k], n_states[k],
+ * omega[k] (HOST [n_states[k]]), Pp[k] / Pq[k] (DEVICE or NULL; Pp and Pq may themselves
+ * be NULL) and stats[k] (or stats NULL) are the per-system arguments of tddft_pcg_solve;
+ * opts (or NULL for each handle's create options) is shared.  status[k] (HOST) receives
+ * each system's return code; the call returns TDDFT_OK when every system was attempted
+ * (check status), TDDFT_E_INVALID on bad arguments.  Results are identical to solving
+ * the systems one after another.  Distinct handles only; no handle may be used by
+ * another thread during the call.  The private streams are not ordered after other work:
+ * device inputs must be complete (e.g. the device synchronised) before the call. */
+int tddft_pcg_solve_batched(tddft_handle *const *hs, int32_t n_sys, const int32_t *n_states,
+                            const tddft_options *opts, double *const *omega, double *const *Pp,
+                            double *const *Pq, tddft_stats *stats, int32_t *status,
+                            int32_t max_workers);
+
 void tddft_destroy(tddft_handle *h);
 
 /* ---- building blocks of the solver, exposed for training and testing -------------------- */

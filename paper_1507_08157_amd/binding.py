@@ -88,7 +88,7 @@ EXPORTS = ("tddft_default_options", "tddft_create", "tddft_nnz_p", "tddft_respon
            "tddft_mlp_create", "tddft_mlp_destroy", "tddft_mlp_n_params", "tddft_mlp_set_params",
            "tddft_mlp_get_params", "tddft_mlp_fit_normalisation", "tddft_mlp_forward",
            "tddft_mlp_train_step", "tddft_mlp_export", "tddft_mlp_import",
-           "tddft_mlp_last_error")
+           "tddft_mlp_last_error", "tddft_pcg_solve_batched")
 
 
 def lib():
@@ -152,7 +152,11 @@ def lib():
                                           C.c_double, C.POINTER(C.c_double), vp], C.c_int),
                 ("tddft_mlp_export", [vp, vp, C.c_int64, C.POINTER(C.c_int64)], C.c_int),
                 ("tddft_mlp_import", [vp, C.c_int64, vp, C.POINTER(C.c_void_p)], C.c_int),
-                ("tddft_mlp_last_error", [vp], C.c_char_p)):
+                ("tddft_mlp_last_error", [vp], C.c_char_p),
+                ("tddft_pcg_solve_batched", [C.POINTER(C.c_void_p), C.c_int32, _i32p,
+                                             C.POINTER(tddft_options), C.POINTER(_f64p),
+                                             C.POINTER(C.c_void_p), C.POINTER(C.c_void_p),
+                                             C.POINTER(tddft_stats), _i32p, C.c_int32], C.c_int)):
             f = getattr(L, name)
             f.argtypes = args
             f.restype = res
@@ -381,6 +385,36 @@ class Handle:
             stats["log_time_ms"] = logs["t"][:k]
             stats["log_gnorm"] = logs["g"][:k]
         return omega, rc, stats
+
+
+def tddft_pcg_solve_batched(handles, n_states, options=None, Pp=None, Pq=None,
+                            max_workers=0):
+    """Solve several systems concurrently; returns [(omega, status, stats dict)] per system.
+    Pp / Pq: None or lists of device tensors (per-system initial and returned vectors)."""
+    import torch
+    n = len(handles)
+    hs = (C.c_void_p * n)(*[h._h for h in handles])
+    ns = np.ascontiguousarray(n_states, dtype=np.int32)
+    omegas = [np.zeros(int(k)) for k in ns]
+    om = (_f64p * n)(*[_ptr(w, C.c_double) for w in omegas])
+    pp = (C.c_void_p * n)(*[_dev(t, "Pp").value for t in Pp]) if Pp is not None else None
+    pq = (C.c_void_p * n)(*[_dev(t, "Pq").value for t in Pq]) if Pq is not None else None
+    st = (tddft_stats * n)()
+    status = np.zeros(n, dtype=np.int32)
+    opt = C.byref(options) if options is not None else None
+    torch.cuda.synchronize()
+    rc = lib().tddft_pcg_solve_batched(hs, n, _ptr(ns, C.c_int32), opt, om, pp, pq, st,
+                                       _ptr(status, C.c_int32), int(max_workers))
+    if rc != TDDFT_OK:
+        raise TddftError(rc, "tddft_pcg_solve_batched: invalid arguments")
+    out = []
+    for k in range(n):
+        s = st[k]
+        out.append((omegas[k], int(status[k]),
+                    dict(iterations=s.iterations, converged=bool(s.converged),
+                         inner_total=s.inner_total, applies=s.applies, fallbacks=s.fallbacks,
+                         setup_ms=s.setup_ms, solve_ms=s.solve_ms, apply_ms=s.apply_ms)))
+    return out
 
 
 def tddft_profile_stage_name(k: int):

@@ -1,6 +1,9 @@
 // C-ABI entry points of libtddft: argument checks, error conversion, dispatch on the
 // handle's precision.  No exception crosses this boundary.
+#include <atomic>
 #include <new>
+#include <set>
+#include <thread>
 
 #include "handle.h"
 #include "learned.h"
@@ -227,6 +230,53 @@ int tddft_pcg_solve(tddft_handle *hd, int32_t n, const tddft_options *opts, doub
     h.last_error = "host allocation failed";
     return TDDFT_E_NOMEM;
   }
+}
+
+int tddft_pcg_solve_batched(tddft_handle *const *hs, int32_t n_sys, const int32_t *n_states,
+                            const tddft_options *opts, double *const *omega, double *const *Pp,
+                            double *const *Pq, tddft_stats *stats, int32_t *status,
+                            int32_t max_workers) {
+  if (!hs || n_sys < 0 || !n_states || !omega || !status || max_workers < 0) return TDDFT_E_INVALID;
+  {
+    std::set<const tddft_handle *> seen;
+    for (int k = 0; k < n_sys; ++k)
+      if (!hs[k] || !seen.insert(hs[k]).second) return TDDFT_E_INVALID;
+  }
+  const int workers = std::max(1, std::min<int>(n_sys, max_workers > 0 ? max_workers : 16));
+  std::atomic<int> next{0};
+  auto work = [&]() {
+    hipStream_t st = nullptr;
+    int dev = -1;
+    for (int k = next++; k < n_sys; k = next++) {
+      Handle &h = hs[k]->h;
+      if (h.device != dev) {
+        if (st) (void)hipStreamDestroy(st);
+        st = nullptr;
+        dev = h.device;
+        if (hipSetDevice(dev) != hipSuccess || hipStreamCreateWithFlags(&st, hipStreamNonBlocking) != hipSuccess) {
+          h.last_error = "tddft_pcg_solve_batched: stream creation failed";
+          status[k] = TDDFT_E_DEVICE;
+          st = nullptr;
+          dev = -1;
+          continue;
+        }
+      }
+      hipStream_t saved = h.stream;
+      h.stream = st;
+      tddft_options o = opts ? *opts : h.opts;
+      o.stream = st;
+      status[k] = tddft_pcg_solve(hs[k], n_states[k], &o, omega[k], Pp ? Pp[k] : nullptr,
+                                  Pq ? Pq[k] : nullptr, stats ? &stats[k] : nullptr);
+      (void)hipStreamSynchronize(st);
+      h.stream = saved;
+    }
+    if (st) (void)hipStreamDestroy(st);
+  };
+  std::vector<std::thread> pool;
+  for (int t = 1; t < workers; ++t) pool.emplace_back(work);
+  work();
+  for (auto &t : pool) t.join();
+  return TDDFT_OK;
 }
 
 void tddft_destroy(tddft_handle *h) { delete h; }
