@@ -15,6 +15,7 @@
 // Grid fields are tile-major complex pairs: state 2k in the real part, 2k+1 in the
 // imaginary part of field k, so the Hartree FFT transforms two states at once.
 #include <algorithm>
+#include <type_traits>
 
 #include "internal.h"
 #include "kernels.h"
@@ -249,6 +250,92 @@ __global__ __launch_bounds__(256) void k_vint(DevTiles tl, const int64_t *__rest
   }
 }
 
+// FP32 variant on MFMA.  Per tile the integrals are a small matrix product
+//   Out[a][(b, s)] = sum_r u_a(r) w_(b,s)(r),   w_(b,s)(r) = o_b(r) V_s(r),
+// with the 64 points as the contraction.  One wave per tile runs it as 16 x 16 output
+// blocks of v_mfma_f32_16x16x4f32; the sum over points is order-free, so lane group
+// q = lane / 16 takes points 16 q .. 16 q + 15 and every operand fragment is a run of 16
+// consecutive samples (wide loads).  Up to 48 u-rows of A stay in registers while the
+// (o-row, state) blocks stream by.
+typedef float v4f __attribute__((ext_vector_type(4)));
+
+template <class S>
+__device__ __forceinline__ void load16(const S *p, float (&o)[16]) {
+#pragma unroll
+  for (int k = 0; k < 16; k += 4) {
+    float t[4];
+    load4<float, S>(p + k, t);
+    o[k] = t[0]; o[k + 1] = t[1]; o[k + 2] = t[2]; o[k + 3] = t[3];
+  }
+}
+
+template <class S, int BL, int BR>
+__global__ __launch_bounds__(256) void k_vint_mfma(DevTiles tl, const int64_t *__restrict__ tbase,
+                                                   const S *__restrict__ usamp,
+                                                   const S *__restrict__ osamp,
+                                                   const float *__restrict__ V, int64_t pair_stride,
+                                                   int ns, float *__restrict__ partial, float scale) {
+  const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  const int t = blockIdx.x * (blockDim.x >> 6) + w;
+  if (t >= tl.nt) return;
+  const int u0 = tl.uptr[t], nua = tl.uptr[t + 1] - u0;
+  const int o0 = tl.optr[t], noa = tl.optr[t + 1] - o0;
+  const int rows_u = nua * BL, rows_o = noa * BR;
+  const int items = rows_o * ns;
+  const int q = lane >> 4, c16 = lane & 15;
+  float *dst = partial + tbase[t] * ns;
+  const float *vt = V + (int64_t)t * TP * 2;
+  const S *ut = usamp + (int64_t)u0 * BL * TP;
+  const S *ot = osamp + (int64_t)o0 * BR * TP;
+  for (int mg = 0; mg < rows_u; mg += 48) {
+    float a[3][16];
+#pragma unroll
+    for (int mb = 0; mb < 3; ++mb) {
+      const int m = mg + mb * 16 + c16;
+      if (m < rows_u) {
+        load16<S>(ut + (int64_t)m * TP + 16 * q, a[mb]);
+      } else {
+#pragma unroll
+        for (int k = 0; k < 16; ++k) a[mb][k] = 0.0f;
+      }
+    }
+    for (int n0 = 0; n0 < items; n0 += 16) {
+      const int n = n0 + c16;
+      const bool active = n < items;
+      const int b = active ? n / ns : 0;
+      const int sidx = active ? n - (n / ns) * ns : 0;
+      float bf[16];
+      {
+        float o[16];
+        load16<S>(ot + (int64_t)b * TP + 16 * q, o);
+        const float *vs = vt + (int64_t)(sidx >> 1) * pair_stride + 32 * q;
+#pragma unroll
+        for (int k = 0; k < 16; k += 2) {
+          float v0, v1;
+          load_comp2<float>(vs + 2 * k, sidx & 1, v0, v1);
+          bf[k] = active ? o[k] * v0 : 0.0f;
+          bf[k + 1] = active ? o[k + 1] * v1 : 0.0f;
+        }
+      }
+#pragma unroll
+      for (int mb = 0; mb < 3; ++mb) {
+        if (mg + mb * 16 >= rows_u) break;
+        v4f acc = {0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+        for (int k = 0; k < 16; ++k) acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a[mb][k], bf[k], acc, 0, 0, 0);
+        if (active) {
+#pragma unroll
+          for (int j = 0; j < 4; ++j) {
+            const int m = mg + mb * 16 + 4 * q + j;
+            if (m < rows_u) dst[(int64_t)m * items + n] = scale * acc[j];
+          }
+        }
+      }
+    }
+  }
+}
+
 // Vout[ob][ldv][E] (columns 0..ns) = sum over the contributions of block ob.  One wave
 // per overlap block, one lane per (element, state); the contribution offsets are
 // wave-uniform (scalar loads) and four contributions are in flight at a time, summed in a
@@ -332,7 +419,11 @@ void potential_integrals(const DevTiles &tl, const DevPartials &pa, int stype, i
   const int E = BL * BR;
   if (prof) prof->begin(ST_VINT, s);
   const unsigned grid = (unsigned)((tl.nt + 3) / 4);
-  TD_SAMPLE(T, stype, TD_GRID_BDIM(BL, BR, hipLaunchKernelGGL((k_vint<T, S, BL, BR>), dim3(grid), dim3(256), 0, s, tl, pa.tbase, reinterpret_cast<const S *>(tl.usamp), reinterpret_cast<const S *>(tl.osamp), V, pair_stride, ns, partial, (T)scale)));
+  if constexpr (std::is_same<T, float>::value) {
+    TD_SAMPLE(T, stype, TD_GRID_BDIM(BL, BR, hipLaunchKernelGGL((k_vint_mfma<S, BL, BR>), dim3(grid), dim3(256), 0, s, tl, pa.tbase, reinterpret_cast<const S *>(tl.usamp), reinterpret_cast<const S *>(tl.osamp), V, pair_stride, ns, partial, (float)scale)));
+  } else {
+    TD_SAMPLE(T, stype, TD_GRID_BDIM(BL, BR, hipLaunchKernelGGL((k_vint<T, S, BL, BR>), dim3(grid), dim3(256), 0, s, tl, pa.tbase, reinterpret_cast<const S *>(tl.usamp), reinterpret_cast<const S *>(tl.osamp), V, pair_stride, ns, partial, (T)scale)));
+  }
   TD_HIP(hipGetLastError());
   if (prof) prof->end(ST_VINT, s);
   if (nblk_out == 0) return;
