@@ -275,19 +275,39 @@ __global__ __launch_bounds__(256) void k_vint_mfma(DevTiles tl, const int64_t *_
                                                    const S *__restrict__ osamp,
                                                    const float *__restrict__ V, int64_t pair_stride,
                                                    int ns, float *__restrict__ partial, float scale) {
+  extern __shared__ unsigned char lds_raw[];
+  constexpr int LD = TP + 4;   // padded rows: the 16-byte reads of different rows use different banks
   const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
   const int t = blockIdx.x * (blockDim.x >> 6) + w;
-  if (t >= tl.nt) return;
-  const int u0 = tl.uptr[t], nua = tl.uptr[t + 1] - u0;
-  const int o0 = tl.optr[t], noa = tl.optr[t + 1] - o0;
+  float *lo = reinterpret_cast<float *>(lds_raw) + (size_t)w * (tl.maxrows_r + ns) * LD;
+  float *lv = lo + (size_t)tl.maxrows_r * LD;
+  int u0 = 0, nua = 0, o0 = 0, noa = 0;
+  if (t < tl.nt) {
+    u0 = tl.uptr[t];
+    nua = tl.uptr[t + 1] - u0;
+    o0 = tl.optr[t];
+    noa = tl.optr[t + 1] - o0;
+  }
   const int rows_u = nua * BL, rows_o = noa * BR;
   const int items = rows_o * ns;
+  // stage the tile's o-rows and the states' potentials (real states, de-interleaved)
+  {
+    const S *ot = osamp + (int64_t)o0 * BR * TP;
+    for (int i = lane; i < rows_o * TP; i += 64) lo[(i / TP) * LD + (i % TP)] = cvt<float>(ot[i]);
+    if (t < tl.nt) {
+      const float *vt = V + (int64_t)t * TP * 2;
+      for (int i = lane; i < ns * TP; i += 64) {
+        const int sidx = i / TP, p = i % TP;
+        lv[sidx * LD + p] = vt[(int64_t)(sidx >> 1) * pair_stride + 2 * p + (sidx & 1)];
+      }
+    }
+  }
+  __syncthreads();
+  if (t >= tl.nt) return;
   const int q = lane >> 4, c16 = lane & 15;
   float *dst = partial + tbase[t] * ns;
-  const float *vt = V + (int64_t)t * TP * 2;
   const S *ut = usamp + (int64_t)u0 * BL * TP;
-  const S *ot = osamp + (int64_t)o0 * BR * TP;
   for (int mg = 0; mg < rows_u; mg += 48) {
     float a[3][16];
 #pragma unroll
@@ -307,15 +327,16 @@ __global__ __launch_bounds__(256) void k_vint_mfma(DevTiles tl, const int64_t *_
       const int sidx = active ? n - (n / ns) * ns : 0;
       float bf[16];
       {
-        float o[16];
-        load16<S>(ot + (int64_t)b * TP + 16 * q, o);
-        const float *vs = vt + (int64_t)(sidx >> 1) * pair_stride + 32 * q;
+        const float *orow = lo + b * LD + 16 * q;
+        const float *vrow = lv + sidx * LD + 16 * q;
 #pragma unroll
-        for (int k = 0; k < 16; k += 2) {
-          float v0, v1;
-          load_comp2<float>(vs + 2 * k, sidx & 1, v0, v1);
-          bf[k] = active ? o[k] * v0 : 0.0f;
-          bf[k + 1] = active ? o[k + 1] * v1 : 0.0f;
+        for (int k = 0; k < 16; k += 4) {
+          const float4 o4 = *reinterpret_cast<const float4 *>(orow + k);
+          const float4 v4 = *reinterpret_cast<const float4 *>(vrow + k);
+          bf[k] = active ? o4.x * v4.x : 0.0f;
+          bf[k + 1] = active ? o4.y * v4.y : 0.0f;
+          bf[k + 2] = active ? o4.z * v4.z : 0.0f;
+          bf[k + 3] = active ? o4.w * v4.w : 0.0f;
         }
       }
 #pragma unroll
@@ -420,7 +441,9 @@ void potential_integrals(const DevTiles &tl, const DevPartials &pa, int stype, i
   if (prof) prof->begin(ST_VINT, s);
   const unsigned grid = (unsigned)((tl.nt + 3) / 4);
   if constexpr (std::is_same<T, float>::value) {
-    TD_SAMPLE(T, stype, TD_GRID_BDIM(BL, BR, hipLaunchKernelGGL((k_vint_mfma<S, BL, BR>), dim3(grid), dim3(256), 0, s, tl, pa.tbase, reinterpret_cast<const S *>(tl.usamp), reinterpret_cast<const S *>(tl.osamp), V, pair_stride, ns, partial, (float)scale)));
+    const size_t lds = 4 * (size_t)(tl.maxrows_r + ns) * (TP + 4) * sizeof(float);
+    if (lds > tl.lds_limit) throw Error{TDDFT_E_INVALID, "too many functions per grid tile for the LDS budget"};
+    TD_SAMPLE(T, stype, TD_GRID_BDIM(BL, BR, hipLaunchKernelGGL((k_vint_mfma<S, BL, BR>), dim3(grid), dim3(256), lds, s, tl, pa.tbase, reinterpret_cast<const S *>(tl.usamp), reinterpret_cast<const S *>(tl.osamp), V, pair_stride, ns, partial, (float)scale)));
   } else {
     TD_SAMPLE(T, stype, TD_GRID_BDIM(BL, BR, hipLaunchKernelGGL((k_vint<T, S, BL, BR>), dim3(grid), dim3(256), 0, s, tl, pa.tbase, reinterpret_cast<const S *>(tl.usamp), reinterpret_cast<const S *>(tl.osamp), V, pair_stride, ns, partial, (T)scale)));
   }
