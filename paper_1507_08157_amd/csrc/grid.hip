@@ -160,9 +160,10 @@ __global__ __launch_bounds__(256) void k_density(DevTiles tl, const S *__restric
 // for the tile's 64 points in registers (wide loads of the o-row and of the complex-pair
 // field), then for every u-row a of the tile sums u_a(r) w(r); u_a's row is wave-uniform and
 // arrives in SGPRs through scalar loads, so the inner loop is FMAs with one scalar and one
-// vector operand.  Each tile writes its sums, coalesced, to its own range of a partial-sum
-// buffer [function pair][state]; k_vint_reduce adds them per overlap block in a fixed
-// order (no atomics, reproducible).
+// vector operand.  Each tile writes its sums to its own range of a partial-sum buffer,
+// contribution-major ([(u-atom, o-atom)][r][c][state], so every contribution is one
+// contiguous run); k_vint_reduce adds them per overlap block in a fixed order (no
+// atomics, reproducible).
 template <class T, class S>
 __device__ __forceinline__ void load4(const S *p, T (&o)[4]) {
   o[0] = cvt<T>(p[0]); o[1] = cvt<T>(p[1]); o[2] = cvt<T>(p[2]); o[3] = cvt<T>(p[3]);
@@ -244,7 +245,8 @@ __global__ __launch_bounds__(256) void k_vint(DevTiles tl, const int64_t *__rest
           s2 += a2 * wv[q + 2];
           s3 += a3 * wv[q + 3];
         }
-        if (active) dst[(int64_t)(i * BL + r) * rows_o * ns + item] = scale * ((s0 + s1) + (s2 + s3));
+        if (active)
+          dst[((((int64_t)i * noa + b / BR) * BL + r) * BR + b % BR) * ns + s] = scale * ((s0 + s1) + (s2 + s3));
       }
     }
   }
@@ -346,10 +348,15 @@ __global__ __launch_bounds__(256) void k_vint_mfma(DevTiles tl, const int64_t *_
 #pragma unroll
         for (int k = 0; k < 16; ++k) acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a[mb][k], bf[k], acc, 0, 0, 0);
         if (active) {
+          // contribution-major: [(u-atom, o-atom)][r][c][state]
+          const int jo = b / BR, c = b - (b / BR) * BR;
 #pragma unroll
           for (int j = 0; j < 4; ++j) {
             const int m = mg + mb * 16 + 4 * q + j;
-            if (m < rows_u) dst[(int64_t)m * items + n] = scale * acc[j];
+            if (m < rows_u) {
+              const int io = m / BL, r = m - (m / BL) * BL;
+              dst[((((int64_t)io * noa + jo) * BL + r) * BR + c) * ns + sidx] = scale * acc[j];
+            }
           }
         }
       }
@@ -358,14 +365,14 @@ __global__ __launch_bounds__(256) void k_vint_mfma(DevTiles tl, const int64_t *_
 }
 
 // Vout[ob][ldv][E] (columns 0..ns) = sum over the contributions of block ob.  One wave
-// per overlap block, one lane per (element, state); the contribution offsets are
-// wave-uniform (scalar loads) and four contributions are in flight at a time, summed in a
-// fixed order.
+// per overlap block, one lane per (element, state); each contribution is a contiguous run
+// of E * ns partial sums.  The wave fetches 64 contribution offsets at once with one vector
+// load and broadcasts them lane by lane, keeping eight partial-sum loads in flight; the
+// sum order is fixed (reproducible).
 template <class T>
-__global__ __launch_bounds__(256) void k_vint_reduce(int64_t nblk, int ns, int E, int BR,
+__global__ __launch_bounds__(256) void k_vint_reduce(int64_t nblk, int ns, int E,
                                                      const int64_t *__restrict__ cptr,
                                                      const int64_t *__restrict__ cbase,
-                                                     const int32_t *__restrict__ crs,
                                                      const T *__restrict__ partial,
                                                      T *__restrict__ Vout, int ldv) {
   const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -374,19 +381,36 @@ __global__ __launch_bounds__(256) void k_vint_reduce(int64_t nblk, int ns, int E
   if (ob >= nblk) return;
   const int per = ns * E;
   const int64_t q0 = cptr[ob], q1 = cptr[ob + 1];
-  for (int idx = lane; idx < per; idx += 64) {
-    const int e = idx / ns, s = idx - (idx / ns) * ns;
-    const int r = e / BR, c = e - (e / BR) * BR;
-    T a0 = T(0), a1 = T(0), a2 = T(0), a3 = T(0);
-    int64_t q = q0;
-    for (; q + 4 <= q1; q += 4) {
-      a0 += partial[(cbase[q] + (int64_t)r * crs[q] + c) * ns + s];
-      a1 += partial[(cbase[q + 1] + (int64_t)r * crs[q + 1] + c) * ns + s];
-      a2 += partial[(cbase[q + 2] + (int64_t)r * crs[q + 2] + c) * ns + s];
-      a3 += partial[(cbase[q + 3] + (int64_t)r * crs[q + 3] + c) * ns + s];
+  for (int idx0 = 0; idx0 < per; idx0 += 64) {
+    const int idx = idx0 + lane;
+    const bool on = idx < per;
+    const int64_t off = on ? idx : 0;
+    T a[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) a[u] = T(0);
+    for (int64_t qb = q0; qb < q1; qb += 64) {
+      const int cnt = (int)(q1 - qb < 64 ? q1 - qb : 64);
+      const int64_t mine = qb + lane < q1 ? cbase[qb + lane] * ns : 0;
+      const int lo = (int)(uint32_t)mine, hi = (int)(uint32_t)(mine >> 32);
+      int k = 0;
+      for (; k + 8 <= cnt; k += 8) {
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+          const int64_t base = ((int64_t)(uint32_t)__builtin_amdgcn_readlane(hi, k + u) << 32) |
+                               (uint32_t)__builtin_amdgcn_readlane(lo, k + u);
+          a[u] += partial[base + off];
+        }
+      }
+      for (; k < cnt; ++k) {
+        const int64_t base = ((int64_t)(uint32_t)__builtin_amdgcn_readlane(hi, k) << 32) |
+                             (uint32_t)__builtin_amdgcn_readlane(lo, k);
+        a[0] += partial[base + off];
+      }
     }
-    for (; q < q1; ++q) a0 += partial[(cbase[q] + (int64_t)r * crs[q] + c) * ns + s];
-    Vout[(ob * ldv + s) * E + e] = (a0 + a1) + (a2 + a3);
+    if (on) {
+      const int e = idx / ns, st = idx - (idx / ns) * ns;
+      Vout[(ob * ldv + st) * E + e] = ((a[0] + a[1]) + (a[2] + a[3])) + ((a[4] + a[5]) + (a[6] + a[7]));
+    }
   }
 }
 
@@ -451,8 +475,8 @@ void potential_integrals(const DevTiles &tl, const DevPartials &pa, int stype, i
   if (prof) prof->end(ST_VINT, s);
   if (nblk_out == 0) return;
   if (prof) prof->begin(ST_VINT_REDUCE, s);
-  hipLaunchKernelGGL((k_vint_reduce<T>), dim3((unsigned)((nblk_out + 3) / 4)), dim3(256), 0, s, nblk_out, ns, E, BR,
-                     pa.cptr, pa.cbase, pa.crs, partial, Vout, ldv);
+  hipLaunchKernelGGL((k_vint_reduce<T>), dim3((unsigned)((nblk_out + 3) / 4)), dim3(256), 0, s, nblk_out, ns, E,
+                     pa.cptr, pa.cbase, partial, Vout, ldv);
   TD_HIP(hipGetLastError());
   if (prof) prof->end(ST_VINT_REDUCE, s);
 }

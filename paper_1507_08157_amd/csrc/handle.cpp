@@ -244,7 +244,8 @@ static void upload_bf16(DevBuf<__hip_bfloat16> &dst, const std::vector<double> &
 }
 
 // Per-tile partial sums of the potential integrals: tile t owns u-rows x o-rows function
-// pairs from tbase[t] on (u-rows outer); every (tile, u-atom i, o-atom j) with its block
+// pairs from tbase[t] on, contribution-major ((u-atom i, o-atom j) outer, then the block's
+// rows and columns); every (tile, u-atom i, o-atom j) with its block
 // (I, J) in O is one contribution, listed per O block in tile order (a fixed summation
 // order, so results are reproducible).
 static void build_partials(Handle &h, const HostSetTiles &tu, const HostSetTiles &to,
@@ -266,27 +267,23 @@ static void build_partials(Handle &h, const HostSetTiles &tu, const HostSetTiles
   }
   for (int64_t k = 0; k < O.nnzb(); ++k) cptr[k + 1] += cptr[k];
   std::vector<int64_t> cbase(cptr[O.nnzb()]);
-  std::vector<int32_t> crs(cptr[O.nnzb()]);
   std::vector<int64_t> fillp(cptr.begin(), cptr.end() - 1);
   size_t q = 0;
   for (int t = 0; t < nt; ++t) {
     const int nua = tu.ptr[t + 1] - tu.ptr[t], noa = to.ptr[t + 1] - to.ptr[t];
-    const int rows_o = noa * h.BO;
     for (int i = 0; i < nua; ++i)
       for (int j = 0; j < noa; ++j, ++q) {
         const int64_t k = cblk[q];
         if (k < 0) continue;
-        cbase[fillp[k]] = tbase[t] + (int64_t)i * h.BU * rows_o + (int64_t)j * h.BO;
-        crs[fillp[k]++] = rows_o;
+        cbase[fillp[k]++] = tbase[t] + ((int64_t)i * noa + j) * h.BU * h.BO;
       }
   }
   hipStream_t s = h.stream;
   h.pa_tbase.upload(tbase, s);
   h.pa_cptr.upload(cptr, s);
   h.pa_cbase.upload(cbase, s);
-  h.pa_crs.upload(crs, s);
   TD_HIP(hipStreamSynchronize(s));
-  h.partials = DevPartials{total, h.pa_tbase.p, h.pa_cptr.p, h.pa_cbase.p, h.pa_crs.p};
+  h.partials = DevPartials{total, h.pa_tbase.p, h.pa_cptr.p, h.pa_cbase.p};
 }
 
 // ---------------------------------------------------------------------------------------

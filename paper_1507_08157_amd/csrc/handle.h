@@ -82,7 +82,6 @@ struct Handle {
   int maxrows_uo = 0, maxrows_oo = 0;
   int maxrows_o = 0;           // max over tiles of o-rows (o-atoms * BO)
   DevBuf<int64_t> pa_tbase, pa_cptr, pa_cbase;
-  DevBuf<int32_t> pa_crs;
   DevPartials partials{};
   double mean_u_per_tile = 0, mean_o_per_tile = 0;
   int64_t pair_points = 0;     // sum over tiles of (u rows * o rows) * TP (work measure)

@@ -57,13 +57,13 @@ struct DevTiles {
 };
 
 // Per-tile partial sums of the potential integrals ([function pair][state], tiles in order,
-// u-rows outer) and the fixed-order table that sums them per overlap block.
+// contribution-major within a tile) and the fixed-order table that sums them per overlap
+// block.
 struct DevPartials {
   int64_t total = 0;                  // function pairs over all tiles (values per state)
   const int64_t *tbase = nullptr;     // [nt] first function pair of each tile
   const int64_t *cptr = nullptr;      // [n_out_blocks + 1] contributions per overlap block
   const int64_t *cbase = nullptr;     // per contribution: function pair of its (0, 0) element
-  const int32_t *crs = nullptr;       // per contribution: function pairs per u-row of its tile
 };
 
 enum SampleType { SAMPLE_F64 = 0, SAMPLE_F32 = 1, SAMPLE_BF16 = 2 };
