@@ -517,7 +517,7 @@ void create_handle(Handle &h, const tddft_system &sys, const tddft_options &o) {
 
   // ---- FFT plan, rho0 = 2 sum o K^v o and f_xc (FP64 from FP64 samples)
   build_fft_plan(h.fft, h.n, s);
-  h.partial.alloc((size_t)h.max_parts * 1024);
+  h.partial.alloc((size_t)h.max_parts * 4096);
   h.small_dev.alloc(8192);
   {
     DevBuf<double> rho((size_t)nt * TP * 2);

@@ -102,7 +102,7 @@ struct Handle {
   Work w_apply, w_pcg, w_small;
   DevBuf<double> partial;      // gram partial sums
   DevBuf<double> small_dev;    // coefficient / result staging
-  int max_parts = 256;
+  int max_parts = 1024;        // gram: workgroups of partial sums (x 4096 pairs)
 
   // timing
   hipEvent_t ev0 = nullptr, ev1 = nullptr;

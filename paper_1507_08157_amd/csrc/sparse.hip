@@ -21,7 +21,9 @@
 namespace tddft {
 
 // ---------------------------------------------------------------------------------------
-template <class T, int BU, int BO>
+// One thread per (output block, group of CW columns): every operand block pair is read once
+// for CW columns (the fixed block of A or B is shared, the column-set blocks are contiguous).
+template <class T, int BU, int BO, int CW>
 __global__ __launch_bounds__(256) void k_spmm_left(int64_t nout, int ncol,
                                                    const int64_t *__restrict__ ptr,
                                                    const int2 *__restrict__ pairs,
@@ -30,42 +32,52 @@ __global__ __launch_bounds__(256) void k_spmm_left(int64_t nout, int ncol,
                                                    T *__restrict__ C, int ldc, int cc0,
                                                    double alpha, int accumulate) {
   constexpr int E = BU * BO;
+  const int ng = (ncol + CW - 1) / CW;
   const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (gid >= nout * ncol) return;
-  const int64_t k = gid / ncol;
-  const int m = (int)(gid - k * ncol);
-  T acc[E];
+  if (gid >= nout * ng) return;
+  const int64_t k = gid / ng;
+  const int m0 = (int)(gid - k * ng) * CW;
+  const int nm = min(CW, ncol - m0);
+  T acc[CW][E];
 #pragma unroll
-  for (int e = 0; e < E; ++e) acc[e] = T(0);
+  for (int u = 0; u < CW; ++u)
+#pragma unroll
+    for (int e = 0; e < E; ++e) acc[u][e] = T(0);
   const int64_t q1 = ptr[k + 1];
   for (int64_t q = ptr[k]; q < q1; ++q) {
     const int2 pr = pairs[q];
     const T *a = A + (int64_t)pr.x * (BU * BU);
-    const T *x = X + ((int64_t)pr.y * ldx + xc0 + m) * E;
-    T xv[E];
+    T av[BU * BU];
 #pragma unroll
-    for (int e = 0; e < E; ++e) xv[e] = x[e];
+    for (int i = 0; i < BU * BU; ++i) av[i] = a[i];
+    const T *x = X + ((int64_t)pr.y * ldx + xc0 + m0) * E;
 #pragma unroll
-    for (int r = 0; r < BU; ++r)
+    for (int u = 0; u < CW; ++u) {
+      if (u < nm) {
+        T xv[E];
 #pragma unroll
-      for (int t = 0; t < BU; ++t) {
-        const T ar = a[r * BU + t];
+        for (int e = 0; e < E; ++e) xv[e] = x[u * E + e];
 #pragma unroll
-        for (int c = 0; c < BO; ++c) acc[r * BO + c] += ar * xv[t * BO + c];
+        for (int r = 0; r < BU; ++r)
+#pragma unroll
+          for (int t = 0; t < BU; ++t)
+#pragma unroll
+            for (int c = 0; c < BO; ++c) acc[u][r * BO + c] += av[r * BU + t] * xv[t * BO + c];
       }
+    }
   }
-  T *c = C + (k * ldc + cc0 + m) * E;
   const T al = (T)alpha;
-  if (accumulate) {
 #pragma unroll
-    for (int e = 0; e < E; ++e) c[e] += al * acc[e];
-  } else {
+  for (int u = 0; u < CW; ++u) {
+    if (u < nm) {
+      T *c = C + (k * ldc + cc0 + m0 + u) * E;
 #pragma unroll
-    for (int e = 0; e < E; ++e) c[e] = al * acc[e];
+      for (int e = 0; e < E; ++e) c[e] = accumulate ? c[e] + al * acc[u][e] : al * acc[u][e];
+    }
   }
 }
 
-template <class T, int BU, int BO>
+template <class T, int BU, int BO, int CW>
 __global__ __launch_bounds__(256) void k_spmm_right(int64_t nout, int ncol,
                                                     const int64_t *__restrict__ ptr,
                                                     const int2 *__restrict__ pairs,
@@ -74,38 +86,48 @@ __global__ __launch_bounds__(256) void k_spmm_right(int64_t nout, int ncol,
                                                     T *__restrict__ C, int ldc, int cc0,
                                                     double alpha, int accumulate) {
   constexpr int E = BU * BO;
+  const int ng = (ncol + CW - 1) / CW;
   const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (gid >= nout * ncol) return;
-  const int64_t k = gid / ncol;
-  const int m = (int)(gid - k * ncol);
-  T acc[E];
+  if (gid >= nout * ng) return;
+  const int64_t k = gid / ng;
+  const int m0 = (int)(gid - k * ng) * CW;
+  const int nm = min(CW, ncol - m0);
+  T acc[CW][E];
 #pragma unroll
-  for (int e = 0; e < E; ++e) acc[e] = T(0);
+  for (int u = 0; u < CW; ++u)
+#pragma unroll
+    for (int e = 0; e < E; ++e) acc[u][e] = T(0);
   const int64_t q1 = ptr[k + 1];
   for (int64_t q = ptr[k]; q < q1; ++q) {
     const int2 pr = pairs[q];
-    const T *x = X + ((int64_t)pr.x * ldx + xc0 + m) * E;
     const T *b = B + (int64_t)pr.y * (BO * BO);
-    T xv[E];
+    T bv[BO * BO];
 #pragma unroll
-    for (int e = 0; e < E; ++e) xv[e] = x[e];
+    for (int i = 0; i < BO * BO; ++i) bv[i] = b[i];
+    const T *x = X + ((int64_t)pr.x * ldx + xc0 + m0) * E;
 #pragma unroll
-    for (int t = 0; t < BO; ++t)
+    for (int u = 0; u < CW; ++u) {
+      if (u < nm) {
+        T xv[E];
 #pragma unroll
-      for (int c = 0; c < BO; ++c) {
-        const T bv = b[t * BO + c];
+        for (int e = 0; e < E; ++e) xv[e] = x[u * E + e];
 #pragma unroll
-        for (int r = 0; r < BU; ++r) acc[r * BO + c] += xv[r * BO + t] * bv;
+        for (int t = 0; t < BO; ++t)
+#pragma unroll
+          for (int c = 0; c < BO; ++c)
+#pragma unroll
+            for (int r = 0; r < BU; ++r) acc[u][r * BO + c] += xv[r * BO + t] * bv[t * BO + c];
       }
+    }
   }
-  T *c = C + (k * ldc + cc0 + m) * E;
   const T al = (T)alpha;
-  if (accumulate) {
 #pragma unroll
-    for (int e = 0; e < E; ++e) c[e] += al * acc[e];
-  } else {
+  for (int u = 0; u < CW; ++u) {
+    if (u < nm) {
+      T *c = C + (k * ldc + cc0 + m0 + u) * E;
 #pragma unroll
-    for (int e = 0; e < E; ++e) c[e] = al * acc[e];
+      for (int e = 0; e < E; ++e) c[e] = accumulate ? c[e] + al * acc[u][e] : al * acc[u][e];
+    }
   }
 }
 
@@ -261,8 +283,9 @@ void spmm_left(const DevPlan &pl, int bu, int bo, const T *A, const T *X, int ld
       return;
     }
   }
-  const int64_t n = pl.nout * ncol;
-  TD_BDIM_DISPATCH(bu, bo, hipLaunchKernelGGL((k_spmm_left<T, BU, BO>), dim3(nblocks(n, 256)),
+  constexpr int CW = 1;   // one column per thread: grouping columns measured slower here
+  const int64_t n = pl.nout * ((ncol + CW - 1) / CW);
+  TD_BDIM_DISPATCH(bu, bo, hipLaunchKernelGGL((k_spmm_left<T, BU, BO, CW>), dim3(nblocks(n, 256)),
                                               dim3(256), 0, s, pl.nout, ncol, pl.ptr.p,
                                               pl.pairs.p, A, X, ldx, xc0, C, ldc, cc0, alpha,
                                               acc ? 1 : 0));
@@ -283,8 +306,9 @@ void spmm_right(const DevPlan &pl, int bu, int bo, const T *X, int ldx, int xc0,
       return;
     }
   }
-  const int64_t n = pl.nout * ncol;
-  TD_BDIM_DISPATCH(bu, bo, hipLaunchKernelGGL((k_spmm_right<T, BU, BO>), dim3(nblocks(n, 256)),
+  constexpr int CW = 1;   // one column per thread: grouping columns measured slower here
+  const int64_t n = pl.nout * ((ncol + CW - 1) / CW);
+  TD_BDIM_DISPATCH(bu, bo, hipLaunchKernelGGL((k_spmm_right<T, BU, BO, CW>), dim3(nblocks(n, 256)),
                                               dim3(256), 0, s, pl.nout, ncol, pl.ptr.p,
                                               pl.pairs.p, X, ldx, xc0, B, C, ldc, cc0, alpha,
                                               acc ? 1 : 0));
@@ -293,99 +317,117 @@ void spmm_right(const DevPlan &pl, int bu, int bo, const T *X, int ldx, int xc0,
 
 // ---------------------------------------------------------------------------------------
 // Y[blk][yc0 + j][e] = beta_j Y + sum_s sum_i C_s[j][i] X_s[blk][xc0_s + i][e]
+// One thread per (block, element) computes a chunk of 8 output columns at a time in FP64;
+// the coefficients are wave-uniform and arrive through scalar loads.
 template <class T>
 __global__ __launch_bounds__(256) void k_lincomb(int64_t nblk, int E, LcArgs a) {
   const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const int64_t per = (int64_t)a.nout * E;
-  if (gid >= nblk * per) return;
-  const int64_t blk = gid / per;
-  const int rem = (int)(gid - blk * per);
-  const int j = rem / E;
-  const int e = rem - j * E;
-  T *y = (T *)a.Y + ((blk * a.ldy + a.yc0 + j) * E + e);
-  double acc = a.beta ? a.beta[j] * (double)(*y) : 0.0;
-  for (int s = 0; s < a.nsrc; ++s) {
-    const LcSrc &src = a.src[s];
-    const T *x = (const T *)src.X + ((blk * src.ldx + src.xc0) * E + e);
-    const double *c = src.C + (int64_t)j * src.nin;
-    for (int i = 0; i < src.nin; ++i) acc += c[i] * (double)x[(int64_t)i * E];
+  if (gid >= nblk * E) return;
+  const int64_t blk = gid / E;
+  const int e = (int)(gid - blk * E);
+  constexpr int JC = 8;
+  for (int j0 = 0; j0 < a.nout; j0 += JC) {
+    const int nj = min(JC, a.nout - j0);
+    double acc[JC];
+    T *y = (T *)a.Y + ((blk * a.ldy + a.yc0 + j0) * E + e);
+#pragma unroll
+    for (int jj = 0; jj < JC; ++jj)
+      acc[jj] = (jj < nj && a.beta) ? a.beta[j0 + jj] * (double)y[(int64_t)jj * E] : 0.0;
+    for (int si = 0; si < a.nsrc; ++si) {
+      const LcSrc &src = a.src[si];
+      const T *x = (const T *)src.X + ((blk * src.ldx + src.xc0) * E + e);
+      const double *c = src.C + (int64_t)j0 * src.nin;
+      for (int i = 0; i < src.nin; ++i) {
+        const double xv = (double)x[(int64_t)i * E];
+#pragma unroll
+        for (int jj = 0; jj < JC; ++jj)
+          if (jj < nj) acc[jj] += c[(int64_t)jj * src.nin + i] * xv;
+      }
+    }
+#pragma unroll
+    for (int jj = 0; jj < JC; ++jj)
+      if (jj < nj) y[(int64_t)jj * E] = (T)acc[jj];
   }
-  *y = (T)acc;
 }
 
 template <class T>
 void lincomb(int64_t nblk, int E, const LcArgs &a, hipStream_t s) {
-  const int64_t n = nblk * a.nout * E;
-  if (n == 0) return;
+  const int64_t n = nblk * E;
+  if (n == 0 || a.nout == 0) return;
   hipLaunchKernelGGL((k_lincomb<T>), dim3(nblocks(n, 256)), dim3(256), 0, s, nblk, E, a);
   TD_HIP(hipGetLastError());
 }
 
 // ---------------------------------------------------------------------------------------
 // FP64 Gram matrix of two column sets: out[i * n2 + j] = sum X[., xc0+i, .] Y[., yc0+j, .]
-// (diag: out[i] = sum X[., xc0+i, .] Y[., yc0+i, .]).  Two passes, fixed order.
+// (diag: out[i] = sum X[., xc0+i, .] Y[., yc0+i, .]).  Each workgroup takes a 16 x 16 tile
+// of column pairs and a contiguous range of elements; the four waves run
+// v_mfma_f64_16x16x4f64 over interleaved 4-element steps (FP64 products and sums), the
+// wave results are added in LDS in a fixed order, and a second kernel adds the
+// workgroups' partial tiles in a fixed order.
+typedef double v4d __attribute__((ext_vector_type(4)));
+constexpr int kGramMaxPairs = 4096;   // up to 64 x 64 columns
+
 template <class T>
-__global__ __launch_bounds__(256) void k_gram_partial(int64_t nblk, int E, const T *__restrict__ X,
+__global__ __launch_bounds__(256) void k_gram_partial(int64_t nelem, int E, const T *__restrict__ X,
                                                       int ldx, int xc0, int n1,
                                                       const T *__restrict__ Y, int ldy, int yc0,
-                                                      int n2, int diag, int cb,
+                                                      int n2, int diag, int64_t per_part,
                                                       double *__restrict__ partial) {
-  extern __shared__ double lds[];
-  double *xs = lds;                       // [cb][n1][E]
-  double *ys = lds + (size_t)cb * n1 * E; // [cb][n2][E]
-  const int npair = diag ? n1 : n1 * n2;
-  constexpr int MAXQ = 4;
-  double acc[MAXQ];
+  __shared__ double red[4][256];
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int q = lane >> 4, m = lane & 15;
+  const int i0 = blockIdx.y * 16, j0 = diag ? i0 : blockIdx.z * 16;
+  const int ii = i0 + m, jj = j0 + m;
+  const bool xi = ii < n1, yj = jj < n2;
+  const int64_t k0 = (int64_t)blockIdx.x * per_part;
+  const int64_t k1 = k0 + per_part < nelem ? k0 + per_part : nelem;
+  v4d acc = {0.0, 0.0, 0.0, 0.0};
+  // four steps of four elements per wave in flight: loads first, then the products
+  for (int64_t kb = k0 + 4 * w; kb < k1; kb += 64) {
+    double av[4], bv[4];
 #pragma unroll
-  for (int u = 0; u < MAXQ; ++u) acc[u] = 0.0;
-  const int64_t nchunk = (nblk + cb - 1) / cb;
-  for (int64_t ch = blockIdx.x; ch < nchunk; ch += gridDim.x) {
-    const int64_t b0 = ch * cb;
-    const int nb = (int)min((int64_t)cb, nblk - b0);
-    __syncthreads();
-    for (int t = threadIdx.x; t < nb * n1 * E; t += blockDim.x) {
-      const int b = t / (n1 * E);
-      const int r = t - b * n1 * E;
-      const int i = r / E, e = r - i * E;
-      xs[t] = (double)X[((b0 + b) * ldx + xc0 + i) * E + e];
-    }
-    for (int t = threadIdx.x; t < nb * n2 * E; t += blockDim.x) {
-      const int b = t / (n2 * E);
-      const int r = t - b * n2 * E;
-      const int j = r / E, e = r - j * E;
-      ys[t] = (double)Y[((b0 + b) * ldy + yc0 + j) * E + e];
-    }
-    __syncthreads();
-#pragma unroll
-    for (int u = 0; u < MAXQ; ++u) {
-      const int q = threadIdx.x + u * blockDim.x;
-      if (q < npair) {
-        const int i = diag ? q : q / n2;
-        const int j = diag ? q : q - i * n2;
-        double s = 0.0;
-        for (int b = 0; b < nb; ++b) {
-          const double *xr = xs + ((size_t)b * n1 + i) * E;
-          const double *yr = ys + ((size_t)b * n2 + j) * E;
-          for (int e = 0; e < E; ++e) s += xr[e] * yr[e];
-        }
-        acc[u] += s;
+    for (int u = 0; u < 4; ++u) {
+      const int64_t k = kb + 16 * u + q;
+      av[u] = 0.0;
+      bv[u] = 0.0;
+      if (k < k1) {
+        const int64_t blk = k / E;
+        const int e = (int)(k - blk * E);
+        if (xi) av[u] = (double)X[(blk * ldx + xc0 + ii) * E + e];
+        if (yj) bv[u] = (double)Y[(blk * ldy + yc0 + jj) * E + e];
       }
     }
-  }
 #pragma unroll
-  for (int u = 0; u < MAXQ; ++u) {
-    const int q = threadIdx.x + u * blockDim.x;
-    if (q < npair) partial[(size_t)blockIdx.x * npair + q] = acc[u];
+    for (int u = 0; u < 4; ++u) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av[u], bv[u], acc, 0, 0, 0);
+  }
+  // D of the FP64 16x16x4 product: lane holds column lane % 16 and, in its r-th register,
+  // row 4 r + lane / 16 (the FP32 variant interleaves rows the other way)
+#pragma unroll
+  for (int r = 0; r < 4; ++r) red[w][(4 * r + q) * 16 + m] = acc[r];
+  __syncthreads();
+  const int npair = diag ? n1 : n1 * n2;
+  const int t = threadIdx.x;   // tile entry (row t / 16, column t % 16)
+  const int ti = i0 + t / 16, tj = j0 + t % 16;
+  if (ti < n1 && tj < n2 && (!diag || ti == tj)) {
+    const double v = (red[0][t] + red[1][t]) + (red[2][t] + red[3][t]);
+    const int qo = diag ? ti : ti * n2 + tj;
+    partial[(int64_t)blockIdx.x * npair + qo] = v;
   }
 }
 
-__global__ void k_gram_reduce(int nparts, int npair, const double *__restrict__ partial,
-                              double *__restrict__ out) {
-  const int q = blockIdx.x * blockDim.x + threadIdx.x;
+// one wave per pair: lanes take parts lane, lane + 64, ... and a fixed butterfly adds them
+__global__ __launch_bounds__(256) void k_gram_reduce(int nparts, int npair,
+                                                     const double *__restrict__ partial,
+                                                     double *__restrict__ out) {
+  const int q = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
   if (q >= npair) return;
   double s = 0.0;
-  for (int p = 0; p < nparts; ++p) s += partial[(size_t)p * npair + q];
-  out[q] = s;
+  for (int p = lane; p < nparts; p += 64) s += partial[(size_t)p * npair + q];
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off);
+  if (lane == 0) out[q] = s;
 }
 
 template <class T>
@@ -393,17 +435,18 @@ void gram(int64_t nblk, int E, const T *X, int ldx, int xc0, int n1, const T *Y,
           int yc0, int n2, bool diag, double *partial, int max_parts, double *out,
           hipStream_t s) {
   const int npair = diag ? n1 : n1 * n2;
-  if (npair > 4 * 256) throw Error{TDDFT_E_INVALID, "gram: too many column pairs"};
-  int cb = (int)(24576 / ((size_t)(n1 + n2) * E * sizeof(double)));
-  if (cb < 1) cb = 1;
-  if (cb > 64) cb = 64;
-  const int64_t nchunk = (nblk + cb - 1) / cb;
-  int parts = (int)std::min<int64_t>(std::max<int64_t>(nchunk, 1), max_parts);
-  const size_t lds = (size_t)cb * (n1 + n2) * E * sizeof(double);
-  hipLaunchKernelGGL((k_gram_partial<T>), dim3(parts), dim3(256), lds, s, nblk, E, X, ldx, xc0,
-                     n1, Y, ldy, yc0, n2, diag ? 1 : 0, cb, partial);
+  if (npair > kGramMaxPairs) throw Error{TDDFT_E_INVALID, "gram: too many column pairs"};
+  const int64_t nelem = nblk * E;
+  // element ranges per workgroup: multiples of 64 (four waves x four steps of four elements)
+  int parts = (int)std::min<int64_t>(max_parts, std::max<int64_t>(1, nelem / 256));
+  int64_t per = (nelem + parts - 1) / parts;
+  per = std::max<int64_t>(64, (per + 63) / 64 * 64);
+  parts = (int)std::max<int64_t>(1, (nelem + per - 1) / per);
+  const int ti = (n1 + 15) / 16, tj = diag ? 1 : (n2 + 15) / 16;
+  hipLaunchKernelGGL((k_gram_partial<T>), dim3(parts, ti, tj), dim3(256), 0, s, nelem, E, X, ldx, xc0,
+                     n1, Y, ldy, yc0, n2, diag ? 1 : 0, per, partial);
   TD_HIP(hipGetLastError());
-  hipLaunchKernelGGL(k_gram_reduce, dim3(nblocks(npair, 256)), dim3(256), 0, s, parts, npair,
+  hipLaunchKernelGGL(k_gram_reduce, dim3((unsigned)((npair + 3) / 4)), dim3(256), 0, s, parts, npair,
                      partial, out);
   TD_HIP(hipGetLastError());
 }
