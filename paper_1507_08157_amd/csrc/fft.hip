@@ -191,7 +191,7 @@ __global__ __launch_bounds__(256) void k_fft_x_fwd(GeomDev g, AxisDev ax,
   using T2 = typename C2<T>::type;
   extern __shared__ unsigned char lds_raw[];
   T2 *a = reinterpret_cast<T2 *>(lds_raw);
-  const int ldl = g.nx;
+  const int ldl = g.nx + 1;   // odd row length (in complex values): lines start on different banks
   T2 *b = a + 16 * ldl;
   const int row = blockIdx.x;           // ty + nty * tz
   const int ty = row % g.nty, tz = row / g.nty;
@@ -224,7 +224,7 @@ __global__ __launch_bounds__(256) void k_fft_y(GeomDev g, AxisDev ax,
   using T2 = typename C2<T>::type;
   extern __shared__ unsigned char lds_raw[];
   T2 *a = reinterpret_cast<T2 *>(lds_raw);
-  const int ldl = g.ny;
+  const int ldl = g.ny + 1;
   T2 *b = a + XB * ldl;
   const int nxb = (g.nx + XB - 1) / XB;
   const int xb = blockIdx.x % nxb, z = blockIdx.x / nxb;
@@ -253,7 +253,7 @@ __global__ __launch_bounds__(256) void k_fft_z_poisson(GeomDev g, AxisDev ax,
   using T2 = typename C2<T>::type;
   extern __shared__ unsigned char lds_raw[];
   T2 *a = reinterpret_cast<T2 *>(lds_raw);
-  const int ldl = g.nz;
+  const int ldl = g.nz + 1;
   T2 *b = a + XB * ldl;
   const int nxb = (g.nx + XB - 1) / XB;
   const int xb = blockIdx.x % nxb, y = blockIdx.x / nxb;
@@ -300,7 +300,7 @@ __global__ __launch_bounds__(256) void k_fft_x_inv(GeomDev g, AxisDev ax,
   using T2 = typename C2<T>::type;
   extern __shared__ unsigned char lds_raw[];
   T2 *a = reinterpret_cast<T2 *>(lds_raw);
-  const int ldl = g.nx;
+  const int ldl = g.nx + 1;   // odd row length (in complex values): lines start on different banks
   T2 *b = a + 16 * ldl;
   const int row = blockIdx.x;
   const int ty = row % g.nty, tz = row / g.nty;
@@ -370,9 +370,9 @@ void hartree_xc(const GridGeom &gg, const FFTPlan &plan, int npair, T *fields, T
   const double scale = 4.0 * pi / ((double)gg.n[0] * gg.n[1] * gg.n[2]);
   const unsigned rows = (unsigned)(gg.nty * gg.ntz);
   const unsigned nxb = (unsigned)((gg.n[0] + XB - 1) / XB);
-  const size_t lx = 2 * 16 * (size_t)gg.n[0] * sizeof(T2);
-  const size_t ly = 2 * XB * (size_t)gg.n[1] * sizeof(T2);
-  const size_t lz = 2 * XB * (size_t)gg.n[2] * sizeof(T2);
+  const size_t lx = 2 * 16 * (size_t)(gg.n[0] + 1) * sizeof(T2);
+  const size_t ly = 2 * XB * (size_t)(gg.n[1] + 1) * sizeof(T2);
+  const size_t lz = 2 * XB * (size_t)(gg.n[2] + 1) * sizeof(T2);
   Prof dummy;
   Prof &pf = prof ? *prof : dummy;
   pf.begin(ST_FFT_X_FWD, s);
