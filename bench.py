@@ -138,6 +138,8 @@ def measured_traffic(stage, workload, precision):
     """HBM bytes per launch from the committed rocprofv3 counter summary, or None when the
     kernel's source has changed since the counters were taken."""
     sym = KERNEL_SYMBOL.get(stage)
+    if stage == "vint" and precision != "fp64":
+        sym = "k_vint_mfma"   # the FP32 potential integrals run on MFMA
     path = TRAFFIC_FILE.format(workload=workload, precision=precision)
     if sym is None or not os.path.exists(path):
         return None
@@ -343,10 +345,10 @@ def main():
         model = open(model_path, "rb").read() if os.path.exists(model_path) else None
         handles = {}
         # mixed precision with each preconditioner: Eq. precond by CG, none, learned
-        runs = [("fp32_cg", "fp32", "cg"), ("fp32_none", "fp32", "none"),
-                ("bf16_cg", "bf16", "cg")]
+        runs = [("fp32_cg", "fp32", "cg"), ("fp32_cg_adaptive", "fp32", "cg"),
+                ("fp32_none", "fp32", "none"), ("bf16_cg", "bf16", "cg")]
         if model is not None:
-            runs.insert(2, ("fp32_learned", "fp32", "learned"))
+            runs.insert(3, ("fp32_learned", "fp32", "learned"))
         for key, mode, pc in runs:
             if mode not in handles:
                 handles[mode] = h if mode == a.precision else binding.tddft_create(arrays, precision=mode)
@@ -354,6 +356,8 @@ def main():
             kw = dict(precision=mode, precond=pc, tol_omega=1e-8, max_iter=300)
             if pc == "learned":
                 kw["model"] = model
+            if key.endswith("_adaptive"):
+                kw["eps_loose"] = 0.1   # inner tolerance 0.1 |g|/|g_0|, down to eps_tol
             o = binding.tddft_default_options(**kw)
             P1, P2 = L0.clone(), L0.clone()
             w, rc, st = hm.tddft_pcg_solve(n, o, P1, P2, log_capacity=2000)

@@ -119,6 +119,9 @@ typedef struct {
   const void *model;         /* learned-preconditioner weights blob, or NULL           */
   int64_t  model_bytes;
   void    *stream;           /* hipStream_t, or NULL for the default stream             */
+  double   eps_loose;        /* > eps_tol: adaptive inner tolerance eps_loose |g| / |g_0|
+                                (max_i ||g_i||_S now and at the first iteration) clamped
+                                to [eps_tol, eps_loose] (Sec. IV.A); 0 = constant eps_tol */
 } tddft_options;
 
 /* Per-solve statistics (host memory, caller-owned).  The log arrays are optional. */
@@ -164,7 +167,7 @@ typedef struct {
 typedef struct tddft_handle tddft_handle;
 
 /* Defaults: FP64, ALDA exchange, rho_floor 1e-10, coupling 1, KSDIFF_CG, eps_tol 1e-4,
- * tol_omega 1e-7, max_iter 300, max_inner 50, refresh 10, restart 20, seed 0. */
+ * tol_omega 1e-7, max_iter 300, max_inner 50, refresh 10, restart 20, seed 0, eps_loose 0. */
 void tddft_default_options(tddft_options *opts);
 
 /* Build a handle for one system (Sec. III.A: sparse K^v, K^c, S and H, the cutoff

@@ -47,6 +47,7 @@ class Options:
     precond: str = "cg"          # "cg" (Eq. precond solved by CG), "none" or "learned"
     scaling: np.ndarray | None = None   # learned: elementwise gradient scaling [n_u, n_o]
     eps_tol: float = 1e-4
+    eps_loose: float = 0.0       # > eps_tol: inner tolerance eps_loose |g|/|g_0| in [eps_tol, eps_loose]
     tol_omega: float = 1e-7
     max_iter: int = 300
     max_inner: int = 50
@@ -72,6 +73,7 @@ class Solver:
         self.o = opts
         self.complete = bool(np.all(op.mask_L == 1))
         self.fallbacks = 0
+        self.eps = opts.eps_tol
 
     # -- metric helpers -------------------------------------------------------------------
     def cov(self, X):
@@ -123,7 +125,7 @@ class Solver:
         active = rr0 > 0
         steps = np.zeros(len(g), dtype=int)
         for _ in range(self.o.max_inner):
-            active &= rr > (self.o.eps_tol ** 2) * rr0
+            active &= rr > (self.eps ** 2) * rr0
             if not np.any(active):
                 break
             Ld = np.stack([self.op.T(x) for x in d])
@@ -161,7 +163,7 @@ class Solver:
         active = rr0 > 0
         steps = np.zeros(len(r), dtype=int)
         for _ in range(self.o.max_inner):
-            active &= rr > (self.o.eps_tol ** 2) * rr0
+            active &= rr > (self.eps ** 2) * rr0
             if not np.any(active):
                 break
             Hd = self.hess_L(d)
@@ -300,6 +302,13 @@ class Solver:
             gnorm = np.sqrt(np.einsum("sikl,sikl->i", g, np.stack([self.cov(g[0]),
                                                                    self.cov(g[1])])))
             hist.append(omega.copy())
+            # inner tolerance: constant, or loose while the gradient is large (Sec. IV.A)
+            if it == 0:
+                g0 = float(np.max(gnorm))
+            self.eps = self.o.eps_tol
+            if self.o.eps_loose > self.o.eps_tol and g0 > 0:
+                self.eps = min(self.o.eps_loose,
+                               max(self.o.eps_tol, self.o.eps_loose * float(np.max(gnorm)) / g0))
             if omega_prev is not None and np.max(np.abs(omega - omega_prev)) < self.o.tol_omega \
                     and np.max(gnorm) < np.sqrt(self.o.tol_omega):
                 converged = True

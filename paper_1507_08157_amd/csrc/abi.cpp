@@ -70,6 +70,7 @@ void tddft_default_options(tddft_options *o) {
   o->model = nullptr;
   o->model_bytes = 0;
   o->stream = nullptr;
+  o->eps_loose = 0.0;
 }
 
 int tddft_abi_version(void) { return TDDFT_ABI_VERSION; }

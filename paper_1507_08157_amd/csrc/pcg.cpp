@@ -532,6 +532,7 @@ static int solve_impl(Handle &h, int n, const tddft_options &o, double *omega, d
   std::vector<double> w(n), w_prev(n, 0.0);
   bool converged = false, have_prev = false, have_dir = false, restart_next = false;
   int it = 0, stalls = 0;
+  double gmax0 = 0.0;
   const double sqrt_tol = std::sqrt(o.tol_omega);
   Mat Nm((size_t)n * n);
   for (it = 0; it <= o.max_iter; ++it) {
@@ -566,6 +567,12 @@ static int solve_impl(Handle &h, int n, const tddft_options &o, double *omega, d
     }
     for (double v : w)
       if (!std::isfinite(v)) throw Error{TDDFT_E_NOT_PD, "non-finite Tsiper functional"};
+    // inner tolerance: constant, or loose while the gradient is still large and tightened as
+    // it falls (Sec. IV.A: loose and tight tolerances converge alike in the first iterations)
+    if (it == 0) gmax0 = gmax;
+    double eps_cur = o.eps_tol;
+    if (o.eps_loose > o.eps_tol && gmax0 > 0.0)
+      eps_cur = std::min(o.eps_loose, std::max(o.eps_tol, o.eps_loose * gmax / gmax0));
     if (have_prev) {
       double dw = 0.0;
       for (int i = 0; i < n; ++i) dw = std::max(dw, std::fabs(w[i] - w_prev[i]));
@@ -597,7 +604,7 @@ static int solve_impl(Handle &h, int n, const tddft_options &o, double *omega, d
           S.copy(nM, set(Lz), set(G));
         } else {
           inner_total += ksdiff_cg(S, h, set(G), set(Gc), set(Lz), set(Lres), set(Lresc), set(Ld),
-                                   set(Ldc), set(LHd), set(LHdc), set(Ltmp), o.eps_tol, o.max_inner);
+                                   set(Ldc), set(LHd), set(LHdc), set(Ltmp), eps_cur, o.max_inner);
         }
       }
     } else {
@@ -628,7 +635,7 @@ static int solve_impl(Handle &h, int n, const tddft_options &o, double *omega, d
       std::vector<char> active(nc);
       for (int c = 0; c < nc; ++c) active[c] = rr0[c] > 0.0;
       std::vector<int> steps(nc, 0);
-      const double tol2 = o.eps_tol * o.eps_tol;
+      const double tol2 = eps_cur * eps_cur;
       for (int k = 0; k < o.max_inner; ++k) {
         bool any = false;
         for (int c = 0; c < nc; ++c) {

@@ -134,3 +134,13 @@ def test_pcg_no_convergence_status(small_dense):
     w, rc, st, _, _ = _solve(small_dense, tol_omega=1e-12, max_iter=2)
     assert rc == binding.TDDFT_E_NO_CONVERGENCE
     assert np.all(np.isfinite(w)) and not st["converged"]
+
+
+@pytest.mark.parametrize("name", ["small_dense", "tiny"])
+def test_pcg_adaptive_inner_tolerance(name, request):
+    from conftest import cached_system
+    from oracle.casida import Casida
+    s = cached_system(name)
+    w, rc, st, _, _ = _solve(s, tol_omega=1e-10, eps_loose=0.1)
+    assert st["converged"]
+    assert np.max(np.abs(w - Casida(s).omega_hermitian()[:s.cfg.n_states])) < 1e-9

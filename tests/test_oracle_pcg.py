@@ -159,3 +159,13 @@ def test_truncated_iterates_are_variational(small_trunc):
     sums = np.array([np.sum(h) for h in r.history])
     assert np.all(sums >= np.sum(w_sub) - 1e-10)
     assert np.all(np.diff(sums) <= 1e-12 * np.abs(sums[:-1]))
+
+
+def test_adaptive_inner_tolerance_reaches_brute_force(dense):
+    """A loose inner tolerance early on, tightened with the gradient, changes the path but
+    not the minimum."""
+    s, op, cs = dense
+    n = s.cfg.n_states
+    r = Solver(op, Options(n_states=n, eps_loose=0.1, tol_omega=1e-10, max_iter=300)).solve(s.guess())
+    assert r.converged
+    assert np.max(np.abs(r.omega - cs.omega_hermitian()[:n])) < 1e-9
