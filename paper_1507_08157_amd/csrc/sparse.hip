@@ -132,9 +132,9 @@ __global__ __launch_bounds__(256) void k_spmm_right(int64_t nout, int ncol,
 }
 
 // ---------------------------------------------------------------------------------------
-// Dense path (FP32).  When both operands and the output of a masked product have complete
+// Dense path (FP32 and FP64).  When both operands and the output of a masked product have complete
 // block patterns, the product is a plain dense matrix product; it runs on MFMA
-// (v_mfma_f32_16x16x4f32) with 64 x 64 output tiles per workgroup (4 waves, each 32 x 32
+// (v_mfma_f32_16x16x4f32 / v_mfma_f64_16x16x4f64) with 64 x 64 output tiles per workgroup (4 waves, each 32 x 32
 // as 2 x 2 MFMA blocks) and k-slabs of 32 staged in LDS straight from the padded-block
 // layouts:
 //   left  C = A X:  A [di*BU x dk*BU] in BU x BU blocks, X a column set on dk x dj blocks;
@@ -144,15 +144,28 @@ __global__ __launch_bounds__(256) void k_spmm_right(int64_t nout, int ncol,
 typedef float v4f __attribute__((ext_vector_type(4)));
 constexpr int GM = 64, GN = 64, GK = 32;
 
-template <int BU, int BO, bool LEFT>
+typedef double v4d_g __attribute__((ext_vector_type(4)));
+
+template <class T> struct MfmaAcc;
+template <> struct MfmaAcc<float> { using type = v4f; };
+template <> struct MfmaAcc<double> { using type = v4d_g; };
+
+template <class T>
+__device__ __forceinline__ typename MfmaAcc<T>::type mfma16x16x4(T a, T b, typename MfmaAcc<T>::type c) {
+  if constexpr (std::is_same<T, float>::value) return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+  else return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+
+template <class T, int BU, int BO, bool LEFT>
 __global__ __launch_bounds__(256) void k_gemm_blocks(int di, int dk, int dj, int ncol,
-                                                     const float *__restrict__ A,
-                                                     const float *__restrict__ B, int ldx, int xc0,
-                                                     float *__restrict__ C, int ldc, int cc0,
-                                                     float alpha, int accumulate) {
+                                                     const T *__restrict__ A,
+                                                     const T *__restrict__ B, int ldx, int xc0,
+                                                     T *__restrict__ C, int ldc, int cc0,
+                                                     T alpha, int accumulate) {
+  using VA = typename MfmaAcc<T>::type;
   constexpr int E = BU * BO;
-  __shared__ float As[GK][GM + 1];
-  __shared__ float Bs[GK][GN + 1];
+  __shared__ T As[GK][GM + 1];
+  __shared__ T Bs[GK][GN + 1];
   const int M = LEFT ? di * BU : di * BU * ncol;
   const int N = LEFT ? dj * ncol * BO : dj * BO;
   const int K = LEFT ? dk * BU : dk * BO;
@@ -194,38 +207,39 @@ __global__ __launch_bounds__(256) void k_gemm_blocks(int di, int dk, int dj, int
   const bool bval = n0 + bnl < N;
   const int64_t bcol = bval ? colB(n0 + bnl) : 0;
   const int wm = (w >> 1) * 32, wn = (w & 1) * 32;
-  v4f acc[2][2];
+  VA acc[2][2];
 #pragma unroll
   for (int a = 0; a < 2; ++a)
 #pragma unroll
-    for (int b = 0; b < 2; ++b) acc[a][b] = v4f{0.f, 0.f, 0.f, 0.f};
+    for (int b = 0; b < 2; ++b) acc[a][b] = VA{T(0), T(0), T(0), T(0)};
   for (int k0 = 0; k0 < K; k0 += GK) {
     {
       const int k = k0 + ak;
       const bool kv = k < K;
       const int64_t kp = kv ? kA(k) : 0;
 #pragma unroll
-      for (int q = 0; q < 8; ++q) As[ak][ar + 8 * q] = (kv && aval[q]) ? A[arow[q] + kp] : 0.0f;
+      for (int q = 0; q < 8; ++q) As[ak][ar + 8 * q] = (kv && aval[q]) ? A[arow[q] + kp] : T(0);
     }
 #pragma unroll
     for (int q = 0; q < 8; ++q) {
       const int kl = bkl + 4 * q, k = k0 + kl;
-      Bs[kl][bnl] = (k < K && bval) ? B[bcol + kB(k)] : 0.0f;
+      Bs[kl][bnl] = (k < K && bval) ? B[bcol + kB(k)] : T(0);
     }
     __syncthreads();
 #pragma unroll
     for (int kk = 0; kk < GK; kk += 4) {
       const int kr = kk + (lane >> 4), c16 = lane & 15;
-      const float a0 = As[kr][wm + c16], a1 = As[kr][wm + 16 + c16];
-      const float b0 = Bs[kr][wn + c16], b1 = Bs[kr][wn + 16 + c16];
-      acc[0][0] = __builtin_amdgcn_mfma_f32_16x16x4f32(a0, b0, acc[0][0], 0, 0, 0);
-      acc[0][1] = __builtin_amdgcn_mfma_f32_16x16x4f32(a0, b1, acc[0][1], 0, 0, 0);
-      acc[1][0] = __builtin_amdgcn_mfma_f32_16x16x4f32(a1, b0, acc[1][0], 0, 0, 0);
-      acc[1][1] = __builtin_amdgcn_mfma_f32_16x16x4f32(a1, b1, acc[1][1], 0, 0, 0);
+      const T a0 = As[kr][wm + c16], a1 = As[kr][wm + 16 + c16];
+      const T b0 = Bs[kr][wn + c16], b1 = Bs[kr][wn + 16 + c16];
+      acc[0][0] = mfma16x16x4<T>(a0, b0, acc[0][0]);
+      acc[0][1] = mfma16x16x4<T>(a0, b1, acc[0][1]);
+      acc[1][0] = mfma16x16x4<T>(a1, b0, acc[1][0]);
+      acc[1][1] = mfma16x16x4<T>(a1, b1, acc[1][1]);
     }
     __syncthreads();
   }
-  // D of 16x16x4: lane holds column lane % 16, rows 4 (lane / 16) + j
+  // D of 16x16x4: lane holds column lane % 16 and, in register j, row 4 (lane / 16) + j
+  // (FP32) or row 4 j + lane / 16 (FP64)
 #pragma unroll
   for (int nb = 0; nb < 2; ++nb) {
     const int n = n0 + wn + nb * 16 + (lane & 15);
@@ -241,7 +255,7 @@ __global__ __launch_bounds__(256) void k_gemm_blocks(int di, int dk, int dj, int
     for (int mb = 0; mb < 2; ++mb)
 #pragma unroll
       for (int j = 0; j < 4; ++j) {
-        const int i = i0 + wm + mb * 16 + 4 * (lane >> 4) + j;
+        const int i = i0 + wm + mb * 16 + (std::is_same<T, float>::value ? 4 * (lane >> 4) + j : 4 * j + (lane >> 4));
         if (i >= M) continue;
         int64_t crow;
         if (LEFT) {
@@ -250,8 +264,8 @@ __global__ __launch_bounds__(256) void k_gemm_blocks(int di, int dk, int dj, int
           const int I = i / (BU * ncol), rem = i - I * (BU * ncol), r = rem / ncol, m = rem - r * ncol;
           crow = ((int64_t)I * dj * ldc + cc0 + m) * E + r * BO;
         }
-        float *cp = C + crow + ccol;
-        const float v = alpha * acc[mb][nb][j];
+        T *cp = C + crow + ccol;
+        const T v = alpha * acc[mb][nb][j];
         *cp = accumulate ? *cp + v : v;
       }
   }
@@ -273,15 +287,13 @@ template <class T>
 void spmm_left(const DevPlan &pl, int bu, int bo, const T *A, const T *X, int ldx, int xc0,
                T *C, int ldc, int cc0, int ncol, double alpha, bool acc, hipStream_t s) {
   if (pl.nout == 0 || ncol == 0) return;
-  if constexpr (std::is_same<T, float>::value) {
-    if (pl.di > 0) {
-      const dim3 grid((unsigned)((pl.dj * ncol * bo + GN - 1) / GN), (unsigned)((pl.di * bu + GM - 1) / GM));
-      TD_BDIM_DISPATCH(bu, bo, hipLaunchKernelGGL((k_gemm_blocks<BU, BO, true>), grid, dim3(256), 0, s,
-                                                  pl.di, pl.dk, pl.dj, ncol, A, X, ldx, xc0, C, ldc,
-                                                  cc0, (float)alpha, acc ? 1 : 0));
-      TD_HIP(hipGetLastError());
-      return;
-    }
+  if (pl.di > 0) {
+    const dim3 grid((unsigned)((pl.dj * ncol * bo + GN - 1) / GN), (unsigned)((pl.di * bu + GM - 1) / GM));
+    TD_BDIM_DISPATCH(bu, bo, hipLaunchKernelGGL((k_gemm_blocks<T, BU, BO, true>), grid, dim3(256), 0, s,
+                                                pl.di, pl.dk, pl.dj, ncol, A, X, ldx, xc0, C, ldc,
+                                                cc0, (T)alpha, acc ? 1 : 0));
+    TD_HIP(hipGetLastError());
+    return;
   }
   constexpr int CW = 1;   // one column per thread: grouping columns measured slower here
   const int64_t n = pl.nout * ((ncol + CW - 1) / CW);
@@ -296,15 +308,13 @@ template <class T>
 void spmm_right(const DevPlan &pl, int bu, int bo, const T *X, int ldx, int xc0, const T *B,
                 T *C, int ldc, int cc0, int ncol, double alpha, bool acc, hipStream_t s) {
   if (pl.nout == 0 || ncol == 0) return;
-  if constexpr (std::is_same<T, float>::value) {
-    if (pl.di > 0) {
-      const dim3 grid((unsigned)((pl.dj * bo + GN - 1) / GN), (unsigned)((pl.di * bu * ncol + GM - 1) / GM));
-      TD_BDIM_DISPATCH(bu, bo, hipLaunchKernelGGL((k_gemm_blocks<BU, BO, false>), grid, dim3(256), 0, s,
-                                                  pl.di, pl.dk, pl.dj, ncol, X, B, ldx, xc0, C, ldc,
-                                                  cc0, (float)alpha, acc ? 1 : 0));
-      TD_HIP(hipGetLastError());
-      return;
-    }
+  if (pl.di > 0) {
+    const dim3 grid((unsigned)((pl.dj * bo + GN - 1) / GN), (unsigned)((pl.di * bu * ncol + GM - 1) / GM));
+    TD_BDIM_DISPATCH(bu, bo, hipLaunchKernelGGL((k_gemm_blocks<T, BU, BO, false>), grid, dim3(256), 0, s,
+                                                pl.di, pl.dk, pl.dj, ncol, X, B, ldx, xc0, C, ldc,
+                                                cc0, (T)alpha, acc ? 1 : 0));
+    TD_HIP(hipGetLastError());
+    return;
   }
   constexpr int CW = 1;   // one column per thread: grouping columns measured slower here
   const int64_t n = pl.nout * ((ncol + CW - 1) / CW);
