@@ -60,22 +60,24 @@ __device__ __forceinline__ void load2<double, __hip_bfloat16>(const __hip_bfloat
 }
 
 // ---------------------------------------------------------------------------------------
-// Response density.  One wave per tile, one lane per grid point.  The tile's right-set rows
-// are staged in LDS as [atom][point][BR] (one wide LDS read per atom); for every left atom
-// i the partial sums psi_s,r = sum_j P_s[(i,r),(j,.)] . o_j are built from wave-uniform P
+// Response density.  One wave per tile, one lane per grid point.  For every left atom i
+// the partial sums psi_s,r = sum_j P_s[(i,r),(j,.)] . o_j are built from wave-uniform P
 // blocks (all NS states of a block are contiguous, so they arrive in SGPRs through a few
-// scalar loads and feed the FMAs as scalar operands), then rho_s += u_(i,r) psi_s,r.
-template <class T, int NS, int BL, int BR, bool FULL>
+// scalar loads and feed the FMAs as scalar operands), then rho_s += u_(i,r) psi_s,r.  The
+// o-rows are read straight from the tile's samples (coalesced, L1-resident across i): no
+// LDS, so occupancy is set by registers alone.
+template <class T, class S, int NS, int BL, int BR, bool FULL>
 __device__ __forceinline__ void density_pairs(const int32_t *__restrict__ pid, int noa,
                                               const T *__restrict__ X, int64_t xoff, int ldx,
-                                              int nk, const T *lo, int lane, T (&tmp)[NS][BL]) {
+                                              int nk, const S *__restrict__ os, int lane,
+                                              T (&tmp)[NS][BL]) {
   constexpr int E = BL * BR;
   for (int j = 0; j < noa; ++j) {
     const int pb = pid[j];
     if (pb < 0) continue;
     T o[BR];
 #pragma unroll
-    for (int c = 0; c < BR; ++c) o[c] = lo[(j * TP + lane) * BR + c];
+    for (int c = 0; c < BR; ++c) o[c] = cvt<T>(os[(j * BR + c) * TP + lane]);
     const T *Pj = X + ((int64_t)pb * ldx) * E + xoff;
 #pragma unroll
     for (int k = 0; k < NS; ++k) {
@@ -94,27 +96,14 @@ __global__ __launch_bounds__(256) void k_density(DevTiles tl, const S *__restric
                                                  const int32_t *__restrict__ pidx,
                                                  const T *__restrict__ X, int ldx, int xc0, int ns,
                                                  T *__restrict__ out, int64_t pair_stride, T scale) {
-  extern __shared__ unsigned char lds_raw[];
   constexpr int NS = sizeof(T) == 8 ? 4 : 8;   // states per pass (P of a block fits in SGPRs)
   const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
   const int t = blockIdx.x * (blockDim.x >> 6) + w;
-  T *lo = reinterpret_cast<T *>(lds_raw) + (size_t)w * tl.maxrows_r * TP;
-  int nua = 0, noa = 0, u0 = 0, o0 = 0;
-  if (t < tl.nt) {
-    u0 = tl.uptr[t];
-    nua = tl.uptr[t + 1] - u0;
-    o0 = tl.optr[t];
-    noa = tl.optr[t + 1] - o0;
-  }
-  {
-    const S *os = osamp + (int64_t)o0 * BR * TP;
-    for (int j = 0; j < noa; ++j)
-#pragma unroll
-      for (int c = 0; c < BR; ++c) lo[(j * TP + lane) * BR + c] = cvt<T>(os[(j * BR + c) * TP + lane]);
-  }
-  __syncthreads();
   if (t >= tl.nt) return;
+  const int u0 = tl.uptr[t], nua = tl.uptr[t + 1] - u0;
+  const int o0 = tl.optr[t], noa = tl.optr[t + 1] - o0;
+  const S *os = osamp + (int64_t)o0 * BR * TP;
   using T2 = typename Vec2<T>::type;
   const int32_t *pid = pidx + tl.pptr[t];
   for (int s0 = 0; s0 < ns; s0 += NS) {
@@ -130,9 +119,9 @@ __global__ __launch_bounds__(256) void k_density(DevTiles tl, const S *__restric
         for (int r = 0; r < BL; ++r) tmp[k][r] = T(0);
       const int64_t xoff = (int64_t)(xc0 + s0) * BL * BR;
       if (nk == NS)
-        density_pairs<T, NS, BL, BR, true>(pid + i * noa, noa, X, xoff, ldx, nk, lo, lane, tmp);
+        density_pairs<T, S, NS, BL, BR, true>(pid + i * noa, noa, X, xoff, ldx, nk, os, lane, tmp);
       else
-        density_pairs<T, NS, BL, BR, false>(pid + i * noa, noa, X, xoff, ldx, nk, lo, lane, tmp);
+        density_pairs<T, S, NS, BL, BR, false>(pid + i * noa, noa, X, xoff, ldx, nk, os, lane, tmp);
       const S *us = usamp + ((int64_t)(u0 + i) * BL) * TP + lane;
 #pragma unroll
       for (int r = 0; r < BL; ++r) {
@@ -447,10 +436,8 @@ template <class T>
 void density(const DevTiles &tl, int stype, int BL, int BR, const T *X, int ldx, int xc0, int ns,
              T *out, int64_t pair_stride, double scale, hipStream_t s) {
   if (tl.nt == 0 || ns == 0) return;
-  const size_t per_wave = (size_t)tl.maxrows_r * TP * sizeof(T);
-  if (per_wave > tl.lds_limit) throw Error{TDDFT_E_INVALID, "too many functions per grid tile for the LDS budget"};
-  const int waves = (int)std::max<size_t>(1, std::min<size_t>(4, tl.lds_limit / std::max<size_t>(per_wave, 1)));
-  const size_t lds = (size_t)waves * per_wave;
+  const int waves = 4;
+  const size_t lds = 0;
   const unsigned grid = (unsigned)((tl.nt + waves - 1) / waves);
   TD_SAMPLE(T, stype, TD_GRID_BDIM(BL, BR, hipLaunchKernelGGL((k_density<T, S, BL, BR>), dim3(grid), dim3(64 * waves), lds, s, tl, reinterpret_cast<const S *>(tl.usamp), reinterpret_cast<const S *>(tl.osamp), tl.pidx, X, ldx, xc0, ns, out, pair_stride, (T)scale)));
   TD_HIP(hipGetLastError());
