@@ -372,6 +372,16 @@ def main():
                 hm.close()
         out["time_to_omega"] = solves
         out["omega_fp64"] = [float(x) for x in w64]
+        # Tamm-Dancoff comparison (B = 0): same system, FP32, CG preconditioner
+        ht = binding.tddft_create(arrays, precision="fp32", tda=1)
+        o = binding.tddft_default_options(precision="fp32", tda=1, tol_omega=1e-8, max_iter=300)
+        wt, rct, stt = ht.tddft_pcg_solve(n, o, L0.clone(), L0.clone())
+        ht.close()
+        out["tda"] = {"omega": [float(x) for x in wt], "iterations": stt["iterations"],
+                      "solve_s": stt["solve_ms"] / 1e3, "converged": stt["converged"],
+                      "min_shift_vs_full_Ha": float(np.min(wt - w64))}
+        log(f"TDA PCG: rc={rct} iters={stt['iterations']} omega_TDA - omega_full >= "
+            f"{out['tda']['min_shift_vs_full_Ha']:.2e} Ha")
         if h64 is not h:
             h64.close()
 

@@ -122,6 +122,10 @@ typedef struct {
   double   eps_loose;        /* > eps_tol: adaptive inner tolerance eps_loose |g| / |g_0|
                                 (max_i ||g_i||_S now and at the first iteration) clamped
                                 to [eps_tol, eps_loose] (Sec. IV.A); 0 = constant eps_tol */
+  int32_t  tda;              /* 1: Tamm-Dancoff mode (B = 0, Sec. II.B): both halves see
+                                A = D + K, f_p = A P^p and f_q = A P^q; the solver keeps
+                                p = q (started from Pq) and returns eig(A).  Fixed at
+                                tddft_create like xc */
 } tddft_options;
 
 /* Per-solve statistics (host memory, caller-owned).  The log arrays are optional. */

@@ -27,7 +27,7 @@ class Operator:
     synthetic generator: S, H, K for both sets, the function sets and the pattern M)."""
 
     def __init__(self, sysm, xc: bool = True, hartree: bool = True, rho_floor: float = 1e-10,
-                 coupling_scale: float = 1.0):
+                 coupling_scale: float = 1.0, tda: bool = False):
         self.sys = sysm
         self.N = sysm.cfg.N
         self.L = sysm.cfg.L
@@ -40,6 +40,8 @@ class Operator:
         self.xc = xc
         self.hartree = hartree
         self.coupling_scale = coupling_scale
+        # Tamm-Dancoff approximation (Sec. II.B): B = 0, both halves see A = D + K
+        self.tda = tda
         self.rho_floor = rho_floor
         self.KcHu = self.Kc @ self.Hu
         self.HoKv = self.Ho @ self.Kv
@@ -70,9 +72,11 @@ class Operator:
         return grid.potential_integrals(self.N, self.h, self.sys.vir, self.sys.occ, V)
 
     def coupling(self, Pq: np.ndarray) -> np.ndarray:
-        """2 mask_M(K^c V_SCF[P^q] K^v) (times the optional test coupling scale)."""
+        """2 mask_M(K^c V_SCF[P^q] K^v) (times the optional test coupling scale); the factor
+        is 1 in the Tamm-Dancoff mode (A = D + K instead of A + B = D + 2K)."""
         Vm = self.vscf(Pq)
-        return self.coupling_scale * 2.0 * self.mask * (self.Kc @ Vm @ self.Kv)
+        factor = 1.0 if self.tda else 2.0
+        return self.coupling_scale * factor * self.mask * (self.Kc @ Vm @ self.Kv)
 
     # -- the operator ---------------------------------------------------------------------
     def apply(self, Pp: np.ndarray, Pq: np.ndarray):
@@ -83,6 +87,8 @@ class Operator:
         fq = np.stack([self.T(x) for x in Pq])
         if self.xc or self.hartree:
             fq = fq + self.coupling(Pq)
+            if self.tda:
+                fp = fp + self.coupling(Pp)
         return fp, fq
 
     # -- metric and projection -------------------------------------------------------------

@@ -71,6 +71,7 @@ void tddft_default_options(tddft_options *o) {
   o->model_bytes = 0;
   o->stream = nullptr;
   o->eps_loose = 0.0;
+  o->tda = 0;
 }
 
 int tddft_abi_version(void) { return TDDFT_ABI_VERSION; }
@@ -211,9 +212,9 @@ int tddft_pcg_solve(tddft_handle *hd, int32_t n, const tddft_options *opts, doub
   }
   tddft_options o = opts ? *opts : h.opts;
   if (o.precision != h.opts.precision || o.xc != h.opts.xc || o.rho_floor != h.opts.rho_floor ||
-      o.coupling_scale != h.opts.coupling_scale) {
-    h.last_error = "tddft_pcg_solve: precision, xc, rho_floor and coupling_scale are fixed at "
-                   "tddft_create and must match the handle's";
+      o.coupling_scale != h.opts.coupling_scale || o.tda != h.opts.tda) {
+    h.last_error = "tddft_pcg_solve: precision, xc, rho_floor, coupling_scale and tda are fixed "
+                   "at tddft_create and must match the handle's";
     return TDDFT_E_INVALID;
   }
   if (!(o.eps_tol > 0.0) || !(o.tol_omega > 0.0) || o.max_iter < 0 || o.max_inner < 0) {

@@ -584,7 +584,7 @@ void covariant_sets(Handle &h, int ncol, const T *X, int ldx, int x0, T *F, int 
 
 template <class T>
 void apply_sets(Handle &h, int n, const T *X, int ldx, int xp0, int xq0, T *F, int ldf, int fp0,
-                int fq0, bool coupling) {
+                int fq0, bool coupling, bool p_is_q) {
   hipStream_t s = h.stream;
   if (xq0 == xp0 + n && fq0 == fp0 + n) {
     kshift_sets<T>(h, 2 * n, X, ldx, xp0, F, ldf, fp0);
@@ -614,27 +614,41 @@ void apply_sets(Handle &h, int n, const T *X, int ldx, int xp0, int xq0, T *F, i
   DevTiles tl = h.tiles_uo;
   tl.usamp = h.usamp();
   tl.osamp = h.osamp();
-  h.prof.begin(ST_DENSITY, s);
-  density<T>(tl, st, h.BU, h.BO, X, ldx, xq0, n, fields, pstride, 1.0, s);
-  h.prof.end(ST_DENSITY, s);
-  hartree_xc<T>(h.geom, h.fft, npair, fields, work, h.fxc<T>(), h.opts.xc == TDDFT_XC_ALDA_X, s, &h.prof);
-  for (int s0 = 0; s0 < n; s0 += chunk) {
-    const int ns = std::min(chunk, n - s0);
-    // Vout columns s0.. of a set with n columns: offset the pointer by s0 * E
-    potential_integrals<T>(tl, h.partials, st, h.BU, h.BO, fields + (int64_t)(s0 / 2) * pstride, pstride,
-                           ns, part, Vset + (size_t)s0 * h.E, n, h.nO, h.dV, s, &h.prof);
+  // the coupling term K^c V_SCF[X] K^v of a group of n columns, added to F columns f0s
+  // with factor: full TDDFT 2 s on the q half (A + B = D + 2K); Tamm-Dancoff s on both
+  // halves (A = D + K), computed once when p and q hold the same vectors
+  auto couple = [&](int xc0, std::initializer_list<int> f0s, double factor) {
+    h.prof.begin(ST_DENSITY, s);
+    density<T>(tl, st, h.BU, h.BO, X, ldx, xc0, n, fields, pstride, 1.0, s);
+    h.prof.end(ST_DENSITY, s);
+    hartree_xc<T>(h.geom, h.fft, npair, fields, work, h.fxc<T>(), h.opts.xc == TDDFT_XC_ALDA_X, s, &h.prof);
+    for (int s0 = 0; s0 < n; s0 += chunk) {
+      const int ns = std::min(chunk, n - s0);
+      // Vout columns s0.. of a set with n columns: offset the pointer by s0 * E
+      potential_integrals<T>(tl, h.partials, st, h.BU, h.BO, fields + (int64_t)(s0 / 2) * pstride, pstride,
+                             ns, part, Vset + (size_t)s0 * h.E, n, h.nO, h.dV, s, &h.prof);
+    }
+    h.prof.begin(ST_SANDWICH_LEFT, s);
+    spmm_left<T>(h.pSw1, h.BU, h.BO, h.Kc.ptr<T>(), Vset, n, 0, Y, n, 0, n, 1.0, false, s);
+    h.prof.end(ST_SANDWICH_LEFT, s);
+    for (int f0 : f0s) {
+      h.prof.begin(ST_SANDWICH_RIGHT, s);
+      spmm_right<T>(h.pSw2, h.BU, h.BO, Y, n, 0, h.Kv.ptr<T>(), F, ldf, f0, n, factor, true, s);
+      h.prof.end(ST_SANDWICH_RIGHT, s);
+    }
+  };
+  if (!h.opts.tda) {
+    couple(xq0, {fq0}, 2.0 * h.opts.coupling_scale);
+  } else if (p_is_q) {
+    couple(xq0, {fp0, fq0}, h.opts.coupling_scale);
+  } else {
+    couple(xp0, {fp0}, h.opts.coupling_scale);
+    couple(xq0, {fq0}, h.opts.coupling_scale);
   }
-  h.prof.begin(ST_SANDWICH_LEFT, s);
-  spmm_left<T>(h.pSw1, h.BU, h.BO, h.Kc.ptr<T>(), Vset, n, 0, Y, n, 0, n, 1.0, false, s);
-  h.prof.end(ST_SANDWICH_LEFT, s);
-  h.prof.begin(ST_SANDWICH_RIGHT, s);
-  spmm_right<T>(h.pSw2, h.BU, h.BO, Y, n, 0, h.Kv.ptr<T>(), F, ldf, fq0, n,
-                2.0 * h.opts.coupling_scale, true, s);
-  h.prof.end(ST_SANDWICH_RIGHT, s);
 }
 
 #define TD_INST_APPLY(T)                                                                      \
-  template void apply_sets<T>(Handle &, int, const T *, int, int, int, T *, int, int, int, bool); \
+  template void apply_sets<T>(Handle &, int, const T *, int, int, int, T *, int, int, int, bool, bool); \
   template void kshift_sets<T>(Handle &, int, const T *, int, int, T *, int, int);             \
   template void project_sets<T>(Handle &, int, const T *, int, int, T *, int, int);            \
   template void project_t_sets<T>(Handle &, int, const T *, int, int, T *, int, int);          \

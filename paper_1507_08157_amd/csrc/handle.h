@@ -122,7 +122,7 @@ void create_handle(Handle &h, const tddft_system &sys, const tddft_options &o);
 // X: column set on R with ld columns; p columns [xp0, xp0 + n), q columns [xq0, xq0 + n).
 template <class T>
 void apply_sets(Handle &h, int n, const T *X, int ldx, int xp0, int xq0, T *F, int ldf, int fp0,
-                int fq0, bool coupling);
+                int fq0, bool coupling, bool p_is_q = false);
 template <class T>
 void kshift_sets(Handle &h, int ncol, const T *X, int ldx, int x0, T *F, int ldf, int f0);
 // Pi(L) = K^c S^u L S^o K^v: L on M, result on R

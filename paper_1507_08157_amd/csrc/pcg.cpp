@@ -452,7 +452,8 @@ static int solve_impl(Handle &h, int n, const tddft_options &o, double *omega, d
   float apply_ms = 0.0f;
   auto apply = [&](const T *X, T *Fo) {
     TD_HIP(hipEventRecord(h.ev0, s));
-    apply_sets<T>(h, n, X, nc, 0, n, Fo, nc, 0, n, true);
+    // Tamm-Dancoff: p and q hold the same vectors throughout (same start, same updates)
+    apply_sets<T>(h, n, X, nc, 0, n, Fo, nc, 0, n, true, h.opts.tda != 0);
     TD_HIP(hipEventRecord(h.ev1, s));
     TD_HIP(hipEventSynchronize(h.ev1));
     float ms = 0.0f;
@@ -468,7 +469,7 @@ static int solve_impl(Handle &h, int n, const tddft_options &o, double *omega, d
   {
     T *tmpR = set(T1);
     if (Pp && Pq) {
-      pack<T>(nR, h.BU, h.BO, n, Pp, h.nnzR, h.r_voff.p, h.r_shape.p, tmpR, nc, 0, s);
+      pack<T>(nR, h.BU, h.BO, n, h.opts.tda ? Pq : Pp, h.nnzR, h.r_voff.p, h.r_shape.p, tmpR, nc, 0, s);
       pack<T>(nR, h.BU, h.BO, n, Pq, h.nnzR, h.r_voff.p, h.r_shape.p, tmpR, nc, n, s);
     } else {
       // seeded N(0,1) (SplitMix64 + Box-Muller), the same matrix for p and q

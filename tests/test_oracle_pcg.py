@@ -169,3 +169,17 @@ def test_adaptive_inner_tolerance_reaches_brute_force(dense):
     r = Solver(op, Options(n_states=n, eps_loose=0.1, tol_omega=1e-10, max_iter=300)).solve(s.guess())
     assert r.converged
     assert np.max(np.abs(r.omega - cs.omega_hermitian()[:n])) < 1e-9
+
+
+def test_tamm_dancoff_mode_reaches_tda_brute_force(dense):
+    """B = 0: the Tsiper functional of p = q is the Rayleigh quotient of A, so the solver
+    returns the lowest eigenvalues of A (dense TDA diagonalisation), which lie above the
+    full-TDDFT ones."""
+    s, _, cs = dense
+    n = s.cfg.n_states
+    op = Operator(s, tda=True)
+    r = Solver(op, Options(n_states=n, tol_omega=1e-10, max_iter=300)).solve(s.guess())
+    assert r.converged
+    ref = cs.omega_tda()[:n]
+    assert np.max(np.abs(r.omega - ref)) < 1e-9
+    assert np.all(ref >= cs.omega_hermitian()[:n] - 1e-12)
