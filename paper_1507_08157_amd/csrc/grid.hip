@@ -246,7 +246,7 @@ __global__ __launch_bounds__(256) void k_vint(DevTiles tl, const int64_t *__rest
 // with the 64 points as the contraction.  One wave per tile runs it as 16 x 16 output
 // blocks of v_mfma_f32_16x16x4f32; the sum over points is order-free, so lane group
 // q = lane / 16 takes points 16 q .. 16 q + 15 and every operand fragment is a run of 16
-// consecutive samples (wide loads).  Up to 48 u-rows of A stay in registers while the
+// consecutive samples (wide loads).  Up to 32 u-rows of A stay in registers while the
 // (o-row, state) blocks stream by.
 typedef float v4f __attribute__((ext_vector_type(4)));
 
@@ -268,6 +268,7 @@ __global__ __launch_bounds__(256) void k_vint_mfma(DevTiles tl, const int64_t *_
                                                    int ns, float *__restrict__ partial, float scale) {
   extern __shared__ unsigned char lds_raw[];
   constexpr int LD = TP + 4;   // padded rows: the 16-byte reads of different rows use different banks
+  constexpr int MG = 2;        // 16-row blocks of u-rows held in registers at a time
   const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
   const int t = blockIdx.x * (blockDim.x >> 6) + w;
@@ -299,10 +300,10 @@ __global__ __launch_bounds__(256) void k_vint_mfma(DevTiles tl, const int64_t *_
   const int q = lane >> 4, c16 = lane & 15;
   float *dst = partial + tbase[t] * ns;
   const S *ut = usamp + (int64_t)u0 * BL * TP;
-  for (int mg = 0; mg < rows_u; mg += 48) {
-    float a[3][16];
+  for (int mg = 0; mg < rows_u; mg += 16 * MG) {
+    float a[MG][16];
 #pragma unroll
-    for (int mb = 0; mb < 3; ++mb) {
+    for (int mb = 0; mb < MG; ++mb) {
       const int m = mg + mb * 16 + c16;
       if (m < rows_u) {
         load16<S>(ut + (int64_t)m * TP + 16 * q, a[mb]);
@@ -331,7 +332,7 @@ __global__ __launch_bounds__(256) void k_vint_mfma(DevTiles tl, const int64_t *_
         }
       }
 #pragma unroll
-      for (int mb = 0; mb < 3; ++mb) {
+      for (int mb = 0; mb < MG; ++mb) {
         if (mg + mb * 16 >= rows_u) break;
         v4f acc = {0.0f, 0.0f, 0.0f, 0.0f};
 #pragma unroll
