@@ -244,6 +244,8 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--stage-steps", type=int, default=10,
+                    help="applies of the profiled (serialized) stage pass")
     ap.add_argument("--workload", default="prec")
     ap.add_argument("--precision", default="fp32", choices=["fp64", "fp32", "bf16"])
     ap.add_argument("--no-solve", action="store_true")
@@ -290,30 +292,40 @@ def main():
     for _ in range(a.warmup):
         h.tddft_apply(Pp, Pq, fp, fq)
     torch.cuda.synchronize()
+    # timed region: exactly `steps` applies, no profiling (the K-shift products overlap the
+    # coupling term on the handle's second stream)
+    value = None
+    dt = 0.0
+    if a.steps > 0:
+        t1 = time.perf_counter()
+        for _ in range(a.steps):
+            h.tddft_apply(Pp, Pq, fp, fq)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t1
+        value = n * a.steps / dt
+        log(f"{a.steps} applies x {n} states in {dt * 1e3:.1f} ms -> {value:.1f} state-applies/s")
+    # stage pass: the same applies with per-stage HIP events; while profiling is on the
+    # stages run one after another on the handle's stream, so each stage time is its own
     h.tddft_profile(True)
     torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    for _ in range(a.steps):
+    for _ in range(a.stage_steps):
         h.tddft_apply(Pp, Pq, fp, fq)
     torch.cuda.synchronize()
-    dt = time.perf_counter() - t1
     prof = h.tddft_profile_read()
     h.tddft_profile(False)
-    value = n * a.steps / dt
-    log(f"{a.steps} applies x {n} states in {dt * 1e3:.1f} ms -> {value:.1f} state-applies/s")
-    log("stages (ms per launch): " + ", ".join(
+    log("stages (ms per launch, serialized): " + ", ".join(
         f"{k}={v[0] / max(v[1], 1):.3f}" for k, v in prof.items() if v[1]))
     roof = roofline(info, prof, n, prec, a.workload, a.precision)
 
     out = {
         "metric": "(A±B)P1 applies/sec + time to omega within 1e-5 Ha, learned/mixed "
                   "vs plain PCG",
-        "value": round(value, 2),
+        "value": round(value, 2) if value is not None else None,
         "unit": "state-applies/s",
         "n_gpus": 1,
         "steps": a.steps,
         "warmup": a.warmup,
-        "ms_per_step": round(dt * 1e3 / a.steps, 4),
+        "ms_per_step": round(dt * 1e3 / a.steps, 4) if a.steps > 0 else None,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,

@@ -307,6 +307,9 @@ const char *tddft_mlp_last_error(const tddft_mlp *m);
 
 /* Device-time profiling of the kernel stages (HIP events recorded on the handle's stream
  * around each stage; enabling it adds event records and host waits, not extra kernels).
+ * Outside profiling an application runs its K-shift products on a second stream of the
+ * handle, beside the coupling term; while profiling is on, every stage runs on the
+ * handle's stream one after another, so that each stage's time is its own.
  * tddft_profile(h, 1) enables and zeroes the counters, tddft_profile(h, 0) disables.
  * tddft_profile_read copies up to cap entries of accumulated milliseconds and execution
  * counts per stage (caller-owned host arrays) and returns the number of stages;

@@ -91,6 +91,34 @@ __device__ __forceinline__ void dft(typename C2<T>::type (&v)[R]) {
     v[2].x = a0.x - a2.x; v[2].y = a0.y - a2.y;
     v[1].x = a1.x + a3.x; v[1].y = a1.y + a3.y;
     v[3].x = a1.x - a3.x; v[3].y = a1.y - a3.y;
+  } else if constexpr (R == 8) {
+    // X[2m] = DFT4(v[k] + v[k+4]),  X[2m+1] = DFT4((v[k] - v[k+4]) w^k),  w = e^{SIGN i pi/4}
+    const T h = (T)0.707106781186547524401;
+    T2 a[4], b[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      a[k].x = v[k].x + v[k + 4].x; a[k].y = v[k].y + v[k + 4].y;
+      b[k].x = v[k].x - v[k + 4].x; b[k].y = v[k].y - v[k + 4].y;
+    }
+    {
+      const T x = b[1].x, y = b[1].y;
+      b[1].x = (x - SIGN * y) * h; b[1].y = (SIGN * x + y) * h;
+    }
+    {
+      const T x = b[2].x, y = b[2].y;
+      b[2].x = -SIGN * y; b[2].y = SIGN * x;
+    }
+    {
+      const T x = b[3].x, y = b[3].y;
+      b[3].x = (-x - SIGN * y) * h; b[3].y = (SIGN * x - y) * h;
+    }
+    dft<T, 4, SIGN>(a);
+    dft<T, 4, SIGN>(b);
+#pragma unroll
+    for (int m = 0; m < 4; ++m) {
+      v[2 * m] = a[m];
+      v[2 * m + 1] = b[m];
+    }
   } else {
     T2 o[R];
 #pragma unroll
@@ -149,8 +177,55 @@ __device__ void fft_pass(const typename C2<T>::type *__restrict__ in,
   }
 }
 
-// full transform of the lines in buffer a (scratch b); returns the buffer with the result
-template <class T, int SIGN>
+// In-place variant of a pass: each thread first reads the inputs of all its butterflies
+// (at most max(1, 8 / R) of them), the workgroup synchronises, and the results then
+// overwrite the same buffer.  One LDS buffer instead of two doubles the workgroups a CU can
+// hold; the host takes this form when every pass of the axis fits (nlines * N / R <=
+// max(1, 8 / R) * blockDim) and the axis has no factor 7 (whose O(R^2) DFT would raise the
+// register count of every pass, and with it cost the occupancy gained).
+template <class T, int R, int SIGN>
+__device__ void fft_pass_inplace(typename C2<T>::type *__restrict__ buf, int N, int Ns, int ldl,
+                                 int nlines, const typename C2<T>::type *__restrict__ tw) {
+  using T2 = typename C2<T>::type;
+  constexpr int NIT = R >= 8 ? 1 : 8 / R;
+  const int nb = N / R;
+  const int total = nlines * nb;
+  T2 v[NIT][R];
+#pragma unroll
+  for (int it = 0; it < NIT; ++it) {
+    const int q = threadIdx.x + it * blockDim.x;
+    if (q < total) {
+      const int line = q / nb, j = q - line * nb;
+#pragma unroll
+      for (int r = 0; r < R; ++r) v[it][r] = buf[line * ldl + j + r * nb];
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int it = 0; it < NIT; ++it) {
+    const int q = threadIdx.x + it * blockDim.x;
+    if (q < total) {
+      const int line = q / nb, j = q - line * nb;
+      const int k = j % Ns;
+      if (Ns > 1) {
+#pragma unroll
+        for (int r = 1; r < R; ++r) {
+          T2 w = tw[k * (R - 1) + r - 1];
+          if (SIGN > 0) w.y = -w.y;
+          v[it][r] = cmul(v[it][r], w);
+        }
+      }
+      dft<T, R, SIGN>(v[it]);
+      const int d = (j - k) * R + k;
+#pragma unroll
+      for (int r = 0; r < R; ++r) buf[line * ldl + d + r * Ns] = v[it][r];
+    }
+  }
+}
+
+// full transform of the lines in buffer a (scratch b, unused when INPL); returns the
+// buffer with the result
+template <class T, int SIGN, bool INPL>
 __device__ typename C2<T>::type *fft_lines(typename C2<T>::type *a, typename C2<T>::type *b,
                                            int ldl, int nlines, const AxisDev &ax,
                                            const typename C2<T>::type *tw) {
@@ -158,18 +233,29 @@ __device__ typename C2<T>::type *fft_lines(typename C2<T>::type *a, typename C2<
   for (int p = 0; p < ax.npass; ++p) {
     const int R = ax.radix[p];
     const typename C2<T>::type *t = tw + ax.tw_off[p];
-    switch (R) {
-      case 2: fft_pass<T, 2, SIGN>(a, b, ax.n, Ns, ldl, nlines, t); break;
-      case 3: fft_pass<T, 3, SIGN>(a, b, ax.n, Ns, ldl, nlines, t); break;
-      case 4: fft_pass<T, 4, SIGN>(a, b, ax.n, Ns, ldl, nlines, t); break;
-      case 5: fft_pass<T, 5, SIGN>(a, b, ax.n, Ns, ldl, nlines, t); break;
-      case 7: fft_pass<T, 7, SIGN>(a, b, ax.n, Ns, ldl, nlines, t); break;
-      default: fft_pass<T, 8, SIGN>(a, b, ax.n, Ns, ldl, nlines, t); break;
+    if constexpr (INPL) {
+      switch (R) {
+        case 2: fft_pass_inplace<T, 2, SIGN>(a, ax.n, Ns, ldl, nlines, t); break;
+        case 3: fft_pass_inplace<T, 3, SIGN>(a, ax.n, Ns, ldl, nlines, t); break;
+        case 4: fft_pass_inplace<T, 4, SIGN>(a, ax.n, Ns, ldl, nlines, t); break;
+        case 5: fft_pass_inplace<T, 5, SIGN>(a, ax.n, Ns, ldl, nlines, t); break;
+        default: fft_pass_inplace<T, 8, SIGN>(a, ax.n, Ns, ldl, nlines, t); break;
+      }
+      __syncthreads();
+    } else {
+      switch (R) {
+        case 2: fft_pass<T, 2, SIGN>(a, b, ax.n, Ns, ldl, nlines, t); break;
+        case 3: fft_pass<T, 3, SIGN>(a, b, ax.n, Ns, ldl, nlines, t); break;
+        case 4: fft_pass<T, 4, SIGN>(a, b, ax.n, Ns, ldl, nlines, t); break;
+        case 5: fft_pass<T, 5, SIGN>(a, b, ax.n, Ns, ldl, nlines, t); break;
+        case 7: fft_pass<T, 7, SIGN>(a, b, ax.n, Ns, ldl, nlines, t); break;
+        default: fft_pass<T, 8, SIGN>(a, b, ax.n, Ns, ldl, nlines, t); break;
+      }
+      __syncthreads();
+      typename C2<T>::type *tmp = a;
+      a = b;
+      b = tmp;
     }
-    __syncthreads();
-    typename C2<T>::type *tmp = a;
-    a = b;
-    b = tmp;
     Ns *= R;
   }
   return a;
@@ -183,7 +269,7 @@ struct GeomDev {
 
 // ---- pass 1: x forward, tile-major -> natural ---------------------------------------------
 // one workgroup per row of tiles (ty, tz): 16 x-lines, contiguous in the tile-major layout
-template <class T>
+template <class T, bool INPL>
 __global__ __launch_bounds__(256) void k_fft_x_fwd(GeomDev g, AxisDev ax,
                                                    const typename C2<T>::type *__restrict__ tw,
                                                    const typename C2<T>::type *__restrict__ fields,
@@ -192,7 +278,7 @@ __global__ __launch_bounds__(256) void k_fft_x_fwd(GeomDev g, AxisDev ax,
   extern __shared__ unsigned char lds_raw[];
   T2 *a = reinterpret_cast<T2 *>(lds_raw);
   const int ldl = g.nx + 1;   // odd row length (in complex values): lines start on different banks
-  T2 *b = a + 16 * ldl;
+  T2 *b = INPL ? a : a + 16 * ldl;
   const int row = blockIdx.x;           // ty + nty * tz
   const int ty = row % g.nty, tz = row / g.nty;
   const int pair = blockIdx.y;
@@ -205,7 +291,7 @@ __global__ __launch_bounds__(256) void k_fft_x_fwd(GeomDev g, AxisDev ax,
     if (x < g.nx) a[l * ldl + x] = src[e];
   }
   __syncthreads();
-  T2 *res = fft_lines<T, -1>(a, b, ldl, 16, ax, tw);
+  T2 *res = fft_lines<T, -1, INPL>(a, b, ldl, 16, ax, tw);
   for (int e = threadIdx.x; e < 16 * g.nx; e += blockDim.x) {
     const int l = e / g.nx, x = e - l * g.nx;
     const int y = ty * 4 + (l & 3), z = tz * 4 + (l >> 2);
@@ -217,7 +303,7 @@ __global__ __launch_bounds__(256) void k_fft_x_fwd(GeomDev g, AxisDev ax,
 // ---- pass 2/4: y lines in place ---------------------------------------------------------
 constexpr int XB = 16;   // x-columns per workgroup in the strided passes
 
-template <class T, int SIGN>
+template <class T, int SIGN, bool INPL>
 __global__ __launch_bounds__(256) void k_fft_y(GeomDev g, AxisDev ax,
                                                const typename C2<T>::type *__restrict__ tw,
                                                typename C2<T>::type *__restrict__ work) {
@@ -225,7 +311,7 @@ __global__ __launch_bounds__(256) void k_fft_y(GeomDev g, AxisDev ax,
   extern __shared__ unsigned char lds_raw[];
   T2 *a = reinterpret_cast<T2 *>(lds_raw);
   const int ldl = g.ny + 1;
-  T2 *b = a + XB * ldl;
+  T2 *b = INPL ? a : a + XB * ldl;
   const int nxb = (g.nx + XB - 1) / XB;
   const int xb = blockIdx.x % nxb, z = blockIdx.x / nxb;
   const int x0 = xb * XB;
@@ -236,7 +322,7 @@ __global__ __launch_bounds__(256) void k_fft_y(GeomDev g, AxisDev ax,
     if (l < nl) a[l * ldl + y] = base[(int64_t)y * g.nx + l];
   }
   __syncthreads();
-  T2 *res = fft_lines<T, SIGN>(a, b, ldl, nl, ax, tw);
+  T2 *res = fft_lines<T, SIGN, INPL>(a, b, ldl, nl, ax, tw);
   for (int e = threadIdx.x; e < XB * g.ny; e += blockDim.x) {
     const int y = e / XB, l = e - y * XB;
     if (l < nl) base[(int64_t)y * g.nx + l] = res[l * ldl + y];
@@ -244,7 +330,7 @@ __global__ __launch_bounds__(256) void k_fft_y(GeomDev g, AxisDev ax,
 }
 
 // ---- pass 3: z lines, forward, Poisson kernel, inverse -----------------------------------
-template <class T>
+template <class T, bool INPL>
 __global__ __launch_bounds__(256) void k_fft_z_poisson(GeomDev g, AxisDev ax,
                                                        const typename C2<T>::type *__restrict__ tw,
                                                        typename C2<T>::type *__restrict__ work,
@@ -254,7 +340,7 @@ __global__ __launch_bounds__(256) void k_fft_z_poisson(GeomDev g, AxisDev ax,
   extern __shared__ unsigned char lds_raw[];
   T2 *a = reinterpret_cast<T2 *>(lds_raw);
   const int ldl = g.nz + 1;
-  T2 *b = a + XB * ldl;
+  T2 *b = INPL ? a : a + XB * ldl;
   const int nxb = (g.nx + XB - 1) / XB;
   const int xb = blockIdx.x % nxb, y = blockIdx.x / nxb;
   const int x0 = xb * XB;
@@ -266,7 +352,7 @@ __global__ __launch_bounds__(256) void k_fft_z_poisson(GeomDev g, AxisDev ax,
     if (l < nl) a[l * ldl + z] = base[(int64_t)z * plane + l];
   }
   __syncthreads();
-  T2 *res = fft_lines<T, -1>(a, b, ldl, nl, ax, tw);
+  T2 *res = fft_lines<T, -1, INPL>(a, b, ldl, nl, ax, tw);
   // multiply by 4 pi / |G|^2 (G = 0 -> 0) including the 1/(nx ny nz) normalisation
   const int ky = y <= g.ny / 2 ? y : y - g.ny;
   for (int e = threadIdx.x; e < nl * g.nz; e += blockDim.x) {
@@ -282,8 +368,8 @@ __global__ __launch_bounds__(256) void k_fft_z_poisson(GeomDev g, AxisDev ax,
     res[l * ldl + z] = v;
   }
   __syncthreads();
-  T2 *other = (res == a) ? b : a;
-  T2 *res2 = fft_lines<T, 1>(res, other, ldl, nl, ax, tw);
+  T2 *other = INPL ? res : ((res == a) ? b : a);
+  T2 *res2 = fft_lines<T, 1, INPL>(res, other, ldl, nl, ax, tw);
   for (int e = threadIdx.x; e < XB * g.nz; e += blockDim.x) {
     const int z = e / XB, l = e - z * XB;
     if (l < nl) base[(int64_t)z * plane + l] = res2[l * ldl + z];
@@ -291,7 +377,7 @@ __global__ __launch_bounds__(256) void k_fft_z_poisson(GeomDev g, AxisDev ax,
 }
 
 // ---- pass 5: x inverse, natural -> tile-major, plus f_xc rho ---------------------------------
-template <class T>
+template <class T, bool INPL>
 __global__ __launch_bounds__(256) void k_fft_x_inv(GeomDev g, AxisDev ax,
                                                    const typename C2<T>::type *__restrict__ tw,
                                                    const typename C2<T>::type *__restrict__ work,
@@ -301,7 +387,7 @@ __global__ __launch_bounds__(256) void k_fft_x_inv(GeomDev g, AxisDev ax,
   extern __shared__ unsigned char lds_raw[];
   T2 *a = reinterpret_cast<T2 *>(lds_raw);
   const int ldl = g.nx + 1;   // odd row length (in complex values): lines start on different banks
-  T2 *b = a + 16 * ldl;
+  T2 *b = INPL ? a : a + 16 * ldl;
   const int row = blockIdx.x;
   const int ty = row % g.nty, tz = row / g.nty;
   const int pair = blockIdx.y;
@@ -315,7 +401,7 @@ __global__ __launch_bounds__(256) void k_fft_x_inv(GeomDev g, AxisDev ax,
     a[l * ldl + x] = v;
   }
   __syncthreads();
-  T2 *res = fft_lines<T, 1>(a, b, ldl, 16, ax, tw);
+  T2 *res = fft_lines<T, 1, INPL>(a, b, ldl, 16, ax, tw);
   T2 *dst = fields + pair * g.pair_tile + (int64_t)row * g.ntx * TP;
   const T *fx = fxc + (int64_t)row * g.ntx * TP;
   const int ntot = g.ntx * TP;
@@ -370,31 +456,46 @@ void hartree_xc(const GridGeom &gg, const FFTPlan &plan, int npair, T *fields, T
   const double scale = 4.0 * pi / ((double)gg.n[0] * gg.n[1] * gg.n[2]);
   const unsigned rows = (unsigned)(gg.nty * gg.ntz);
   const unsigned nxb = (unsigned)((gg.n[0] + XB - 1) / XB);
-  const size_t lx = 2 * 16 * (size_t)(gg.n[0] + 1) * sizeof(T2);
-  const size_t ly = 2 * XB * (size_t)(gg.n[1] + 1) * sizeof(T2);
-  const size_t lz = 2 * XB * (size_t)(gg.n[2] + 1) * sizeof(T2);
+  // in-place passes (one LDS buffer) when every radix pass of the axis fits the per-thread
+  // butterfly budget of fft_pass_inplace for 16 lines on 256 threads
+  auto inplace = [](const AxisFFT &a) {
+    for (int R : a.radix)
+      if (R == 7 || 16 * (a.n / R) > (R >= 8 ? 1 : 8 / R) * 256) return false;
+    return true;
+  };
+  const bool ix = inplace(plan.ax[0]), iy = inplace(plan.ax[1]), iz = inplace(plan.ax[2]);
+  const size_t lx = (ix ? 1 : 2) * 16 * (size_t)(gg.n[0] + 1) * sizeof(T2);
+  const size_t ly = (iy ? 1 : 2) * XB * (size_t)(gg.n[1] + 1) * sizeof(T2);
+  const size_t lz = (iz ? 1 : 2) * XB * (size_t)(gg.n[2] + 1) * sizeof(T2);
   Prof dummy;
   Prof &pf = prof ? *prof : dummy;
   pf.begin(ST_FFT_X_FWD, s);
-  hipLaunchKernelGGL((k_fft_x_fwd<T>), dim3(rows, npair), dim3(256), lx, s, g, ax, tw + off[0], F, W);
+  if (ix) hipLaunchKernelGGL((k_fft_x_fwd<T, true>), dim3(rows, npair), dim3(256), lx, s, g, ax, tw + off[0], F, W);
+  else hipLaunchKernelGGL((k_fft_x_fwd<T, false>), dim3(rows, npair), dim3(256), lx, s, g, ax, tw + off[0], F, W);
   TD_HIP(hipGetLastError());
   pf.end(ST_FFT_X_FWD, s);
   pf.begin(ST_FFT_Y_FWD, s);
-  hipLaunchKernelGGL((k_fft_y<T, -1>), dim3(nxb * gg.n[2], npair), dim3(256), ly, s, g, ay, tw + off[1], W);
+  if (iy) hipLaunchKernelGGL((k_fft_y<T, -1, true>), dim3(nxb * gg.n[2], npair), dim3(256), ly, s, g, ay, tw + off[1], W);
+  else hipLaunchKernelGGL((k_fft_y<T, -1, false>), dim3(nxb * gg.n[2], npair), dim3(256), ly, s, g, ay, tw + off[1], W);
   TD_HIP(hipGetLastError());
   pf.end(ST_FFT_Y_FWD, s);
   pf.begin(ST_FFT_Z_POISSON, s);
-  hipLaunchKernelGGL((k_fft_z_poisson<T>), dim3(nxb * gg.n[1], npair), dim3(256), lz, s, g, az,
-                     tw + off[2], W, gx, gy, gz, scale);
+  if (iz) hipLaunchKernelGGL((k_fft_z_poisson<T, true>), dim3(nxb * gg.n[1], npair), dim3(256), lz, s, g, az,
+                             tw + off[2], W, gx, gy, gz, scale);
+  else hipLaunchKernelGGL((k_fft_z_poisson<T, false>), dim3(nxb * gg.n[1], npair), dim3(256), lz, s, g, az,
+                          tw + off[2], W, gx, gy, gz, scale);
   TD_HIP(hipGetLastError());
   pf.end(ST_FFT_Z_POISSON, s);
   pf.begin(ST_FFT_Y_INV, s);
-  hipLaunchKernelGGL((k_fft_y<T, 1>), dim3(nxb * gg.n[2], npair), dim3(256), ly, s, g, ay, tw + off[1], W);
+  if (iy) hipLaunchKernelGGL((k_fft_y<T, 1, true>), dim3(nxb * gg.n[2], npair), dim3(256), ly, s, g, ay, tw + off[1], W);
+  else hipLaunchKernelGGL((k_fft_y<T, 1, false>), dim3(nxb * gg.n[2], npair), dim3(256), ly, s, g, ay, tw + off[1], W);
   TD_HIP(hipGetLastError());
   pf.end(ST_FFT_Y_INV, s);
   pf.begin(ST_FFT_X_INV, s);
-  hipLaunchKernelGGL((k_fft_x_inv<T>), dim3(rows, npair), dim3(256), lx, s, g, ax, tw + off[0], W, F,
-                     fxc, use_fxc ? 1 : 0);
+  if (ix) hipLaunchKernelGGL((k_fft_x_inv<T, true>), dim3(rows, npair), dim3(256), lx, s, g, ax, tw + off[0], W, F,
+                             fxc, use_fxc ? 1 : 0);
+  else hipLaunchKernelGGL((k_fft_x_inv<T, false>), dim3(rows, npair), dim3(256), lx, s, g, ax, tw + off[0], W, F,
+                          fxc, use_fxc ? 1 : 0);
   TD_HIP(hipGetLastError());
   pf.end(ST_FFT_X_INV, s);
 }

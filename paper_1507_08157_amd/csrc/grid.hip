@@ -283,25 +283,10 @@ __global__ __launch_bounds__(256) void k_vint_mfma(DevTiles tl, const int64_t *_
   }
   const int rows_u = nua * BL, rows_o = noa * BR;
   const int items = rows_o * ns;
-  // stage the tile's o-rows and the states' potentials (real states, de-interleaved)
-  {
-    const S *ot = osamp + (int64_t)o0 * BR * TP;
-    for (int i = lane; i < rows_o * TP; i += 64) lo[(i / TP) * LD + (i % TP)] = cvt<float>(ot[i]);
-    if (t < tl.nt) {
-      const float *vt = V + (int64_t)t * TP * 2;
-      for (int i = lane; i < ns * TP; i += 64) {
-        const int sidx = i / TP, p = i % TP;
-        lv[sidx * LD + p] = vt[(int64_t)(sidx >> 1) * pair_stride + 2 * p + (sidx & 1)];
-      }
-    }
-  }
-  __syncthreads();
-  if (t >= tl.nt) return;
   const int q = lane >> 4, c16 = lane & 15;
-  float *dst = partial + tbase[t] * ns;
   const S *ut = usamp + (int64_t)u0 * BL * TP;
-  for (int mg = 0; mg < rows_u; mg += 16 * MG) {
-    float a[MG][16];
+  float a[MG][16];
+  auto load_u = [&](int mg) {
 #pragma unroll
     for (int mb = 0; mb < MG; ++mb) {
       const int m = mg + mb * 16 + c16;
@@ -312,6 +297,50 @@ __global__ __launch_bounds__(256) void k_vint_mfma(DevTiles tl, const int64_t *_
         for (int k = 0; k < 16; ++k) a[mb][k] = 0.0f;
       }
     }
+  };
+  // the first u-row blocks are requested before the staging loads, so that both are in
+  // flight together
+  load_u(0);
+  // stage the tile's o-rows (four samples per load) and the states' potentials (one complex
+  // pair per load, de-interleaved into the two real states).  Loads go out in batches of
+  // four per lane before any LDS write, so a batch costs one memory round trip.
+  {
+    const S *ot = osamp + (int64_t)o0 * BR * TP;
+    const float *vt = V + (int64_t)t * TP * 2;
+    const int n_o4 = rows_o * (TP / 4);
+    const int n_v2 = t < tl.nt ? ((ns + 1) / 2) * TP : 0;
+    for (int i0 = lane; i0 < n_o4 || i0 < n_v2; i0 += 4 * 64) {
+      float o4[4][4];
+      float2 v2[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int i = i0 + 64 * u;
+        if (i < n_o4) load4<float, S>(ot + 4 * i, o4[u]);
+        if (i < n_v2) {
+          const int sp = i / TP, p = i % TP;
+          v2[u] = *reinterpret_cast<const float2 *>(vt + (int64_t)sp * pair_stride + 2 * p);
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int i = i0 + 64 * u;
+        if (i < n_o4) {
+          float *d = lo + (i / (TP / 4)) * LD + 4 * (i % (TP / 4));
+          *reinterpret_cast<float4 *>(d) = make_float4(o4[u][0], o4[u][1], o4[u][2], o4[u][3]);
+        }
+        if (i < n_v2) {
+          const int sp = i / TP, p = i % TP;
+          lv[(2 * sp) * LD + p] = v2[u].x;
+          if (2 * sp + 1 < ns) lv[(2 * sp + 1) * LD + p] = v2[u].y;
+        }
+      }
+    }
+  }
+  __syncthreads();
+  if (t >= tl.nt) return;
+  float *dst = partial + tbase[t] * ns;
+  for (int mg = 0; mg < rows_u; mg += 16 * MG) {
+    if (mg > 0) load_u(mg);
     for (int n0 = 0; n0 < items; n0 += 16) {
       const int n = n0 + c16;
       const bool active = n < items;
@@ -354,52 +383,65 @@ __global__ __launch_bounds__(256) void k_vint_mfma(DevTiles tl, const int64_t *_
   }
 }
 
-// Vout[ob][ldv][E] (columns 0..ns) = sum over the contributions of block ob.  One wave
-// per overlap block, one lane per (element, state); each contribution is a contiguous run
-// of E * ns partial sums.  The wave fetches 64 contribution offsets at once with one vector
-// load and broadcasts them lane by lane, keeping eight partial-sum loads in flight; the
-// sum order is fixed (reproducible).
-template <class T>
-__global__ __launch_bounds__(256) void k_vint_reduce(int64_t nblk, int ns, int E,
+// Vout[ob][ldv][E] (columns 0..ns) = sum over the contributions of block ob.  Each
+// contribution is a contiguous run of per = E * ns partial sums, read as per / V vectors
+// of V elements.  One wave per overlap block: when a run needs at most 64 lanes, the wave
+// splits into G = 64 / (per / V) lane groups that walk the block's contributions G at a
+// time (group g takes contributions g, g + G, ...), eight loads in flight per lane; the
+// groups' sums are then added into group 0 in group order.  Longer runs are covered in
+// chunks of 64 lanes with G = 1.  Contribution indices arrive 64 at a time with one vector
+// load and reach the groups by lane shuffles.  Every sum has a fixed order (reproducible).
+template <class T, int V>
+__global__ __launch_bounds__(256) void k_vint_reduce(int64_t nblk, int ns, int E, int G,
                                                      const int64_t *__restrict__ cptr,
-                                                     const int64_t *__restrict__ cbase,
+                                                     const int32_t *__restrict__ cidx,
                                                      const T *__restrict__ partial,
                                                      T *__restrict__ Vout, int ldv) {
+  using TV = T __attribute__((ext_vector_type(V)));
   const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
   const int64_t ob = (int64_t)blockIdx.x * (blockDim.x >> 6) + w;
   if (ob >= nblk) return;
   const int per = ns * E;
+  const int lpc = per / V;
+  const int g = G > 1 ? lane / lpc : 0;
+  const int jl = G > 1 ? lane - g * lpc : lane;
   const int64_t q0 = cptr[ob], q1 = cptr[ob + 1];
-  for (int idx0 = 0; idx0 < per; idx0 += 64) {
-    const int idx = idx0 + lane;
-    const bool on = idx < per;
-    const int64_t off = on ? idx : 0;
-    T a[8];
+  for (int j0 = 0; j0 < lpc; j0 += 64) {
+    const int j = j0 + jl;
+    const bool on = g < G && j < lpc;
+    const int64_t off = on ? (int64_t)j * V : 0;
+    TV a[8];
 #pragma unroll
-    for (int u = 0; u < 8; ++u) a[u] = T(0);
+    for (int u = 0; u < 8; ++u) a[u] = TV(0);
     for (int64_t qb = q0; qb < q1; qb += 64) {
       const int cnt = (int)(q1 - qb < 64 ? q1 - qb : 64);
-      const int64_t mine = qb + lane < q1 ? cbase[qb + lane] * ns : 0;
-      const int lo = (int)(uint32_t)mine, hi = (int)(uint32_t)(mine >> 32);
-      int k = 0;
-      for (; k + 8 <= cnt; k += 8) {
+      const int mine = qb + lane < q1 ? cidx[qb + lane] : 0;
+      // rounds of eight steps of G contributions (the last round predicated), so that
+      // every round keeps eight independent loads in flight
+      for (int k = 0; k * G < cnt; k += 8) {
 #pragma unroll
         for (int u = 0; u < 8; ++u) {
-          const int64_t base = ((int64_t)(uint32_t)__builtin_amdgcn_readlane(hi, k + u) << 32) |
-                               (uint32_t)__builtin_amdgcn_readlane(lo, k + u);
-          a[u] += partial[base + off];
+          const int src = (k + u) * G + g;
+          const int c = __shfl(mine, src & 63);
+          if (on && src < cnt) a[u] += *reinterpret_cast<const TV *>(partial + (int64_t)c * per + off);
         }
       }
-      for (; k < cnt; ++k) {
-        const int64_t base = ((int64_t)(uint32_t)__builtin_amdgcn_readlane(hi, k) << 32) |
-                             (uint32_t)__builtin_amdgcn_readlane(lo, k);
-        a[0] += partial[base + off];
-      }
     }
-    if (on) {
-      const int e = idx / ns, st = idx - (idx / ns) * ns;
-      Vout[(ob * ldv + st) * E + e] = ((a[0] + a[1]) + (a[2] + a[3])) + ((a[4] + a[5]) + (a[6] + a[7]));
+    const TV sum = ((a[0] + a[1]) + (a[2] + a[3])) + ((a[4] + a[5]) + (a[6] + a[7]));
+    TV tot = sum;
+    for (int gg = 1; gg < G; ++gg) {
+      TV x;
+#pragma unroll
+      for (int c = 0; c < V; ++c) x[c] = __shfl(sum[c], gg * lpc + jl);
+      tot += x;
+    }
+    if (g == 0 && j < lpc) {
+#pragma unroll
+      for (int c = 0; c < V; ++c) {
+        const int idx = j * V + c, e = idx / ns, st = idx - (idx / ns) * ns;
+        Vout[(ob * ldv + st) * E + e] = tot[c];
+      }
     }
   }
 }
@@ -463,8 +505,19 @@ void potential_integrals(const DevTiles &tl, const DevPartials &pa, int stype, i
   if (prof) prof->end(ST_VINT, s);
   if (nblk_out == 0) return;
   if (prof) prof->begin(ST_VINT_REDUCE, s);
-  hipLaunchKernelGGL((k_vint_reduce<T>), dim3((unsigned)((nblk_out + 3) / 4)), dim3(256), 0, s, nblk_out, ns, E,
-                     pa.cptr, pa.cbase, partial, Vout, ldv);
+  // widest vector that divides a contribution run (16 bytes at most)
+  const int per = ns * E;
+  constexpr int VW = 16 / sizeof(T);
+  const int vw = per % VW == 0 ? VW : (per % 2 == 0 ? 2 : 1);
+  const int lpc = per / vw;
+  const int G = lpc <= 64 ? 64 / lpc : 1;
+  const dim3 grid_r((unsigned)((nblk_out + 3) / 4));
+  if (vw == VW)
+    hipLaunchKernelGGL((k_vint_reduce<T, VW>), grid_r, dim3(256), 0, s, nblk_out, ns, E, G, pa.cptr, pa.cidx, partial, Vout, ldv);
+  else if (vw == 2)
+    hipLaunchKernelGGL((k_vint_reduce<T, 2>), grid_r, dim3(256), 0, s, nblk_out, ns, E, G, pa.cptr, pa.cidx, partial, Vout, ldv);
+  else
+    hipLaunchKernelGGL((k_vint_reduce<T, 1>), grid_r, dim3(256), 0, s, nblk_out, ns, E, G, pa.cptr, pa.cidx, partial, Vout, ldv);
   TD_HIP(hipGetLastError());
   if (prof) prof->end(ST_VINT_REDUCE, s);
 }

@@ -13,6 +13,9 @@ Handle::~Handle() {
   prof.destroy();
   if (ev0) (void)hipEventDestroy(ev0);
   if (ev1) (void)hipEventDestroy(ev1);
+  if (ev_fork) (void)hipEventDestroy(ev_fork);
+  if (ev_join) (void)hipEventDestroy(ev_join);
+  if (side) (void)hipStreamDestroy(side);
 }
 
 const void *Handle::usamp() const {
@@ -245,14 +248,14 @@ static void upload_bf16(DevBuf<__hip_bfloat16> &dst, const std::vector<double> &
 
 // Per-tile partial sums of the potential integrals: tile t owns u-rows x o-rows function
 // pairs from tbase[t] on, contribution-major ((u-atom i, o-atom j) outer, then the block's
-// rows and columns); every (tile, u-atom i, o-atom j) with its block
-// (I, J) in O is one contribution, listed per O block in tile order (a fixed summation
-// order, so results are reproducible).
+// rows and columns); every (tile, u-atom i, o-atom j) is one contribution to its overlap
+// block (I, J) in O, listed per block in tile order (a fixed summation order, so results
+// are reproducible).  Tiles write contiguously; the per-block sums gather.
 static void build_partials(Handle &h, const HostSetTiles &tu, const HostSetTiles &to,
                            const Pattern &O) {
   const int nt = h.nt;
   std::vector<int64_t> tbase(nt, 0), cptr(O.nnzb() + 1, 0);
-  std::vector<int64_t> cblk;   // per (tile, i, j) in order: the O block (or -1)
+  std::vector<int64_t> cblk;   // per (tile, i, j) in order: the O block
   int64_t total = 0;
   for (int t = 0; t < nt; ++t) {
     const int nua = tu.ptr[t + 1] - tu.ptr[t], noa = to.ptr[t + 1] - to.ptr[t];
@@ -261,29 +264,23 @@ static void build_partials(Handle &h, const HostSetTiles &tu, const HostSetTiles
     for (int i = 0; i < nua; ++i)
       for (int j = 0; j < noa; ++j) {
         const int64_t k = O.find(tu.atoms[tu.ptr[t] + i], to.atoms[to.ptr[t] + j]);
+        TD_REQUIRE(k >= 0, "internal: tile pair outside the overlap pattern");
         cblk.push_back(k);
-        if (k >= 0) cptr[k + 1]++;
+        cptr[k + 1]++;
       }
   }
+  TD_REQUIRE((int64_t)cblk.size() < INT32_MAX, "too many partial-sum contributions");
   for (int64_t k = 0; k < O.nnzb(); ++k) cptr[k + 1] += cptr[k];
-  std::vector<int64_t> cbase(cptr[O.nnzb()]);
+  // contribution q (tile order) is function pair q * E of the buffer
+  std::vector<int32_t> cidx(cptr[O.nnzb()]);
   std::vector<int64_t> fillp(cptr.begin(), cptr.end() - 1);
-  size_t q = 0;
-  for (int t = 0; t < nt; ++t) {
-    const int nua = tu.ptr[t + 1] - tu.ptr[t], noa = to.ptr[t + 1] - to.ptr[t];
-    for (int i = 0; i < nua; ++i)
-      for (int j = 0; j < noa; ++j, ++q) {
-        const int64_t k = cblk[q];
-        if (k < 0) continue;
-        cbase[fillp[k]++] = tbase[t] + ((int64_t)i * noa + j) * h.BU * h.BO;
-      }
-  }
+  for (size_t q = 0; q < cblk.size(); ++q) cidx[fillp[cblk[q]]++] = (int32_t)q;
   hipStream_t s = h.stream;
   h.pa_tbase.upload(tbase, s);
   h.pa_cptr.upload(cptr, s);
-  h.pa_cbase.upload(cbase, s);
+  h.pa_cidx.upload(cidx, s);
   TD_HIP(hipStreamSynchronize(s));
-  h.partials = DevPartials{total, h.pa_tbase.p, h.pa_cptr.p, h.pa_cbase.p};
+  h.partials = DevPartials{total, h.pa_tbase.p, h.pa_cptr.p, h.pa_cidx.p};
 }
 
 // ---------------------------------------------------------------------------------------
@@ -365,6 +362,9 @@ void create_handle(Handle &h, const tddft_system &sys, const tddft_options &o) {
   h.lds_limit = (size_t)lds;
   TD_HIP(hipEventCreate(&h.ev0));
   TD_HIP(hipEventCreate(&h.ev1));
+  TD_HIP(hipStreamCreateWithFlags(&h.side, hipStreamNonBlocking));
+  TD_HIP(hipEventCreateWithFlags(&h.ev_fork, hipEventDisableTiming));
+  TD_HIP(hipEventCreateWithFlags(&h.ev_join, hipEventDisableTiming));
 
   // ---- fixed products (exact, host FP64) and the response pattern R of K^c S^u L S^o K^v
   HostBsr KcHu = host_product(Kc, Hu, product_pattern(Kc.pat, Hu.pat));
@@ -546,13 +546,19 @@ static int stype_of(const Handle &h) {
 }
 
 template <class T>
+static void kshift_on(Handle &h, hipStream_t s, int ncol, const T *X, int ldx, int x0, T *F, int ldf,
+                      int f0) {
+  h.prof.begin(ST_KSHIFT_LEFT, s);
+  spmm_left<T>(h.pT_left, h.BU, h.BO, h.KcHu.ptr<T>(), X, ldx, x0, F, ldf, f0, ncol, 1.0, false, s);
+  h.prof.end(ST_KSHIFT_LEFT, s);
+  h.prof.begin(ST_KSHIFT_RIGHT, s);
+  spmm_right<T>(h.pT_right, h.BU, h.BO, X, ldx, x0, h.HoKv.ptr<T>(), F, ldf, f0, ncol, -1.0, true, s);
+  h.prof.end(ST_KSHIFT_RIGHT, s);
+}
+
+template <class T>
 void kshift_sets(Handle &h, int ncol, const T *X, int ldx, int x0, T *F, int ldf, int f0) {
-  h.prof.begin(ST_KSHIFT_LEFT, h.stream);
-  spmm_left<T>(h.pT_left, h.BU, h.BO, h.KcHu.ptr<T>(), X, ldx, x0, F, ldf, f0, ncol, 1.0, false, h.stream);
-  h.prof.end(ST_KSHIFT_LEFT, h.stream);
-  h.prof.begin(ST_KSHIFT_RIGHT, h.stream);
-  spmm_right<T>(h.pT_right, h.BU, h.BO, X, ldx, x0, h.HoKv.ptr<T>(), F, ldf, f0, ncol, -1.0, true, h.stream);
-  h.prof.end(ST_KSHIFT_RIGHT, h.stream);
+  kshift_on<T>(h, h.stream, ncol, X, ldx, x0, F, ldf, f0);
 }
 
 template <class T>
@@ -586,20 +592,36 @@ template <class T>
 void apply_sets(Handle &h, int n, const T *X, int ldx, int xp0, int xq0, T *F, int ldf, int fp0,
                 int fq0, bool coupling, bool p_is_q) {
   hipStream_t s = h.stream;
-  if (xq0 == xp0 + n && fq0 == fp0 + n) {
-    kshift_sets<T>(h, 2 * n, X, ldx, xp0, F, ldf, fp0);
-  } else {
-    kshift_sets<T>(h, n, X, ldx, xp0, F, ldf, fp0);
-    kshift_sets<T>(h, n, X, ldx, xq0, F, ldf, fq0);
+  // The K-shift term writes F and the coupling term adds into it last; up to that add the
+  // two read only X. With a coupling term the K-shift products run on the handle's second
+  // stream, forked after the work queued so far on s and joined before the first add.
+  // While stage profiling is on, everything stays on s, so that each stage's event time
+  // is its own.
+  const bool with_coupling = coupling && h.opts.xc != TDDFT_HXC_NONE;
+  const bool fork = with_coupling && !h.prof.on;
+  hipStream_t ks = fork ? h.side : s;
+  if (fork) {
+    TD_HIP(hipEventRecord(h.ev_fork, s));
+    TD_HIP(hipStreamWaitEvent(ks, h.ev_fork, 0));
   }
-  if (!coupling || h.opts.xc == TDDFT_HXC_NONE) return;
+  if (xq0 == xp0 + n && fq0 == fp0 + n) {
+    kshift_on<T>(h, ks, 2 * n, X, ldx, xp0, F, ldf, fp0);
+  } else {
+    kshift_on<T>(h, ks, n, X, ldx, xp0, F, ldf, fp0);
+    kshift_on<T>(h, ks, n, X, ldx, xq0, F, ldf, fq0);
+  }
+  if (!with_coupling) return;
+  if (fork) TD_HIP(hipEventRecord(h.ev_join, ks));
+  bool joined = !fork;
   const int npair = (n + 1) / 2;
   const int64_t pstride = (int64_t)h.nt * TP * 2;
   const int64_t wstride = (int64_t)h.n[0] * h.n[1] * h.n[2] * 2;
-  const size_t bytes_f = (size_t)npair * pstride * sizeof(T);
-  const size_t bytes_w = (size_t)npair * wstride * sizeof(T);
-  const size_t bytes_v = (size_t)h.nO * n * h.E * sizeof(T);
-  const size_t bytes_y = (size_t)h.nM2 * n * h.E * sizeof(T);
+  // sub-buffers start on 256-byte boundaries (vector loads of the partial sums)
+  auto al = [](size_t b) { return (b + 255) & ~(size_t)255; };
+  const size_t bytes_f = al((size_t)npair * pstride * sizeof(T));
+  const size_t bytes_w = al((size_t)npair * wstride * sizeof(T));
+  const size_t bytes_v = al((size_t)h.nO * n * h.E * sizeof(T));
+  const size_t bytes_y = al((size_t)h.nM2 * n * h.E * sizeof(T));
   // potential integrals in chunks of at most 8 states (chunk starts stay even), which
   // bounds the per-tile partial-sum buffer
   const int chunk = std::min(n, 8);
@@ -631,6 +653,10 @@ void apply_sets(Handle &h, int n, const T *X, int ldx, int xp0, int xq0, T *F, i
     h.prof.begin(ST_SANDWICH_LEFT, s);
     spmm_left<T>(h.pSw1, h.BU, h.BO, h.Kc.ptr<T>(), Vset, n, 0, Y, n, 0, n, 1.0, false, s);
     h.prof.end(ST_SANDWICH_LEFT, s);
+    if (!joined) {
+      TD_HIP(hipStreamWaitEvent(s, h.ev_join, 0));
+      joined = true;
+    }
     for (int f0 : f0s) {
       h.prof.begin(ST_SANDWICH_RIGHT, s);
       spmm_right<T>(h.pSw2, h.BU, h.BO, Y, n, 0, h.Kv.ptr<T>(), F, ldf, f0, n, factor, true, s);

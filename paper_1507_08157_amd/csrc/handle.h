@@ -81,7 +81,8 @@ struct Handle {
   DevTiles tiles_uo{}, tiles_oo{};
   int maxrows_uo = 0, maxrows_oo = 0;
   int maxrows_o = 0;           // max over tiles of o-rows (o-atoms * BO)
-  DevBuf<int64_t> pa_tbase, pa_cptr, pa_cbase;
+  DevBuf<int64_t> pa_tbase, pa_cptr;
+  DevBuf<int32_t> pa_cidx;
   DevPartials partials{};
   double mean_u_per_tile = 0, mean_o_per_tile = 0;
   int64_t pair_points = 0;     // sum over tiles of (u rows * o rows) * TP (work measure)
@@ -103,6 +104,11 @@ struct Handle {
   DevBuf<double> partial;      // gram partial sums
   DevBuf<double> small_dev;    // coefficient / result staging
   int max_parts = 1024;        // gram: workgroups of partial sums (x 4096 pairs)
+
+  // second stream of the handle: the K-shift products of an application run there beside
+  // the grid pipeline of the coupling term (fork and join through ev_fork / ev_join)
+  hipStream_t side = nullptr;
+  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
 
   // timing
   hipEvent_t ev0 = nullptr, ev1 = nullptr;

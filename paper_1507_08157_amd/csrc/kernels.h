@@ -63,7 +63,8 @@ struct DevPartials {
   int64_t total = 0;                  // function pairs over all tiles (values per state)
   const int64_t *tbase = nullptr;     // [nt] first function pair of each tile
   const int64_t *cptr = nullptr;      // [n_out_blocks + 1] contributions per overlap block
-  const int64_t *cbase = nullptr;     // per contribution: function pair of its (0, 0) element
+  const int32_t *cidx = nullptr;      // per contribution: its index in the partial-sum buffer
+                                      // (function pair of its (0, 0) element / E)
 };
 
 enum SampleType { SAMPLE_F64 = 0, SAMPLE_F32 = 1, SAMPLE_BF16 = 2 };

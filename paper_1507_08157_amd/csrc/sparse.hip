@@ -135,8 +135,8 @@ __global__ __launch_bounds__(256) void k_spmm_right(int64_t nout, int ncol,
 // Dense path (FP32 and FP64).  When both operands and the output of a masked product have complete
 // block patterns, the product is a plain dense matrix product; it runs on MFMA
 // (v_mfma_f32_16x16x4f32 / v_mfma_f64_16x16x4f64) with 64 x 64 output tiles per workgroup (4 waves, each 32 x 32
-// as 2 x 2 MFMA blocks) and k-slabs of 32 staged in LDS straight from the padded-block
-// layouts:
+// as 2 x 2 MFMA blocks) and double-buffered k-slabs of 32 staged in LDS straight from the
+// padded-block layouts:
 //   left  C = A X:  A [di*BU x dk*BU] in BU x BU blocks, X a column set on dk x dj blocks;
 //                   rows (I, r), columns (J, m, c), k = (K, t)
 //   right C = X B:  X a column set on di x dk blocks, B [dk*BO x dj*BO] in BO x BO blocks;
@@ -156,6 +156,28 @@ __device__ __forceinline__ typename MfmaAcc<T>::type mfma16x16x4(T a, T b, typen
   else return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
 }
 
+// Operand order inside a k-slab: the sum over k is order-free, so in MFMA step s (0..7) lane
+// group q = lane / 16 supplies k = 8 q + s for both operands.  Every lane then needs eight
+// consecutive k of one row of A and one column of B, stored k-contiguous in LDS ([row][k]
+// with rows padded to GKP, which keeps the 16-byte reads of 8 neighbouring rows on
+// distinct banks) and fetched with wide LDS reads.  Two LDS buffers: the next slab's global
+// loads are in flight while the current slab is multiplied, one barrier per slab.
+constexpr int GKP = GK + 4;
+
+template <class T>
+__device__ __forceinline__ void lds_load8(const T *p, T (&o)[8]) {
+  if constexpr (std::is_same<T, float>::value) {
+    const float4 x = reinterpret_cast<const float4 *>(p)[0], y = reinterpret_cast<const float4 *>(p)[1];
+    o[0] = x.x; o[1] = x.y; o[2] = x.z; o[3] = x.w; o[4] = y.x; o[5] = y.y; o[6] = y.z; o[7] = y.w;
+  } else {
+#pragma unroll
+    for (int k = 0; k < 8; k += 2) {
+      const double2 x = reinterpret_cast<const double2 *>(p + k)[0];
+      o[k] = x.x; o[k + 1] = x.y;
+    }
+  }
+}
+
 template <class T, int BU, int BO, bool LEFT>
 __global__ __launch_bounds__(256) void k_gemm_blocks(int di, int dk, int dj, int ncol,
                                                      const T *__restrict__ A,
@@ -164,8 +186,8 @@ __global__ __launch_bounds__(256) void k_gemm_blocks(int di, int dk, int dj, int
                                                      T alpha, int accumulate) {
   using VA = typename MfmaAcc<T>::type;
   constexpr int E = BU * BO;
-  __shared__ T As[GK][GM + 1];
-  __shared__ T Bs[GK][GN + 1];
+  __shared__ __align__(16) T As[2][GM][GKP];
+  __shared__ __align__(16) T Bs[2][GN][GKP];
   const int M = LEFT ? di * BU : di * BU * ncol;
   const int N = LEFT ? dj * ncol * BO : dj * BO;
   const int K = LEFT ? dk * BU : dk * BO;
@@ -193,7 +215,8 @@ __global__ __launch_bounds__(256) void k_gemm_blocks(int di, int dk, int dj, int
     if (LEFT) return (int64_t)(k / BU) * dj * ldxE + (k % BU) * BO;
     return (int64_t)(k / BO) * dj * (BO * BO) + (k % BO) * BO;
   };
-  // A tile: thread -> k = tid % GK, rows tid / GK + 8 q; B tile: n = tid % GN, k = tid / GN + 4 q
+  // global staging: A thread -> k = tid % GK, rows tid / GK + 8 q; B thread -> n = tid % GN,
+  // k = tid / GN + 4 q
   const int ak = tid % GK, ar = tid / GK;
   int64_t arow[8];
   bool aval[8];
@@ -206,37 +229,54 @@ __global__ __launch_bounds__(256) void k_gemm_blocks(int di, int dk, int dj, int
   const int bnl = tid % GN, bkl = tid / GN;
   const bool bval = n0 + bnl < N;
   const int64_t bcol = bval ? colB(n0 + bnl) : 0;
+  T ra[8], rb[8];
+  auto fetch = [&](int k0) {
+    const int k = k0 + ak;
+    const bool kv = k < K;
+    const int64_t kp = kv ? kA(k) : 0;
+#pragma unroll
+    for (int q = 0; q < 8; ++q) ra[q] = (kv && aval[q]) ? A[arow[q] + kp] : T(0);
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      const int kb = k0 + bkl + 4 * q;
+      rb[q] = (kb < K && bval) ? B[bcol + kB(kb)] : T(0);
+    }
+  };
+  auto stage = [&](int buf) {
+#pragma unroll
+    for (int q = 0; q < 8; ++q) As[buf][ar + 8 * q][ak] = ra[q];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) Bs[buf][bnl][bkl + 4 * q] = rb[q];
+  };
   const int wm = (w >> 1) * 32, wn = (w & 1) * 32;
+  const int q4 = lane >> 4, c16 = lane & 15;
   VA acc[2][2];
 #pragma unroll
   for (int a = 0; a < 2; ++a)
 #pragma unroll
     for (int b = 0; b < 2; ++b) acc[a][b] = VA{T(0), T(0), T(0), T(0)};
+  fetch(0);
+  stage(0);
+  __syncthreads();
+  int buf = 0;
   for (int k0 = 0; k0 < K; k0 += GK) {
-    {
-      const int k = k0 + ak;
-      const bool kv = k < K;
-      const int64_t kp = kv ? kA(k) : 0;
+    const bool more = k0 + GK < K;
+    if (more) fetch(k0 + GK);
+    T a0[8], a1[8], b0[8], b1[8];
+    lds_load8<T>(&As[buf][wm + c16][8 * q4], a0);
+    lds_load8<T>(&As[buf][wm + 16 + c16][8 * q4], a1);
+    lds_load8<T>(&Bs[buf][wn + c16][8 * q4], b0);
+    lds_load8<T>(&Bs[buf][wn + 16 + c16][8 * q4], b1);
 #pragma unroll
-      for (int q = 0; q < 8; ++q) As[ak][ar + 8 * q] = (kv && aval[q]) ? A[arow[q] + kp] : T(0);
+    for (int st = 0; st < 8; ++st) {
+      acc[0][0] = mfma16x16x4<T>(a0[st], b0[st], acc[0][0]);
+      acc[0][1] = mfma16x16x4<T>(a0[st], b1[st], acc[0][1]);
+      acc[1][0] = mfma16x16x4<T>(a1[st], b0[st], acc[1][0]);
+      acc[1][1] = mfma16x16x4<T>(a1[st], b1[st], acc[1][1]);
     }
-#pragma unroll
-    for (int q = 0; q < 8; ++q) {
-      const int kl = bkl + 4 * q, k = k0 + kl;
-      Bs[kl][bnl] = (k < K && bval) ? B[bcol + kB(k)] : T(0);
-    }
+    if (more) stage(buf ^ 1);
     __syncthreads();
-#pragma unroll
-    for (int kk = 0; kk < GK; kk += 4) {
-      const int kr = kk + (lane >> 4), c16 = lane & 15;
-      const T a0 = As[kr][wm + c16], a1 = As[kr][wm + 16 + c16];
-      const T b0 = Bs[kr][wn + c16], b1 = Bs[kr][wn + 16 + c16];
-      acc[0][0] = mfma16x16x4<T>(a0, b0, acc[0][0]);
-      acc[0][1] = mfma16x16x4<T>(a0, b1, acc[0][1]);
-      acc[1][0] = mfma16x16x4<T>(a1, b0, acc[1][0]);
-      acc[1][1] = mfma16x16x4<T>(a1, b1, acc[1][1]);
-    }
-    __syncthreads();
+    buf ^= 1;
   }
   // D of 16x16x4: lane holds column lane % 16 and, in register j, row 4 (lane / 16) + j
   // (FP32) or row 4 j + lane / 16 (FP64)
