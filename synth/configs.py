@@ -96,5 +96,13 @@ def small_odd(seed: int = 13) -> Config:
                   R_K=None, R_M=8.0, n_states=2, seed=seed)
 
 
+def small_crowded(seed: int = 17) -> Config:
+    """24 atoms in a 12 bohr cube, 48^3 (radix 2 and 3), dense: 6 to 18 o-atoms per grid
+    tile (the other small systems stay below 10), for the per-tile staging of the grid
+    kernels."""
+    return Config(name="small_crowded", n_atoms=24, L=12.0, N=48, r_c=4.0, n_occ=16,
+                  n_vir=32, R_K=None, R_M=None, n_states=5, seed=seed)
+
+
 BY_NAME = {"tiny": tiny, "prec": prec, "small_dense": small_dense,
-           "small_trunc": small_trunc, "small_odd": small_odd}
+           "small_trunc": small_trunc, "small_odd": small_odd, "small_crowded": small_crowded}

@@ -80,6 +80,22 @@ def test_apply_reduced_precision(small_trunc, precision, bound):
     assert err_q < bound * np.max(np.abs(coup)) + 2e-5 * np.max(np.abs(fq_ref))
 
 
+@pytest.mark.parametrize("precision,tol", [("fp64", TOL_FP64), ("fp32", 2e-5)])
+def test_apply_crowded_tiles(precision, tol):
+    """Tiles with 6 to 18 o-atoms (the grid kernels stage per-tile operands in batches
+    sized by the atom count) and 5 states (a partial last pass of the density in both
+    precisions)."""
+    from conftest import cached_system
+    s = cached_system("small_crowded")
+    fp, fq, fp_ref, fq_ref, op, Pq = _run(s, 0, precision, 5, seed=21)
+    assert rel_err(fp, fp_ref) < tol
+    if precision == "fp64":
+        assert rel_err(fq, fq_ref) < tol
+    else:
+        err_q = np.max(np.abs(fq - fq_ref))
+        assert err_q < 2e-5 * np.max(np.abs(fq_ref))
+
+
 def test_apply_tiny_power_of_two_grid():
     from conftest import cached_system
     s = cached_system("tiny")
