@@ -72,8 +72,12 @@ __device__ __forceinline__ void density_pairs(const int32_t *__restrict__ pid, i
                                               int nk, const S *__restrict__ os, int lane,
                                               T (&tmp)[NS][BL]) {
   constexpr int E = BL * BR;
+  // the block index of the next pair is requested together with this pair's P block, so a
+  // pair costs one round trip instead of two dependent ones
+  int pb_next = noa > 0 ? pid[0] : -1;
   for (int j = 0; j < noa; ++j) {
-    const int pb = pid[j];
+    const int pb = pb_next;
+    if (j + 1 < noa) pb_next = pid[j + 1];
     if (pb < 0) continue;
     T o[BR];
 #pragma unroll

@@ -27,6 +27,21 @@ void spmm_right(const DevPlan &pl, int bu, int bo, const T *X, int ldx, int xc0,
                 T *C, int ldc, int cc0, int ncol, double alpha, bool acc, hipStream_t s);
 template <class T>
 void lincomb(int64_t nblk, int E, const LcArgs &a, hipStream_t s);
+
+// Diagonal form: every source and the output share one column-set layout (ld = nc, column
+// offset 0) and the coefficient matrices are diagonal, so
+//   Y[k] = beta[c] Y[k] + sum_s d_s[c] X_s[k],   c = (k / E) % nc,
+// over the flat element index k; the coefficients travel in the kernel arguments.
+constexpr int kLcDiagMax = 64;
+struct LcDiagArgs {
+  void *Y;
+  const void *X[3];
+  int nsrc, has_beta;
+  double beta[kLcDiagMax];
+  double d[3][kLcDiagMax];
+};
+template <class T>
+void lincomb_diag(int64_t nblk, int E, int nc, const LcDiagArgs &a, hipStream_t s);
 template <class T>
 void gram(int64_t nblk, int E, const T *X, int ldx, int xc0, int n1, const T *Y, int ldy,
           int yc0, int n2, bool diag, double *partial, int max_parts, double *out,

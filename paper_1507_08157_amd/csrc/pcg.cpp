@@ -261,25 +261,51 @@ struct Solver {
     stage_off += (c.size() + 31) & ~(size_t)31;
     return dp;
   }
-  // Y = sum of up to 3 sources with coefficient matrices [nc][nc] (+ beta Y), all on nblk blocks
-  void lc(int64_t nblk, T *Y, const double *beta, std::initializer_list<std::pair<const T *, Mat>> src) {
-    LcArgs a{};
-    a.Y = Y;
-    a.ldy = nc;
-    a.yc0 = 0;
-    a.nout = nc;
-    a.beta = beta;
-    a.nsrc = 0;
-    for (auto &sr : src) {
-      LcSrc &x = a.src[a.nsrc++];
-      x.X = sr.first;
-      x.ldx = nc;
-      x.xc0 = 0;
-      x.nin = nc;
-      x.C = coef(sr.second);
-    }
+  // Y = sum of up to 3 sources with coefficient matrices [nc][nc] (+ diag(beta) Y when beta
+  // is given: host values, one per column), all on nblk blocks.  When every matrix is
+  // diagonal the streaming form runs with the coefficients in its kernel arguments (no
+  // upload); otherwise the matrices are staged to the device.
+  void lc(int64_t nblk, T *Y, const std::vector<double> *beta,
+          std::initializer_list<std::pair<const T *, Mat>> src) {
+    bool diagonal = nc <= kLcDiagMax && src.size() <= 3;
+    for (auto &sr : src)
+      for (int i = 0; i < nc && diagonal; ++i)
+        for (int j = 0; j < nc; ++j)
+          if (i != j && sr.second[(size_t)i * nc + j] != 0.0) {
+            diagonal = false;
+            break;
+          }
     h.prof.begin(ST_LINCOMB, s);
-    lincomb<T>(nblk, E, a, s);
+    if (diagonal) {
+      LcDiagArgs a{};
+      a.Y = Y;
+      a.has_beta = beta != nullptr;
+      for (int c = 0; c < nc; ++c) a.beta[c] = beta ? (*beta)[c] : 0.0;
+      a.nsrc = 0;
+      for (auto &sr : src) {
+        a.X[a.nsrc] = sr.first;
+        for (int c = 0; c < nc; ++c) a.d[a.nsrc][c] = sr.second[(size_t)c * nc + c];
+        ++a.nsrc;
+      }
+      lincomb_diag<T>(nblk, E, nc, a, s);
+    } else {
+      LcArgs a{};
+      a.Y = Y;
+      a.ldy = nc;
+      a.yc0 = 0;
+      a.nout = nc;
+      a.beta = beta ? coef(*beta) : nullptr;
+      a.nsrc = 0;
+      for (auto &sr : src) {
+        LcSrc &x = a.src[a.nsrc++];
+        x.X = sr.first;
+        x.ldx = nc;
+        x.xc0 = 0;
+        x.nin = nc;
+        x.C = coef(sr.second);
+      }
+      lincomb<T>(nblk, E, a, s);
+    }
     h.prof.end(ST_LINCOMB, s);
   }
   Mat eye(double v = 1.0) {
@@ -294,8 +320,8 @@ struct Solver {
   }
   void copy(int64_t nblk, T *Y, const T *X) { lc(nblk, Y, nullptr, {{X, eye()}}); }
   void axpy(int64_t nblk, T *Y, double a, const T *X) {   // Y += a X
-    std::vector<double> one(nc, 1.0);
-    lc(nblk, Y, coef(one), {{X, eye(a)}});
+    const std::vector<double> one(nc, 1.0);
+    lc(nblk, Y, &one, {{X, eye(a)}});
   }
   // block-diagonal transform [[Tp,0],[0,Tq]] of the columns, in place (via tmp)
   void transform(int64_t nblk, T *X, T *tmp, const Mat &Tp, const Mat &Tq) {
@@ -373,8 +399,8 @@ int ksdiff_cg(Solver<T> &S, Handle &h, const T *g, const T *gc, T *zk, T *res, T
     }
     if (!any) break;
     covariant_sets<T>(h, nc, Lk, nc, 0, Lkc, nc, 0);
-    std::vector<double> ones(nc, 1.0);
-    const double *b1 = S.coef(ones);
+    const std::vector<double> ones(nc, 1.0);
+    const std::vector<double> *b1 = &ones;
     S.lc(nb, zk, b1, {{dk, S.diag(alpha)}});
     S.lc(nb, res, b1, {{Lk, S.diag(nalpha)}});
     S.lc(nb, resc, b1, {{Lkc, S.diag(nalpha)}});
@@ -391,7 +417,7 @@ int ksdiff_cg(Solver<T> &S, Handle &h, const T *g, const T *gc, T *zk, T *res, T
       keep[c] = active[c] ? beta : 1.0;
       take[c] = active[c] ? 1.0 : 0.0;
     }
-    const double *bk = S.coef(keep);
+    const std::vector<double> *bk = &keep;
     S.lc(nb, dk, bk, {{res, S.diag(take)}});
     S.lc(nb, dkc, bk, {{resc, S.diag(take)}});
     ++iters;
@@ -661,8 +687,8 @@ static int solve_impl(Handle &h, int n, const tddft_options &o, double *omega, d
           any |= (bool)active[c];
         }
         if (!any) break;
-        std::vector<double> ones(nc, 1.0);
-        const double *b1 = S.coef(ones);
+        const std::vector<double> ones(nc, 1.0);
+        const std::vector<double> *b1 = &ones;
         S.lc(nM, zk, b1, {{dk, S.diag(alpha)}});
         S.lc(nM, res, b1, {{Hd, S.diag(nalpha)}});
         const size_t qr = S.gram_q(nM, res, 0, nc, res, 0, nc, true);
@@ -678,7 +704,7 @@ static int solve_impl(Handle &h, int n, const tddft_options &o, double *omega, d
           keep[c] = active[c] ? beta : 1.0;
           take[c] = active[c] ? 1.0 : 0.0;
         }
-        S.lc(nM, dk, S.coef(keep), {{res, S.diag(take)}});
+        S.lc(nM, dk, &keep, {{res, S.diag(take)}});
         inner_total++;
       }
       // columns that never stepped keep z = r
@@ -710,8 +736,8 @@ static int solve_impl(Handle &h, int n, const tddft_options &o, double *omega, d
     proj(set(Lz), set(T2));
     cov(set(T2), set(T1));
     if (beta > 0.0) {
-      std::vector<double> bv(nc, beta);
-      const double *bb = S.coef(bv);
+      const std::vector<double> bv(nc, beta);
+      const std::vector<double> *bb = &bv;
       S.lc(nR, set(D), bb, {{set(T2), S.eye(-1.0)}});
       S.lc(nR, set(Dc), bb, {{set(T1), S.eye(-1.0)}});
       const size_t qd = S.gram_q(nR, set(D), 0, nc, set(Gc), 0, nc, true);

@@ -408,6 +408,84 @@ void lincomb(int64_t nblk, int E, const LcArgs &a, hipStream_t s) {
   TD_HIP(hipGetLastError());
 }
 
+// Diagonal linear combination, streaming: four consecutive elements per thread (16-byte
+// accesses when the sets allow), FP64 arithmetic in the same order as k_lincomb (beta Y
+// first, then the sources in order), so both forms round alike.  The coefficients are
+// copied from the kernel arguments into LDS once per workgroup.
+template <class T, bool VEC>
+__global__ __launch_bounds__(256) void k_lincomb_diag(int64_t n, int E, int nc, LcDiagArgs a) {
+  __shared__ double cb[kLcDiagMax];
+  __shared__ double cd[3][kLcDiagMax];
+  for (int i = threadIdx.x; i < nc; i += blockDim.x) {
+    cb[i] = a.beta[i];
+    cd[0][i] = a.d[0][i];
+    cd[1][i] = a.d[1][i];
+    cd[2][i] = a.d[2][i];
+  }
+  __syncthreads();
+  const int64_t k0 = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) * 4;
+  if (k0 >= n) return;
+  T *Y = (T *)a.Y;
+  T y[4], x[3][4];
+  if (VEC) {
+    using T4 = T __attribute__((ext_vector_type(4)));
+    const T4 yv = a.has_beta ? *reinterpret_cast<const T4 *>(Y + k0) : T4(0);
+#pragma unroll
+    for (int u = 0; u < 4; ++u) y[u] = yv[u];
+#pragma unroll
+    for (int si = 0; si < 3; ++si)
+      if (si < a.nsrc) {
+        const T4 xv = *reinterpret_cast<const T4 *>((const T *)a.X[si] + k0);
+#pragma unroll
+        for (int u = 0; u < 4; ++u) x[si][u] = xv[u];
+      }
+  } else {
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int64_t k = k0 + u;
+      y[u] = (a.has_beta && k < n) ? Y[k] : T(0);
+#pragma unroll
+      for (int si = 0; si < 3; ++si)
+        if (si < a.nsrc) x[si][u] = k < n ? ((const T *)a.X[si])[k] : T(0);
+    }
+  }
+  T out[4];
+#pragma unroll
+  for (int u = 0; u < 4; ++u) {
+    const int c = (int)(((k0 + u) / E) % nc);
+    double acc = a.has_beta ? cb[c] * (double)y[u] : 0.0;
+#pragma unroll
+    for (int si = 0; si < 3; ++si)
+      if (si < a.nsrc) acc += cd[si][c] * (double)x[si][u];
+    out[u] = (T)acc;
+  }
+  if (VEC) {
+    using T4 = T __attribute__((ext_vector_type(4)));
+    T4 ov;
+#pragma unroll
+    for (int u = 0; u < 4; ++u) ov[u] = out[u];
+    *reinterpret_cast<T4 *>(Y + k0) = ov;
+  } else {
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+      if (k0 + u < n) Y[k0 + u] = out[u];
+  }
+}
+
+template <class T>
+void lincomb_diag(int64_t nblk, int E, int nc, const LcDiagArgs &a, hipStream_t s) {
+  const int64_t n = nblk * nc * E;
+  if (n == 0) return;
+  if (nc > kLcDiagMax || a.nsrc < 0 || a.nsrc > 3) throw Error{TDDFT_E_INVALID, "lincomb_diag: bad arguments"};
+  const uintptr_t al = 4 * sizeof(T);   // four-element vectors, naturally aligned
+  bool vec = n % 4 == 0 && (uintptr_t)a.Y % al == 0;
+  for (int i = 0; i < a.nsrc; ++i) vec = vec && (uintptr_t)a.X[i] % al == 0;
+  const unsigned grid = nblocks((n + 3) / 4, 256);
+  if (vec) hipLaunchKernelGGL((k_lincomb_diag<T, true>), dim3(grid), dim3(256), 0, s, n, E, nc, a);
+  else hipLaunchKernelGGL((k_lincomb_diag<T, false>), dim3(grid), dim3(256), 0, s, n, E, nc, a);
+  TD_HIP(hipGetLastError());
+}
+
 // ---------------------------------------------------------------------------------------
 // FP64 Gram matrix of two column sets: out[i * n2 + j] = sum X[., xc0+i, .] Y[., yc0+j, .]
 // (diag: out[i] = sum X[., xc0+i, .] Y[., yc0+i, .]).  Each workgroup takes a 16 x 16 tile
@@ -603,6 +681,7 @@ void fill(T *p, int64_t n, T v, hipStream_t s) {
   template void spmm_right<T>(const DevPlan &, int, int, const T *, int, int, const T *, T *,    \
                               int, int, int, double, bool, hipStream_t);                         \
   template void lincomb<T>(int64_t, int, const LcArgs &, hipStream_t);                          \
+  template void lincomb_diag<T>(int64_t, int, int, const LcDiagArgs &, hipStream_t);            \
   template void gram<T>(int64_t, int, const T *, int, int, int, const T *, int, int, int, bool,  \
                         double *, int, double *, hipStream_t);                                   \
   template void pack<T>(int64_t, int, int, int, const double *, int64_t, const int64_t *,        \
