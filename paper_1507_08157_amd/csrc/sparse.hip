@@ -558,12 +558,78 @@ __global__ __launch_bounds__(256) void k_gram_reduce(int nparts, int npair,
   if (lane == 0) out[q] = s;
 }
 
+// Diagonal Gram (out[c] = sum X[., xc0+c, .] Y[., yc0+c, .], n1 <= 64 columns), streaming:
+// thread (b, c) of a workgroup takes column c of blocks p0 + b, p0 + b + R, ... of the
+// workgroup's block range (R = 256 / n1 rows of threads; the n1 threads of a row read one
+// block's columns, contiguous), four blocks of loads in flight, products summed in FP64 in
+// a fixed order; the rows are then added in row order through LDS.
+template <class T, int E>
+__global__ __launch_bounds__(256) void k_gram_diag_partial(int64_t nblk, const T *__restrict__ X,
+                                                           int ldx, int xc0,
+                                                           const T *__restrict__ Y, int ldy, int yc0,
+                                                           int n1, int64_t per_part,
+                                                           double *__restrict__ partial) {
+  __shared__ double red[256];
+  const int R = 256 / n1;
+  const int b = (int)threadIdx.x / n1, c = (int)threadIdx.x - b * n1;
+  const int64_t p0 = (int64_t)blockIdx.x * per_part;
+  const int64_t p1 = p0 + per_part < nblk ? p0 + per_part : nblk;
+  double acc = 0.0;
+  if (b < R) {
+    for (int64_t blk0 = p0 + b; blk0 < p1; blk0 += 4 * (int64_t)R) {
+      T xv[4][E], yv[4][E];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int64_t blk = blk0 + (int64_t)u * R;
+        const T *x = X + (blk * ldx + xc0 + c) * E;
+        const T *y = Y + (blk * ldy + yc0 + c) * E;
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+          xv[u][e] = blk < p1 ? x[e] : T(0);
+          yv[u][e] = blk < p1 ? y[e] : T(0);
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+#pragma unroll
+        for (int e = 0; e < E; ++e) acc += (double)xv[u][e] * (double)yv[u][e];
+    }
+  }
+  red[threadIdx.x] = acc;
+  __syncthreads();
+  if ((int)threadIdx.x < n1) {
+    double t = 0.0;
+    for (int r = 0; r < R; ++r) t += red[r * n1 + threadIdx.x];
+    partial[(size_t)blockIdx.x * n1 + threadIdx.x] = t;
+  }
+}
+
 template <class T>
 void gram(int64_t nblk, int E, const T *X, int ldx, int xc0, int n1, const T *Y, int ldy,
           int yc0, int n2, bool diag, double *partial, int max_parts, double *out,
           hipStream_t s) {
   const int npair = diag ? n1 : n1 * n2;
   if (npair > kGramMaxPairs) throw Error{TDDFT_E_INVALID, "gram: too many column pairs"};
+  if (diag && n1 >= 1 && n1 <= 64 && (E == 1 || E == 4 || E == 6 || E == 9 || E == 16)) {
+    // about eight blocks per thread
+    const int R = 256 / n1;
+    int64_t per = std::max<int64_t>((int64_t)8 * R, (nblk + max_parts - 1) / max_parts);
+    const int parts = (int)std::max<int64_t>(1, (nblk + per - 1) / per);
+#define TD_GRAM_DIAG(EE)                                                                              \
+  hipLaunchKernelGGL((k_gram_diag_partial<T, EE>), dim3(parts), dim3(256), 0, s, nblk, X, ldx, xc0, Y, \
+                     ldy, yc0, n1, per, partial)
+    if (E == 1) TD_GRAM_DIAG(1);
+    else if (E == 4) TD_GRAM_DIAG(4);
+    else if (E == 6) TD_GRAM_DIAG(6);
+    else if (E == 9) TD_GRAM_DIAG(9);
+    else TD_GRAM_DIAG(16);
+#undef TD_GRAM_DIAG
+    TD_HIP(hipGetLastError());
+    hipLaunchKernelGGL(k_gram_reduce, dim3((unsigned)((npair + 3) / 4)), dim3(256), 0, s, parts, npair,
+                       partial, out);
+    TD_HIP(hipGetLastError());
+    return;
+  }
   const int64_t nelem = nblk * E;
   // element ranges per workgroup: multiples of 64 (four waves x four steps of four elements)
   int parts = (int)std::min<int64_t>(max_parts, std::max<int64_t>(1, nelem / 256));
