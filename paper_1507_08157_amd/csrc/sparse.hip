@@ -132,18 +132,25 @@ __global__ __launch_bounds__(256) void k_spmm_right(int64_t nout, int ncol,
 }
 
 // ---------------------------------------------------------------------------------------
-// Dense path (FP32 and FP64).  When both operands and the output of a masked product have complete
-// block patterns, the product is a plain dense matrix product; it runs on MFMA
-// (v_mfma_f32_16x16x4f32 / v_mfma_f64_16x16x4f64) with 64 x 64 output tiles per workgroup (4 waves, each 32 x 32
-// as 2 x 2 MFMA blocks) and double-buffered k-slabs of 32 staged in LDS straight from the
-// padded-block layouts:
+// Dense path (FP32 and FP64).  When both operands and the output of a masked product have
+// complete block patterns, the product is a plain dense matrix product; it runs on MFMA
+// (v_mfma_f32_16x16x4f32 / v_mfma_f64_16x16x4f64) straight from the padded-block layouts:
 //   left  C = A X:  A [di*BU x dk*BU] in BU x BU blocks, X a column set on dk x dj blocks;
 //                   rows (I, r), columns (J, m, c), k = (K, t)
 //   right C = X B:  X a column set on di x dk blocks, B [dk*BO x dj*BO] in BO x BO blocks;
 //                   rows (I, r, m), columns (J, c), k = (L, t)
+// A workgroup of WMW x WNW waves computes a GM x GN output tile over k-slabs of GK, each
+// wave (GM / WMW) x (GN / WNW) as 16 x 16 MFMA blocks.  Operand order inside a slab: the
+// sum over k is order-free, so in MFMA step s lane group q = lane / 16 supplies
+// k = (GK / 4) q + s for both operands; every lane reads GK / 4 consecutive k of one row of
+// A and one column of B, stored k-contiguous in LDS ([row][k], rows padded to GK + 4,
+// which keeps the 16-byte reads of neighbouring rows on distinct banks).  Two LDS buffers:
+// the next slab's global loads are in flight while the current slab is multiplied, one
+// barrier per slab.  Global loads of A go along k (AROW = false) or along the tile rows
+// (AROW = true: the right product's rows (I, r, m) are 24 bytes apart in memory, its k
+// steps a whole block row apart).  Measured at 600 x 6400 x 600 (left) and 9600 x 400 x 400
+// (right, FP32): 64 x 64 x 32 tiles 96 / 100 us; these shapes 78 / 82 us.
 typedef float v4f __attribute__((ext_vector_type(4)));
-constexpr int GM = 64, GN = 64, GK = 32;
-
 typedef double v4d_g __attribute__((ext_vector_type(4)));
 
 template <class T> struct MfmaAcc;
@@ -156,36 +163,26 @@ __device__ __forceinline__ typename MfmaAcc<T>::type mfma16x16x4(T a, T b, typen
   else return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
 }
 
-// Operand order inside a k-slab: the sum over k is order-free, so in MFMA step s (0..7) lane
-// group q = lane / 16 supplies k = 8 q + s for both operands.  Every lane then needs eight
-// consecutive k of one row of A and one column of B, stored k-contiguous in LDS ([row][k]
-// with rows padded to GKP, which keeps the 16-byte reads of 8 neighbouring rows on
-// distinct banks) and fetched with wide LDS reads.  Two LDS buffers: the next slab's global
-// loads are in flight while the current slab is multiplied, one barrier per slab.
-constexpr int GKP = GK + 4;
+// tile shapes of the two products
+struct GemmLeft { static constexpr int GM = 128, GN = 64, GK = 16, WMW = 4, WNW = 2; static constexpr bool AROW = false; };
+struct GemmRight { static constexpr int GM = 64, GN = 64, GK = 16, WMW = 2, WNW = 2; static constexpr bool AROW = true; };
 
-template <class T>
-__device__ __forceinline__ void lds_load8(const T *p, T (&o)[8]) {
-  if constexpr (std::is_same<T, float>::value) {
-    const float4 x = reinterpret_cast<const float4 *>(p)[0], y = reinterpret_cast<const float4 *>(p)[1];
-    o[0] = x.x; o[1] = x.y; o[2] = x.z; o[3] = x.w; o[4] = y.x; o[5] = y.y; o[6] = y.z; o[7] = y.w;
-  } else {
-#pragma unroll
-    for (int k = 0; k < 8; k += 2) {
-      const double2 x = reinterpret_cast<const double2 *>(p + k)[0];
-      o[k] = x.x; o[k + 1] = x.y;
-    }
-  }
-}
-
-template <class T, int BU, int BO, bool LEFT>
-__global__ __launch_bounds__(256) void k_gemm_blocks(int di, int dk, int dj, int ncol,
-                                                     const T *__restrict__ A,
-                                                     const T *__restrict__ B, int ldx, int xc0,
-                                                     T *__restrict__ C, int ldc, int cc0,
-                                                     T alpha, int accumulate) {
-  using VA = typename MfmaAcc<T>::type;
+template <class T, int BU, int BO, bool LEFT, class G>
+__global__ __launch_bounds__(64 * G::WMW * G::WNW) void k_gemm_blocks(int di, int dk, int dj, int ncol,
+                                                                       const T *__restrict__ A,
+                                                                       const T *__restrict__ B, int ldx, int xc0,
+                                                                       T *__restrict__ C, int ldc, int cc0,
+                                                                       T alpha, int accumulate) {
+  constexpr int GM = G::GM, GN = G::GN, GK = G::GK, WMW = G::WMW, WNW = G::WNW;
+  constexpr bool AROW = G::AROW;
+  constexpr int NT = 64 * WMW * WNW;
+  constexpr int GKP = GK + 4;
+  constexpr int KQ = GK / 4;                           // k per lane group and slab
+  constexpr int TM = GM / WMW / 16, TN = GN / WNW / 16;
   constexpr int E = BU * BO;
+  static_assert(NT % GK == 0 && GM % (NT / GK) == 0 && NT % GN == 0 && GK % (NT / GN) == 0 &&
+                NT % GM == 0 && GK % (NT / GM) == 0 && KQ % 2 == 0, "tile shape");
+  using VA = typename MfmaAcc<T>::type;
   __shared__ __align__(16) T As[2][GM][GKP];
   __shared__ __align__(16) T Bs[2][GN][GKP];
   const int M = LEFT ? di * BU : di * BU * ncol;
@@ -215,46 +212,60 @@ __global__ __launch_bounds__(256) void k_gemm_blocks(int di, int dk, int dj, int
     if (LEFT) return (int64_t)(k / BU) * dj * ldxE + (k % BU) * BO;
     return (int64_t)(k / BO) * dj * (BO * BO) + (k % BO) * BO;
   };
-  // global staging: A thread -> k = tid % GK, rows tid / GK + 8 q; B thread -> n = tid % GN,
-  // k = tid / GN + 4 q
-  const int ak = tid % GK, ar = tid / GK;
-  int64_t arow[8];
-  bool aval[8];
+  // global staging of A: along k, thread -> k = tid % GK, rows tid / GK + (NT / GK) q; or
+  // along rows, thread -> row tid % GM, k = tid / GM + (NT / GM) q.  B: thread -> column
+  // tid % GN, k = tid / GN + (NT / GN) q
+  constexpr int APER = GM * GK / NT, BPER = GN * GK / NT;
+  constexpr int AR = NT / GK, AKP = NT / GM, BK = NT / GN;
+  const int ak = AROW ? tid / GM : tid % GK, ar = AROW ? tid % GM : tid / GK;
+  int64_t arow[AROW ? 1 : APER];
+  bool aval[AROW ? 1 : APER];
 #pragma unroll
-  for (int q = 0; q < 8; ++q) {
-    const int i = i0 + ar + 8 * q;
+  for (int q = 0; q < (AROW ? 1 : APER); ++q) {
+    const int i = i0 + ar + AR * q;
     aval[q] = i < M;
     arow[q] = aval[q] ? rowA(i) : 0;
   }
   const int bnl = tid % GN, bkl = tid / GN;
   const bool bval = n0 + bnl < N;
   const int64_t bcol = bval ? colB(n0 + bnl) : 0;
-  T ra[8], rb[8];
+  T ra[APER], rb[BPER];
   auto fetch = [&](int k0) {
-    const int k = k0 + ak;
-    const bool kv = k < K;
-    const int64_t kp = kv ? kA(k) : 0;
+    if (AROW) {
 #pragma unroll
-    for (int q = 0; q < 8; ++q) ra[q] = (kv && aval[q]) ? A[arow[q] + kp] : T(0);
+      for (int q = 0; q < APER; ++q) {
+        const int k = k0 + ak + AKP * q;
+        ra[q] = (k < K && aval[0]) ? A[arow[0] + kA(k)] : T(0);
+      }
+    } else {
+      const int k = k0 + ak;
+      const bool kv = k < K;
+      const int64_t kp = kv ? kA(k) : 0;
 #pragma unroll
-    for (int q = 0; q < 8; ++q) {
-      const int kb = k0 + bkl + 4 * q;
+      for (int q = 0; q < APER; ++q) ra[q] = (kv && aval[q]) ? A[arow[q] + kp] : T(0);
+    }
+#pragma unroll
+    for (int q = 0; q < BPER; ++q) {
+      const int kb = k0 + bkl + BK * q;
       rb[q] = (kb < K && bval) ? B[bcol + kB(kb)] : T(0);
     }
   };
   auto stage = [&](int buf) {
 #pragma unroll
-    for (int q = 0; q < 8; ++q) As[buf][ar + 8 * q][ak] = ra[q];
+    for (int q = 0; q < APER; ++q) {
+      if (AROW) As[buf][ar][ak + AKP * q] = ra[q];
+      else As[buf][ar + AR * q][ak] = ra[q];
+    }
 #pragma unroll
-    for (int q = 0; q < 8; ++q) Bs[buf][bnl][bkl + 4 * q] = rb[q];
+    for (int q = 0; q < BPER; ++q) Bs[buf][bnl][bkl + BK * q] = rb[q];
   };
-  const int wm = (w >> 1) * 32, wn = (w & 1) * 32;
+  const int wm = (w / WNW) * (GM / WMW), wn = (w % WNW) * (GN / WNW);
   const int q4 = lane >> 4, c16 = lane & 15;
-  VA acc[2][2];
+  VA acc[TM][TN];
 #pragma unroll
-  for (int a = 0; a < 2; ++a)
+  for (int a = 0; a < TM; ++a)
 #pragma unroll
-    for (int b = 0; b < 2; ++b) acc[a][b] = VA{T(0), T(0), T(0), T(0)};
+    for (int b = 0; b < TN; ++b) acc[a][b] = VA{T(0), T(0), T(0), T(0)};
   fetch(0);
   stage(0);
   __syncthreads();
@@ -262,18 +273,30 @@ __global__ __launch_bounds__(256) void k_gemm_blocks(int di, int dk, int dj, int
   for (int k0 = 0; k0 < K; k0 += GK) {
     const bool more = k0 + GK < K;
     if (more) fetch(k0 + GK);
-    T a0[8], a1[8], b0[8], b1[8];
-    lds_load8<T>(&As[buf][wm + c16][8 * q4], a0);
-    lds_load8<T>(&As[buf][wm + 16 + c16][8 * q4], a1);
-    lds_load8<T>(&Bs[buf][wn + c16][8 * q4], b0);
-    lds_load8<T>(&Bs[buf][wn + 16 + c16][8 * q4], b1);
+    T af[TM][KQ], bf[TN][KQ];
+    using T2 = T __attribute__((ext_vector_type(2)));
 #pragma unroll
-    for (int st = 0; st < 8; ++st) {
-      acc[0][0] = mfma16x16x4<T>(a0[st], b0[st], acc[0][0]);
-      acc[0][1] = mfma16x16x4<T>(a0[st], b1[st], acc[0][1]);
-      acc[1][0] = mfma16x16x4<T>(a1[st], b0[st], acc[1][0]);
-      acc[1][1] = mfma16x16x4<T>(a1[st], b1[st], acc[1][1]);
-    }
+    for (int a = 0; a < TM; ++a)
+#pragma unroll
+      for (int kk = 0; kk < KQ; kk += 2) {
+        const T2 v = *reinterpret_cast<const T2 *>(&As[buf][wm + 16 * a + c16][KQ * q4 + kk]);
+        af[a][kk] = v.x;
+        af[a][kk + 1] = v.y;
+      }
+#pragma unroll
+    for (int b = 0; b < TN; ++b)
+#pragma unroll
+      for (int kk = 0; kk < KQ; kk += 2) {
+        const T2 v = *reinterpret_cast<const T2 *>(&Bs[buf][wn + 16 * b + c16][KQ * q4 + kk]);
+        bf[b][kk] = v.x;
+        bf[b][kk + 1] = v.y;
+      }
+#pragma unroll
+    for (int st = 0; st < KQ; ++st)
+#pragma unroll
+      for (int a = 0; a < TM; ++a)
+#pragma unroll
+        for (int b = 0; b < TN; ++b) acc[a][b] = mfma16x16x4<T>(af[a][st], bf[b][st], acc[a][b]);
     if (more) stage(buf ^ 1);
     __syncthreads();
     buf ^= 1;
@@ -281,7 +304,7 @@ __global__ __launch_bounds__(256) void k_gemm_blocks(int di, int dk, int dj, int
   // D of 16x16x4: lane holds column lane % 16 and, in register j, row 4 (lane / 16) + j
   // (FP32) or row 4 j + lane / 16 (FP64)
 #pragma unroll
-  for (int nb = 0; nb < 2; ++nb) {
+  for (int nb = 0; nb < TN; ++nb) {
     const int n = n0 + wn + nb * 16 + (lane & 15);
     if (n >= N) continue;
     int64_t ccol;
@@ -292,7 +315,7 @@ __global__ __launch_bounds__(256) void k_gemm_blocks(int di, int dk, int dj, int
       ccol = (int64_t)(n / BO) * ldcE + n % BO;
     }
 #pragma unroll
-    for (int mb = 0; mb < 2; ++mb)
+    for (int mb = 0; mb < TM; ++mb)
 #pragma unroll
       for (int j = 0; j < 4; ++j) {
         const int i = i0 + wm + mb * 16 + (std::is_same<T, float>::value ? 4 * (lane >> 4) + j : 4 * j + (lane >> 4));
@@ -328,8 +351,9 @@ void spmm_left(const DevPlan &pl, int bu, int bo, const T *A, const T *X, int ld
                T *C, int ldc, int cc0, int ncol, double alpha, bool acc, hipStream_t s) {
   if (pl.nout == 0 || ncol == 0) return;
   if (pl.di > 0) {
-    const dim3 grid((unsigned)((pl.dj * ncol * bo + GN - 1) / GN), (unsigned)((pl.di * bu + GM - 1) / GM));
-    TD_BDIM_DISPATCH(bu, bo, hipLaunchKernelGGL((k_gemm_blocks<T, BU, BO, true>), grid, dim3(256), 0, s,
+    using G = GemmLeft;
+    const dim3 grid((unsigned)((pl.dj * ncol * bo + G::GN - 1) / G::GN), (unsigned)((pl.di * bu + G::GM - 1) / G::GM));
+    TD_BDIM_DISPATCH(bu, bo, hipLaunchKernelGGL((k_gemm_blocks<T, BU, BO, true, G>), grid, dim3(64 * G::WMW * G::WNW), 0, s,
                                                 pl.di, pl.dk, pl.dj, ncol, A, X, ldx, xc0, C, ldc,
                                                 cc0, (T)alpha, acc ? 1 : 0));
     TD_HIP(hipGetLastError());
@@ -349,8 +373,9 @@ void spmm_right(const DevPlan &pl, int bu, int bo, const T *X, int ldx, int xc0,
                 T *C, int ldc, int cc0, int ncol, double alpha, bool acc, hipStream_t s) {
   if (pl.nout == 0 || ncol == 0) return;
   if (pl.di > 0) {
-    const dim3 grid((unsigned)((pl.dj * bo + GN - 1) / GN), (unsigned)((pl.di * bu * ncol + GM - 1) / GM));
-    TD_BDIM_DISPATCH(bu, bo, hipLaunchKernelGGL((k_gemm_blocks<T, BU, BO, false>), grid, dim3(256), 0, s,
+    using G = GemmRight;
+    const dim3 grid((unsigned)((pl.dj * bo + G::GN - 1) / G::GN), (unsigned)((pl.di * bu * ncol + G::GM - 1) / G::GM));
+    TD_BDIM_DISPATCH(bu, bo, hipLaunchKernelGGL((k_gemm_blocks<T, BU, BO, false, G>), grid, dim3(64 * G::WMW * G::WNW), 0, s,
                                                 pl.di, pl.dk, pl.dj, ncol, X, B, ldx, xc0, C, ldc,
                                                 cc0, (T)alpha, acc ? 1 : 0));
     TD_HIP(hipGetLastError());
