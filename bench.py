@@ -116,12 +116,13 @@ TRAFFIC_FILE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "profile
                             "hbm_traffic_{workload}_{precision}.txt")
 
 
-def kernel_source_hash(symbol, path=KERNEL_SOURCE):
-    """sha256 of a kernel's source text: from its template line to the closing brace."""
-    try:
-        lines = open(path).read().split("\n")
-    except OSError:
-        return None
+# device helpers whose text is part of a kernel's measured code
+KERNEL_HELPERS = {"k_density": ["density_pairs", "load2"], "k_vint_mfma": ["load16", "load4"],
+                  "k_vint_reduce": []}
+
+
+def _function_text(lines, symbol):
+    """Source text of a function: from its template line to its closing brace."""
     for i, ln in enumerate(lines):
         if f"void {symbol}(" in ln:
             j = i
@@ -130,8 +131,22 @@ def kernel_source_hash(symbol, path=KERNEL_SOURCE):
             k = i
             while k < len(lines) and lines[k] != "}":
                 k += 1
-            return hashlib.sha256("\n".join(lines[j:k + 1]).encode()).hexdigest()
+            return "\n".join(lines[j:k + 1])
     return None
+
+
+def kernel_source_hash(symbol, path=KERNEL_SOURCE):
+    """sha256 of a kernel's source text and of the device helpers it inlines."""
+    try:
+        lines = open(path).read().split("\n")
+    except OSError:
+        return None
+    text = _function_text(lines, symbol)
+    if text is None:
+        return None
+    for helper in KERNEL_HELPERS.get(symbol, []):
+        text += "\n" + (_function_text(lines, helper) or "")
+    return hashlib.sha256(text.encode()).hexdigest()
 
 
 def measured_traffic(stage, workload, precision):
