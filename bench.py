@@ -330,7 +330,7 @@ def main():
     h.tddft_profile(False)
     log("stages (ms per launch, serialized): " + ", ".join(
         f"{k}={v[0] / max(v[1], 1):.3f}" for k, v in prof.items() if v[1]))
-    roof = roofline(info, prof, n, prec, a.workload, a.precision)
+    roof = roofline(info, prof, n, prec, a.workload, a.precision) if a.stage_steps > 0 else None
 
     out = {
         "metric": "(A±B)P1 applies/sec + time to omega within 1e-5 Ha, learned/mixed "

@@ -594,25 +594,31 @@ void apply_sets(Handle &h, int n, const T *X, int ldx, int xp0, int xq0, T *F, i
   hipStream_t s = h.stream;
   // The K-shift term writes F and the coupling term adds into it last; up to that add the
   // two read only X. With a coupling term the K-shift products run on the handle's second
-  // stream, forked after the work queued so far on s and joined before the first add.
-  // While stage profiling is on, everything stays on s, so that each stage's event time
-  // is its own.
+  // stream, forked once the first response density is queued on s (so that they overlap
+  // the FFTs, the integrals and their reduce rather than the density) and joined before the
+  // first add.  While stage profiling is on, everything stays on s, so that each stage's
+  // event time is its own.
   const bool with_coupling = coupling && h.opts.xc != TDDFT_HXC_NONE;
   const bool fork = with_coupling && !h.prof.on;
-  hipStream_t ks = fork ? h.side : s;
-  if (fork) {
-    TD_HIP(hipEventRecord(h.ev_fork, s));
-    TD_HIP(hipStreamWaitEvent(ks, h.ev_fork, 0));
-  }
-  if (xq0 == xp0 + n && fq0 == fp0 + n) {
-    kshift_on<T>(h, ks, 2 * n, X, ldx, xp0, F, ldf, fp0);
-  } else {
-    kshift_on<T>(h, ks, n, X, ldx, xp0, F, ldf, fp0);
-    kshift_on<T>(h, ks, n, X, ldx, xq0, F, ldf, fq0);
-  }
+  auto kshift_all = [&](hipStream_t ks) {
+    if (xq0 == xp0 + n && fq0 == fp0 + n) {
+      kshift_on<T>(h, ks, 2 * n, X, ldx, xp0, F, ldf, fp0);
+    } else {
+      kshift_on<T>(h, ks, n, X, ldx, xp0, F, ldf, fp0);
+      kshift_on<T>(h, ks, n, X, ldx, xq0, F, ldf, fq0);
+    }
+  };
+  if (!fork) kshift_all(s);
   if (!with_coupling) return;
-  if (fork) TD_HIP(hipEventRecord(h.ev_join, ks));
-  bool joined = !fork;
+  bool forked = !fork, joined = !fork;
+  auto fork_kshift = [&]() {
+    if (forked) return;
+    TD_HIP(hipEventRecord(h.ev_fork, s));
+    TD_HIP(hipStreamWaitEvent(h.side, h.ev_fork, 0));
+    kshift_all(h.side);
+    TD_HIP(hipEventRecord(h.ev_join, h.side));
+    forked = true;
+  };
   const int npair = (n + 1) / 2;
   const int64_t pstride = (int64_t)h.nt * TP * 2;
   const int64_t wstride = (int64_t)h.n[0] * h.n[1] * h.n[2] * 2;
@@ -643,6 +649,7 @@ void apply_sets(Handle &h, int n, const T *X, int ldx, int xp0, int xq0, T *F, i
     h.prof.begin(ST_DENSITY, s);
     density<T>(tl, st, h.BU, h.BO, X, ldx, xc0, n, fields, pstride, 1.0, s);
     h.prof.end(ST_DENSITY, s);
+    fork_kshift();
     hartree_xc<T>(h.geom, h.fft, npair, fields, work, h.fxc<T>(), h.opts.xc == TDDFT_XC_ALDA_X, s, &h.prof);
     for (int s0 = 0; s0 < n; s0 += chunk) {
       const int ns = std::min(chunk, n - s0);
