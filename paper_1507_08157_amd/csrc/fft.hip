@@ -261,6 +261,10 @@ __device__ typename C2<T>::type *fft_lines(typename C2<T>::type *a, typename C2<
   return a;
 }
 
+// global loads each thread keeps in flight when staging lines (one memory round trip per
+// batch: a loop with a run-time trip count would otherwise wait on every iteration)
+constexpr int kLoadBatch = 8;
+
 struct GeomDev {
   int nx, ny, nz, ntx, nty, ntz;
   int64_t pair_tile;   // elements (complex) per field in tile-major layout
@@ -284,11 +288,22 @@ __global__ __launch_bounds__(256) void k_fft_x_fwd(GeomDev g, AxisDev ax,
   const int pair = blockIdx.y;
   const T2 *src = fields + pair * g.pair_tile + (int64_t)row * g.ntx * TP;
   const int ntot = g.ntx * TP;
-  for (int e = threadIdx.x; e < ntot; e += blockDim.x) {
-    const int tx = e / TP, p = e - (e / TP) * TP;
-    const int px = p & 3, l = p >> 2;
-    const int x = tx * 4 + px;
-    if (x < g.nx) a[l * ldl + x] = src[e];
+  // loads in batches of kLoadBatch per thread, all in flight before the LDS writes
+  for (int b0 = 0; b0 < ntot; b0 += kLoadBatch * 256) {
+    T2 v[kLoadBatch];
+#pragma unroll
+    for (int u = 0; u < kLoadBatch; ++u) {
+      const int e = b0 + u * 256 + (int)threadIdx.x;
+      if (e < ntot) v[u] = src[e];
+    }
+#pragma unroll
+    for (int u = 0; u < kLoadBatch; ++u) {
+      const int e = b0 + u * 256 + (int)threadIdx.x;
+      const int tx = e / TP, p = e - (e / TP) * TP;
+      const int px = p & 3, l = p >> 2;
+      const int x = tx * 4 + px;
+      if (e < ntot && x < g.nx) a[l * ldl + x] = v[u];
+    }
   }
   __syncthreads();
   T2 *res = fft_lines<T, -1, INPL>(a, b, ldl, 16, ax, tw);
@@ -317,9 +332,20 @@ __global__ __launch_bounds__(256) void k_fft_y(GeomDev g, AxisDev ax,
   const int x0 = xb * XB;
   const int nl = min(XB, g.nx - x0);
   T2 *base = work + blockIdx.y * g.pair_work + (int64_t)z * g.ny * g.nx + x0;
-  for (int e = threadIdx.x; e < XB * g.ny; e += blockDim.x) {
-    const int y = e / XB, l = e - y * XB;
-    if (l < nl) a[l * ldl + y] = base[(int64_t)y * g.nx + l];
+  for (int b0 = 0; b0 < XB * g.ny; b0 += kLoadBatch * 256) {
+    T2 v[kLoadBatch];
+#pragma unroll
+    for (int u = 0; u < kLoadBatch; ++u) {
+      const int e = b0 + u * 256 + (int)threadIdx.x;
+      const int y = e / XB, l = e - y * XB;
+      if (e < XB * g.ny && l < nl) v[u] = base[(int64_t)y * g.nx + l];
+    }
+#pragma unroll
+    for (int u = 0; u < kLoadBatch; ++u) {
+      const int e = b0 + u * 256 + (int)threadIdx.x;
+      const int y = e / XB, l = e - y * XB;
+      if (e < XB * g.ny && l < nl) a[l * ldl + y] = v[u];
+    }
   }
   __syncthreads();
   T2 *res = fft_lines<T, SIGN, INPL>(a, b, ldl, nl, ax, tw);
@@ -347,9 +373,20 @@ __global__ __launch_bounds__(256) void k_fft_z_poisson(GeomDev g, AxisDev ax,
   const int nl = min(XB, g.nx - x0);
   const int64_t plane = (int64_t)g.ny * g.nx;
   T2 *base = work + blockIdx.y * g.pair_work + (int64_t)y * g.nx + x0;
-  for (int e = threadIdx.x; e < XB * g.nz; e += blockDim.x) {
-    const int z = e / XB, l = e - z * XB;
-    if (l < nl) a[l * ldl + z] = base[(int64_t)z * plane + l];
+  for (int b0 = 0; b0 < XB * g.nz; b0 += kLoadBatch * 256) {
+    T2 v[kLoadBatch];
+#pragma unroll
+    for (int u = 0; u < kLoadBatch; ++u) {
+      const int e = b0 + u * 256 + (int)threadIdx.x;
+      const int z = e / XB, l = e - z * XB;
+      if (e < XB * g.nz && l < nl) v[u] = base[(int64_t)z * plane + l];
+    }
+#pragma unroll
+    for (int u = 0; u < kLoadBatch; ++u) {
+      const int e = b0 + u * 256 + (int)threadIdx.x;
+      const int z = e / XB, l = e - z * XB;
+      if (e < XB * g.nz && l < nl) a[l * ldl + z] = v[u];
+    }
   }
   __syncthreads();
   T2 *res = fft_lines<T, -1, INPL>(a, b, ldl, nl, ax, tw);
@@ -391,38 +428,62 @@ __global__ __launch_bounds__(256) void k_fft_x_inv(GeomDev g, AxisDev ax,
   const int row = blockIdx.x;
   const int ty = row % g.nty, tz = row / g.nty;
   const int pair = blockIdx.y;
-  for (int e = threadIdx.x; e < 16 * g.nx; e += blockDim.x) {
-    const int l = e / g.nx, x = e - l * g.nx;
-    const int y = ty * 4 + (l & 3), z = tz * 4 + (l >> 2);
-    T2 v;
-    v.x = T(0);
-    v.y = T(0);
-    if (y < g.ny && z < g.nz) v = work[pair * g.pair_work + ((int64_t)z * g.ny + y) * g.nx + x];
-    a[l * ldl + x] = v;
+  for (int b0 = 0; b0 < 16 * g.nx; b0 += kLoadBatch * 256) {
+    T2 v[kLoadBatch];
+#pragma unroll
+    for (int u = 0; u < kLoadBatch; ++u) {
+      const int e = b0 + u * 256 + (int)threadIdx.x;
+      const int l = e / g.nx, x = e - l * g.nx;
+      const int y = ty * 4 + (l & 3), z = tz * 4 + (l >> 2);
+      v[u].x = T(0);
+      v[u].y = T(0);
+      if (e < 16 * g.nx && y < g.ny && z < g.nz) v[u] = work[pair * g.pair_work + ((int64_t)z * g.ny + y) * g.nx + x];
+    }
+#pragma unroll
+    for (int u = 0; u < kLoadBatch; ++u) {
+      const int e = b0 + u * 256 + (int)threadIdx.x;
+      const int l = e / g.nx, x = e - l * g.nx;
+      if (e < 16 * g.nx) a[l * ldl + x] = v[u];
+    }
   }
   __syncthreads();
   T2 *res = fft_lines<T, 1, INPL>(a, b, ldl, 16, ax, tw);
   T2 *dst = fields + pair * g.pair_tile + (int64_t)row * g.ntx * TP;
   const T *fx = fxc + (int64_t)row * g.ntx * TP;
   const int ntot = g.ntx * TP;
-  for (int e = threadIdx.x; e < ntot; e += blockDim.x) {
-    const int tx = e / TP, p = e - (e / TP) * TP;
-    const int px = p & 3, l = p >> 2;
-    const int x = tx * 4 + px;
-    const int y = ty * 4 + (l & 3), z = tz * 4 + (l >> 2);
-    T2 v;
-    v.x = T(0);
-    v.y = T(0);
-    if (x < g.nx && y < g.ny && z < g.nz) {
-      v = res[l * ldl + x];
-      if (use_fxc) {
-        const T2 rho = dst[e];
-        const T f = fx[e];
-        v.x += f * rho.x;
-        v.y += f * rho.y;
+  for (int b0 = 0; b0 < ntot; b0 += kLoadBatch * 256) {
+    T2 rho[kLoadBatch];
+    T f[kLoadBatch];
+    if (use_fxc) {
+#pragma unroll
+      for (int u = 0; u < kLoadBatch; ++u) {
+        const int e = b0 + u * 256 + (int)threadIdx.x;
+        if (e < ntot) {
+          rho[u] = dst[e];
+          f[u] = fx[e];
+        }
       }
     }
-    dst[e] = v;
+#pragma unroll
+    for (int u = 0; u < kLoadBatch; ++u) {
+      const int e = b0 + u * 256 + (int)threadIdx.x;
+      if (e >= ntot) continue;
+      const int tx = e / TP, p = e - (e / TP) * TP;
+      const int px = p & 3, l = p >> 2;
+      const int x = tx * 4 + px;
+      const int y = ty * 4 + (l & 3), z = tz * 4 + (l >> 2);
+      T2 v;
+      v.x = T(0);
+      v.y = T(0);
+      if (x < g.nx && y < g.ny && z < g.nz) {
+        v = res[l * ldl + x];
+        if (use_fxc) {
+          v.x += f[u] * rho[u].x;
+          v.y += f[u] * rho[u].y;
+        }
+      }
+      dst[e] = v;
+    }
   }
 }
 
