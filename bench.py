@@ -254,6 +254,36 @@ def batch_solves(systems, precision="fp32"):
             "converged": int(sum(1 for b in bat if b[2]["converged"]))}
 
 
+def joint_apply(sysj, precision, steps, warmup, plain_value):
+    """Applies of the same workload in the joint unoccupied representation (u-set = o- and
+    u-functions of every atom, K^c the complement projector of Eq. proj): throughput and
+    its cost relative to the plain u-set."""
+    import torch
+    from paper_1507_08157_amd import binding
+    from synth import abi as sabi
+    n = sysj.cfg.n_states
+    hj = binding.tddft_create(sabi.system_arrays(sysj), precision=precision)
+    info = hj.tddft_get_info()
+    rng = np.random.default_rng(2025)
+    X = rng.standard_normal((2, n, sysj.vir.n_fn, sysj.occ.n_fn)) * sysj.fn_mask()[None, None]
+    Pp = torch.from_numpy(sabi.dense_to_p(sysj, X[0])).cuda()
+    Pq = torch.from_numpy(sabi.dense_to_p(sysj, X[1])).cuda()
+    fp, fq = torch.empty_like(Pp), torch.empty_like(Pq)
+    for _ in range(warmup):
+        hj.tddft_apply(Pp, Pq, fp, fq)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    for _ in range(steps):
+        hj.tddft_apply(Pp, Pq, fp, fq)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t1
+    hj.close()
+    v = n * steps / dt
+    return {"value": round(v, 2), "unit": "state-applies/s", "ms_per_apply": round(dt * 1e3 / steps, 4),
+            "cost_vs_plain_u_set": round(plain_value / v, 3), "u_functions_per_atom": sysj.vir.n_per_atom,
+            "pair_points": int(info["pair_points"]), "blocks_r": int(info["blocks_r"])}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -266,6 +296,8 @@ def main():
     ap.add_argument("--no-solve", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MiB")
+    ap.add_argument("--no-joint", action="store_true",
+                    help="skip the apply in the joint unoccupied representation (Eq. proj)")
     ap.add_argument("--batch", type=int, default=0, metavar="K",
                     help="also time K systems of the batch workload solved one after another "
                          "and through tddft_pcg_solve_batched")
@@ -285,6 +317,11 @@ def main():
     sysm = build_workload(a.workload)
     arrays = sabi.system_arrays(sysm)
     log(f"workload {a.workload}: generated in {time.perf_counter() - t0:.1f} s")
+    sys_joint = None
+    if not a.no_joint and a.workload == "prec":
+        t0 = time.perf_counter()
+        sys_joint = build_workload("prec_joint")
+        log(f"workload prec_joint: generated in {time.perf_counter() - t0:.1f} s")
     n = sysm.cfg.n_states
     prec = binding.PRECISION[a.precision]
     h = binding.tddft_create(arrays, precision=a.precision)
@@ -353,6 +390,10 @@ def main():
         "roofline": roof,
         "stage_ms_per_launch": {k: round(v[0] / v[1], 4) for k, v in prof.items() if v[1]},
     }
+
+    if sys_joint is not None and value is not None:
+        out["joint"] = joint_apply(sys_joint, a.precision, a.steps, a.warmup, value)
+        log(f"joint representation: {out['joint']}")
 
     if not a.no_solve:
         # reference: plain FP64 PCG converged to 1e-9 Ha

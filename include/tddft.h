@@ -66,10 +66,13 @@ extern "C" {
 #define TDDFT_PC_KSDIFF_CG  1  /* solve Eq. precond by CG to relative tolerance eps_tol    */
 #define TDDFT_PC_LEARNED    2  /* learned block correction, KSDIFF_CG as fallback          */
 
-/* Block-sparse matrix in BSR form with variable block sizes.  Blocks are dense and
- * row-major; their values are concatenated in (block row, colind) order.  rowptr and
- * colind describe the block pattern; colind is sorted within each block row.  For a
- * pattern-only matrix (M) val is NULL. */
+/* Block-sparse matrix in BSR form with variable block sizes (1 to 5 functions per atom).
+ * Blocks are dense and row-major; their values are concatenated in (block row, colind)
+ * order.  rowptr and colind describe the block pattern; colind is sorted within each block
+ * row.  For a pattern-only matrix (M) val is NULL.  The largest u-set and o-set blocks set
+ * the padded shape BU x BO of the kernels, which must be one of 3 x 2, 1 x 1, 2 x 2,
+ * 3 x 3, 4 x 4 or 5 x 2 (the joint unoccupied representation of Eq. proj: o- and
+ * u-functions of an atom in one u-set block); other shapes fail with TDDFT_E_INVALID. */
 typedef struct {
   int32_t nbr, nbc;          /* number of block rows / block columns (atoms)            */
   const int32_t *row_off;    /* [nbr+1] first function of each block row               */

@@ -34,7 +34,7 @@ class Operator:
         self.h = sysm.cfg.h
         self.Su, self.Hu, self.Kc = sysm.S_u, sysm.H_u, sysm.K_c
         self.So, self.Ho, self.Kv = sysm.S_o, sysm.H_o, sysm.K_v
-        nb = (sysm.cfg.n_u, sysm.cfg.n_o)
+        nb = (sysm.vir.n_per_atom, sysm.occ.n_per_atom)
         self.mask_L = np.kron(sysm.M, np.ones(nb))
         self.mask = np.kron(response_pattern(sysm), np.ones(nb))
         self.xc = xc
@@ -113,6 +113,7 @@ def response_pattern(sysm) -> np.ndarray:
 
     def blocks(A, b):
         return (np.abs(A.reshape(nA, b, nA, b)).max(axis=(1, 3)) > 0).astype(np.int64)
-    pu = blocks(sysm.K_c, sysm.cfg.n_u) @ blocks(sysm.S_u, sysm.cfg.n_u)
-    po = blocks(sysm.S_o, sysm.cfg.n_o) @ blocks(sysm.K_v, sysm.cfg.n_o)
+    nu, no = sysm.vir.n_per_atom, sysm.occ.n_per_atom
+    pu = blocks(sysm.K_c, nu) @ blocks(sysm.S_u, nu)
+    po = blocks(sysm.S_o, no) @ blocks(sysm.K_v, no)
     return ((pu > 0).astype(np.int64) @ sysm.M.astype(np.int64) @ (po > 0).astype(np.int64)) > 0

@@ -44,7 +44,7 @@ def _box_centres(fs, h):
 def block_features(sysm, blocks: np.ndarray) -> np.ndarray:
     """[number of true entries of `blocks`, n_features] in row-major block order."""
     cfg = sysm.cfg
-    bu, bo = cfg.n_u, cfg.n_o
+    bu, bo = sysm.vir.n_per_atom, sysm.occ.n_per_atom
     nA = cfg.n_atoms
     fu, fo = [], []
     for I in range(nA):
@@ -71,7 +71,7 @@ def block_features(sysm, blocks: np.ndarray) -> np.ndarray:
 
 def block_view(sysm, X: np.ndarray, blocks: np.ndarray) -> np.ndarray:
     """[k, n_u, n_o] -> [k, number of blocks, n_u_per_atom * n_o_per_atom] (row-major blocks)."""
-    bu, bo = sysm.cfg.n_u, sysm.cfg.n_o
+    bu, bo = sysm.vir.n_per_atom, sysm.occ.n_per_atom
     nA = sysm.cfg.n_atoms
     Xb = X.reshape(X.shape[0], nA, bu, nA, bo).transpose(0, 1, 3, 2, 4)
     I, J = np.nonzero(blocks)
@@ -80,7 +80,7 @@ def block_view(sysm, X: np.ndarray, blocks: np.ndarray) -> np.ndarray:
 
 def expand_blocks(sysm, vals: np.ndarray, blocks: np.ndarray) -> np.ndarray:
     """[number of blocks, n_u_per_atom * n_o_per_atom] -> dense [n_u, n_o] (zero outside)."""
-    bu, bo = sysm.cfg.n_u, sysm.cfg.n_o
+    bu, bo = sysm.vir.n_per_atom, sysm.occ.n_per_atom
     nA = sysm.cfg.n_atoms
     out = np.zeros((nA, nA, bu, bo))
     I, J = np.nonzero(blocks)

@@ -100,7 +100,11 @@ __global__ __launch_bounds__(256) void k_density(DevTiles tl, const S *__restric
                                                  const int32_t *__restrict__ pidx,
                                                  const T *__restrict__ X, int ldx, int xc0, int ns,
                                                  T *__restrict__ out, int64_t pair_stride, T scale) {
-  constexpr int NS = sizeof(T) == 8 ? 4 : 8;   // states per pass (P of a block fits in SGPRs)
+  // states per pass: a P block (NS * BL * BR values) within 48 SGPRs, NS even (fields hold
+  // state pairs): 8 in FP32 and 4 in FP64 for 3 x 2 blocks
+  constexpr int kSlots = sizeof(T) == 8 ? 24 : 48, kMax = sizeof(T) == 8 ? 4 : 8;
+  constexpr int NSe = (kSlots / (BL * BR)) & ~1;
+  constexpr int NS = NSe < 2 ? 2 : (NSe > kMax ? kMax : NSe);
   const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
   const int t = blockIdx.x * (blockDim.x >> 6) + w;
@@ -469,6 +473,7 @@ __global__ void k_alda(int64_t npts, const T *__restrict__ rho, double floor, T 
     else if (BL_ == 1 && BR_ == 1) { constexpr int BL = 1, BR = 1; __VA_ARGS__; } \
     else if (BL_ == 3 && BR_ == 3) { constexpr int BL = 3, BR = 3; __VA_ARGS__; } \
     else if (BL_ == 4 && BR_ == 4) { constexpr int BL = 4, BR = 4; __VA_ARGS__; } \
+    else if (BL_ == 5 && BR_ == 2) { constexpr int BL = 5, BR = 2; __VA_ARGS__; } \
     else throw Error{TDDFT_E_INVALID, "unsupported padded block shape"};        \
   } while (0)
 

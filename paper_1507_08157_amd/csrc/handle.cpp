@@ -60,7 +60,7 @@ static std::vector<int> read_offsets(const int32_t *off, int nb, const char *wha
   TD_REQUIRE(v[0] == 0, std::string(what) + ": block offsets must start at 0");
   for (int i = 0; i < nb; ++i) {
     const int sz = v[i + 1] - v[i];
-    TD_REQUIRE(sz >= 1 && sz <= 4, std::string(what) + ": block sizes must be 1..4");
+    TD_REQUIRE(sz >= 1 && sz <= 5, std::string(what) + ": block sizes must be 1..5");
   }
   return v;
 }
@@ -321,12 +321,16 @@ void create_handle(Handle &h, const tddft_system &sys, const tddft_options &o) {
   int bo = 0, bu = 0;
   for (int i = 0; i < h.nbo; ++i) bo = std::max(bo, h.ooff[i + 1] - h.ooff[i]);
   for (int i = 0; i < h.nbu; ++i) bu = std::max(bu, h.uoff[i + 1] - h.uoff[i]);
-  // padded shapes supported by the kernels: (1,1) (2,2) (3,2) (3,3) (4,4)
+  // padded shapes supported by the kernels: (1,1) (2,2) (3,2) (3,3) (5,2) (4,4); every
+  // block is copied into a padded one, so the padded shape must cover the largest block
   if (bu <= 1 && bo <= 1) { h.BU = 1; h.BO = 1; }
   else if (bu <= 2 && bo <= 2) { h.BU = 2; h.BO = 2; }
   else if (bu <= 3 && bo <= 2) { h.BU = 3; h.BO = 2; }
   else if (bu <= 3 && bo <= 3) { h.BU = 3; h.BO = 3; }
+  else if (bu <= 5 && bo <= 2) { h.BU = 5; h.BO = 2; }
   else { h.BU = 4; h.BO = 4; }
+  TD_REQUIRE(bu <= h.BU && bo <= h.BO,
+             "unsupported block sizes: at most 4 u- and 4 o-functions per atom, or 5 and 2");
   h.E = h.BU * h.BO;
 
   HostBsr So = read_bsr(sys.S_o, h.ooff, h.ooff, h.BO, h.BO, "S_o");

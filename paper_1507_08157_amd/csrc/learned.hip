@@ -22,68 +22,69 @@ int n_features(int bu, int bo) { return bu * (bu + 1) + bo * (bo + 1) + bu + bo 
 // ascending, written to out[0..n); out[n..B) = 0.  Cholesky S = L L^T, C = L^-1 H L^-T,
 // cyclic Jacobi rotations on C.
 static void small_gen_eig(int n, int B, const double *S, const double *H, double *out) {
-  double L[16] = {0}, C[16] = {0}, Y[16] = {0};
+  constexpr int LD = 5;   // largest block
+  double L[LD * LD] = {0}, C[LD * LD] = {0}, Y[LD * LD] = {0};
   for (int j = 0; j < n; ++j) {
     double d = S[j * B + j];
-    for (int k = 0; k < j; ++k) d -= L[j * 4 + k] * L[j * 4 + k];
+    for (int k = 0; k < j; ++k) d -= L[j * LD + k] * L[j * LD + k];
     TD_REQUIRE(d > 0.0, "diagonal overlap block is not positive definite");
-    L[j * 4 + j] = std::sqrt(d);
+    L[j * LD + j] = std::sqrt(d);
     for (int i = j + 1; i < n; ++i) {
       double v = S[i * B + j];
-      for (int k = 0; k < j; ++k) v -= L[i * 4 + k] * L[j * 4 + k];
-      L[i * 4 + j] = v / L[j * 4 + j];
+      for (int k = 0; k < j; ++k) v -= L[i * LD + k] * L[j * LD + k];
+      L[i * LD + j] = v / L[j * LD + j];
     }
   }
   // Y = L^-1 H (forward substitution per column), C = Y L^-T
   for (int c = 0; c < n; ++c)
     for (int i = 0; i < n; ++i) {
       double v = H[i * B + c];
-      for (int k = 0; k < i; ++k) v -= L[i * 4 + k] * Y[k * 4 + c];
-      Y[i * 4 + c] = v / L[i * 4 + i];
+      for (int k = 0; k < i; ++k) v -= L[i * LD + k] * Y[k * LD + c];
+      Y[i * LD + c] = v / L[i * LD + i];
     }
   for (int r = 0; r < n; ++r)
     for (int j = 0; j < n; ++j) {
-      double v = Y[r * 4 + j];
-      for (int k = 0; k < j; ++k) v -= C[r * 4 + k] * L[j * 4 + k];
-      C[r * 4 + j] = v / L[j * 4 + j];
+      double v = Y[r * LD + j];
+      for (int k = 0; k < j; ++k) v -= C[r * LD + k] * L[j * LD + k];
+      C[r * LD + j] = v / L[j * LD + j];
     }
   for (int i = 0; i < n; ++i)
-    for (int j = i + 1; j < n; ++j) C[i * 4 + j] = C[j * 4 + i] = 0.5 * (C[i * 4 + j] + C[j * 4 + i]);
+    for (int j = i + 1; j < n; ++j) C[i * LD + j] = C[j * LD + i] = 0.5 * (C[i * LD + j] + C[j * LD + i]);
   for (int sweep = 0; sweep < 50; ++sweep) {
     double off = 0.0, tot = 0.0;
     for (int i = 0; i < n; ++i)
       for (int j = 0; j < n; ++j) {
-        tot += C[i * 4 + j] * C[i * 4 + j];
-        if (i != j) off += C[i * 4 + j] * C[i * 4 + j];
+        tot += C[i * LD + j] * C[i * LD + j];
+        if (i != j) off += C[i * LD + j] * C[i * LD + j];
       }
     if (off <= 1e-30 * tot) break;
     for (int p = 0; p < n; ++p)
       for (int q = p + 1; q < n; ++q) {
-        const double apq = C[p * 4 + q];
+        const double apq = C[p * LD + q];
         if (apq == 0.0) continue;
-        const double theta = (C[q * 4 + q] - C[p * 4 + p]) / (2.0 * apq);
+        const double theta = (C[q * LD + q] - C[p * LD + p]) / (2.0 * apq);
         const double tt = (theta >= 0 ? 1.0 : -1.0) / (std::fabs(theta) + std::sqrt(theta * theta + 1.0));
         const double c = 1.0 / std::sqrt(tt * tt + 1.0), sn = tt * c;
         for (int k = 0; k < n; ++k) {   // columns p, q
-          const double a = C[k * 4 + p], b = C[k * 4 + q];
-          C[k * 4 + p] = c * a - sn * b;
-          C[k * 4 + q] = sn * a + c * b;
+          const double a = C[k * LD + p], b = C[k * LD + q];
+          C[k * LD + p] = c * a - sn * b;
+          C[k * LD + q] = sn * a + c * b;
         }
         for (int k = 0; k < n; ++k) {   // rows p, q
-          const double a = C[p * 4 + k], b = C[q * 4 + k];
-          C[p * 4 + k] = c * a - sn * b;
-          C[q * 4 + k] = sn * a + c * b;
+          const double a = C[p * LD + k], b = C[q * LD + k];
+          C[p * LD + k] = c * a - sn * b;
+          C[q * LD + k] = sn * a + c * b;
         }
       }
   }
-  for (int i = 0; i < B; ++i) out[i] = i < n ? C[i * 4 + i] : 0.0;
+  for (int i = 0; i < B; ++i) out[i] = i < n ? C[i * LD + i] : 0.0;
   std::sort(out, out + n);
 }
 
 void build_features(Handle &h, const HostBsr &Su, const HostBsr &Hu, const HostBsr &So,
                     const HostBsr &Ho, const tddft_system &sys) {
   const int bu = h.BU, bo = h.BO;
-  TD_REQUIRE(bu <= 4 && bo <= 4, "block size");
+  TD_REQUIRE(bu <= 5 && bo <= 5, "block size");
   const int nf = n_features(bu, bo);
   struct Atom {
     std::vector<double> su, hu, eig;

@@ -341,6 +341,7 @@ __global__ __launch_bounds__(64 * G::WMW * G::WNW) void k_gemm_blocks(int di, in
     else if (BU_ == 2 && BO_ == 2) { constexpr int BU = 2, BO = 2; __VA_ARGS__; } \
     else if (BU_ == 3 && BO_ == 3) { constexpr int BU = 3, BO = 3; __VA_ARGS__; } \
     else if (BU_ == 4 && BO_ == 4) { constexpr int BU = 4, BO = 4; __VA_ARGS__; } \
+    else if (BU_ == 5 && BO_ == 2) { constexpr int BU = 5, BO = 2; __VA_ARGS__; } \
     else throw Error{TDDFT_E_INVALID, "unsupported padded block shape"};     \
   } while (0)
 
@@ -635,7 +636,7 @@ void gram(int64_t nblk, int E, const T *X, int ldx, int xc0, int n1, const T *Y,
           hipStream_t s) {
   const int npair = diag ? n1 : n1 * n2;
   if (npair > kGramMaxPairs) throw Error{TDDFT_E_INVALID, "gram: too many column pairs"};
-  if (diag && n1 >= 1 && n1 <= 64 && (E == 1 || E == 4 || E == 6 || E == 9 || E == 16)) {
+  if (diag && n1 >= 1 && n1 <= 64 && (E == 1 || E == 4 || E == 6 || E == 9 || E == 10 || E == 16)) {
     // about eight blocks per thread
     const int R = 256 / n1;
     int64_t per = std::max<int64_t>((int64_t)8 * R, (nblk + max_parts - 1) / max_parts);
@@ -647,6 +648,7 @@ void gram(int64_t nblk, int E, const T *X, int ldx, int xc0, int n1, const T *Y,
     else if (E == 4) TD_GRAM_DIAG(4);
     else if (E == 6) TD_GRAM_DIAG(6);
     else if (E == 9) TD_GRAM_DIAG(9);
+    else if (E == 10) TD_GRAM_DIAG(10);
     else TD_GRAM_DIAG(16);
 #undef TD_GRAM_DIAG
     TD_HIP(hipGetLastError());

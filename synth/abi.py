@@ -70,7 +70,7 @@ def system_arrays(sysm) -> dict:
     """Everything tddft_create needs, as contiguous numpy arrays."""
     cfg = sysm.cfg
     nA = cfg.n_atoms
-    no, nu = cfg.n_o, cfg.n_u
+    no, nu = sysm.occ.n_per_atom, sysm.vir.n_per_atom
     out = dict(n=np.array([cfg.N] * 3, dtype=np.int32), L=np.array([cfg.L] * 3))
     out["occ"] = _functions(sysm.occ, cfg.N)
     out["vir"] = _functions(sysm.vir, cfg.N)
@@ -97,14 +97,15 @@ def response_blocks(sysm) -> np.ndarray:
 
     def bmul(X, Y):
         return (X.astype(np.int32) @ Y.astype(np.int32)) > 0
-    left = bmul(nz(sysm.K_c, sysm.cfg.n_u), nz(sysm.S_u, sysm.cfg.n_u))
-    right = bmul(nz(sysm.S_o, sysm.cfg.n_o), nz(sysm.K_v, sysm.cfg.n_o))
+    nu, no = sysm.vir.n_per_atom, sysm.occ.n_per_atom
+    left = bmul(nz(sysm.K_c, nu), nz(sysm.S_u, nu))
+    right = bmul(nz(sysm.S_o, no), nz(sysm.K_v, no))
     return bmul(bmul(left, sysm.M), right)
 
 
 def _index(sysm, blocks) -> np.ndarray:
     cfg = sysm.cfg
-    nu, no = cfg.n_u, cfg.n_o
+    nu, no = sysm.vir.n_per_atom, sysm.occ.n_per_atom
     idx = []
     nofn = sysm.occ.n_fn
     for I in range(cfg.n_atoms):

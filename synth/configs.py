@@ -104,5 +104,23 @@ def small_crowded(seed: int = 17) -> Config:
                   n_vir=32, R_K=None, R_M=None, n_states=5, seed=seed)
 
 
+def prec_joint(seed: int = 1000) -> Config:
+    """`prec` in the joint unoccupied representation (u-set = o- and u-functions of every
+    atom, 5 per atom; K^c the complement projector of Eq. proj)."""
+    c = prec(seed)
+    d = dict(c.__dict__)
+    d.update(name="prec_joint", joint=True)
+    return Config(**d)
+
+
+def small_joint(seed: int = 11) -> Config:
+    """`small_dense` in the joint unoccupied representation."""
+    c = small_dense(seed)
+    d = dict(c.__dict__)
+    d.update(name="small_joint", joint=True)
+    return Config(**d)
+
+
 BY_NAME = {"tiny": tiny, "prec": prec, "small_dense": small_dense,
-           "small_trunc": small_trunc, "small_odd": small_odd, "small_crowded": small_crowded}
+           "small_trunc": small_trunc, "small_odd": small_odd, "small_crowded": small_crowded,
+           "prec_joint": prec_joint, "small_joint": small_joint}

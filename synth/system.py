@@ -67,6 +67,10 @@ class Config:
     min_sep: float = 2.5
     gap_margin: float = 0.05
     mcweeny_steps: int = 2
+    # joint unoccupied representation (Eq. proj): the u-set is every function of an atom,
+    # o-functions first (n_o + n_u per atom), and K^c is the complement projector
+    # S^-1 - S^-1 S^{.o} K^v S^{o.} S^-1 of the occupied space within that set
+    joint: bool = False
 
     @property
     def h(self) -> float:
@@ -129,7 +133,7 @@ class System:
 
     def fn_mask(self) -> np.ndarray:
         """Function-level mask of M, [n_u_fn, n_o_fn]."""
-        return np.kron(self.M, np.ones((self.cfg.n_u, self.cfg.n_o))).astype(bool)
+        return np.kron(self.M, np.ones((self.vir.n_per_atom, self.occ.n_per_atom))).astype(bool)
 
 
 def _min_image(d: np.ndarray, L: float) -> np.ndarray:
@@ -344,15 +348,29 @@ def _build(cfg: Config, seed: int) -> System:
     S_uo = S[np.ix_(u_sel, o_sel)]
 
     eps_o, B = scipy.linalg.eigh(H_o, S_o)
-    eps_u, A = scipy.linalg.eigh(H_u, S_u)
     occ_idx = np.arange(cfg.n_occ)
     homo = eps_o[cfg.n_occ - 1]
-    above = np.nonzero(eps_u > homo + cfg.gap_margin)[0]
-    if len(above) < cfg.n_vir:
-        raise _NotEnoughStates(f"seed {seed}: {len(above)} u-states above threshold")
-    vir_idx = above[:cfg.n_vir]
     K_v = B[:, occ_idx] @ B[:, occ_idx].T
-    K_c = A[:, vir_idx] @ A[:, vir_idx].T
+    if cfg.joint:
+        if cfg.R_K is not None:
+            raise ValueError("joint representation: untruncated kernels only")
+        # the u-set is the whole per-atom function list; S^-1 S^{.o} selects the o-positions
+        S_u, H_u, S_uo = S, H, S[:, o_sel]
+        K_c = np.linalg.inv(S)
+        K_c[np.ix_(o_sel, o_sel)] -= K_v
+        # levels of the complement: H projected onto range(K^c) in an S-orthonormal basis.
+        # With independently drawn o- and u-functions these reach below the HOMO (mixing in
+        # the u-functions lowers the joint spectrum), so A - B is not positive definite and
+        # only the operator application is meaningful on such systems
+        eps_u = complement_levels(H_u, S_u, K_c)
+        vir_idx = np.arange(len(eps_u))
+    else:
+        eps_u, A = scipy.linalg.eigh(H_u, S_u)
+        above = np.nonzero(eps_u > homo + cfg.gap_margin)[0]
+        if len(above) < cfg.n_vir:
+            raise _NotEnoughStates(f"seed {seed}: {len(above)} u-states above threshold")
+        vir_idx = above[:cfg.n_vir]
+        K_c = A[:, vir_idx] @ A[:, vir_idx].T
 
     if cfg.R_K is None:
         maskK = np.ones((nA, nA), dtype=bool)
@@ -376,12 +394,23 @@ def _build(cfg: Config, seed: int) -> System:
 
     occ = FunctionSet(cfg.n_o, origins.copy(), extents.copy(),
                       [v[:cfg.n_o].copy() for v in allv])
-    vir = FunctionSet(cfg.n_u, origins.copy(), extents.copy(),
-                      [v[cfg.n_o:].copy() for v in allv])
+    if cfg.joint:
+        vir = FunctionSet(nf, origins.copy(), extents.copy(), [v.copy() for v in allv])
+    else:
+        vir = FunctionSet(cfg.n_u, origins.copy(), extents.copy(),
+                          [v[cfg.n_o:].copy() for v in allv])
     cfg_used = cfg if seed == cfg.seed else _with_seed(cfg, seed)
     return System(cfg=cfg_used, pos=pos, occ=occ, vir=vir, S_o=S_o, H_o=H_o, K_v=K_v,
                   S_u=S_u, H_u=H_u, K_c=K_c, S_uo=S_uo, M=M, maskK=maskK, eps_o=eps_o,
                   eps_u=eps_u, occ_idx=occ_idx, vir_idx=vir_idx, idem_err=idem)
+
+
+def complement_levels(H: np.ndarray, S: np.ndarray, K: np.ndarray) -> np.ndarray:
+    """Eigenvalues of H restricted to range(K) for an S-idempotent K (K S K = K): with
+    C an S-orthonormal basis of that range, the eigenvalues of C^T H C, ascending."""
+    w, V = scipy.linalg.eigh(S @ K @ S, S)
+    C = V[:, w > 0.5]
+    return np.linalg.eigvalsh(0.5 * (C.T @ H @ C + (C.T @ H @ C).T))
 
 
 def _with_seed(cfg: Config, seed: int) -> Config:

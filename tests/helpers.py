@@ -15,7 +15,7 @@ XC_MODES = {  # C-ABI coupling kernel -> oracle switches
 
 def response_mask(sysm):
     """Function-level mask of the response pattern (blocks of K^c S^u L S^o K^v, L on M)."""
-    return np.kron(sabi.response_blocks(sysm), np.ones((sysm.cfg.n_u, sysm.cfg.n_o))).astype(bool)
+    return np.kron(sabi.response_blocks(sysm), np.ones((sysm.vir.n_per_atom, sysm.occ.n_per_atom))).astype(bool)
 
 
 def random_p(sysm, n, seed):

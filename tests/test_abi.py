@@ -126,9 +126,42 @@ def test_rejects_box_larger_than_cell(arrays):
 
 def test_rejects_block_size(arrays):
     a = _copy(arrays)
-    # one o-block of 5 functions
+    # one o-block of 6 functions
     off = a["S_o"]["row_off"].copy()
-    off[1:] = off[1:] + 3
+    off[1:] = off[1:] + 4
     off[-1] = a["S_o"]["row_off"][-1]
     a["S_o"]["row_off"] = off
-    _expect_invalid(a, "block sizes must be 1..4")
+    _expect_invalid(a, "block sizes must be 1..5")
+
+
+def test_joint_blocks_pass_the_host_checks():
+    """5 u-functions x 2 o-functions per atom (the joint representation) select the 5 x 2
+    padded shape: every host-side step, which copies each block into its padded one, runs
+    to the first device call (on a machine without a GPU that call fails cleanly)."""
+    from conftest import cached_system
+    s = cached_system("small_joint")
+    try:
+        h = binding.tddft_create(sabi.system_arrays(s), precision="fp64")
+    except binding.TddftError as e:
+        assert e.code == binding.TDDFT_E_DEVICE, str(e)
+        return
+    info = h.tddft_get_info()
+    h.close()
+    assert (info["block_rows"], info["block_cols"]) == (5, 2)
+
+
+def test_rejects_uncovered_block_shape(arrays):
+    """5 u-functions with 3 o-functions per atom fit no padded shape."""
+    a = _copy(arrays)
+    for name in ("S_o", "H_o", "K_v"):
+        off = a[name]["row_off"].copy()
+        off[1:] = off[1:] + 1                 # first o-block: 3 functions
+        off[-1] = a[name]["row_off"][-1]
+        a[name]["row_off"] = off
+    uoff = a["S_u"]["row_off"].copy()
+    uoff[1:] = uoff[1:] + 2                   # first u-block: 5 functions
+    uoff[-1] = a["S_u"]["row_off"][-1]
+    a["S_u"]["row_off"] = uoff
+    with pytest.raises(binding.TddftError) as e:
+        binding.tddft_create(a)
+    assert e.value.code == binding.TDDFT_E_INVALID

@@ -1,0 +1,33 @@
+"""GPU parity of the operator application in the joint unoccupied representation (Eq. proj:
+5 u-functions per atom, K^c the complement projector) against the FP64 oracle."""
+import numpy as np
+import pytest
+
+from helpers import gpu_handle, random_p, rel_err, to_dev
+from oracle.apply import Operator
+from synth import abi as sabi
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.mark.parametrize("precision,tol", [("fp64", 1e-11), ("fp32", 2e-5)])
+def test_joint_apply(precision, tol):
+    from conftest import cached_system
+    s = cached_system("small_joint")
+    print(f"[joint] apply {precision}", flush=True)
+    op = Operator(s)
+    Pp = random_p(s, 3, 31)
+    Pq = random_p(s, 3, 131)
+    fp_ref, fq_ref = op.apply(Pp, Pq)
+    h = gpu_handle(s, precision=precision)
+    info = h.tddft_get_info()
+    fp, fq = h.tddft_apply(to_dev(sabi.dense_to_p(s, Pp)), to_dev(sabi.dense_to_p(s, Pq)))
+    fp = sabi.p_to_dense(s, fp.cpu().numpy())
+    fq = sabi.p_to_dense(s, fq.cpu().numpy())
+    h.close()
+    assert info["block_rows"] == 5 and info["block_cols"] == 2
+    assert rel_err(fp, fp_ref) < tol
+    if precision == "fp64":
+        assert rel_err(fq, fq_ref) < tol
+    else:
+        assert np.max(np.abs(fq - fq_ref)) < tol * np.max(np.abs(fq_ref))
