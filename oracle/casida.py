@@ -19,14 +19,28 @@ from . import grid
 
 def kernel_states(H, S, K, tol=1e-8):
     """Eigenpairs of (H, S) spanned by the density kernel K: weights w = a^T S K S a are
-    1 for states in K and 0 otherwise."""
+    1 for states in K and 0 otherwise.  When K projects onto a subspace that no set of
+    eigenvectors of (H, S) spans (the complement projector of the joint representation,
+    Sec. II.C, Eq. proj), the states are those of H restricted to range(K): with C an
+    S-orthonormal basis of the range, the eigenpairs of C^T H C."""
     eps, C = scipy.linalg.eigh(H, S)
     w = np.einsum("ia,ij,jk,kl,la->a", C, S, K, S, C)
     sel = np.nonzero(w > 0.5)[0]
-    if np.max(np.abs(w[sel] - 1.0)) > tol or (len(sel) < len(w) and
-                                               np.max(np.abs(w[w <= 0.5])) > tol):
-        raise ValueError("density kernel is not a projector onto eigenstates")
-    return eps[sel], C[:, sel]
+    if np.max(np.abs(w[sel] - 1.0)) <= tol and (len(sel) == len(w) or
+                                                np.max(np.abs(w[w <= 0.5])) <= tol):
+        return eps[sel], C[:, sel]
+    return projected_states(H, S, K)
+
+
+def projected_states(H, S, K, tol=1e-8):
+    """States of H in range(K) for an S-idempotent K (K S K = K)."""
+    if np.linalg.norm(K @ S @ K - K) > tol * np.linalg.norm(K):
+        raise ValueError("density kernel is not idempotent")
+    wk, V = scipy.linalg.eigh(S @ K @ S, S)          # S-orthonormal; 1 on range(K), 0 off it
+    B = V[:, wk > 0.5]
+    Hp = B.T @ H @ B
+    e, U = np.linalg.eigh(0.5 * (Hp + Hp.T))
+    return e, B @ U
 
 
 class Casida:

@@ -71,6 +71,9 @@ class Config:
     # o-functions first (n_o + n_u per atom), and K^c is the complement projector
     # S^-1 - S^-1 S^{.o} K^v S^{o.} S^-1 of the occupied space within that set
     joint: bool = False
+    # width factor of the u-functions (the o-functions keep w_lo..w_hi): narrower
+    # u-functions carry more kinetic energy and leave the lowest joint states o-like
+    u_width_scale: float = 1.0
 
     @property
     def h(self) -> float:
@@ -192,7 +195,7 @@ def _atom_functions(cfg: Config, R: np.ndarray, n_fn: int, rng: np.random.Genera
     inside = r2 <= cfg.r_c * cfg.r_c
     vals = np.zeros((n_fn, ext[2], ext[1], ext[0]))
     for k in range(n_fn):
-        w = rng.uniform(cfg.w_lo, cfg.w_hi)
+        w = rng.uniform(cfg.w_lo, cfg.w_hi) * (cfg.u_width_scale if k >= cfg.n_o else 1.0)
         coef = rng.standard_normal(len(_MONOMIALS))
         poly = np.zeros_like(r2)
         for c, (px, py, pz) in zip(coef, _MONOMIALS):

@@ -31,3 +31,19 @@ def test_joint_apply(precision, tol):
         assert rel_err(fq, fq_ref) < tol
     else:
         assert np.max(np.abs(fq - fq_ref)) < tol * np.max(np.abs(fq_ref))
+
+
+def test_joint_solve_reaches_brute_force():
+    """FP64 PCG in the joint representation converges to the brute-force Casida spectrum
+    built from the states of H in the complement of the occupied space."""
+    from conftest import cached_system
+    from oracle.casida import Casida
+    from paper_1507_08157_amd import binding
+    s = cached_system("small_joint")
+    n = s.cfg.n_states
+    print("[joint] solve fp64", flush=True)
+    h = gpu_handle(s, precision="fp64")
+    w, rc, st = h.tddft_pcg_solve(n, binding.tddft_default_options(tol_omega=1e-10, max_iter=300))
+    h.close()
+    ref = Casida(s).omega_hermitian()[:n]
+    assert st["converged"] and np.max(np.abs(w - ref)) < 1e-9

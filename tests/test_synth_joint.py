@@ -40,3 +40,30 @@ def test_complement_projector(joint):
     full = K.copy()
     full[np.ix_(o_sel, o_sel)] += s.K_v
     assert np.max(np.abs(full @ S - np.eye(S.shape[0]))) < 1e-9
+
+
+def test_projected_states_reduce_to_eigenstates():
+    """For an eigenstate projector (the plain u-set) the projected-state construction gives
+    the same levels as the eigenstates K^c is built from."""
+    from oracle.casida import projected_states
+    s = cached_system("small_dense")
+    e, C = projected_states(s.H_u, s.S_u, s.K_c)
+    assert np.allclose(e, s.eps_u[s.vir_idx], atol=1e-10)
+    assert np.allclose(C.T @ s.S_u @ C, np.eye(len(e)), atol=1e-10)
+
+
+def test_joint_brute_force_and_solver(joint):
+    """Joint representation with a gapped complement: the Casida spectrum from the projected
+    states is positive, its two forms agree, and the oracle's PCG reaches it."""
+    from oracle.apply import Operator
+    from oracle.casida import Casida
+    from oracle.pcg import Options, Solver
+    s = joint
+    assert s.eps_u[0] > s.eps_o[s.cfg.n_occ - 1] + s.cfg.gap_margin
+    c = Casida(s)
+    assert c.D.min() > 0
+    n = s.cfg.n_states
+    w = c.omega_hermitian()[:n]
+    assert np.allclose(w, c.omega_nonhermitian()[:n], atol=1e-10)
+    res = Solver(Operator(s), Options(n_states=n, tol_omega=1e-10, max_iter=300)).solve(s.guess(n))
+    assert np.max(np.abs(np.asarray(res.omega) - w)) < 1e-9
