@@ -108,11 +108,16 @@ class Operator:
 
 def response_pattern(sysm) -> np.ndarray:
     """Atom-block pattern of K^c S^u L S^o K^v for L on M (boolean products of the block
-    patterns of the factors)."""
+    patterns of the factors).  A factor's pattern is its nonzero blocks plus every atom's
+    own block: density matrices are truncated by a radius (Sec. V: the truncation gives them
+    the pattern of the overlap matrices), so an atom's own block belongs to the pattern even
+    where its values vanish (an atom that carries no occupied or no unoccupied weight)."""
     nA = sysm.cfg.n_atoms
 
     def blocks(A, b):
-        return (np.abs(A.reshape(nA, b, nA, b)).max(axis=(1, 3)) > 0).astype(np.int64)
+        m = (np.abs(A.reshape(nA, b, nA, b)).max(axis=(1, 3)) > 0).astype(np.int64)
+        np.fill_diagonal(m, 1)
+        return m
     nu, no = sysm.vir.n_per_atom, sysm.occ.n_per_atom
     pu = blocks(sysm.K_c, nu) @ blocks(sysm.S_u, nu)
     po = blocks(sysm.S_o, no) @ blocks(sysm.K_v, no)

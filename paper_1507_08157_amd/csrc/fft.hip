@@ -12,6 +12,8 @@
 //   pass 3  z-lines, forward, times the Poisson kernel, inverse     in place
 //   pass 4  y-lines, inverse   in place
 //   pass 5  x-lines, inverse, plus f_xc rho          work array -> tile-major fields
+#include <algorithm>
+
 #include "internal.h"
 #include "kernels.h"
 
@@ -488,6 +490,24 @@ __global__ __launch_bounds__(256) void k_fft_x_inv(GeomDev g, AxisDev ax,
 }
 
 // ---------------------------------------------------------------------------------------
+// in-place passes (one LDS buffer) when every radix pass of the axis fits the per-thread
+// butterfly budget of fft_pass_inplace for 16 lines on 256 threads
+static bool axis_inplace(const AxisFFT &a) {
+  for (int R : a.radix)
+    if (R == 7 || 16 * (a.n / R) > (R >= 8 ? 1 : 8 / R) * 256) return false;
+  return true;
+}
+
+// LDS of one workgroup of an axis pass (line buffers of odd stride n + 1)
+static size_t axis_lds_bytes(const AxisFFT &a, int lines, size_t elem) {
+  return (axis_inplace(a) ? 1 : 2) * (size_t)lines * (a.n + 1) * elem;
+}
+
+size_t fft_lds_bytes(const FFTPlan &plan, size_t elem) {
+  return std::max({axis_lds_bytes(plan.ax[0], 16, elem), axis_lds_bytes(plan.ax[1], XB, elem),
+                   axis_lds_bytes(plan.ax[2], XB, elem)});
+}
+
 static AxisDev axis_dev(const AxisFFT &a) {
   AxisDev d{};
   d.n = a.n;
@@ -517,17 +537,10 @@ void hartree_xc(const GridGeom &gg, const FFTPlan &plan, int npair, T *fields, T
   const double scale = 4.0 * pi / ((double)gg.n[0] * gg.n[1] * gg.n[2]);
   const unsigned rows = (unsigned)(gg.nty * gg.ntz);
   const unsigned nxb = (unsigned)((gg.n[0] + XB - 1) / XB);
-  // in-place passes (one LDS buffer) when every radix pass of the axis fits the per-thread
-  // butterfly budget of fft_pass_inplace for 16 lines on 256 threads
-  auto inplace = [](const AxisFFT &a) {
-    for (int R : a.radix)
-      if (R == 7 || 16 * (a.n / R) > (R >= 8 ? 1 : 8 / R) * 256) return false;
-    return true;
-  };
-  const bool ix = inplace(plan.ax[0]), iy = inplace(plan.ax[1]), iz = inplace(plan.ax[2]);
-  const size_t lx = (ix ? 1 : 2) * 16 * (size_t)(gg.n[0] + 1) * sizeof(T2);
-  const size_t ly = (iy ? 1 : 2) * XB * (size_t)(gg.n[1] + 1) * sizeof(T2);
-  const size_t lz = (iz ? 1 : 2) * XB * (size_t)(gg.n[2] + 1) * sizeof(T2);
+  const bool ix = axis_inplace(plan.ax[0]), iy = axis_inplace(plan.ax[1]), iz = axis_inplace(plan.ax[2]);
+  const size_t lx = axis_lds_bytes(plan.ax[0], 16, sizeof(T2));
+  const size_t ly = axis_lds_bytes(plan.ax[1], XB, sizeof(T2));
+  const size_t lz = axis_lds_bytes(plan.ax[2], XB, sizeof(T2));
   Prof dummy;
   Prof &pf = prof ? *prof : dummy;
   pf.begin(ST_FFT_X_FWD, s);

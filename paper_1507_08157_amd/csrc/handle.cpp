@@ -521,6 +521,8 @@ void create_handle(Handle &h, const tddft_system &sys, const tddft_options &o) {
 
   // ---- FFT plan, rho0 = 2 sum o K^v o and f_xc (FP64 from FP64 samples)
   build_fft_plan(h.fft, h.n, s);
+  TD_REQUIRE(fft_lds_bytes(h.fft, h.precision == TDDFT_FP64 ? 16 : 8) <= h.lds_limit,
+             "grid dimensions too large for the FFT's line buffers in LDS");
   h.partial.alloc((size_t)h.max_parts * 4096);
   h.small_dev.alloc(8192);
   {

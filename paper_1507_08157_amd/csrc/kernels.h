@@ -114,4 +114,7 @@ template <class T>
 void hartree_xc(const GridGeom &g, const FFTPlan &plan, int npair, T *fields, T *work,
                 const T *fxc, bool use_fxc, hipStream_t s, Prof *prof);
 
+// largest LDS request of the FFT passes for complex values of `elem` bytes
+size_t fft_lds_bytes(const FFTPlan &plan, size_t elem);
+
 }  // namespace tddft

@@ -123,6 +123,25 @@ def small_joint(seed: int = 13) -> Config:
     return Config(**d)
 
 
+def separated(seed: int = 3, N: int = 64) -> Config:
+    """4 atoms with narrow function boxes (r_c 1.5 bohr) in a 20 bohr cell: no two atoms
+    overlap, every matrix is block-diagonal, and the 2 occupied states sit on two of the
+    atoms, so K^v (and K^c) have vanishing diagonal blocks."""
+    return Config(name="separated", n_atoms=4, L=20.0, N=N, r_c=1.5, n_occ=2, n_vir=4,
+                  R_K=None, R_M=None, n_states=1, seed=seed)
+
+
+def wide_grid(seed: int = 3) -> Config:
+    """`separated` on a 320^3 grid (radix 8, 8, 5): an axis too long for the in-place FFT
+    passes, so the transforms take the two-buffer form with line buffers of 2 x 16 x 321
+    complex values per workgroup."""
+    c = separated(seed, N=320)
+    d = dict(c.__dict__)
+    d.update(name="wide_grid")
+    return Config(**d)
+
+
 BY_NAME = {"tiny": tiny, "prec": prec, "small_dense": small_dense,
            "small_trunc": small_trunc, "small_odd": small_odd, "small_crowded": small_crowded,
-           "prec_joint": prec_joint, "small_joint": small_joint}
+           "prec_joint": prec_joint, "small_joint": small_joint, "separated": separated,
+           "wide_grid": wide_grid}

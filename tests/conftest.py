@@ -36,5 +36,10 @@ def small_trunc():
 
 
 @pytest.fixture(scope="session")
+def separated():
+    return cached_system("separated")
+
+
+@pytest.fixture(scope="session")
 def small_odd():
     return cached_system("small_odd")

@@ -1,7 +1,7 @@
 """GPU parity of tddft_apply (Eq. operator_RPA) against the FP64 oracle, element by element
 on M, for every coupling mode, precision mode and test geometry (dense and truncated
 patterns, grids of 40^3 (radix 2, 5), 45^3 (radix 3, 5; ragged tiles), 70^3 (radix 2, 5, 7;
-ragged tiles) and 64^3)."""
+ragged tiles), 64^3 and 320^3 (two-buffer FFT passes), and well-separated atoms)."""
 import sys
 
 import numpy as np
@@ -32,7 +32,7 @@ def _run(sysm, xc, precision, n, seed=1):
     return fp, fq, fp_ref, fq_ref, op, Pq
 
 
-@pytest.mark.parametrize("name", ["small_dense", "small_odd", "small_trunc"])
+@pytest.mark.parametrize("name", ["small_dense", "small_odd", "small_trunc", "separated"])
 @pytest.mark.parametrize("xc", [2, 1, 0])
 def test_apply_fp64(name, xc, request):
     s = request.getfixturevalue(name)
@@ -43,9 +43,10 @@ def test_apply_fp64(name, xc, request):
     assert np.all(fp[:, outside] == 0) and np.all(fq[:, outside] == 0)
 
 
-@pytest.mark.parametrize("name", ["small_dense", "small_odd", "small_trunc"])
+@pytest.mark.parametrize("name", ["small_dense", "small_odd", "small_trunc", "separated"])
 def test_response_pattern_matches_independent_constructions(name, request):
-    """The library's response pattern equals the generator's and the oracle's."""
+    """The library's response pattern equals the generator's and the oracle's (`separated`:
+    block-diagonal factors with vanishing diagonal blocks of K^v and K^c)."""
     from oracle.apply import response_pattern
     from synth import abi as sabi
     s = request.getfixturevalue(name)
@@ -101,6 +102,30 @@ def test_apply_tiny_power_of_two_grid():
     s = cached_system("tiny")
     fp, fq, fp_ref, fq_ref, _, _ = _run(s, 0, "fp64", 3, seed=7)
     assert rel_err(fq, fq_ref) < TOL_FP64
+
+
+def test_apply_grid_beyond_in_place_ffts():
+    """320^3 grid: the FFT passes use two line buffers per workgroup.  In FP64 they need
+    2 x 16 x 321 x 16 B = 164352 B, more than a workgroup's LDS (160 KiB on MI355X), and
+    creation refuses the grid with a clear error.  In FP32 (half that) the apply either
+    runs, at the FP32 bound against the oracle, or is refused the same way when the
+    device reports less LDS per workgroup."""
+    from conftest import cached_system
+    from paper_1507_08157_amd import binding
+    s = cached_system("wide_grid")
+    print("[apply] wide_grid fp64 creation", flush=True)
+    with pytest.raises(binding.TddftError) as e:
+        gpu_handle(s, precision="fp64")
+    assert e.value.code == binding.TDDFT_E_INVALID and "LDS" in str(e.value)
+    try:
+        h = gpu_handle(s, precision="fp32")
+    except binding.TddftError as e32:
+        assert e32.code == binding.TDDFT_E_INVALID and "LDS" in str(e32)
+        return
+    h.close()
+    fp, fq, fp_ref, fq_ref, _, _ = _run(s, 0, "fp32", 1, seed=5)
+    assert rel_err(fp, fp_ref) < 2e-5
+    assert rel_err(fq, fq_ref) < 2e-5
 
 
 @pytest.mark.parametrize("n", [0, 33])

@@ -183,3 +183,33 @@ def test_tamm_dancoff_mode_reaches_tda_brute_force(dense):
     ref = cs.omega_tda()[:n]
     assert np.max(np.abs(r.omega - ref)) < 1e-9
     assert np.all(ref >= cs.omega_hermitian()[:n] - 1e-12)
+
+
+def test_response_pattern_keeps_blocks_of_atoms_without_weight():
+    """Well-separated atoms: the occupied states sit on two of four atoms, so K^v has
+    vanishing diagonal blocks.  The response pattern still holds every atom's own block
+    (density matrices are truncated by radius, Sec. V), and on P = Pi(L) the blocks that
+    only this reading adds are exactly zero, as is the operator there: the reading changes
+    nothing for the P the method produces, only which blocks an arbitrary P may occupy."""
+    from conftest import cached_system
+    from oracle.apply import response_pattern
+    s = cached_system("separated")
+    nA = s.cfg.n_atoms
+    no, nu = s.occ.n_per_atom, s.vir.n_per_atom
+    kv = np.abs(s.K_v.reshape(nA, no, nA, no)).max(axis=(1, 3))
+    kc = np.abs(s.K_c.reshape(nA, nu, nA, nu)).max(axis=(1, 3))
+    assert (np.diag(kv) == 0).any() and (np.diag(kc) == 0).any()
+    assert (kv[~np.eye(nA, dtype=bool)] == 0).all()
+    R = response_pattern(s)
+    assert R.all()
+    # blocks the numerical pattern of the factors would drop
+    num = np.outer(np.diag(kc) > 0, np.diag(kv) > 0)
+    extra = np.kron(R & ~num, np.ones((nu, no), dtype=bool))
+    assert extra.any()
+    op = Operator(s, xc=True, hartree=True)
+    rng = np.random.default_rng(4)
+    L = op.truncate(rng.standard_normal((nA * nu, nA * no)))
+    P = op.project(L)
+    assert np.abs(P).max() > 0 and (P[extra] == 0).all()
+    fp, fq = op.apply(P[None], P[None])
+    assert (fp[0][extra] == 0).all() and (fq[0][extra] == 0).all()
