@@ -117,7 +117,7 @@ TRAFFIC_FILE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "profile
 
 
 # device helpers whose text is part of a kernel's measured code
-KERNEL_HELPERS = {"k_density": ["density_pairs", "load2"], "k_vint_mfma": ["load16", "load4"],
+KERNEL_HELPERS = {"k_density": ["density_chunk"], "k_vint_mfma": ["load16", "load4"],
                   "k_vint_reduce": []}
 
 

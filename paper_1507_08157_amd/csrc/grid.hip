@@ -60,28 +60,23 @@ __device__ __forceinline__ void load2<double, __hip_bfloat16>(const __hip_bfloat
 }
 
 // ---------------------------------------------------------------------------------------
-// Response density.  One wave per tile, one lane per grid point.  For every left atom i
-// the partial sums psi_s,r = sum_j P_s[(i,r),(j,.)] . o_j are built from wave-uniform P
-// blocks (all NS states of a block are contiguous, so they arrive in SGPRs through a few
-// scalar loads and feed the FMAs as scalar operands), then rho_s += u_(i,r) psi_s,r.  The
-// o-rows are read straight from the tile's samples (coalesced, L1-resident across i): no
-// LDS, so occupancy is set by registers alone.
-template <class T, class S, int NS, int BL, int BR, bool FULL>
-__device__ __forceinline__ void density_pairs(const int32_t *__restrict__ pid, int noa,
+// Response density.  One wave per tile, one lane per grid point.  The tile's o-atoms are
+// taken in chunks of JC whose o-rows are loaded once into registers; for every left atom i
+// the partial sums psi_s,r = sum_j P_s[(i,r),(j,.)] . o_j over the chunk are built from
+// wave-uniform P blocks (all NS states of a block are contiguous, so they arrive in SGPRs
+// through a few scalar loads and feed the FMAs as scalar operands), then
+// rho_s += u_(i,r) psi_s,r.  The pair loop thus issues only the scalar loads of P: the
+// o-rows are not re-read per left atom.  No LDS, so occupancy is set by registers alone.
+template <class T, class S, int NS, int BL, int BR, int JC, bool FULL>
+__device__ __forceinline__ void density_chunk(const int32_t *__restrict__ pid, int nj,
                                               const T *__restrict__ X, int64_t xoff, int ldx,
-                                              int nk, const S *__restrict__ os, int lane,
-                                              T (&tmp)[NS][BL]) {
+                                              int nk, const T (&o)[JC][BR], T (&tmp)[NS][BL]) {
   constexpr int E = BL * BR;
-  // the block index of the next pair is requested together with this pair's P block, so a
-  // pair costs one round trip instead of two dependent ones
-  int pb_next = noa > 0 ? pid[0] : -1;
-  for (int j = 0; j < noa; ++j) {
-    const int pb = pb_next;
-    if (j + 1 < noa) pb_next = pid[j + 1];
-    if (pb < 0) continue;
-    T o[BR];
 #pragma unroll
-    for (int c = 0; c < BR; ++c) o[c] = cvt<T>(os[(j * BR + c) * TP + lane]);
+  for (int j = 0; j < JC; ++j) {
+    if (j >= nj) break;
+    const int pb = pid[j];
+    if (pb < 0) continue;
     const T *Pj = X + ((int64_t)pb * ldx) * E + xoff;
 #pragma unroll
     for (int k = 0; k < NS; ++k) {
@@ -89,7 +84,7 @@ __device__ __forceinline__ void density_pairs(const int32_t *__restrict__ pid, i
 #pragma unroll
       for (int r = 0; r < BL; ++r)
 #pragma unroll
-        for (int c = 0; c < BR; ++c) tmp[k][r] += Pj[k * E + r * BR + c] * o[c];
+        for (int c = 0; c < BR; ++c) tmp[k][r] += Pj[k * E + r * BR + c] * o[j][c];
     }
   }
 }
@@ -105,6 +100,8 @@ __global__ __launch_bounds__(256) void k_density(DevTiles tl, const S *__restric
   constexpr int kSlots = sizeof(T) == 8 ? 24 : 48, kMax = sizeof(T) == 8 ? 4 : 8;
   constexpr int NSe = (kSlots / (BL * BR)) & ~1;
   constexpr int NS = NSe < 2 ? 2 : (NSe > kMax ? kMax : NSe);
+  // o-atoms per register chunk: 8 x BR rows in FP32, 4 x BR in FP64
+  constexpr int JC = sizeof(T) == 8 ? 4 : 8;
   const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
   const int t = blockIdx.x * (blockDim.x >> 6) + w;
@@ -116,26 +113,35 @@ __global__ __launch_bounds__(256) void k_density(DevTiles tl, const S *__restric
   const int32_t *pid = pidx + tl.pptr[t];
   for (int s0 = 0; s0 < ns; s0 += NS) {
     const int nk = min(NS, ns - s0);
+    const int64_t xoff = (int64_t)(xc0 + s0) * BL * BR;
     T acc[NS];
 #pragma unroll
     for (int k = 0; k < NS; ++k) acc[k] = T(0);
-    for (int i = 0; i < nua; ++i) {
-      T tmp[NS][BL];
+    for (int j0 = 0; j0 < noa; j0 += JC) {
+      const int nj = min(JC, noa - j0);
+      T o[JC][BR];
 #pragma unroll
-      for (int k = 0; k < NS; ++k)
+      for (int j = 0; j < JC; ++j)
 #pragma unroll
-        for (int r = 0; r < BL; ++r) tmp[k][r] = T(0);
-      const int64_t xoff = (int64_t)(xc0 + s0) * BL * BR;
-      if (nk == NS)
-        density_pairs<T, S, NS, BL, BR, true>(pid + i * noa, noa, X, xoff, ldx, nk, os, lane, tmp);
-      else
-        density_pairs<T, S, NS, BL, BR, false>(pid + i * noa, noa, X, xoff, ldx, nk, os, lane, tmp);
-      const S *us = usamp + ((int64_t)(u0 + i) * BL) * TP + lane;
+        for (int c = 0; c < BR; ++c)
+          o[j][c] = j < nj ? cvt<T>(os[((j0 + j) * BR + c) * TP + lane]) : T(0);
+      for (int i = 0; i < nua; ++i) {
+        T tmp[NS][BL];
 #pragma unroll
-      for (int r = 0; r < BL; ++r) {
-        const T u = cvt<T>(us[r * TP]);
+        for (int k = 0; k < NS; ++k)
 #pragma unroll
-        for (int k = 0; k < NS; ++k) acc[k] += u * tmp[k][r];
+          for (int r = 0; r < BL; ++r) tmp[k][r] = T(0);
+        if (nk == NS)
+          density_chunk<T, S, NS, BL, BR, JC, true>(pid + i * noa + j0, nj, X, xoff, ldx, nk, o, tmp);
+        else
+          density_chunk<T, S, NS, BL, BR, JC, false>(pid + i * noa + j0, nj, X, xoff, ldx, nk, o, tmp);
+        const S *us = usamp + ((int64_t)(u0 + i) * BL) * TP + lane;
+#pragma unroll
+        for (int r = 0; r < BL; ++r) {
+          const T u = cvt<T>(us[r * TP]);
+#pragma unroll
+          for (int k = 0; k < NS; ++k) acc[k] += u * tmp[k][r];
+        }
       }
     }
     T *dst = out + (int64_t)(s0 / 2) * pair_stride + ((int64_t)t * TP + lane) * 2;
