@@ -125,7 +125,22 @@ __global__ __launch_bounds__(256) void k_density(DevTiles tl, const S *__restric
 #pragma unroll
         for (int c = 0; c < BR; ++c)
           o[j][c] = j < nj ? cvt<T>(os[((j0 + j) * BR + c) * TP + lane]) : T(0);
+      // u-rows of the next left atom are requested before this atom's pair loop, so their
+      // round trip overlaps the scalar loads and FMAs of the pairs
+      const S *us = usamp + ((int64_t)u0 * BL) * TP + lane;
+      S un[BL];
+      if (nua > 0) {
+#pragma unroll
+        for (int r = 0; r < BL; ++r) un[r] = us[r * TP];
+      }
       for (int i = 0; i < nua; ++i) {
+        T u[BL];
+#pragma unroll
+        for (int r = 0; r < BL; ++r) u[r] = cvt<T>(un[r]);
+        if (i + 1 < nua) {
+#pragma unroll
+          for (int r = 0; r < BL; ++r) un[r] = us[((i + 1) * BL + r) * TP];
+        }
         T tmp[NS][BL];
 #pragma unroll
         for (int k = 0; k < NS; ++k)
@@ -135,13 +150,10 @@ __global__ __launch_bounds__(256) void k_density(DevTiles tl, const S *__restric
           density_chunk<T, S, NS, BL, BR, JC, true>(pid + i * noa + j0, nj, X, xoff, ldx, nk, o, tmp);
         else
           density_chunk<T, S, NS, BL, BR, JC, false>(pid + i * noa + j0, nj, X, xoff, ldx, nk, o, tmp);
-        const S *us = usamp + ((int64_t)(u0 + i) * BL) * TP + lane;
 #pragma unroll
-        for (int r = 0; r < BL; ++r) {
-          const T u = cvt<T>(us[r * TP]);
+        for (int r = 0; r < BL; ++r)
 #pragma unroll
-          for (int k = 0; k < NS; ++k) acc[k] += u * tmp[k][r];
-        }
+          for (int k = 0; k < NS; ++k) acc[k] += u[r] * tmp[k][r];
       }
     }
     T *dst = out + (int64_t)(s0 / 2) * pair_stride + ((int64_t)t * TP + lane) * 2;
