@@ -141,26 +141,40 @@ __device__ __forceinline__ void dft(typename C2<T>::type (&v)[R]) {
   }
 }
 
+// Division by a run-time divisor d through a host-computed multiplier m = ceil(2^32 / d)
+// (m = 0 for d = 1): floor(q / d) = mulhi(q, m).  With e = m d - 2^32 < d, the quotient is
+// exact whenever q e < 2^32, so for all q < 2^16 and d < 2^16; every index divided here is
+// below 16 * 4096 = 2^16 and every divisor at most 4096.
+__host__ __device__ inline uint32_t div_magic(int d) {
+  return d <= 1 ? 0u : (uint32_t)((((uint64_t)1 << 32) + (uint64_t)d - 1) / (uint64_t)d);
+}
+__device__ __forceinline__ int fdiv(int q, uint32_t m) {
+  return m ? (int)__umulhi((uint32_t)q, m) : q;
+}
+
 struct AxisDev {
   int n, npass;
   int radix[12];
   int tw_off[12];
+  uint32_t m_nb[12];   // div_magic(n / radix[p])
+  uint32_t m_ns[12];   // div_magic(product of the radices before pass p)
 };
 
 // one Stockham pass over `nlines` lines (stride ldl) of length N held in LDS
 template <class T, int R, int SIGN>
 __device__ void fft_pass(const typename C2<T>::type *__restrict__ in,
                          typename C2<T>::type *__restrict__ out, int N, int Ns, int ldl,
-                         int nlines, const typename C2<T>::type *__restrict__ tw) {
+                         int nlines, const typename C2<T>::type *__restrict__ tw, uint32_t m_nb,
+                         uint32_t m_ns) {
   using T2 = typename C2<T>::type;
   const int nb = N / R;
   const int total = nlines * nb;
   for (int q = threadIdx.x; q < total; q += blockDim.x) {
-    const int line = q / nb;
+    const int line = fdiv(q, m_nb);
     const int j = q - line * nb;
     const T2 *src = in + line * ldl;
     T2 *dst = out + line * ldl;
-    const int k = j % Ns;
+    const int k = j - fdiv(j, m_ns) * Ns;
     T2 v[R];
 #pragma unroll
     for (int r = 0; r < R; ++r) v[r] = src[j + r * nb];
@@ -187,7 +201,8 @@ __device__ void fft_pass(const typename C2<T>::type *__restrict__ in,
 // register count of every pass, and with it cost the occupancy gained).
 template <class T, int R, int SIGN>
 __device__ void fft_pass_inplace(typename C2<T>::type *__restrict__ buf, int N, int Ns, int ldl,
-                                 int nlines, const typename C2<T>::type *__restrict__ tw) {
+                                 int nlines, const typename C2<T>::type *__restrict__ tw,
+                                 uint32_t m_nb, uint32_t m_ns) {
   using T2 = typename C2<T>::type;
   constexpr int NIT = R >= 8 ? 1 : 8 / R;
   const int nb = N / R;
@@ -197,7 +212,7 @@ __device__ void fft_pass_inplace(typename C2<T>::type *__restrict__ buf, int N, 
   for (int it = 0; it < NIT; ++it) {
     const int q = threadIdx.x + it * blockDim.x;
     if (q < total) {
-      const int line = q / nb, j = q - line * nb;
+      const int line = fdiv(q, m_nb), j = q - line * nb;
 #pragma unroll
       for (int r = 0; r < R; ++r) v[it][r] = buf[line * ldl + j + r * nb];
     }
@@ -207,8 +222,8 @@ __device__ void fft_pass_inplace(typename C2<T>::type *__restrict__ buf, int N, 
   for (int it = 0; it < NIT; ++it) {
     const int q = threadIdx.x + it * blockDim.x;
     if (q < total) {
-      const int line = q / nb, j = q - line * nb;
-      const int k = j % Ns;
+      const int line = fdiv(q, m_nb), j = q - line * nb;
+      const int k = j - fdiv(j, m_ns) * Ns;
       if (Ns > 1) {
 #pragma unroll
         for (int r = 1; r < R; ++r) {
@@ -237,21 +252,21 @@ __device__ typename C2<T>::type *fft_lines(typename C2<T>::type *a, typename C2<
     const typename C2<T>::type *t = tw + ax.tw_off[p];
     if constexpr (INPL) {
       switch (R) {
-        case 2: fft_pass_inplace<T, 2, SIGN>(a, ax.n, Ns, ldl, nlines, t); break;
-        case 3: fft_pass_inplace<T, 3, SIGN>(a, ax.n, Ns, ldl, nlines, t); break;
-        case 4: fft_pass_inplace<T, 4, SIGN>(a, ax.n, Ns, ldl, nlines, t); break;
-        case 5: fft_pass_inplace<T, 5, SIGN>(a, ax.n, Ns, ldl, nlines, t); break;
-        default: fft_pass_inplace<T, 8, SIGN>(a, ax.n, Ns, ldl, nlines, t); break;
+        case 2: fft_pass_inplace<T, 2, SIGN>(a, ax.n, Ns, ldl, nlines, t, ax.m_nb[p], ax.m_ns[p]); break;
+        case 3: fft_pass_inplace<T, 3, SIGN>(a, ax.n, Ns, ldl, nlines, t, ax.m_nb[p], ax.m_ns[p]); break;
+        case 4: fft_pass_inplace<T, 4, SIGN>(a, ax.n, Ns, ldl, nlines, t, ax.m_nb[p], ax.m_ns[p]); break;
+        case 5: fft_pass_inplace<T, 5, SIGN>(a, ax.n, Ns, ldl, nlines, t, ax.m_nb[p], ax.m_ns[p]); break;
+        default: fft_pass_inplace<T, 8, SIGN>(a, ax.n, Ns, ldl, nlines, t, ax.m_nb[p], ax.m_ns[p]); break;
       }
       __syncthreads();
     } else {
       switch (R) {
-        case 2: fft_pass<T, 2, SIGN>(a, b, ax.n, Ns, ldl, nlines, t); break;
-        case 3: fft_pass<T, 3, SIGN>(a, b, ax.n, Ns, ldl, nlines, t); break;
-        case 4: fft_pass<T, 4, SIGN>(a, b, ax.n, Ns, ldl, nlines, t); break;
-        case 5: fft_pass<T, 5, SIGN>(a, b, ax.n, Ns, ldl, nlines, t); break;
-        case 7: fft_pass<T, 7, SIGN>(a, b, ax.n, Ns, ldl, nlines, t); break;
-        default: fft_pass<T, 8, SIGN>(a, b, ax.n, Ns, ldl, nlines, t); break;
+        case 2: fft_pass<T, 2, SIGN>(a, b, ax.n, Ns, ldl, nlines, t, ax.m_nb[p], ax.m_ns[p]); break;
+        case 3: fft_pass<T, 3, SIGN>(a, b, ax.n, Ns, ldl, nlines, t, ax.m_nb[p], ax.m_ns[p]); break;
+        case 4: fft_pass<T, 4, SIGN>(a, b, ax.n, Ns, ldl, nlines, t, ax.m_nb[p], ax.m_ns[p]); break;
+        case 5: fft_pass<T, 5, SIGN>(a, b, ax.n, Ns, ldl, nlines, t, ax.m_nb[p], ax.m_ns[p]); break;
+        case 7: fft_pass<T, 7, SIGN>(a, b, ax.n, Ns, ldl, nlines, t, ax.m_nb[p], ax.m_ns[p]); break;
+        default: fft_pass<T, 8, SIGN>(a, b, ax.n, Ns, ldl, nlines, t, ax.m_nb[p], ax.m_ns[p]); break;
       }
       __syncthreads();
       typename C2<T>::type *tmp = a;
@@ -271,6 +286,7 @@ struct GeomDev {
   int nx, ny, nz, ntx, nty, ntz;
   int64_t pair_tile;   // elements (complex) per field in tile-major layout
   int64_t pair_work;   // elements per field in natural layout
+  uint32_t m_nx, m_nz; // div_magic(nx), div_magic(nz)
 };
 
 // ---- pass 1: x forward, tile-major -> natural ---------------------------------------------
@@ -310,7 +326,7 @@ __global__ __launch_bounds__(256) void k_fft_x_fwd(GeomDev g, AxisDev ax,
   __syncthreads();
   T2 *res = fft_lines<T, -1, INPL>(a, b, ldl, 16, ax, tw);
   for (int e = threadIdx.x; e < 16 * g.nx; e += blockDim.x) {
-    const int l = e / g.nx, x = e - l * g.nx;
+    const int l = fdiv(e, g.m_nx), x = e - l * g.nx;
     const int y = ty * 4 + (l & 3), z = tz * 4 + (l >> 2);
     if (y < g.ny && z < g.nz)
       work[pair * g.pair_work + ((int64_t)z * g.ny + y) * g.nx + x] = res[l * ldl + x];
@@ -395,12 +411,15 @@ __global__ __launch_bounds__(256) void k_fft_z_poisson(GeomDev g, AxisDev ax,
   // multiply by 4 pi / |G|^2 (G = 0 -> 0) including the 1/(nx ny nz) normalisation
   const int ky = y <= g.ny / 2 ? y : y - g.ny;
   for (int e = threadIdx.x; e < nl * g.nz; e += blockDim.x) {
-    const int l = e / g.nz, z = e - l * g.nz;
+    const int l = fdiv(e, g.m_nz), z = e - l * g.nz;
     const int x = x0 + l;
     const int kx = x <= g.nx / 2 ? x : x - g.nx;
     const int kz = z <= g.nz / 2 ? z : z - g.nz;
-    const double G2 = (gx * kx) * (gx * kx) + (gy * ky) * (gy * ky) + (gz * kz) * (gz * kz);
-    const T f = G2 > 0.0 ? (T)(scale / G2) : T(0);
+    // in the field's precision (a double division per value would cost more than the
+    // transform's own arithmetic in FP32)
+    const T fx = (T)gx * (T)kx, fy = (T)gy * (T)ky, fz = (T)gz * (T)kz;
+    const T G2 = fx * fx + fy * fy + fz * fz;
+    const T f = G2 > T(0) ? (T)scale / G2 : T(0);
     T2 v = res[l * ldl + z];
     v.x *= f;
     v.y *= f;
@@ -435,7 +454,7 @@ __global__ __launch_bounds__(256) void k_fft_x_inv(GeomDev g, AxisDev ax,
 #pragma unroll
     for (int u = 0; u < kLoadBatch; ++u) {
       const int e = b0 + u * 256 + (int)threadIdx.x;
-      const int l = e / g.nx, x = e - l * g.nx;
+      const int l = fdiv(e, g.m_nx), x = e - l * g.nx;
       const int y = ty * 4 + (l & 3), z = tz * 4 + (l >> 2);
       v[u].x = T(0);
       v[u].y = T(0);
@@ -444,7 +463,7 @@ __global__ __launch_bounds__(256) void k_fft_x_inv(GeomDev g, AxisDev ax,
 #pragma unroll
     for (int u = 0; u < kLoadBatch; ++u) {
       const int e = b0 + u * 256 + (int)threadIdx.x;
-      const int l = e / g.nx, x = e - l * g.nx;
+      const int l = fdiv(e, g.m_nx), x = e - l * g.nx;
       if (e < 16 * g.nx) a[l * ldl + x] = v[u];
     }
   }
@@ -512,9 +531,13 @@ static AxisDev axis_dev(const AxisFFT &a) {
   AxisDev d{};
   d.n = a.n;
   d.npass = (int)a.radix.size();
+  int ns = 1;
   for (int i = 0; i < d.npass; ++i) {
     d.radix[i] = a.radix[i];
     d.tw_off[i] = a.tw_off[i];
+    d.m_nb[i] = div_magic(a.n / a.radix[i]);
+    d.m_ns[i] = div_magic(ns);
+    ns *= a.radix[i];
   }
   return d;
 }
@@ -525,7 +548,8 @@ void hartree_xc(const GridGeom &gg, const FFTPlan &plan, int npair, T *fields, T
   using T2 = typename C2<T>::type;
   if (npair == 0) return;
   GeomDev g{gg.n[0], gg.n[1], gg.n[2], gg.ntx, gg.nty, gg.ntz,
-            (int64_t)gg.ntx * gg.nty * gg.ntz * TP, (int64_t)gg.n[0] * gg.n[1] * gg.n[2]};
+            (int64_t)gg.ntx * gg.nty * gg.ntz * TP, (int64_t)gg.n[0] * gg.n[1] * gg.n[2],
+            div_magic(gg.n[0]), div_magic(gg.n[2])};
   const T2 *tw = reinterpret_cast<const T2 *>(std::is_same<T, double>::value ? (const void *)plan.tw64.p
                                                                              : (const void *)plan.tw32.p);
   int off[3] = {0, plan.ax[0].tw_len, plan.ax[0].tw_len + plan.ax[1].tw_len};
