@@ -141,17 +141,8 @@ __device__ __forceinline__ void dft(typename C2<T>::type (&v)[R]) {
   }
 }
 
-// Division by a run-time divisor d through a host-computed multiplier m = ceil(2^32 / d)
-// (m = 0 for d = 1): floor(q / d) = mulhi(q, m).  With e = m d - 2^32 < d, the quotient is
-// exact whenever q e < 2^32, so for all q < 2^16 and d < 2^16; every index divided here is
-// below 16 * 4096 = 2^16 and every divisor at most 4096.
-__host__ __device__ inline uint32_t div_magic(int d) {
-  return d <= 1 ? 0u : (uint32_t)((((uint64_t)1 << 32) + (uint64_t)d - 1) / (uint64_t)d);
-}
-__device__ __forceinline__ int fdiv(int q, uint32_t m) {
-  return m ? (int)__umulhi((uint32_t)q, m) : q;
-}
-
+// Index divisions by run-time sizes use fdiv (kernels.h): every index divided here is below
+// 16 * 4096 = 2^16 and every divisor at most 4096, where the multiply-high is exact.
 struct AxisDev {
   int n, npass;
   int radix[12];

@@ -5,6 +5,17 @@
 
 namespace tddft {
 
+// Division by a run-time divisor d through a host-computed multiplier m = ceil(2^32 / d)
+// (m = 0 for d = 1): floor(q / d) = mulhi(q, m).  With e = m d - 2^32 < d, the quotient is
+// exact whenever q e < 2^32, e.g. for all q, d < 2^16, or whenever q d <= 2^32.  A
+// run-time 32-bit division costs about fifteen instructions, a 64-bit one several times that.
+__host__ __device__ inline uint32_t div_magic(int d) {
+  return d <= 1 ? 0u : (uint32_t)((((uint64_t)1 << 32) + (uint64_t)d - 1) / (uint64_t)d);
+}
+#ifdef __HIPCC__
+__device__ __forceinline__ uint32_t fdiv(uint32_t q, uint32_t m) { return m ? __umulhi(q, m) : q; }
+#endif
+
 // ---- column-set linear combinations ------------------------------------------------------
 struct LcSrc {
   const void *X;

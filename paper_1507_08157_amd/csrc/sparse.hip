@@ -315,22 +315,42 @@ __global__ __launch_bounds__(64 * G::WMW * G::WNW) void k_gemm_blocks(int di, in
       ccol = (int64_t)(n / BO) * ldcE + n % BO;
     }
 #pragma unroll
-    for (int mb = 0; mb < TM; ++mb)
+    for (int mb = 0; mb < TM; ++mb) {
+      // the lane's rows in this 16-row block: ib + j (FP32) or ib + 4 j (FP64)
+      constexpr int step = std::is_same<T, float>::value ? 1 : 4;
+      const int ib = i0 + wm + mb * 16 + (std::is_same<T, float>::value ? 4 * (lane >> 4) : (lane >> 4));
+      // right product: row i = (I BU + r) ncol + m, decomposed once and then advanced row by
+      // row (a run-time division per row would dominate the epilogue)
+      int I = 0, r = 0, m = 0;
+      if (!LEFT) {
+        I = ib / (BU * ncol);
+        const int rem = ib - I * (BU * ncol);
+        r = rem / ncol;
+        m = rem - r * ncol;
+      }
 #pragma unroll
       for (int j = 0; j < 4; ++j) {
-        const int i = i0 + wm + mb * 16 + (std::is_same<T, float>::value ? 4 * (lane >> 4) + j : 4 * j + (lane >> 4));
-        if (i >= M) continue;
-        int64_t crow;
-        if (LEFT) {
-          crow = (int64_t)(i / BU) * dj * ldcE + (i % BU) * BO;
-        } else {
-          const int I = i / (BU * ncol), rem = i - I * (BU * ncol), r = rem / ncol, m = rem - r * ncol;
-          crow = ((int64_t)I * dj * ldc + cc0 + m) * E + r * BO;
+        const int i = ib + step * j;
+        if (i < M) {
+          int64_t crow;
+          if (LEFT) crow = (int64_t)(i / BU) * dj * ldcE + (i % BU) * BO;
+          else crow = ((int64_t)I * dj * ldc + cc0 + m) * E + r * BO;
+          T *cp = C + crow + ccol;
+          const T v = alpha * acc[mb][nb][j];
+          *cp = accumulate ? *cp + v : v;
         }
-        T *cp = C + crow + ccol;
-        const T v = alpha * acc[mb][nb][j];
-        *cp = accumulate ? *cp + v : v;
+        if (!LEFT) {
+          m += step;
+          while (m >= ncol) {
+            m -= ncol;
+            if (++r == BU) {
+              r = 0;
+              ++I;
+            }
+          }
+        }
       }
+    }
   }
 }
 
@@ -438,8 +458,9 @@ void lincomb(int64_t nblk, int E, const LcArgs &a, hipStream_t s) {
 // accesses when the sets allow), FP64 arithmetic in the same order as k_lincomb (beta Y
 // first, then the sources in order), so both forms round alike.  The coefficients are
 // copied from the kernel arguments into LDS once per workgroup.
-template <class T, bool VEC>
-__global__ __launch_bounds__(256) void k_lincomb_diag(int64_t n, int E, int nc, LcDiagArgs a) {
+template <class T, bool VEC, bool FAST>
+__global__ __launch_bounds__(256) void k_lincomb_diag(int64_t n, int E, int nc, uint32_t mE,
+                                                      uint32_t mnc, LcDiagArgs a) {
   __shared__ double cb[kLcDiagMax];
   __shared__ double cd[3][kLcDiagMax];
   for (int i = threadIdx.x; i < nc; i += blockDim.x) {
@@ -475,10 +496,29 @@ __global__ __launch_bounds__(256) void k_lincomb_diag(int64_t n, int E, int nc, 
         if (si < a.nsrc) x[si][u] = k < n ? ((const T *)a.X[si])[k] : T(0);
     }
   }
+  // column of each element: ((k0 + u) / E) % nc, with one division per thread when the host
+  // has checked that the multiply-high form is exact (FAST), then stepped element by element
+  int cols[4];
+  if (FAST) {
+    const uint32_t q = fdiv((uint32_t)k0, mE);
+    int rem = (int)((uint32_t)k0 - q * (uint32_t)E);
+    int col = (int)(q - fdiv(q, mnc) * (uint32_t)nc);
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      cols[u] = col;
+      if (++rem == E) {
+        rem = 0;
+        col = col + 1 == nc ? 0 : col + 1;
+      }
+    }
+  } else {
+#pragma unroll
+    for (int u = 0; u < 4; ++u) cols[u] = (int)(((k0 + u) / E) % nc);
+  }
   T out[4];
 #pragma unroll
   for (int u = 0; u < 4; ++u) {
-    const int c = (int)(((k0 + u) / E) % nc);
+    const int c = cols[u];
     double acc = a.has_beta ? cb[c] * (double)y[u] : 0.0;
 #pragma unroll
     for (int si = 0; si < 3; ++si)
@@ -507,8 +547,13 @@ void lincomb_diag(int64_t nblk, int E, int nc, const LcDiagArgs &a, hipStream_t 
   bool vec = n % 4 == 0 && (uintptr_t)a.Y % al == 0;
   for (int i = 0; i < a.nsrc; ++i) vec = vec && (uintptr_t)a.X[i] % al == 0;
   const unsigned grid = nblocks((n + 3) / 4, 256);
-  if (vec) hipLaunchKernelGGL((k_lincomb_diag<T, true>), dim3(grid), dim3(256), 0, s, n, E, nc, a);
-  else hipLaunchKernelGGL((k_lincomb_diag<T, false>), dim3(grid), dim3(256), 0, s, n, E, nc, a);
+  // multiply-high divisions are exact when q d <= 2^32 for both: k < n by E, k / E by nc
+  const bool fast = (double)n * E <= 4294967296.0 && ((double)(n / E) + 1.0) * nc <= 4294967296.0;
+  const uint32_t mE = div_magic(E), mnc = div_magic(nc);
+  if (vec && fast) hipLaunchKernelGGL((k_lincomb_diag<T, true, true>), dim3(grid), dim3(256), 0, s, n, E, nc, mE, mnc, a);
+  else if (vec) hipLaunchKernelGGL((k_lincomb_diag<T, true, false>), dim3(grid), dim3(256), 0, s, n, E, nc, mE, mnc, a);
+  else if (fast) hipLaunchKernelGGL((k_lincomb_diag<T, false, true>), dim3(grid), dim3(256), 0, s, n, E, nc, mE, mnc, a);
+  else hipLaunchKernelGGL((k_lincomb_diag<T, false, false>), dim3(grid), dim3(256), 0, s, n, E, nc, mE, mnc, a);
   TD_HIP(hipGetLastError());
 }
 
@@ -522,8 +567,9 @@ void lincomb_diag(int64_t nblk, int E, int nc, const LcDiagArgs &a, hipStream_t 
 typedef double v4d __attribute__((ext_vector_type(4)));
 constexpr int kGramMaxPairs = 4096;   // up to 64 x 64 columns
 
-template <class T>
-__global__ __launch_bounds__(256) void k_gram_partial(int64_t nelem, int E, const T *__restrict__ X,
+template <class T, bool FAST>
+__global__ __launch_bounds__(256) void k_gram_partial(int64_t nelem, int E, uint32_t mE,
+                                                      const T *__restrict__ X,
                                                       int ldx, int xc0, int n1,
                                                       const T *__restrict__ Y, int ldy, int yc0,
                                                       int n2, int diag, int64_t per_part,
@@ -546,7 +592,8 @@ __global__ __launch_bounds__(256) void k_gram_partial(int64_t nelem, int E, cons
       av[u] = 0.0;
       bv[u] = 0.0;
       if (k < k1) {
-        const int64_t blk = k / E;
+        // block of element k: multiply-high when exact (FAST), else a 64-bit division
+        const int64_t blk = FAST ? (int64_t)fdiv((uint32_t)k, mE) : k / E;
         const int e = (int)(k - blk * E);
         if (xi) av[u] = (double)X[(blk * ldx + xc0 + ii) * E + e];
         if (yj) bv[u] = (double)Y[(blk * ldy + yc0 + jj) * E + e];
@@ -664,8 +711,13 @@ void gram(int64_t nblk, int E, const T *X, int ldx, int xc0, int n1, const T *Y,
   per = std::max<int64_t>(64, (per + 63) / 64 * 64);
   parts = (int)std::max<int64_t>(1, (nelem + per - 1) / per);
   const int ti = (n1 + 15) / 16, tj = diag ? 1 : (n2 + 15) / 16;
-  hipLaunchKernelGGL((k_gram_partial<T>), dim3(parts, ti, tj), dim3(256), 0, s, nelem, E, X, ldx, xc0,
-                     n1, Y, ldy, yc0, n2, diag ? 1 : 0, per, partial);
+  const uint32_t mE = div_magic(E);
+  if ((double)nelem * E <= 4294967296.0)
+    hipLaunchKernelGGL((k_gram_partial<T, true>), dim3(parts, ti, tj), dim3(256), 0, s, nelem, E, mE, X, ldx,
+                       xc0, n1, Y, ldy, yc0, n2, diag ? 1 : 0, per, partial);
+  else
+    hipLaunchKernelGGL((k_gram_partial<T, false>), dim3(parts, ti, tj), dim3(256), 0, s, nelem, E, mE, X, ldx,
+                       xc0, n1, Y, ldy, yc0, n2, diag ? 1 : 0, per, partial);
   TD_HIP(hipGetLastError());
   hipLaunchKernelGGL(k_gram_reduce, dim3((unsigned)((npair + 3) / 4)), dim3(256), 0, s, parts, npair,
                      partial, out);
