@@ -43,9 +43,13 @@ __global__ __launch_bounds__(256) void k_spmm_left(int64_t nout, int ncol,
   for (int u = 0; u < CW; ++u)
 #pragma unroll
     for (int e = 0; e < E; ++e) acc[u][e] = T(0);
-  const int64_t q1 = ptr[k + 1];
-  for (int64_t q = ptr[k]; q < q1; ++q) {
-    const int2 pr = pairs[q];
+  const int64_t q0 = ptr[k], q1 = ptr[k + 1];
+  // the next pair's indices are requested with this pair's operand loads, so a pair costs
+  // one memory round trip instead of two dependent ones
+  int2 pr_next = q0 < q1 ? pairs[q0] : make_int2(0, 0);
+  for (int64_t q = q0; q < q1; ++q) {
+    const int2 pr = pr_next;
+    if (q + 1 < q1) pr_next = pairs[q + 1];
     const T *a = A + (int64_t)pr.x * (BU * BU);
     T av[BU * BU];
 #pragma unroll
@@ -97,9 +101,12 @@ __global__ __launch_bounds__(256) void k_spmm_right(int64_t nout, int ncol,
   for (int u = 0; u < CW; ++u)
 #pragma unroll
     for (int e = 0; e < E; ++e) acc[u][e] = T(0);
-  const int64_t q1 = ptr[k + 1];
-  for (int64_t q = ptr[k]; q < q1; ++q) {
-    const int2 pr = pairs[q];
+  const int64_t q0 = ptr[k], q1 = ptr[k + 1];
+  // next pair's indices requested with this pair's operand loads (one round trip per pair)
+  int2 pr_next = q0 < q1 ? pairs[q0] : make_int2(0, 0);
+  for (int64_t q = q0; q < q1; ++q) {
+    const int2 pr = pr_next;
+    if (q + 1 < q1) pr_next = pairs[q + 1];
     const T *b = B + (int64_t)pr.y * (BO * BO);
     T bv[BO * BO];
 #pragma unroll
