@@ -440,7 +440,20 @@ __global__ __launch_bounds__(256) void k_lincomb(int64_t nblk, int E, LcArgs a) 
       const LcSrc &src = a.src[si];
       const T *x = (const T *)src.X + ((blk * src.ldx + src.xc0) * E + e);
       const double *c = src.C + (int64_t)j0 * src.nin;
-      for (int i = 0; i < src.nin; ++i) {
+      // source columns in steps of four loads in flight (a loop with one load per step
+      // would wait on every load); the sum order over i is unchanged
+      int i = 0;
+      for (; i + 4 <= src.nin; i += 4) {
+        double xv[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) xv[u] = (double)x[(int64_t)(i + u) * E];
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+#pragma unroll
+          for (int jj = 0; jj < JC; ++jj)
+            if (jj < nj) acc[jj] += c[(int64_t)jj * src.nin + i + u] * xv[u];
+      }
+      for (; i < src.nin; ++i) {
         const double xv = (double)x[(int64_t)i * E];
 #pragma unroll
         for (int jj = 0; jj < JC; ++jj)
