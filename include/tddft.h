@@ -14,7 +14,8 @@
  *
  * Patterns.  M is the cutoff pattern of the auxiliary matrices L (Sec. III.A, Eq.
  * auxiliary); the response kernels are P = K^c S^u L S^o K^v and live on the response
- * pattern R: the blocks that product reaches from M (computed by tddft_create, exported by
+ * pattern R: the blocks that product reaches from M, or M itself in the linear-scaling
+ * mode (tddft_options.truncate_p, Sec. IV.C) (computed by tddft_create, exported by
  * tddft_response_pattern).  Response-kernel arrays at this interface hold the values of R's
  * blocks in (block row, block column) order, each block dense row-major.
  *
@@ -25,8 +26,9 @@
  *     ownership and may free them on return.
  *   - Device arrays passed to tddft_apply / tddft_pcg_solve are caller-owned device
  *     memory of the GPU that was current at tddft_create; they must not alias each
- *     other.  Work is issued on the options' stream (NULL = the default stream) and the
- *     calls return after it completes.
+ *     other.  Work is issued on the stream given at tddft_create (NULL = the default
+ *     stream) and the calls return after it completes; a solve whose options name another
+ *     stream is ordered after the work already queued there.
  *   - A handle is not thread-safe: use one handle per host thread.
  *   - Grid arrays index points as x + nx * (y + ny * z).
  */
@@ -129,6 +131,12 @@ typedef struct {
                                 A = D + K, f_p = A P^p and f_q = A P^q; the solver keeps
                                 p = q (started from Pq) and returns eig(A).  Fixed at
                                 tddft_create like xc */
+  int32_t  truncate_p;       /* 1: linear-scaling mode of Sec. IV.C: the response kernels
+                                are truncated to M as well, so R = M and the trial vectors
+                                are P = mask_M(K^c S^u L S^o K^v) (the invariance
+                                constraint then holds only approximately, Sec. III.A after
+                                Eq. auxiliary); 0: R is the pattern the exact product
+                                reaches from M.  Fixed at tddft_create */
 } tddft_options;
 
 /* Per-solve statistics (host memory, caller-owned).  The log arrays are optional. */
@@ -174,7 +182,8 @@ typedef struct {
 typedef struct tddft_handle tddft_handle;
 
 /* Defaults: FP64, ALDA exchange, rho_floor 1e-10, coupling 1, KSDIFF_CG, eps_tol 1e-4,
- * tol_omega 1e-7, max_iter 300, max_inner 50, refresh 10, restart 20, seed 0, eps_loose 0. */
+ * tol_omega 1e-7, max_iter 300, max_inner 50, refresh 10, restart 20, seed 0, eps_loose 0,
+ * tda 0, truncate_p 0. */
 void tddft_default_options(tddft_options *opts);
 
 /* Build a handle for one system (Sec. III.A: sparse K^v, K^c, S and H, the cutoff
@@ -222,8 +231,9 @@ int tddft_apply(tddft_handle *h, int32_t n_states, const double *Pp, const doubl
  * once per solve on tddft_block_features, falls back to KSDIFF_CG in any iteration where
  * that is not a descent direction for every state, and, when Pp/Pq are NULL, scales the
  * random initial L block by block by the model's guess head.  opts may be NULL (handle's
- * create options).  stats may be NULL.  precision, xc, rho_floor and coupling_scale belong
- * to the handle: solve options that differ in them are rejected with TDDFT_E_INVALID.
+ * create options).  stats may be NULL.  precision, xc, rho_floor, coupling_scale, tda and
+ * truncate_p belong to the handle: solve options that differ in them are rejected with
+ * TDDFT_E_INVALID.
  * Returns TDDFT_E_NO_CONVERGENCE with the last iterate when max_iter is reached, and
  * TDDFT_W_FALLBACK (converged) when the learned scaling was rejected at least once. */
 int tddft_pcg_solve(tddft_handle *h, int32_t n_states, const tddft_options *opts,

@@ -13,7 +13,9 @@ A + B = D + 2K (Sec. II.A).  Contravariant quantities; the metric is
 
 Truncation (Sec. III.A, Eq. auxiliary): the auxiliary matrices L are truncated to the
 block pattern M; the response kernels are P = K^c S^u L S^o K^v, whose block pattern Mp is
-that of the product (wider than M).  Every product is exact; results are restricted to Mp.
+that of the product (wider than M).  In the linear-scaling mode of Sec. IV.C the response
+kernels are truncated as well, to M itself, so Mp = M and the invariance constraint holds
+only approximately.  Every product is exact; results are restricted to Mp.
 """
 from __future__ import annotations
 
@@ -107,11 +109,16 @@ class Operator:
 
 
 def response_pattern(sysm) -> np.ndarray:
-    """Atom-block pattern of K^c S^u L S^o K^v for L on M (boolean products of the block
-    patterns of the factors).  A factor's pattern is its nonzero blocks plus every atom's
-    own block: density matrices are truncated by a radius (Sec. V: the truncation gives them
-    the pattern of the overlap matrices), so an atom's own block belongs to the pattern even
-    where its values vanish (an atom that carries no occupied or no unoccupied weight)."""
+    """Atom-block pattern Mp of the response kernels.  In the linear-scaling mode (Sec.
+    IV.C: every density matrix, the response kernels included, is truncated) it is M.
+    Otherwise it is the pattern of K^c S^u L S^o K^v for L on M (boolean products of the
+    block patterns of the factors).  A factor's pattern is its nonzero blocks plus every
+    atom's own block: density matrices are truncated by a radius (Sec. IV.C: the truncation
+    gives them the pattern of the overlap matrices), so an atom's own block belongs to the
+    pattern even where its values vanish (an atom that carries no occupied or no
+    unoccupied weight)."""
+    if getattr(sysm.cfg, "mask_p", False):
+        return np.asarray(sysm.M, dtype=bool)
     nA = sysm.cfg.n_atoms
 
     def blocks(A, b):

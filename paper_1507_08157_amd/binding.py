@@ -53,7 +53,8 @@ class tddft_options(C.Structure):
                 ("eps_tol", C.c_double), ("tol_omega", C.c_double), ("max_iter", C.c_int32),
                 ("max_inner", C.c_int32), ("refresh", C.c_int32), ("restart", C.c_int32),
                 ("seed", C.c_uint64), ("model", C.c_void_p), ("model_bytes", C.c_int64),
-                ("stream", C.c_void_p), ("eps_loose", C.c_double), ("tda", C.c_int32)]
+                ("stream", C.c_void_p), ("eps_loose", C.c_double), ("tda", C.c_int32),
+                ("truncate_p", C.c_int32)]
 
 
 class tddft_info(C.Structure):

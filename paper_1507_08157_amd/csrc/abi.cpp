@@ -32,6 +32,12 @@ int guarded(std::string &err, F &&f) {
   } catch (const std::bad_alloc &) {
     err = "host allocation failed";
     return TDDFT_E_NOMEM;
+  } catch (const std::exception &e) {
+    err = e.what();
+    return TDDFT_E_INVALID;
+  } catch (...) {
+    err = "unexpected exception";
+    return TDDFT_E_INVALID;
   }
 }
 
@@ -72,6 +78,7 @@ void tddft_default_options(tddft_options *o) {
   o->stream = nullptr;
   o->eps_loose = 0.0;
   o->tda = 0;
+  o->truncate_p = 0;
 }
 
 int tddft_abi_version(void) { return TDDFT_ABI_VERSION; }
@@ -194,6 +201,9 @@ int tddft_apply(tddft_handle *hd, int32_t n, const double *Pp, const double *Pq,
   } catch (const std::bad_alloc &) {
     h.last_error = "host allocation failed";
     return TDDFT_E_NOMEM;
+  } catch (...) {
+    h.last_error = "tddft_apply: unexpected exception";
+    return TDDFT_E_INVALID;
   }
 }
 
@@ -212,9 +222,10 @@ int tddft_pcg_solve(tddft_handle *hd, int32_t n, const tddft_options *opts, doub
   }
   tddft_options o = opts ? *opts : h.opts;
   if (o.precision != h.opts.precision || o.xc != h.opts.xc || o.rho_floor != h.opts.rho_floor ||
-      o.coupling_scale != h.opts.coupling_scale || o.tda != h.opts.tda) {
-    h.last_error = "tddft_pcg_solve: precision, xc, rho_floor, coupling_scale and tda are fixed "
-                   "at tddft_create and must match the handle's";
+      o.coupling_scale != h.opts.coupling_scale || o.tda != h.opts.tda ||
+      o.truncate_p != h.opts.truncate_p) {
+    h.last_error = "tddft_pcg_solve: precision, xc, rho_floor, coupling_scale, tda and "
+                   "truncate_p are fixed at tddft_create and must match the handle's";
     return TDDFT_E_INVALID;
   }
   if (!(o.eps_tol > 0.0) || !(o.tol_omega > 0.0) || o.max_iter < 0 || o.max_inner < 0) {
@@ -224,6 +235,13 @@ int tddft_pcg_solve(tddft_handle *hd, int32_t n, const tddft_options *opts, doub
   if (o.precond == TDDFT_PC_LEARNED && !o.model) o.precond = TDDFT_PC_KSDIFF_CG;
   if (stats) stats->log_len = 0;
   try {
+    // the solve runs on the handle's stream; work the caller queued on another stream
+    // (the options') is waited for first
+    hipStream_t os = (hipStream_t)o.stream;
+    if (os != h.stream) {
+      TD_HIP(hipEventRecord(h.ev_fork, os));
+      TD_HIP(hipStreamWaitEvent(h.stream, h.ev_fork, 0));
+    }
     return pcg_solve(h, n, o, omega, Pp, Pq, stats);
   } catch (const Error &e) {
     h.last_error = e.msg;
@@ -231,6 +249,12 @@ int tddft_pcg_solve(tddft_handle *hd, int32_t n, const tddft_options *opts, doub
   } catch (const std::bad_alloc &) {
     h.last_error = "host allocation failed";
     return TDDFT_E_NOMEM;
+  } catch (const std::exception &e) {
+    h.last_error = std::string("tddft_pcg_solve: ") + e.what();
+    return TDDFT_E_INVALID;
+  } catch (...) {
+    h.last_error = "tddft_pcg_solve: unexpected exception";
+    return TDDFT_E_INVALID;
   }
 }
 
@@ -263,14 +287,19 @@ int tddft_pcg_solve_batched(tddft_handle *const *hs, int32_t n_sys, const int32_
           continue;
         }
       }
-      hipStream_t saved = h.stream;
-      h.stream = st;
+      // the handle works on this worker's stream for the solve and gets its own stream
+      // back however the solve ends
+      struct StreamSwap {
+        Handle &h;
+        hipStream_t saved;
+        StreamSwap(Handle &hh, hipStream_t s) : h(hh), saved(hh.stream) { h.stream = s; }
+        ~StreamSwap() { h.stream = saved; }
+      } swap(h, st);
       tddft_options o = opts ? *opts : h.opts;
       o.stream = st;
       status[k] = tddft_pcg_solve(hs[k], n_states[k], &o, omega[k], Pp ? Pp[k] : nullptr,
                                   Pq ? Pq[k] : nullptr, stats ? &stats[k] : nullptr);
       (void)hipStreamSynchronize(st);
-      h.stream = saved;
     }
     if (st) (void)hipStreamDestroy(st);
   };

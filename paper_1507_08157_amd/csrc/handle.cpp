@@ -375,7 +375,8 @@ void create_handle(Handle &h, const tddft_system &sys, const tddft_options &o) {
   HostBsr HoKv = host_product(Ho, Kv, product_pattern(Ho.pat, Kv.pat));
   HostBsr KcSu = host_product(Kc, Su, product_pattern(Kc.pat, Su.pat));
   HostBsr SoKv = host_product(So, Kv, product_pattern(So.pat, Kv.pat));
-  h.R = product_pattern(product_pattern(KcSu.pat, h.M), SoKv.pat);
+  // linear-scaling mode (Sec. IV.C): the response kernels are truncated to M as well
+  h.R = o.truncate_p ? h.M : product_pattern(product_pattern(KcSu.pat, h.M), SoKv.pat);
   h.nR = h.R.nnzb();
   {
     std::vector<int64_t> voff(h.nR);

@@ -4,7 +4,8 @@ atom blocks, function boxes with (x, y, z) origins) and move response kernels be
 arithmetic of the method.
 
 Response kernels P^p, P^q live on the response pattern: the blocks K^c S^u L S^o K^v can
-reach from auxiliary matrices L on the truncation pattern M (Eq. auxiliary)."""
+reach from auxiliary matrices L on the truncation pattern M (Eq. auxiliary), or M itself
+when the response kernels are truncated too (the linear-scaling mode)."""
 from __future__ import annotations
 
 import numpy as np
@@ -88,8 +89,11 @@ def system_arrays(sysm) -> dict:
 
 
 def response_blocks(sysm) -> np.ndarray:
-    """Atom pairs (u-atom, o-atom) of the response pattern: the blocks reachable in
+    """Atom pairs (u-atom, o-atom) of the response pattern: M itself when the response
+    kernels are truncated to it (the system's mask_p), else the blocks reachable in
     K^c S^u L S^o K^v from L on M (graph reachability over the nonzero blocks)."""
+    if getattr(sysm.cfg, "mask_p", False):
+        return np.asarray(sysm.M, dtype=bool)
     nA = sysm.cfg.n_atoms
 
     def nz(A, b):

@@ -6,19 +6,19 @@ prec   : 200 atoms, 40 bohr, 128^3, 400 o / 600 u, r_c 7, 8 excitations (precisi
          the throughput workload); complete auxiliary pattern M (see below).
 batch  : 64 systems of 50..300 atoms (uniform), box scaled to keep the density of `prec`,
          grid edge a multiple of 16 in [64, 128], r_c 6, R 20, 4 excitations each.
-scale  : 2000 atoms, 80 bohr, 256^3, 4000 o / 6000 u, r_c 6, truncation 15 bohr
-         (~3 % block fill), 4 excitations; 500- and 1000-atom companions at equal density.
+scale  : 2000 atoms, 80 bohr, 256^3, 4000 o / 6000 u, r_c 6, every density matrix
+         truncated at 15 bohr (~3 % block fill), 4 excitations; 500- and 1000-atom
+         companions at equal density (scale500, scale1000, scale2000).
 Small test systems (several grid tiles, ragged tile tails, non-power-of-two FFTs) are
 defined here too.
 
 n_occ / n_vir beyond `tiny` follow n_occ = round(2 * atoms / 3), n_vir = 2 n_occ.
-The density kernels are never truncated here (R_K = None): these synthetic systems have no
-spectral gap to speak of (level spacing ~1e-3 Ha), so truncated kernels lose idempotency and
-the truncated Tsiper problem acquires spurious negative modes.  Truncation is applied to
-the auxiliary matrices L (pattern M), as in Eq. auxiliary; it keeps the method variational,
-but for these delocalised states the map L -> P has near-zero singular values and the
-optimisation over L converges slowly, so the timed workloads keep M complete and the
-truncated path is exercised by the small test systems.
+`prec` and the batch keep exact density kernels (these synthetic systems have level
+spacings of ~1e-3 Ha and no spectral gap at the Fermi level, so their exact P is
+delocalised).  The linear-scaling family (`scale*`, `small_kt`) truncates every density
+matrix at a radius as Sec. IV.C does: K^v and K^c at R_K with two masked McWeeny steps, and
+the response kernels to the pattern M; with the energy zero mid-gap the non-invariant
+remainder this truncation leaves carries positive energy.
 Seeds: base = 1000 * config_index + system_index.
 """
 from __future__ import annotations
@@ -69,11 +69,43 @@ def training_member(i: int, n_atoms: int = 100, seed0: int = 300000) -> Config:
 
 
 def scale(n_atoms: int = 2000) -> Config:
+    """Linear-scaling size (Sec. IV.C): density kernels truncated at 15 bohr and re-purified,
+    response kernels truncated to the same 15-bohr pattern M, energy zero mid-gap."""
     table = {500: (50.0, 160), 1000: (62.5, 200), 2000: (80.0, 256)}
     L, N = table[n_atoms]
     return Config(name=f"scale{n_atoms}", n_atoms=n_atoms, L=L, N=N, r_c=6.0,
                   n_occ=_occ(n_atoms), n_vir=2 * _occ(n_atoms), R_K=15.0, R_M=15.0,
-                  n_states=4, seed=4000 + n_atoms)
+                  n_states=4, seed=4000 + n_atoms, mask_p=True, energy_zero="midgap")
+
+
+def scale500(seed: int | None = None) -> Config:
+    return scale(500)
+
+
+def scale1000(seed: int | None = None) -> Config:
+    return scale(1000)
+
+
+def scale2000(seed: int | None = None) -> Config:
+    return scale(2000)
+
+
+def small_kt(seed: int = 21) -> Config:
+    """The linear-scaling mode at parity size: 32 atoms at the density of `scale` in a
+    21.875 bohr cube, 70^3 (radix 2, 5, 7; ragged tiles), density kernels truncated at
+    7.5 bohr and re-purified, response kernels truncated to M (7.5 bohr), mid-gap zero."""
+    return Config(name="small_kt", n_atoms=32, L=21.875, N=70, r_c=4.5, n_occ=_occ(32),
+                  n_vir=2 * _occ(32), R_K=7.5, R_M=7.5, n_states=4, seed=seed, mask_p=True,
+                  energy_zero="midgap")
+
+
+def small_kt_exactp(seed: int = 21) -> Config:
+    """`small_kt` with exact response kernels (P = K^c S^u L S^o K^v on the blocks it
+    reaches): truncated density kernels in the variational form of Eq. auxiliary."""
+    c = small_kt(seed)
+    d = dict(c.__dict__)
+    d.update(name="small_kt_exactp", mask_p=False)
+    return Config(**d)
 
 
 # ---- small cases for parity tests ----------------------------------------------------
@@ -141,7 +173,9 @@ def wide_grid(seed: int = 3) -> Config:
     return Config(**d)
 
 
-BY_NAME = {"tiny": tiny, "prec": prec, "small_dense": small_dense,
+BY_NAME = {"tiny": tiny, "prec": prec, "small_dense": small_dense, "small_kt": small_kt,
+           "small_kt_exactp": small_kt_exactp, "scale500": scale500, "scale1000": scale1000,
+           "scale2000": scale2000,
            "small_trunc": small_trunc, "small_odd": small_odd, "small_crowded": small_crowded,
            "prec_joint": prec_joint, "small_joint": small_joint, "separated": separated,
            "wide_grid": wide_grid}

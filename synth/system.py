@@ -29,10 +29,13 @@ so every system is synthetic):
     K^c = sum_c a_c a_c^T over the n_vir lowest eigenvectors of (H^u, S^u) whose
     eigenvalue exceeds eps_HOMO + gap_margin (the literal "next" states can lie below the
     occupied ones in a second, independent basis, which would make A-B indefinite);
+  * optional energy zero mid-gap: H <- H - mu S with mu halfway between the highest
+    occupied o-set level and the lowest level K^c keeps;
   * optional truncation of K at radius R_K followed by masked McWeeny steps
     K <- mask(3 K S K - 2 K S K S K);
   * pattern M: (u-atom I, o-atom J) blocks with minimum-image distance <= R_M (dense if
-    R_M is None);
+    R_M is None); in the linear-scaling mode (mask_p) the response kernels are truncated
+    to M as well (Sec. IV.C), otherwise they live on the blocks K^c S^u L S^o K^v reaches;
   * initial guess L0 ~ N(0,1) on M for each state.
 """
 from __future__ import annotations
@@ -74,6 +77,16 @@ class Config:
     # width factor of the u-functions (the o-functions keep w_lo..w_hi): narrower
     # u-functions carry more kinetic energy and leave the lowest joint states o-like
     u_width_scale: float = 1.0
+    # linear-scaling mode (Sec. IV.C): the response kernels P^p, P^q are truncated to the
+    # pattern M as well (P = mask_M(K^c S^u L S^o K^v)); False keeps P exact on the blocks
+    # the product reaches
+    mask_p: bool = False
+    # energy zero of the cell: "none" keeps the finite-difference Hamiltonian as built;
+    # "midgap" subtracts mu S with mu halfway between the highest occupied o-set level and
+    # the lowest level K^c keeps (the method is invariant under this shift while the
+    # response kernels obey the invariance constraint; once they are truncated it fixes
+    # the sign of the operator on the non-invariant remainder)
+    energy_zero: str = "none"
 
     @property
     def h(self) -> float:
@@ -193,17 +206,16 @@ def _atom_functions(cfg: Config, R: np.ndarray, n_fn: int, rng: np.random.Genera
     Z, Y, X = np.meshgrid(z, y, x, indexing="ij")
     r2 = X * X + Y * Y + Z * Z
     inside = r2 <= cfg.r_c * cfg.r_c
-    vals = np.zeros((n_fn, ext[2], ext[1], ext[0]))
+    widths = np.zeros(n_fn)
+    coefs = np.zeros((n_fn, len(_MONOMIALS)))
     for k in range(n_fn):
-        w = rng.uniform(cfg.w_lo, cfg.w_hi) * (cfg.u_width_scale if k >= cfg.n_o else 1.0)
-        coef = rng.standard_normal(len(_MONOMIALS))
-        poly = np.zeros_like(r2)
-        for c, (px, py, pz) in zip(coef, _MONOMIALS):
-            poly += c * X ** px * Y ** py * Z ** pz
-        f = np.exp(-r2 / (2.0 * w * w)) * poly
-        f[~inside] = 0.0
-        f /= np.sqrt(h ** 3 * np.sum(f * f))
-        vals[k] = f
+        widths[k] = rng.uniform(cfg.w_lo, cfg.w_hi) * (cfg.u_width_scale if k >= cfg.n_o else 1.0)
+        coefs[k] = rng.standard_normal(len(_MONOMIALS))
+    mono = np.stack([X ** px * Y ** py * Z ** pz for (px, py, pz) in _MONOMIALS])
+    poly = np.tensordot(coefs, mono, axes=(1, 0))            # [n_fn, ez, ey, ex]
+    vals = np.exp(-r2[None] / (2.0 * widths[:, None, None, None] ** 2)) * poly
+    vals[:, ~inside] = 0.0
+    vals /= np.sqrt(h ** 3 * np.sum(vals * vals, axis=(1, 2, 3)))[:, None, None, None]
     origin = np.array([lo[2] % N, lo[1] % N, lo[0] % N])      # (z, y, x)
     extent = np.array([ext[2], ext[1], ext[0]])
     return origin, extent, vals
@@ -252,14 +264,29 @@ def _axis_overlap(oa: int, ea: int, ob: int, eb: int, N: int):
     return i[ok], rel[ok]
 
 
+def _as_index(ix):
+    """A contiguous index run as a slice (a view instead of a copy), else the array."""
+    if len(ix) and ix[-1] - ix[0] + 1 == len(ix):
+        return slice(int(ix[0]), int(ix[-1]) + 1)
+    return ix
+
+
 def _box_overlap(oa, ea, ob, eb, N):
     res = []
     for d in range(3):
         ia, ib = _axis_overlap(int(oa[d]), int(ea[d]), int(ob[d]), int(eb[d]), N)
         if len(ia) == 0:
             return None
-        res.append((ia, ib))
+        res.append((_as_index(ia), _as_index(ib)))
     return res
+
+
+def _sub(v, z, y, x):
+    """v[:, z, y, x] for per-axis slices or index arrays, flattened to [n, points]."""
+    v = v[:, z]
+    v = v[:, :, y]
+    v = v[:, :, :, x]
+    return v.reshape(v.shape[0], -1)
 
 
 def _mask_dense(A: np.ndarray, atom_mask: np.ndarray, br: int, bc: int) -> np.ndarray:
@@ -331,10 +358,10 @@ def _build(cfg: Config, seed: int) -> System:
             if ov is None:
                 continue
             (za, zb), (ya, yb), (xa, xb) = ov
-            FI = allv[I][:, za][:, :, ya][:, :, :, xa].reshape(nf, -1)
-            FJ = allv[J][:, zb][:, :, yb][:, :, :, xb].reshape(nf, -1)
-            GJ = Hv[J][:, zb][:, :, yb][:, :, :, xb].reshape(nf, -1)
-            GI = Hv[I][:, za][:, :, ya][:, :, :, xa].reshape(nf, -1)
+            FI = _sub(allv[I], za, ya, xa)
+            FJ = _sub(allv[J], zb, yb, xb)
+            GJ = _sub(Hv[J], zb, yb, xb)
+            GI = _sub(Hv[I], za, ya, xa)
             sIJ = h3 * FI @ FJ.T
             hIJ = 0.5 * h3 * (FI @ GJ.T + GI @ FJ.T)
             S[I * nf:(I + 1) * nf, J * nf:(J + 1) * nf] = sIJ
@@ -374,6 +401,17 @@ def _build(cfg: Config, seed: int) -> System:
             raise _NotEnoughStates(f"seed {seed}: {len(above)} u-states above threshold")
         vir_idx = above[:cfg.n_vir]
         K_c = A[:, vir_idx] @ A[:, vir_idx].T
+
+    if cfg.energy_zero == "midgap":
+        if cfg.joint:
+            raise ValueError("joint representation: energy zero as built only")
+        mu = 0.5 * (homo + eps_u[vir_idx[0]])
+        H_o = H_o - mu * S_o
+        H_u = H_u - mu * S_u
+        eps_o = eps_o - mu
+        eps_u = eps_u - mu
+    elif cfg.energy_zero != "none":
+        raise ValueError(f"unknown energy zero {cfg.energy_zero!r}")
 
     if cfg.R_K is None:
         maskK = np.ones((nA, nA), dtype=bool)

@@ -43,3 +43,13 @@ def separated():
 @pytest.fixture(scope="session")
 def small_odd():
     return cached_system("small_odd")
+
+
+@pytest.fixture(scope="session")
+def small_kt():
+    return cached_system("small_kt")
+
+
+@pytest.fixture(scope="session")
+def small_kt_exactp():
+    return cached_system("small_kt_exactp")

@@ -188,7 +188,7 @@ def test_tamm_dancoff_mode_reaches_tda_brute_force(dense):
 def test_response_pattern_keeps_blocks_of_atoms_without_weight():
     """Well-separated atoms: the occupied states sit on two of four atoms, so K^v has
     vanishing diagonal blocks.  The response pattern still holds every atom's own block
-    (density matrices are truncated by radius, Sec. V), and on P = Pi(L) the blocks that
+    (density matrices are truncated by radius, Sec. IV.C), and on P = Pi(L) the blocks that
     only this reading adds are exactly zero, as is the operator there: the reading changes
     nothing for the P the method produces, only which blocks an arbitrary P may occupy."""
     from conftest import cached_system
