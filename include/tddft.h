@@ -177,6 +177,11 @@ typedef struct {
   int64_t pairs_sandwich;    /* ... of K^c V K^v                                        */
   int64_t partial_pairs;     /* function pairs with per-tile partial integral sums       */
   double  setup_ms;
+  int64_t samples_u_nz;      /* nonzero grid samples of the u-set (points inside spheres) */
+  int64_t samples_o_nz;      /* ... of the o-set                                         */
+  int64_t pair_points_nz;    /* sum over grid points of (u-functions nonzero there) x
+                                (o-functions nonzero there): the method's own work unit of
+                                the response density and the potential integrals          */
 } tddft_info;
 
 typedef struct tddft_handle tddft_handle;

@@ -67,7 +67,9 @@ class tddft_info(C.Structure):
                 ("pairs_kshift", C.c_int64), ("pairs_project", C.c_int64),
                 ("pairs_project_t", C.c_int64),
                 ("pairs_covariant", C.c_int64), ("pairs_sandwich", C.c_int64),
-                ("partial_pairs", C.c_int64), ("setup_ms", C.c_double)]
+                ("partial_pairs", C.c_int64), ("setup_ms", C.c_double),
+                ("samples_u_nz", C.c_int64), ("samples_o_nz", C.c_int64),
+                ("pair_points_nz", C.c_int64)]
 
 
 class tddft_stats(C.Structure):

@@ -167,6 +167,9 @@ int tddft_get_info(const tddft_handle *hd, tddft_info *o) {
   o->pairs_sandwich = h.pSw1.npairs + h.pSw2.npairs;
   o->partial_pairs = h.partials.total;
   o->setup_ms = h.setup_ms;
+  o->samples_u_nz = h.samples_u_nz;
+  o->samples_o_nz = h.samples_o_nz;
+  o->pair_points_nz = h.pair_points_nz;
   return TDDFT_OK;
 }
 

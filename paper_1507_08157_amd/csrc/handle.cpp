@@ -442,6 +442,26 @@ void create_handle(Handle &h, const tddft_system &sys, const tddft_options &o) {
   h.pair_points = pp * TP;
   h.sample_rows_u = (int64_t)tu.ptr[nt] * h.BU;
   h.sample_rows_o = (int64_t)to.ptr[nt] * h.BO;
+  // work of the method itself: per grid point, (u-functions nonzero there) x (o-functions
+  // nonzero there), without the padding of tiles and blocks
+  {
+    int64_t nzu = 0, nzo = 0, ppnz = 0;
+    for (int t = 0; t < nt; ++t) {
+      int cu[TP] = {}, co[TP] = {};
+      for (int64_t r = (int64_t)tu.ptr[t] * h.BU; r < (int64_t)tu.ptr[t + 1] * h.BU; ++r)
+        for (int p = 0; p < TP; ++p) cu[p] += tu.samples[(size_t)r * TP + p] != 0.0;
+      for (int64_t r = (int64_t)to.ptr[t] * h.BO; r < (int64_t)to.ptr[t + 1] * h.BO; ++r)
+        for (int p = 0; p < TP; ++p) co[p] += to.samples[(size_t)r * TP + p] != 0.0;
+      for (int p = 0; p < TP; ++p) {
+        nzu += cu[p];
+        nzo += co[p];
+        ppnz += (int64_t)cu[p] * co[p];
+      }
+    }
+    h.samples_u_nz = nzu;
+    h.samples_o_nz = nzo;
+    h.pair_points_nz = ppnz;
+  }
   h.mean_u_per_tile = (double)tu.ptr[nt] / nt;
   h.mean_o_per_tile = (double)to.ptr[nt] / nt;
   // pattern O: (u-atom, o-atom) pairs sharing a tile

@@ -87,6 +87,7 @@ struct Handle {
   double mean_u_per_tile = 0, mean_o_per_tile = 0;
   int64_t pair_points = 0;     // sum over tiles of (u rows * o rows) * TP (work measure)
   int64_t sample_rows_u = 0, sample_rows_o = 0;
+  int64_t samples_u_nz = 0, samples_o_nz = 0, pair_points_nz = 0;  // nonzero-sample counts
 
   // learned preconditioner: two-atom features of every R block
   int nfeat = 0;
