@@ -141,3 +141,19 @@ def test_apply_rejects_state_count_outside_range(small_dense, n):
         h.tddft_apply(P, P.clone())
     h.close()
     assert e.value.code == binding.TDDFT_E_INVALID
+
+
+def test_info_counts_nonzero_work(small_kt):
+    """tddft_get_info's nonzero-sample and pair-point counts (the work units the benchmark
+    reports) against a direct count on the full grid."""
+    from oracle.grid import to_global
+    s = small_kt
+    h = gpu_handle(s, precision="fp32")
+    info = h.tddft_get_info()
+    h.close()
+    nu = (to_global(s.cfg.N, s.vir) != 0).sum(axis=0)
+    no = (to_global(s.cfg.N, s.occ) != 0).sum(axis=0)
+    assert info["samples_u_nz"] == int(nu.sum())
+    assert info["samples_o_nz"] == int(no.sum())
+    assert info["pair_points_nz"] == int((nu.astype(np.int64) * no).sum())
+    assert info["pair_points"] >= info["pair_points_nz"]
