@@ -222,6 +222,20 @@ int64_t tddft_response_pattern(const tddft_handle *h, int64_t *rowptr, int32_t *
 int tddft_apply(tddft_handle *h, int32_t n_states, const double *Pp, const double *Pq,
                 double *fp, double *fq);
 
+/* tddft_apply without any device allocation, for callers that cannot allocate (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc).  Same
+ * arguments, arithmetic and results as tddft_apply; the column sets, grid fields, FFT
+ * buffer and per-tile partial sums live in one device array that the library holds per GPU
+ * for the life of the process, of tddft_apply_noalloc_limit() bytes (256 MiB).  An
+ * application whose workspace exceeds that (large grids or many states; e.g. a 320^3 grid
+ * at 32 FP32 states) fails with TDDFT_E_INVALID and a message naming the bytes needed.
+ * Every call on a GPU shares that GPU's array: calls that overlap on one GPU (other
+ * threads, other handles, other streams) race.  Nothing in it needs to start at zero.
+ * The handle's GPU must be current. */
+int tddft_apply_noalloc(tddft_handle *h, int32_t n_states, const double *Pp, const double *Pq,
+                        double *fp, double *fq);
+int64_t tddft_apply_noalloc_limit(void);
+
 /* Lowest n_states positive excitation energies by preconditioned CG on the Tsiper sum
  * functional (Secs. III.A-III.C).  omega: HOST [n_states], ascending (Ha).
  * Pp, Pq: DEVICE [n_states][tddft_nnz_p] FP64 (R's layout) or NULL.  On input, if

@@ -91,7 +91,8 @@ EXPORTS = ("tddft_default_options", "tddft_create", "tddft_nnz_p", "tddft_respon
            "tddft_mlp_create", "tddft_mlp_destroy", "tddft_mlp_n_params", "tddft_mlp_set_params",
            "tddft_mlp_get_params", "tddft_mlp_fit_normalisation", "tddft_mlp_forward",
            "tddft_mlp_train_step", "tddft_mlp_export", "tddft_mlp_import",
-           "tddft_mlp_last_error", "tddft_pcg_solve_batched")
+           "tddft_mlp_last_error", "tddft_pcg_solve_batched", "tddft_apply_noalloc",
+           "tddft_apply_noalloc_limit")
 
 
 def lib():
@@ -156,6 +157,8 @@ def lib():
                 ("tddft_mlp_export", [vp, vp, C.c_int64, C.POINTER(C.c_int64)], C.c_int),
                 ("tddft_mlp_import", [vp, C.c_int64, vp, C.POINTER(C.c_void_p)], C.c_int),
                 ("tddft_mlp_last_error", [vp], C.c_char_p),
+                ("tddft_apply_noalloc", [vp, C.c_int32, vp, vp, vp, vp], C.c_int),
+                ("tddft_apply_noalloc_limit", [], C.c_int64),
                 ("tddft_pcg_solve_batched", [C.POINTER(C.c_void_p), C.c_int32, _i32p,
                                              C.POINTER(tddft_options), C.POINTER(_f64p),
                                              C.POINTER(C.c_void_p), C.POINTER(C.c_void_p),
@@ -283,6 +286,15 @@ class Handle:
         fq = torch.empty_like(Pq) if fq is None else fq
         rc = lib().tddft_apply(self._h, n, _dev(Pp, "Pp"), _dev(Pq, "Pq"), _dev(fp, "fp"),
                                _dev(fq, "fq"))
+        if rc != TDDFT_OK:
+            raise self._err(rc)
+        return fp, fq
+
+    def tddft_apply_noalloc(self, Pp, Pq, fp, fq):
+        """tddft_apply through the library's per-GPU workspace (no device allocation);
+        fp and fq must be given."""
+        rc = lib().tddft_apply_noalloc(self._h, Pp.shape[0], _dev(Pp, "Pp"), _dev(Pq, "Pq"),
+                                       _dev(fp, "fp"), _dev(fq, "fq"))
         if rc != TDDFT_OK:
             raise self._err(rc)
         return fp, fq
@@ -427,6 +439,10 @@ def tddft_profile_stage_name(k: int):
 
 def tddft_create(arrays: dict, options: tddft_options | None = None, **kw) -> Handle:
     return Handle(arrays, options, **kw)
+
+
+def tddft_apply_noalloc_limit() -> int:
+    return int(lib().tddft_apply_noalloc_limit())
 
 
 def tddft_abi_version() -> int:

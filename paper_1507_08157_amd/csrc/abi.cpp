@@ -210,6 +210,52 @@ int tddft_apply(tddft_handle *hd, int32_t n, const double *Pp, const double *Pq,
   }
 }
 
+int tddft_apply_noalloc(tddft_handle *hd, int32_t n, const double *Pp, const double *Pq,
+                        double *fp, double *fq) {
+  if (!hd) return TDDFT_E_INVALID;
+  Handle &h = hd->h;
+  h.last_error.clear();
+  if (n < 1 || n > 32 || !Pp || !Pq || !fp || !fq) {
+    h.last_error = "tddft_apply_noalloc: n_states must be in [1, 32] and all arrays non-null";
+    return TDDFT_E_INVALID;
+  }
+  try {
+    int dev = -1;
+    TD_HIP(hipGetDevice(&dev));
+    TD_REQUIRE(dev == h.device && h.scratch, "tddft_apply_noalloc: the handle's GPU must be current");
+    const int nc = 2 * n;
+    auto run = [&](auto tag) {
+      using T = decltype(tag);
+      const size_t elems = (size_t)h.nR * nc * h.E;
+      const size_t xf = (2 * elems * sizeof(T) + 255) & ~(size_t)255;
+      const ApplyLayout lay = apply_layout(h, n, sizeof(T));
+      if (xf + lay.total > scratch_capacity())
+        throw Error{TDDFT_E_INVALID, "tddft_apply_noalloc: " + std::to_string(n) + " states need " +
+                                         std::to_string(xf + lay.total) + " bytes of workspace; the limit is " +
+                                         std::to_string(scratch_capacity()) + " (use tddft_apply)"};
+      unsigned char *base = (unsigned char *)h.scratch;
+      T *X = (T *)base;
+      T *F = X + elems;
+      pack<T>(h.nR, h.BU, h.BO, n, Pp, h.nnzR, h.r_voff.p, h.r_shape.p, X, nc, 0, h.stream);
+      pack<T>(h.nR, h.BU, h.BO, n, Pq, h.nnzR, h.r_voff.p, h.r_shape.p, X, nc, n, h.stream);
+      apply_sets<T>(h, n, X, nc, 0, n, F, nc, 0, n, true, false, base + xf);
+      unpack<T>(h.nR, h.BU, h.BO, n, F, nc, 0, h.r_voff.p, h.r_shape.p, fp, h.nnzR, h.stream);
+      unpack<T>(h.nR, h.BU, h.BO, n, F, nc, n, h.r_voff.p, h.r_shape.p, fq, h.nnzR, h.stream);
+      TD_HIP(hipStreamSynchronize(h.stream));
+    };
+    if (h.precision == TDDFT_FP64) run(double{}); else run(float{});
+    return TDDFT_OK;
+  } catch (const Error &e) {
+    h.last_error = e.msg;
+    return e.code;
+  } catch (...) {
+    h.last_error = "tddft_apply_noalloc: unexpected exception";
+    return TDDFT_E_INVALID;
+  }
+}
+
+int64_t tddft_apply_noalloc_limit(void) { return (int64_t)scratch_capacity(); }
+
 int tddft_pcg_solve(tddft_handle *hd, int32_t n, const tddft_options *opts, double *omega,
                     double *Pp, double *Pq, tddft_stats *stats) {
   if (!hd) return TDDFT_E_INVALID;

@@ -361,6 +361,7 @@ void create_handle(Handle &h, const tddft_system &sys, const tddft_options &o) {
 
   // ---- every host-side check passed: from here on the device is used
   TD_HIP(hipGetDevice(&h.device));
+  h.scratch = scratch_address(h.device);
   int lds = 0;
   TD_HIP(hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, h.device));
   h.lds_limit = (size_t)lds;
@@ -615,9 +616,26 @@ void covariant_sets(Handle &h, int ncol, const T *X, int ldx, int x0, T *F, int 
   h.prof.end(ST_COVARIANT, h.stream);
 }
 
+ApplyLayout apply_layout(const Handle &h, int n, size_t elem) {
+  // sub-buffers start on 256-byte boundaries (vector loads of the partial sums)
+  auto al = [](size_t b) { return (b + 255) & ~(size_t)255; };
+  const int npair = (n + 1) / 2;
+  ApplyLayout l;
+  l.fields = al((size_t)npair * h.nt * TP * 2 * elem);
+  l.work = al((size_t)npair * h.n[0] * h.n[1] * h.n[2] * 2 * elem);
+  l.vset = al((size_t)h.nO * n * h.E * elem);
+  l.y = al((size_t)h.nM2 * n * h.E * elem);
+  // potential integrals in chunks of at most 8 states (chunk starts stay even), which
+  // bounds the per-tile partial-sum buffer
+  l.chunk = std::min(n, 8);
+  l.part = al((size_t)h.partials.total * l.chunk * elem);
+  l.total = l.fields + l.work + l.vset + l.y + l.part + 1024;
+  return l;
+}
+
 template <class T>
 void apply_sets(Handle &h, int n, const T *X, int ldx, int xp0, int xq0, T *F, int ldf, int fp0,
-                int fq0, bool coupling, bool p_is_q) {
+                int fq0, bool coupling, bool p_is_q, unsigned char *ws) {
   hipStream_t s = h.stream;
   // The K-shift term writes F and the coupling term adds into it last; up to that add the
   // two read only X. With a coupling term the K-shift products run on the handle's second
@@ -648,18 +666,10 @@ void apply_sets(Handle &h, int n, const T *X, int ldx, int xp0, int xq0, T *F, i
   };
   const int npair = (n + 1) / 2;
   const int64_t pstride = (int64_t)h.nt * TP * 2;
-  const int64_t wstride = (int64_t)h.n[0] * h.n[1] * h.n[2] * 2;
-  // sub-buffers start on 256-byte boundaries (vector loads of the partial sums)
-  auto al = [](size_t b) { return (b + 255) & ~(size_t)255; };
-  const size_t bytes_f = al((size_t)npair * pstride * sizeof(T));
-  const size_t bytes_w = al((size_t)npair * wstride * sizeof(T));
-  const size_t bytes_v = al((size_t)h.nO * n * h.E * sizeof(T));
-  const size_t bytes_y = al((size_t)h.nM2 * n * h.E * sizeof(T));
-  // potential integrals in chunks of at most 8 states (chunk starts stay even), which
-  // bounds the per-tile partial-sum buffer
-  const int chunk = std::min(n, 8);
-  const size_t bytes_part = (size_t)h.partials.total * chunk * sizeof(T);
-  unsigned char *base = (unsigned char *)h.w_apply.get(bytes_f + bytes_w + bytes_v + bytes_y + bytes_part + 1024);
+  const ApplyLayout lay = apply_layout(h, n, sizeof(T));
+  const int chunk = lay.chunk;
+  const size_t bytes_f = lay.fields, bytes_w = lay.work, bytes_v = lay.vset, bytes_y = lay.y;
+  unsigned char *base = ws ? ws : (unsigned char *)h.w_apply.get(lay.total);
   T *fields = (T *)base;
   T *work = (T *)(base + bytes_f);
   T *Vset = (T *)(base + bytes_f + bytes_w);
@@ -708,7 +718,8 @@ void apply_sets(Handle &h, int n, const T *X, int ldx, int xp0, int xq0, T *F, i
 }
 
 #define TD_INST_APPLY(T)                                                                      \
-  template void apply_sets<T>(Handle &, int, const T *, int, int, int, T *, int, int, int, bool, bool); \
+  template void apply_sets<T>(Handle &, int, const T *, int, int, int, T *, int, int, int, bool, bool, \
+                              unsigned char *);                                              \
   template void kshift_sets<T>(Handle &, int, const T *, int, int, T *, int, int);             \
   template void project_sets<T>(Handle &, int, const T *, int, int, T *, int, int);            \
   template void project_t_sets<T>(Handle &, int, const T *, int, int, T *, int, int);          \

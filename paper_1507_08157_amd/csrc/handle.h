@@ -36,8 +36,13 @@ struct Work {
   }
 };
 
+// allocation-free application: the per-device workspace array (noalloc.hip)
+size_t scratch_capacity();
+void *scratch_address(int device);
+
 struct Handle {
   int device = 0;
+  void *scratch = nullptr;     // this device's copy of the allocation-free workspace
   hipStream_t stream = nullptr;
   tddft_options opts{};
   int precision = TDDFT_FP64;
@@ -126,10 +131,20 @@ template <> inline const float *Handle::fxc<float>() const { return fxc32.p; }
 void create_handle(Handle &h, const tddft_system &sys, const tddft_options &o);
 
 // ---- operator application on column sets (internal precision T) ---------------------------
+// Device workspace of one application of n states with elements of `elem` bytes: grid
+// fields, FFT work buffer, potential-integral matrices on O, sandwich intermediate on M2
+// and the per-tile partial sums, each on a 256-byte boundary.
+struct ApplyLayout {
+  size_t fields = 0, work = 0, vset = 0, y = 0, part = 0, total = 0;
+  int chunk = 0;
+};
+ApplyLayout apply_layout(const Handle &h, int n, size_t elem);
 // X: column set on R with ld columns; p columns [xp0, xp0 + n), q columns [xq0, xq0 + n).
+// ws: device workspace of apply_layout(h, n, sizeof(T)).total bytes, or nullptr for the
+// handle's own (grown on demand).
 template <class T>
 void apply_sets(Handle &h, int n, const T *X, int ldx, int xp0, int xq0, T *F, int ldf, int fp0,
-                int fq0, bool coupling, bool p_is_q = false);
+                int fq0, bool coupling, bool p_is_q = false, unsigned char *ws = nullptr);
 template <class T>
 void kshift_sets(Handle &h, int ncol, const T *X, int ldx, int x0, T *F, int ldf, int f0);
 // Pi(L) = K^c S^u L S^o K^v: L on M, result on R
