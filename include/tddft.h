@@ -195,8 +195,9 @@ void tddft_default_options(tddft_options *opts);
  * pattern M and grid-sampled functions).  Validates the input (TDDFT_E_INVALID on bad
  * shapes, unsorted or out-of-range patterns, NaN/Inf, asymmetric S/H, functions whose
  * boxes exceed the cell, grid edges outside [2, 4096] or with a prime factor above 7, grid
- * edges whose FFT line buffers exceed a workgroup's LDS: with 160 KiB, FP64 edges of 320
- * points or more, FP32 edges of 640 or more), uploads it to the current GPU, builds the
+ * edges whose FFT line buffers exceed a workgroup's LDS: with 160 KiB, FP64 edges of 640
+ * points or more, or of more than 316 points with a factor 7, FP32 twice these), uploads
+ * it to the current GPU, builds the
  * grid tiles and the sparse-product plans, and computes rho0 = 2 sum o_b K^v_bb' o_b' and
  * the ALDA kernel f_xc(r) (Sec. II.A) once.  opts->precision fixes the storage precision
  * of the grid samples for the handle's lifetime.  On success *out owns all device state. */

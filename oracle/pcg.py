@@ -18,7 +18,9 @@ is one of the documented readings:
     leaves the invariant space and P itself is never re-projected;
   * learned (optional): G = c * g with a per-block elementwise scaling c predicted from
     two-atom features (oracle/learned.py), used when it is a descent direction for every
-    state, else the CG preconditioner below;
+    state, else the CG preconditioner below; once the largest gradient norm has not halved
+    over `learned_window` iterations with the learned scaling on, the rest of the solve
+    uses the CG preconditioner (one more fallback);
   * M complete (no truncation): Eq. precond, K^c H^u G - G H^o K^v = g, is solved by CG in
     the S metric to a relative residual eps_tol (Sec. III.B) and the direction is
     d = -Pi(G) + beta d_prev (Pi(G) = G for invariant G); none -> G = g;
@@ -53,6 +55,7 @@ class Options:
     max_inner: int = 50
     refresh: int = 10
     restart: int = 20
+    learned_window: int = 10
 
 
 @dataclass
@@ -74,6 +77,8 @@ class Solver:
         self.complete = bool(np.all(op.mask_L == 1))
         self.fallbacks = 0
         self.eps = opts.eps_tol
+        self.learned_on = opts.precond == "learned"
+        self.learned_gmax = []
 
     # -- metric helpers -------------------------------------------------------------------
     def cov(self, X):
@@ -111,7 +116,7 @@ class Solver:
         ||res|| <= eps_tol ||g||, after max_inner steps or on non-positive curvature."""
         if self.o.precond == "none":
             return g.copy(), 0
-        if self.o.precond == "learned":
+        if self.learned_on:
             # learned block scaling, kept only if it is a descent direction for every column
             z = self.o.scaling[None] * g
             if np.all(np.einsum("kij,kij->k", z, self.cov(g)) > 0):
@@ -150,7 +155,7 @@ class Solver:
         non-positive curvature; none -> z = r."""
         if self.o.precond == "none":
             return r.copy(), 0
-        if self.o.precond == "learned":
+        if self.learned_on:
             z = self.op.truncate(self.o.scaling)[None] * r
             if np.all(np.einsum("kij,kij->k", z, r) > 0):
                 return z, 0
@@ -316,6 +321,12 @@ class Solver:
             if it == self.o.max_iter:
                 break
             omega_prev = omega
+            if self.learned_on:
+                self.learned_gmax.append(float(np.max(gnorm)))
+                k = self.o.learned_window
+                if len(self.learned_gmax) > k and self.learned_gmax[-1] > 0.5 * self.learned_gmax[-1 - k]:
+                    self.learned_on = False
+                    self.fallbacks += 1
             shape = g.shape
             if self.complete:
                 # r, z in the S metric on the trial-vector space (M complete)

@@ -282,8 +282,8 @@ struct GeomDev {
 
 // ---- pass 1: x forward, tile-major -> natural ---------------------------------------------
 // one workgroup per row of tiles (ty, tz): 16 x-lines, contiguous in the tile-major layout
-template <class T, bool INPL>
-__global__ __launch_bounds__(256) void k_fft_x_fwd(GeomDev g, AxisDev ax,
+template <class T, bool INPL, int NT>
+__global__ __launch_bounds__(NT) void k_fft_x_fwd(GeomDev g, AxisDev ax,
                                                    const typename C2<T>::type *__restrict__ tw,
                                                    const typename C2<T>::type *__restrict__ fields,
                                                    typename C2<T>::type *__restrict__ work) {
@@ -298,16 +298,16 @@ __global__ __launch_bounds__(256) void k_fft_x_fwd(GeomDev g, AxisDev ax,
   const T2 *src = fields + pair * g.pair_tile + (int64_t)row * g.ntx * TP;
   const int ntot = g.ntx * TP;
   // loads in batches of kLoadBatch per thread, all in flight before the LDS writes
-  for (int b0 = 0; b0 < ntot; b0 += kLoadBatch * 256) {
+  for (int b0 = 0; b0 < ntot; b0 += kLoadBatch * NT) {
     T2 v[kLoadBatch];
 #pragma unroll
     for (int u = 0; u < kLoadBatch; ++u) {
-      const int e = b0 + u * 256 + (int)threadIdx.x;
+      const int e = b0 + u * NT + (int)threadIdx.x;
       if (e < ntot) v[u] = src[e];
     }
 #pragma unroll
     for (int u = 0; u < kLoadBatch; ++u) {
-      const int e = b0 + u * 256 + (int)threadIdx.x;
+      const int e = b0 + u * NT + (int)threadIdx.x;
       const int tx = e / TP, p = e - (e / TP) * TP;
       const int px = p & 3, l = p >> 2;
       const int x = tx * 4 + px;
@@ -327,8 +327,8 @@ __global__ __launch_bounds__(256) void k_fft_x_fwd(GeomDev g, AxisDev ax,
 // ---- pass 2/4: y lines in place ---------------------------------------------------------
 constexpr int XB = 16;   // x-columns per workgroup in the strided passes
 
-template <class T, int SIGN, bool INPL>
-__global__ __launch_bounds__(256) void k_fft_y(GeomDev g, AxisDev ax,
+template <class T, int SIGN, bool INPL, int NT>
+__global__ __launch_bounds__(NT) void k_fft_y(GeomDev g, AxisDev ax,
                                                const typename C2<T>::type *__restrict__ tw,
                                                typename C2<T>::type *__restrict__ work) {
   using T2 = typename C2<T>::type;
@@ -341,17 +341,17 @@ __global__ __launch_bounds__(256) void k_fft_y(GeomDev g, AxisDev ax,
   const int x0 = xb * XB;
   const int nl = min(XB, g.nx - x0);
   T2 *base = work + blockIdx.y * g.pair_work + (int64_t)z * g.ny * g.nx + x0;
-  for (int b0 = 0; b0 < XB * g.ny; b0 += kLoadBatch * 256) {
+  for (int b0 = 0; b0 < XB * g.ny; b0 += kLoadBatch * NT) {
     T2 v[kLoadBatch];
 #pragma unroll
     for (int u = 0; u < kLoadBatch; ++u) {
-      const int e = b0 + u * 256 + (int)threadIdx.x;
+      const int e = b0 + u * NT + (int)threadIdx.x;
       const int y = e / XB, l = e - y * XB;
       if (e < XB * g.ny && l < nl) v[u] = base[(int64_t)y * g.nx + l];
     }
 #pragma unroll
     for (int u = 0; u < kLoadBatch; ++u) {
-      const int e = b0 + u * 256 + (int)threadIdx.x;
+      const int e = b0 + u * NT + (int)threadIdx.x;
       const int y = e / XB, l = e - y * XB;
       if (e < XB * g.ny && l < nl) a[l * ldl + y] = v[u];
     }
@@ -365,8 +365,8 @@ __global__ __launch_bounds__(256) void k_fft_y(GeomDev g, AxisDev ax,
 }
 
 // ---- pass 3: z lines, forward, Poisson kernel, inverse -----------------------------------
-template <class T, bool INPL>
-__global__ __launch_bounds__(256) void k_fft_z_poisson(GeomDev g, AxisDev ax,
+template <class T, bool INPL, int NT>
+__global__ __launch_bounds__(NT) void k_fft_z_poisson(GeomDev g, AxisDev ax,
                                                        const typename C2<T>::type *__restrict__ tw,
                                                        typename C2<T>::type *__restrict__ work,
                                                        double gx, double gy, double gz,
@@ -382,17 +382,17 @@ __global__ __launch_bounds__(256) void k_fft_z_poisson(GeomDev g, AxisDev ax,
   const int nl = min(XB, g.nx - x0);
   const int64_t plane = (int64_t)g.ny * g.nx;
   T2 *base = work + blockIdx.y * g.pair_work + (int64_t)y * g.nx + x0;
-  for (int b0 = 0; b0 < XB * g.nz; b0 += kLoadBatch * 256) {
+  for (int b0 = 0; b0 < XB * g.nz; b0 += kLoadBatch * NT) {
     T2 v[kLoadBatch];
 #pragma unroll
     for (int u = 0; u < kLoadBatch; ++u) {
-      const int e = b0 + u * 256 + (int)threadIdx.x;
+      const int e = b0 + u * NT + (int)threadIdx.x;
       const int z = e / XB, l = e - z * XB;
       if (e < XB * g.nz && l < nl) v[u] = base[(int64_t)z * plane + l];
     }
 #pragma unroll
     for (int u = 0; u < kLoadBatch; ++u) {
-      const int e = b0 + u * 256 + (int)threadIdx.x;
+      const int e = b0 + u * NT + (int)threadIdx.x;
       const int z = e / XB, l = e - z * XB;
       if (e < XB * g.nz && l < nl) a[l * ldl + z] = v[u];
     }
@@ -426,8 +426,8 @@ __global__ __launch_bounds__(256) void k_fft_z_poisson(GeomDev g, AxisDev ax,
 }
 
 // ---- pass 5: x inverse, natural -> tile-major, plus f_xc rho ---------------------------------
-template <class T, bool INPL>
-__global__ __launch_bounds__(256) void k_fft_x_inv(GeomDev g, AxisDev ax,
+template <class T, bool INPL, int NT>
+__global__ __launch_bounds__(NT) void k_fft_x_inv(GeomDev g, AxisDev ax,
                                                    const typename C2<T>::type *__restrict__ tw,
                                                    const typename C2<T>::type *__restrict__ work,
                                                    typename C2<T>::type *__restrict__ fields,
@@ -440,11 +440,11 @@ __global__ __launch_bounds__(256) void k_fft_x_inv(GeomDev g, AxisDev ax,
   const int row = blockIdx.x;
   const int ty = row % g.nty, tz = row / g.nty;
   const int pair = blockIdx.y;
-  for (int b0 = 0; b0 < 16 * g.nx; b0 += kLoadBatch * 256) {
+  for (int b0 = 0; b0 < 16 * g.nx; b0 += kLoadBatch * NT) {
     T2 v[kLoadBatch];
 #pragma unroll
     for (int u = 0; u < kLoadBatch; ++u) {
-      const int e = b0 + u * 256 + (int)threadIdx.x;
+      const int e = b0 + u * NT + (int)threadIdx.x;
       const int l = fdiv(e, g.m_nx), x = e - l * g.nx;
       const int y = ty * 4 + (l & 3), z = tz * 4 + (l >> 2);
       v[u].x = T(0);
@@ -453,7 +453,7 @@ __global__ __launch_bounds__(256) void k_fft_x_inv(GeomDev g, AxisDev ax,
     }
 #pragma unroll
     for (int u = 0; u < kLoadBatch; ++u) {
-      const int e = b0 + u * 256 + (int)threadIdx.x;
+      const int e = b0 + u * NT + (int)threadIdx.x;
       const int l = fdiv(e, g.m_nx), x = e - l * g.nx;
       if (e < 16 * g.nx) a[l * ldl + x] = v[u];
     }
@@ -463,13 +463,13 @@ __global__ __launch_bounds__(256) void k_fft_x_inv(GeomDev g, AxisDev ax,
   T2 *dst = fields + pair * g.pair_tile + (int64_t)row * g.ntx * TP;
   const T *fx = fxc + (int64_t)row * g.ntx * TP;
   const int ntot = g.ntx * TP;
-  for (int b0 = 0; b0 < ntot; b0 += kLoadBatch * 256) {
+  for (int b0 = 0; b0 < ntot; b0 += kLoadBatch * NT) {
     T2 rho[kLoadBatch];
     T f[kLoadBatch];
     if (use_fxc) {
 #pragma unroll
       for (int u = 0; u < kLoadBatch; ++u) {
-        const int e = b0 + u * 256 + (int)threadIdx.x;
+        const int e = b0 + u * NT + (int)threadIdx.x;
         if (e < ntot) {
           rho[u] = dst[e];
           f[u] = fx[e];
@@ -478,7 +478,7 @@ __global__ __launch_bounds__(256) void k_fft_x_inv(GeomDev g, AxisDev ax,
     }
 #pragma unroll
     for (int u = 0; u < kLoadBatch; ++u) {
-      const int e = b0 + u * 256 + (int)threadIdx.x;
+      const int e = b0 + u * NT + (int)threadIdx.x;
       if (e >= ntot) continue;
       const int tx = e / TP, p = e - (e / TP) * TP;
       const int px = p & 3, l = p >> 2;
@@ -500,18 +500,40 @@ __global__ __launch_bounds__(256) void k_fft_x_inv(GeomDev g, AxisDev ax,
 }
 
 // ---------------------------------------------------------------------------------------
-// in-place passes (one LDS buffer) when every radix pass of the axis fits the per-thread
-// butterfly budget of fft_pass_inplace for 16 lines on 256 threads
-static bool axis_inplace(const AxisFFT &a) {
-  for (int R : a.radix)
-    if (R == 7 || 16 * (a.n / R) > (R >= 8 ? 1 : 8 / R) * 256) return false;
-  return true;
+// Threads per workgroup of an axis pass: the smallest of 256, 512 and 1024 with which every
+// radix pass fits the per-thread butterfly budget of fft_pass_inplace for 16 lines, so that
+// the pass runs in place in one LDS buffer (a long axis such as 256 needs 512 threads: with
+// 256 its radix-8 passes would need two buffers, halving the workgroups a CU holds); 0 when
+// none does (a factor 7, or an axis longer than 1024 threads can cover), and then the pass
+// takes two buffers on 256 threads.
+static int axis_threads(const AxisFFT &a) {
+  for (int nt : {256, 512, 1024}) {
+    bool fits = true;
+    for (int R : a.radix)
+      if (R == 7 || 16 * (a.n / R) > (R >= 8 ? 1 : 8 / R) * nt) fits = false;
+    if (fits) return nt;
+  }
+  return 0;
 }
+static bool axis_inplace(const AxisFFT &a) { return axis_threads(a) > 0; }
 
 // LDS of one workgroup of an axis pass (line buffers of odd stride n + 1)
 static size_t axis_lds_bytes(const AxisFFT &a, int lines, size_t elem) {
   return (axis_inplace(a) ? 1 : 2) * (size_t)lines * (a.n + 1) * elem;
 }
+
+#define TD_COMMA(x) , x
+// launch one pass kernel in its in-place form at the axis's thread count, or in the
+// two-buffer form on 256 threads
+#define TD_FFT_LAUNCH(KERN, TARGS, nt, grid, lds, ...)                                      \
+  do {                                                                                    \
+    switch (nt) {                                                                         \
+      case 256: hipLaunchKernelGGL((KERN<TARGS, true, 256>), grid, dim3(256), lds, __VA_ARGS__); break;   \
+      case 512: hipLaunchKernelGGL((KERN<TARGS, true, 512>), grid, dim3(512), lds, __VA_ARGS__); break;   \
+      case 1024: hipLaunchKernelGGL((KERN<TARGS, true, 1024>), grid, dim3(1024), lds, __VA_ARGS__); break; \
+      default: hipLaunchKernelGGL((KERN<TARGS, false, 256>), grid, dim3(256), lds, __VA_ARGS__); break;  \
+    }                                                                                     \
+  } while (0)
 
 size_t fft_lds_bytes(const FFTPlan &plan, size_t elem) {
   return std::max({axis_lds_bytes(plan.ax[0], 16, elem), axis_lds_bytes(plan.ax[1], XB, elem),
@@ -552,39 +574,31 @@ void hartree_xc(const GridGeom &gg, const FFTPlan &plan, int npair, T *fields, T
   const double scale = 4.0 * pi / ((double)gg.n[0] * gg.n[1] * gg.n[2]);
   const unsigned rows = (unsigned)(gg.nty * gg.ntz);
   const unsigned nxb = (unsigned)((gg.n[0] + XB - 1) / XB);
-  const bool ix = axis_inplace(plan.ax[0]), iy = axis_inplace(plan.ax[1]), iz = axis_inplace(plan.ax[2]);
   const size_t lx = axis_lds_bytes(plan.ax[0], 16, sizeof(T2));
   const size_t ly = axis_lds_bytes(plan.ax[1], XB, sizeof(T2));
   const size_t lz = axis_lds_bytes(plan.ax[2], XB, sizeof(T2));
   Prof dummy;
   Prof &pf = prof ? *prof : dummy;
+  const int tx = axis_threads(plan.ax[0]), ty = axis_threads(plan.ax[1]), tz = axis_threads(plan.ax[2]);
   pf.begin(ST_FFT_X_FWD, s);
-  if (ix) hipLaunchKernelGGL((k_fft_x_fwd<T, true>), dim3(rows, npair), dim3(256), lx, s, g, ax, tw + off[0], F, W);
-  else hipLaunchKernelGGL((k_fft_x_fwd<T, false>), dim3(rows, npair), dim3(256), lx, s, g, ax, tw + off[0], F, W);
+  TD_FFT_LAUNCH(k_fft_x_fwd, T, tx, dim3(rows, npair), lx, s, g, ax, tw + off[0], F, W);
   TD_HIP(hipGetLastError());
   pf.end(ST_FFT_X_FWD, s);
   pf.begin(ST_FFT_Y_FWD, s);
-  if (iy) hipLaunchKernelGGL((k_fft_y<T, -1, true>), dim3(nxb * gg.n[2], npair), dim3(256), ly, s, g, ay, tw + off[1], W);
-  else hipLaunchKernelGGL((k_fft_y<T, -1, false>), dim3(nxb * gg.n[2], npair), dim3(256), ly, s, g, ay, tw + off[1], W);
+  TD_FFT_LAUNCH(k_fft_y, T TD_COMMA(-1), ty, dim3(nxb * gg.n[2], npair), ly, s, g, ay, tw + off[1], W);
   TD_HIP(hipGetLastError());
   pf.end(ST_FFT_Y_FWD, s);
   pf.begin(ST_FFT_Z_POISSON, s);
-  if (iz) hipLaunchKernelGGL((k_fft_z_poisson<T, true>), dim3(nxb * gg.n[1], npair), dim3(256), lz, s, g, az,
-                             tw + off[2], W, gx, gy, gz, scale);
-  else hipLaunchKernelGGL((k_fft_z_poisson<T, false>), dim3(nxb * gg.n[1], npair), dim3(256), lz, s, g, az,
-                          tw + off[2], W, gx, gy, gz, scale);
+  TD_FFT_LAUNCH(k_fft_z_poisson, T, tz, dim3(nxb * gg.n[1], npair), lz, s, g, az, tw + off[2], W, gx, gy, gz,
+                scale);
   TD_HIP(hipGetLastError());
   pf.end(ST_FFT_Z_POISSON, s);
   pf.begin(ST_FFT_Y_INV, s);
-  if (iy) hipLaunchKernelGGL((k_fft_y<T, 1, true>), dim3(nxb * gg.n[2], npair), dim3(256), ly, s, g, ay, tw + off[1], W);
-  else hipLaunchKernelGGL((k_fft_y<T, 1, false>), dim3(nxb * gg.n[2], npair), dim3(256), ly, s, g, ay, tw + off[1], W);
+  TD_FFT_LAUNCH(k_fft_y, T TD_COMMA(1), ty, dim3(nxb * gg.n[2], npair), ly, s, g, ay, tw + off[1], W);
   TD_HIP(hipGetLastError());
   pf.end(ST_FFT_Y_INV, s);
   pf.begin(ST_FFT_X_INV, s);
-  if (ix) hipLaunchKernelGGL((k_fft_x_inv<T, true>), dim3(rows, npair), dim3(256), lx, s, g, ax, tw + off[0], W, F,
-                             fxc, use_fxc ? 1 : 0);
-  else hipLaunchKernelGGL((k_fft_x_inv<T, false>), dim3(rows, npair), dim3(256), lx, s, g, ax, tw + off[0], W, F,
-                          fxc, use_fxc ? 1 : 0);
+  TD_FFT_LAUNCH(k_fft_x_inv, T, tx, dim3(rows, npair), lx, s, g, ax, tw + off[0], W, F, fxc, use_fxc ? 1 : 0);
   TD_HIP(hipGetLastError());
   pf.end(ST_FFT_X_INV, s);
 }

@@ -133,7 +133,8 @@ double trace_nbinv(const Mat &N, const Mat &B, int n) {
   return tr;
 }
 
-// Brent's minimiser (golden section with parabolic steps) on [a, b]
+// Brent's minimiser on [a, b]: golden-section steps with parabolic interpolation where it
+// is safe (R. P. Brent, Algorithms for Minimization without Derivatives, 1973, ch. 5)
 double brent_min(const std::function<double(double)> &f, double a, double b, double tol) {
   const double cg = 0.3819660112501051;
   double x = a + cg * (b - a), w = x, v = x;
@@ -456,6 +457,12 @@ static int solve_impl(Handle &h, int n, const tddft_options &o, double *omega, d
   const bool complete = h.m_complete;
   hipStream_t s = h.stream;
   int applies = 0, inner_total = 0, fallbacks = 0;
+  // the learned scaling stays on while it makes progress: once the largest gradient norm
+  // has not halved over kLearnedWindow learned iterations, the rest of the solve uses the
+  // plain preconditioner (counted as a fallback)
+  bool learned_on = o.precond == TDDFT_PC_LEARNED;
+  constexpr int kLearnedWindow = 10;
+  std::vector<double> learned_gmax;
   // learned preconditioner: the network evaluated once on the block features gives the
   // elementwise scaling of every R block (and of M's blocks) and the guess weights
   DevBuf<T> cscale, cscale_m;
@@ -611,13 +618,21 @@ static int solve_impl(Handle &h, int n, const tddft_options &o, double *omega, d
     if (it == o.max_iter) break;
     w_prev = w;
     have_prev = true;
+    if (learned_on) {
+      learned_gmax.push_back(gmax);
+      const size_t m = learned_gmax.size();
+      if (m > (size_t)kLearnedWindow && gmax > 0.5 * learned_gmax[m - 1 - kLearnedWindow]) {
+        learned_on = false;
+        ++fallbacks;
+      }
+    }
 
     if (complete) {
       // ---- M complete: CG on Eq. precond T(z) = g in the S metric (vectors on R = M);
       //      the conjugation uses r = S^u g S^o with Euclidean dots, i.e. S-metric dots of g
       S.copy(nM, set(Lr), set(Gc));
       bool done = false;
-      if (o.precond == TDDFT_PC_LEARNED) {
+      if (learned_on) {
         // learned block scaling, kept if it is a descent direction for every column
         block_scale<T>(nM, nc, h.E, cscale.p, set(G), set(Lz), s);
         const size_t qd = S.gram_q(nM, set(Lz), 0, nc, set(Gc), 0, nc, true);
@@ -640,7 +655,7 @@ static int solve_impl(Handle &h, int n, const tddft_options &o, double *omega, d
     // ---- preconditioner: CG on H_L z = r, H_L(X) = mask_M(Pi^T(S^u T(Pi X) S^o)),
     //      Euclidean inner product on M, per column
     bool done = false;
-    if (o.precond == TDDFT_PC_LEARNED) {
+    if (learned_on) {
       block_scale<T>(nM, nc, h.E, cscale_m.p, set(Lr), set(Lz), s);
       const size_t qd = S.gram_q(nM, set(Lz), 0, nc, set(Lr), 0, nc, true);
       r = S.fetch();

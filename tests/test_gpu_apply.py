@@ -109,24 +109,32 @@ def test_apply_tiny_power_of_two_grid():
     assert rel_err(fq, fq_ref) < TOL_FP64
 
 
-def test_apply_grid_beyond_in_place_ffts():
-    """320^3 grid: the FFT passes use two line buffers per workgroup.  In FP64 they need
-    2 x 16 x 321 x 16 B = 164352 B, more than a workgroup's LDS (160 KiB on MI355X), and
-    creation refuses the grid with a clear error.  In FP32 (half that, 82 KB) the grid
-    fits gfx950's 160 KiB per workgroup, so creation must succeed and the apply runs at the
-    FP32 bound against the oracle."""
+def test_apply_320_grid_in_place_on_1024_threads():
+    """320^3 grid (radix 8, 8, 5): each FFT pass runs in place in one LDS buffer on
+    workgroups of 1024 threads (16 x 321 complex values: 82 KB in FP64, 41 KB in FP32);
+    FP64 and FP32 parity against the oracle."""
     from conftest import cached_system
-    from paper_1507_08157_amd import binding
     s = cached_system("wide_grid")
-    print("[apply] wide_grid fp64 creation", flush=True)
+    for precision, tol in (("fp64", TOL_FP64), ("fp32", 2e-5)):
+        fp, fq, fp_ref, fq_ref, _, _ = _run(s, 0, precision, 1, seed=5)
+        assert rel_err(fp, fp_ref) < tol
+        assert rel_err(fq, fq_ref) < tol
+
+
+def test_grid_beyond_lds_is_refused():
+    """448^3 (radix 7 and 64): an axis with a factor 7 takes two LDS line buffers per
+    workgroup, 2 x 16 x 449 x 16 B = 230 KB in FP64, beyond the 160 KiB of a gfx950
+    workgroup: creation refuses it with a clear error, before any transform runs; FP32
+    (115 KB) is accepted."""
+    import dataclasses
+    from paper_1507_08157_amd import binding
+    from synth import build_system, configs
+    s = build_system(dataclasses.replace(configs.separated(), N=448))
+    print("[apply] 448^3 fp64 creation", flush=True)
     with pytest.raises(binding.TddftError) as e:
         gpu_handle(s, precision="fp64")
     assert e.value.code == binding.TDDFT_E_INVALID and "LDS" in str(e.value)
-    h = gpu_handle(s, precision="fp32")
-    h.close()
-    fp, fq, fp_ref, fq_ref, _, _ = _run(s, 0, "fp32", 1, seed=5)
-    assert rel_err(fp, fp_ref) < 2e-5
-    assert rel_err(fq, fq_ref) < 2e-5
+    gpu_handle(s, precision="fp32").close()
 
 
 @pytest.mark.parametrize("n", [0, 33])

@@ -1,15 +1,13 @@
-"""Parity at the full size of the throughput workload (200 atoms, 128^3 grid, 400 / 600
-functions, 8 states) in the launch configuration the benchmark times: one tddft_apply of
-all 8 states.
+"""Parity at the full size of the precision-study workload (200 atoms, 128^3 grid, 400 /
+600 functions, exact density kernels, 8 states) in the launch configuration the solver
+times: one tddft_apply of all 8 states, in FP64, FP32 and BF16 samples.
 
-* f_p = T(P^p) (Eq. operator_RPA, no grid work) is compared element by element for every
-  state: the oracle's T-term is two dense products per state;
-* f_q of one sampled state (the last: imaginary half of the last complex field pair) is
-  compared element by element with the oracle's full apply;
-* for all 8 states, the coupling part C(P) = f_q - T(P) = 2 K^c V_SCF[P] K^v must give a
-  symmetric matrix <P_j, C(P_i)>_S, a property that holds at any size: for invariant
-  P = K^c S^u L S^o K^v it is x_j^T 2K x_i with the symmetric Casida coupling K.
-The inputs are such invariant kernels (random L, exact products).
+Every state's f_q is compared element by element with the oracle's full apply: two real
+states share one complex field in the Hartree solve, so each test takes one field pair
+(state 2k in the real part, 2k + 1 in the imaginary part) and the four tests together
+cover both halves of every pair.  f_p = T(P^p) (Eq. operator_RPA, no grid work) is
+compared for all states.  The coupling error is measured against the coupling's own
+size, not against f_q (which the Kohn-Sham-difference term dominates).
 """
 import sys
 
@@ -23,43 +21,53 @@ from synth import abi as sabi
 pytestmark = [pytest.mark.gpu, pytest.mark.timeout(600)]
 
 N_STATES = 8
-SAMPLED = 7
-TOLS = {"fp64": (1e-11, 1e-11, 1e-11), "fp32": (2e-5, 2e-5, 1e-4)}
+# (T-term relative, coupling relative to max |coupling|)
+TOLS = {"fp64": (1e-11, 1e-10), "fp32": (2e-5, 2e-5), "bf16": (2e-5, 2e-2)}
+_GPU = {}
+
+
+def _say(msg):
+    print(f"[full] {msg}", flush=True)
+    sys.stdout.flush()
 
 
 @pytest.fixture(scope="module")
 def full():
     from conftest import cached_system
-    print("[full] generating the 200-atom system", flush=True)
+    _say("generating the 200-atom system")
     s = cached_system("prec")
-    print("[full] oracle set-up", flush=True)
+    _say("oracle set-up")
     op = Operator(s)
     Pp = np.stack([op.project(x) for x in random_p(s, N_STATES, 31)])
     Pq = np.stack([op.project(x) for x in random_p(s, N_STATES, 32)])
-    print("[full] oracle apply of the sampled state", flush=True)
-    _, fq_ref = op.apply(Pp[SAMPLED:SAMPLED + 1], Pq[SAMPLED:SAMPLED + 1])
     tp = np.stack([op.T(x) for x in Pp])
     tq = np.stack([op.T(x) for x in Pq])
-    sys.stdout.flush()
-    return s, op, Pp, Pq, tp, tq, fq_ref[0]
+    return s, op, Pp, Pq, tp, tq
 
 
-@pytest.mark.parametrize("precision", ["fp32", "fp64"])
-def test_full_size_apply(full, precision):
-    s, op, Pp, Pq, tp, tq, fq_ref = full
-    print(f"[full] GPU apply {precision}, {N_STATES} states", flush=True)
-    h = gpu_handle(s, precision=precision)
-    fp, fq = h.tddft_apply(to_dev(sabi.dense_to_p(s, Pp)), to_dev(sabi.dense_to_p(s, Pq)))
-    fp = sabi.p_to_dense(s, fp.cpu().numpy())
-    fq = sabi.p_to_dense(s, fq.cpu().numpy())
-    h.close()
-    tol_t, tol_q, tol_sym = TOLS[precision]
-    assert rel_err(fp, tp) < tol_t
-    coup_ref = fq_ref - tq[SAMPLED]
-    err_q = np.max(np.abs(fq[SAMPLED] - fq_ref))
-    assert err_q < tol_q * np.max(np.abs(fq_ref)), (err_q, np.max(np.abs(coup_ref)))
-    # coupling of all states: <P_j, C(P_i)>_S symmetric
-    C = fq - tq
-    cov = np.stack([op.Su @ x @ op.So for x in Pq])
-    G = np.einsum("jab,iab->ij", cov, C)
-    assert np.max(np.abs(G - G.T)) < tol_sym * np.max(np.abs(G))
+def _gpu(s, Pp, Pq, precision):
+    """One apply of all 8 states per precision (cached for the module)."""
+    if precision not in _GPU:
+        _say(f"GPU apply {precision}, {N_STATES} states")
+        h = gpu_handle(s, precision=precision)
+        fp, fq = h.tddft_apply(to_dev(sabi.dense_to_p(s, Pp)), to_dev(sabi.dense_to_p(s, Pq)))
+        h.close()
+        _GPU[precision] = (sabi.p_to_dense(s, fp.cpu().numpy()), sabi.p_to_dense(s, fq.cpu().numpy()))
+    return _GPU[precision]
+
+
+@pytest.mark.parametrize("pair", [0, 1, 2, 3])
+def test_full_size_apply_field_pair(full, pair):
+    s, op, Pp, Pq, tp, tq = full
+    st = [2 * pair, 2 * pair + 1]
+    _say(f"oracle coupling of states {st}")
+    coup = op.coupling(Pq[st])
+    for precision, (tol_t, tol_c) in TOLS.items():
+        fp, fq = _gpu(s, Pp, Pq, precision)
+        assert rel_err(fp, tp) < tol_t
+        for k, i in enumerate(st):
+            got = fq[i] - tq[i]
+            err = np.max(np.abs(got - coup[k]))
+            _say(f"{precision} state {i} ({'imaginary' if i % 2 else 'real'} half): "
+                 f"coupling max {np.max(np.abs(coup[k])):.3e}, error {err:.2e}")
+            assert err < tol_c * np.max(np.abs(coup[k])) + tol_t * np.max(np.abs(tq[i]))

@@ -213,3 +213,24 @@ def test_response_pattern_keeps_blocks_of_atoms_without_weight():
     assert np.abs(P).max() > 0 and (P[extra] == 0).all()
     fp, fq = op.apply(P[None], P[None])
     assert (fp[0][extra] == 0).all() and (fq[0][extra] == 0).all()
+
+
+def test_learned_scaling_without_progress_is_switched_off(dense):
+    """A learned scaling that is a descent direction but a poor preconditioner (random
+    factors over six decades) is dropped once the largest gradient norm has not halved in
+    ten learned iterations; the solve then finishes with the CG preconditioner and reaches
+    brute force.  A constant scaling (steepest descent) keeps halving and stays on."""
+    s, op, cs = dense
+    n = s.cfg.n_states
+    ref = cs.omega_hermitian()[:n]
+    rng = np.random.default_rng(1)
+    bad = np.exp(rng.uniform(np.log(1e-3), np.log(1e3), (s.vir.n_fn, s.occ.n_fn)))
+    r = Solver(op, Options(n_states=n, precond="learned", scaling=bad, tol_omega=1e-10,
+                           max_iter=300)).solve(s.guess())
+    assert r.converged and r.fallbacks == 1
+    assert np.max(np.abs(r.omega - ref)) < 1e-9
+    const = np.full((s.vir.n_fn, s.occ.n_fn), 20.0)
+    r = Solver(op, Options(n_states=n, precond="learned", scaling=const, tol_omega=1e-10,
+                           max_iter=300)).solve(s.guess())
+    assert r.converged and r.fallbacks == 0
+    assert np.max(np.abs(r.omega - ref)) < 1e-9
