@@ -15,7 +15,14 @@ calls:
 
     python -m paper_1507_08157_amd.learned --out model.bin [--systems 8] [--atoms 100]
 
-trains on synthetic systems of the benchmark's density (seeded generator, see synth/).
+trains on synthetic systems of the benchmark's density (seeded generator, see synth/);
+
+    python -m paper_1507_08157_amd.learned --evaluate model.bin [--systems 50]
+        [--seed 400000] [--json out.json]
+
+solves held-out systems (seeds outside the training range) with the plain Eq. precond
+preconditioner and with the model, from the same guess, and reports the iteration and
+wall-time ratios with bootstrap confidence intervals.
 """
 from __future__ import annotations
 
@@ -89,9 +96,74 @@ def train(datasets, width: int = 128, epochs: int = 30, batch: int = 4096, lr: f
     return m, hist
 
 
+def _gen_member(args):
+    import os
+    sys.path.insert(0, os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
+    from synth import abi as sabi
+    from synth import build_system, configs
+    i, atoms, seed0, n = args
+    s = build_system(configs.training_member(i, atoms, seed0))
+    return s.cfg.seed, sabi.system_arrays(s), sabi.dense_to_p(s, s.guess(n))
+
+
+def evaluate(model: bytes, systems: int = 50, atoms: int = 100, seed0: int = 400000,
+             states: int = 4, precision: str = "fp32", tol_omega: float = 1e-8, log=None):
+    """Plain Eq. precond against the learned preconditioner on held-out systems: per system
+    the outer iterations, wall time, fallbacks and the largest |omega_learned -
+    omega_plain|; summary ratios (learned / plain) with 95 % bootstrap intervals.  The
+    systems are generated by worker processes forked before this process touches the
+    GPU."""
+    import concurrent.futures as cf
+    import multiprocessing as mp
+    import os
+    with cf.ProcessPoolExecutor(max_workers=min(16, os.cpu_count() or 1),
+                                mp_context=mp.get_context("fork")) as ex:
+        members = list(ex.map(_gen_member, [(i, atoms, seed0, states) for i in range(systems)]))
+    import torch
+    rows = []
+    for seed, arrays, guess in members:
+        h = binding.tddft_create(arrays, precision=precision)
+        L0 = torch.from_numpy(np.ascontiguousarray(guess)).cuda()
+        res = {}
+        for kind in ("plain", "learned"):
+            kw = dict(precision=precision, tol_omega=tol_omega, max_iter=300)
+            if kind == "learned":
+                kw.update(precond="learned", model=model)
+            o = binding.tddft_default_options(**kw)
+            w, rc, st = h.tddft_pcg_solve(states, o, L0.clone(), L0.clone())
+            res[kind] = (w, rc, st)
+        h.close()
+        (wp, rcp, sp), (wl, rcl, sl) = res["plain"], res["learned"]
+        row = {"seed": int(seed), "plain_iterations": sp["iterations"],
+               "learned_iterations": sl["iterations"], "plain_s": sp["solve_ms"] / 1e3,
+               "learned_s": sl["solve_ms"] / 1e3, "plain_converged": sp["converged"],
+               "learned_converged": sl["converged"], "fallbacks": sl["fallbacks"],
+               "omega_diff_Ha": float(np.max(np.abs(wl - wp)))}
+        rows.append(row)
+        if log:
+            log(f"seed {seed}: {row}")
+    it = np.array([r["learned_iterations"] / r["plain_iterations"] for r in rows])
+    tm = np.array([r["learned_s"] / r["plain_s"] for r in rows])
+    rng = np.random.default_rng(0)
+
+    def ci(x):
+        b = [np.mean(rng.choice(x, len(x))) for _ in range(2000)]
+        return [float(np.percentile(b, 2.5)), float(np.percentile(b, 97.5))]
+    return {"systems": len(rows), "atoms": atoms, "states": states, "precision": precision,
+            "tol_omega": tol_omega, "iteration_ratio_mean": float(it.mean()),
+            "iteration_ratio_ci95": ci(it), "time_ratio_mean": float(tm.mean()),
+            "time_ratio_ci95": ci(tm),
+            "learned_fewer_iterations": int(np.sum(it < 1.0)),
+            "fallback_engaged": int(sum(1 for r in rows if r["fallbacks"] > 0)),
+            "all_converged": bool(all(r["plain_converged"] and r["learned_converged"] for r in rows)),
+            "max_omega_diff_Ha": float(max(r["omega_diff_Ha"] for r in rows)), "rows": rows}
+
+
 def _main():
     ap = argparse.ArgumentParser()
-    ap.add_argument("--out", required=True)
+    ap.add_argument("--out")
+    ap.add_argument("--evaluate", metavar="MODEL")
+    ap.add_argument("--json")
     ap.add_argument("--systems", type=int, default=8)
     ap.add_argument("--atoms", type=int, default=100)
     ap.add_argument("--states", type=int, default=8)
@@ -99,6 +171,7 @@ def _main():
     ap.add_argument("--epochs", type=int, default=30)
     ap.add_argument("--seed", type=int, default=300000)
     a = ap.parse_args()
+    import json
     import os
     sys.path.insert(0, os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
     from synth import abi as sabi
@@ -106,6 +179,18 @@ def _main():
 
     def log(msg):
         print(f"[train] {msg}", flush=True)
+
+    if a.evaluate:
+        model = open(a.evaluate, "rb").read()
+        out = evaluate(model, systems=a.systems, atoms=a.atoms, seed0=a.seed, log=log)
+        summary = {k: v for k, v in out.items() if k != "rows"}
+        log(json.dumps(summary))
+        if a.json:
+            with open(a.json, "w") as f:
+                json.dump(out, f, indent=1)
+        return
+    if not a.out:
+        ap.error("--out (training) or --evaluate MODEL")
 
     data = []
     for i in range(a.systems):
