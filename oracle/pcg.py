@@ -24,8 +24,9 @@ is one of the documented readings:
   * M complete (no truncation): Eq. precond, K^c H^u G - G H^o K^v = g, is solved by CG in
     the S metric to a relative residual eps_tol (Sec. III.B) and the direction is
     d = -Pi(G) + beta d_prev (Pi(G) = G for invariant G); none -> G = g;
-  * M truncated: the gradient with respect to L is r = mask_M(Pi^T(S^u g S^o)) (chain rule
-    through Pi) and Eq. precond is expressed on L, H_L(X) = mask_M(Pi^T S^u T(Pi X) S^o);
+  * M truncated: the gradient with respect to L is r = mask_M(Pi^T(mask_Mp(S^u g S^o)))
+    (chain rule through P = Pi(L), whose entries lie on Mp) and Eq. precond is expressed on
+    L, H_L(X) = mask_M(Pi^T mask_Mp(S^u T(Pi X) S^o));
     H_L z = r is solved by CG (Euclidean inner product on M) to relative residual eps_tol
     and d = -Pi(z) + beta d_prev, a descent direction by construction; none -> z = r;
   * Polak-Ribiere(+) conjugation, common step lambda for all states, exact line search on
@@ -103,13 +104,16 @@ class Solver:
         return self.op.mask_L[None] * (self.op.KcSu.T @ Y @ self.op.SoKv.T)
 
     def grad_L(self, g):
-        """Gradient with respect to L of the functional whose P-gradient is g."""
-        return self.pi_t(self.cov(g))
+        """Gradient with respect to L of the functional whose P-gradient is g: P has entries
+        only on its pattern Mp, so the covariant gradient counts there only
+        (mask_M(Pi^T(mask_Mp(S^u g S^o))); the inner mask changes nothing when Mp is the
+        pattern the exact product reaches, and matters when P is truncated to M)."""
+        return self.pi_t(self.op.mask[None] * self.cov(g))
 
     def hess_L(self, X):
-        """H_L(X) = mask_M(Pi^T(S^u T(Pi X) S^o)) for X on M."""
+        """H_L(X) = mask_M(Pi^T(mask_Mp(S^u T(Pi X) S^o))) for X on M."""
         P = self.project(X)
-        return self.pi_t(self.cov(np.stack([self.op.T(x) for x in P])))
+        return self.pi_t(self.op.mask[None] * self.cov(np.stack([self.op.T(x) for x in P])))
 
     def precondition_p(self, g):
         """Columns of g: [k, nu, no].  CG on T(G) = g in the S metric, G0 = 0, stop at

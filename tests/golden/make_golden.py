@@ -3,11 +3,15 @@ the synthetic-input generator.
 
     python tests/golden/make_golden.py
 
-small_trunc_pcg.json: the excitation-energy trajectory of the first 15 iterations of the
-preconditioned CG (truncated auxiliary pattern M at 6 bohr, auxiliary-space preconditioner)
-on the `small_trunc` system, from the seeded initial guess, with three inner CG steps per
-iteration (a longer inner solve of this ill-conditioned auxiliary-space system amplifies
-rounding differences between implementations).
+<name>_pcg.json: the excitation-energy trajectory of the first 15 iterations of the
+preconditioned CG (truncated auxiliary pattern M, auxiliary-space preconditioner) from the
+seeded initial guess, with three inner CG steps per iteration (a longer inner solve of
+these ill-conditioned auxiliary-space systems amplifies rounding differences between
+implementations), for
+  small_trunc      exact density kernels, M at 6 bohr;
+  small_kt         density kernels truncated at 7.5 bohr and re-purified, response
+                   kernels truncated to M (the linear-scaling form of Sec. IV.C);
+  small_kt_exactp  the same kernels with exact response kernels (Eq. auxiliary).
 """
 import json
 import os
@@ -21,18 +25,22 @@ from oracle.pcg import Options, Solver  # noqa: E402
 from synth import build_system, configs  # noqa: E402
 
 
-def main():
-    s = build_system(configs.small_trunc())
-    it = 15
-    r = Solver(Operator(s), Options(n_states=s.cfg.n_states, max_iter=it, max_inner=3,
+def trajectory(name, it=15, max_inner=3):
+    s = build_system(configs.BY_NAME[name]())
+    r = Solver(Operator(s), Options(n_states=s.cfg.n_states, max_iter=it, max_inner=max_inner,
                                     tol_omega=1e-12)).solve(s.guess())
-    out = {"system": "small_trunc", "iterations": it, "max_inner": 3,
+    out = {"system": name, "iterations": it, "max_inner": max_inner,
            "omega_history": [list(map(float, w)) for w in r.history],
            "inner_iterations": list(map(int, r.inner_iters)),
            "source": "oracle/pcg.py Solver, FP64"}
-    with open(os.path.join(HERE, "small_trunc_pcg.json"), "w") as f:
+    with open(os.path.join(HERE, f"{name}_pcg.json"), "w") as f:
         json.dump(out, f, indent=1)
-    print(json.dumps(out["omega_history"][-1]))
+    print(name, json.dumps(out["omega_history"][-1]))
+
+
+def main():
+    for name in ("small_trunc", "small_kt", "small_kt_exactp"):
+        trajectory(name)
 
 
 if __name__ == "__main__":
