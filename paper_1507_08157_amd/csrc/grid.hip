@@ -89,17 +89,20 @@ __device__ __forceinline__ void density_chunk(const int32_t *__restrict__ pid, i
   }
 }
 
-template <class T, class S, int BL, int BR>
+template <class T, class S, int BL, int BR, int NSC>
 __global__ __launch_bounds__(256) void k_density(DevTiles tl, const S *__restrict__ usamp,
                                                  const S *__restrict__ osamp,
                                                  const int32_t *__restrict__ pidx,
                                                  const T *__restrict__ X, int ldx, int xc0, int ns,
                                                  T *__restrict__ out, int64_t pair_stride, T scale) {
   // states per pass: a P block (NS * BL * BR values) within 48 SGPRs, NS even (fields hold
-  // state pairs): 8 in FP32 and 4 in FP64 for 3 x 2 blocks
+  // state pairs): 8 in FP32 and 4 in FP64 for 3 x 2 blocks, capped at NSC (the launch takes
+  // the smallest even cap that covers the call's states, so a 4-state call loads 4-state
+  // P blocks and runs the unrolled full-pass path)
   constexpr int kSlots = sizeof(T) == 8 ? 24 : 48, kMax = sizeof(T) == 8 ? 4 : 8;
   constexpr int NSe = (kSlots / (BL * BR)) & ~1;
-  constexpr int NS = NSe < 2 ? 2 : (NSe > kMax ? kMax : NSe);
+  constexpr int NSf = NSe < 2 ? 2 : (NSe > kMax ? kMax : NSe);
+  constexpr int NS = NSf < NSC ? NSf : NSC;
   // o-atoms per register chunk: 8 x BR rows in FP32, 4 x BR in FP64
   constexpr int JC = sizeof(T) == 8 ? 4 : 8;
   const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -509,7 +512,12 @@ void density(const DevTiles &tl, int stype, int BL, int BR, const T *X, int ldx,
   const int waves = 4;
   const size_t lds = 0;
   const unsigned grid = (unsigned)((tl.nt + waves - 1) / waves);
-  TD_SAMPLE(T, stype, TD_GRID_BDIM(BL, BR, hipLaunchKernelGGL((k_density<T, S, BL, BR>), dim3(grid), dim3(64 * waves), lds, s, tl, reinterpret_cast<const S *>(tl.usamp), reinterpret_cast<const S *>(tl.osamp), tl.pidx, X, ldx, xc0, ns, out, pair_stride, (T)scale)));
+  if (ns <= 2)
+    TD_SAMPLE(T, stype, TD_GRID_BDIM(BL, BR, hipLaunchKernelGGL((k_density<T, S, BL, BR, 2>), dim3(grid), dim3(64 * waves), lds, s, tl, reinterpret_cast<const S *>(tl.usamp), reinterpret_cast<const S *>(tl.osamp), tl.pidx, X, ldx, xc0, ns, out, pair_stride, (T)scale)));
+  else if (ns <= 4)
+    TD_SAMPLE(T, stype, TD_GRID_BDIM(BL, BR, hipLaunchKernelGGL((k_density<T, S, BL, BR, 4>), dim3(grid), dim3(64 * waves), lds, s, tl, reinterpret_cast<const S *>(tl.usamp), reinterpret_cast<const S *>(tl.osamp), tl.pidx, X, ldx, xc0, ns, out, pair_stride, (T)scale)));
+  else
+    TD_SAMPLE(T, stype, TD_GRID_BDIM(BL, BR, hipLaunchKernelGGL((k_density<T, S, BL, BR, 8>), dim3(grid), dim3(64 * waves), lds, s, tl, reinterpret_cast<const S *>(tl.usamp), reinterpret_cast<const S *>(tl.osamp), tl.pidx, X, ldx, xc0, ns, out, pair_stride, (T)scale)));
   TD_HIP(hipGetLastError());
 }
 
