@@ -70,12 +70,14 @@ def training_member(i: int, n_atoms: int = 100, seed0: int = 300000) -> Config:
 
 def scale(n_atoms: int = 2000) -> Config:
     """Linear-scaling size (Sec. IV.C): density kernels truncated at 15 bohr and re-purified,
-    response kernels truncated to the same 15-bohr pattern M, energy zero mid-gap."""
+    response kernels truncated to the same 15-bohr pattern M, energy zero mid-gap, atoms
+    numbered along a space-filling curve."""
     table = {500: (50.0, 160), 1000: (62.5, 200), 2000: (80.0, 256)}
     L, N = table[n_atoms]
     return Config(name=f"scale{n_atoms}", n_atoms=n_atoms, L=L, N=N, r_c=6.0,
                   n_occ=_occ(n_atoms), n_vir=2 * _occ(n_atoms), R_K=15.0, R_M=15.0,
-                  n_states=4, seed=4000 + n_atoms, mask_p=True, energy_zero="midgap")
+                  n_states=4, seed=4000 + n_atoms, mask_p=True, energy_zero="midgap",
+                  order="morton")
 
 
 def scale500(seed: int | None = None) -> Config:
@@ -96,7 +98,7 @@ def small_kt(seed: int = 21) -> Config:
     7.5 bohr and re-purified, response kernels truncated to M (7.5 bohr), mid-gap zero."""
     return Config(name="small_kt", n_atoms=32, L=21.875, N=70, r_c=4.5, n_occ=_occ(32),
                   n_vir=2 * _occ(32), R_K=7.5, R_M=7.5, n_states=4, seed=seed, mask_p=True,
-                  energy_zero="midgap")
+                  energy_zero="midgap", order="morton")
 
 
 def small_kt_exactp(seed: int = 21) -> Config:

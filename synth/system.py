@@ -17,7 +17,8 @@ Paper correspondence (arXiv:1507.08157):
 
 Recipe (the paper's molecules, pseudopotentials and optimised NGWFs are not available,
 so every system is synthetic):
-  * atoms uniform in [0, L)^3, minimum-image separation >= min_sep (rejection);
+  * atoms uniform in [0, L)^3, minimum-image separation >= min_sep (rejection), numbered
+    in placement order or along a Z-order curve;
   * each atom carries n_o o-functions and n_u u-functions; each function is
     exp(-r^2 / (2 w^2)) times a random polynomial of degree <= 2 in (r - R) (10 monomials,
     N(0,1) coefficients), w ~ U[w_lo, w_hi], cut to zero beyond r_c, normalised so that
@@ -87,6 +88,11 @@ class Config:
     # response kernels obey the invariance constraint; once they are truncated it fixes
     # the sign of the operator on the non-invariant remainder)
     energy_zero: str = "none"
+    # atom numbering: "placement" (the order atoms were drawn in) or "morton" (along a
+    # Z-order space-filling curve of their positions, as linear-scaling codes number atoms
+    # so that nearby atoms have nearby indices and the sparse matrices cluster near their
+    # diagonal)
+    order: str = "placement"
 
     @property
     def h(self) -> float:
@@ -177,6 +183,16 @@ def _place_atoms(cfg: Config, rng: np.random.Generator) -> np.ndarray:
         pos[n] = p
         n += 1
     return pos
+
+
+def _morton_order(pos: np.ndarray, L: float) -> np.ndarray:
+    """Permutation that sorts positions along a Z-order curve (10 bits per axis)."""
+    q = np.clip((pos / L * 1024).astype(np.int64), 0, 1023)
+    code = np.zeros(len(pos), dtype=np.int64)
+    for b in range(10):
+        for d in range(3):
+            code |= ((q[:, d] >> b) & 1) << (3 * b + d)
+    return np.argsort(code, kind="stable")
 
 
 def _box(center: float, radius: float, h: float, N: int):
@@ -325,6 +341,10 @@ def _build(cfg: Config, seed: int) -> System:
     h, N = cfg.h, cfg.N
     nA = cfg.n_atoms
     pos = _place_atoms(cfg, rng_geo)
+    if cfg.order == "morton":
+        pos = pos[_morton_order(pos, cfg.L)]
+    elif cfg.order != "placement":
+        raise ValueError(f"unknown atom order {cfg.order!r}")
     nf = cfg.n_o + cfg.n_u
     origins = np.zeros((nA, 3), dtype=np.int64)
     extents = np.zeros((nA, 3), dtype=np.int64)
