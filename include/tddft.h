@@ -259,6 +259,19 @@ int64_t tddft_apply_noalloc_limit(void);
 int tddft_pcg_solve(tddft_handle *h, int32_t n_states, const tddft_options *opts,
                     double *omega, double *Pp, double *Pq, tddft_stats *stats);
 
+/* Oscillator strengths of converged excitations in the velocity form (the line strengths
+ * listed with the excitation energies in Sec. IV.A, Table tab:azo, and broadened into the
+ * spectra of Sec. IV.B; the paper prints no formula, and in a periodic cell the position
+ * operator has no matrix elements between the functions):
+ *   f_n = 2 / (3 omega_n) sum_alpha D_n,alpha^2,   D_n,alpha = sum_ab P^p_n,ab G^alpha_ab,
+ *   G^alpha_ab = h^3 sum_r u_a(r) (d_alpha o_b)(r)
+ * with d_alpha the second-order central difference on the periodic grid (G is built once
+ * by tddft_create, FP64) and P^p_n = X_n - Y_n Tsiper-normalised, <p_n, q_n> = 1, as
+ * tddft_pcg_solve returns them.  omega: HOST [n_states]; Pp: DEVICE [n_states][tddft_nnz_p]
+ * FP64; f: HOST [n_states] out; moments: HOST [n_states][3] out (D_n, x y z) or NULL. */
+int tddft_oscillator_strengths(tddft_handle *h, int32_t n_states, const double *omega,
+                               const double *Pp, double *f, double *moments);
+
 /* Solves of several systems at once (a work queue over systems): up to max_workers host
  * threads (0 = one per system, at most 16) each take the next unsolved system and run
  * tddft_pcg_solve on it on a private non-blocking stream of the handle's GPU, so the

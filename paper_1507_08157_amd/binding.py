@@ -92,7 +92,7 @@ EXPORTS = ("tddft_default_options", "tddft_create", "tddft_nnz_p", "tddft_respon
            "tddft_mlp_get_params", "tddft_mlp_fit_normalisation", "tddft_mlp_forward",
            "tddft_mlp_train_step", "tddft_mlp_export", "tddft_mlp_import",
            "tddft_mlp_last_error", "tddft_pcg_solve_batched", "tddft_apply_noalloc",
-           "tddft_apply_noalloc_limit")
+           "tddft_apply_noalloc_limit", "tddft_oscillator_strengths")
 
 
 def lib():
@@ -159,6 +159,7 @@ def lib():
                 ("tddft_mlp_last_error", [vp], C.c_char_p),
                 ("tddft_apply_noalloc", [vp, C.c_int32, vp, vp, vp, vp], C.c_int),
                 ("tddft_apply_noalloc_limit", [], C.c_int64),
+                ("tddft_oscillator_strengths", [vp, C.c_int32, _f64p, vp, _f64p, _f64p], C.c_int),
                 ("tddft_pcg_solve_batched", [C.POINTER(C.c_void_p), C.c_int32, _i32p,
                                              C.POINTER(tddft_options), C.POINTER(_f64p),
                                              C.POINTER(C.c_void_p), C.POINTER(C.c_void_p),
@@ -298,6 +299,18 @@ class Handle:
         if rc != TDDFT_OK:
             raise self._err(rc)
         return fp, fq
+
+    def tddft_oscillator_strengths(self, omega, Pp):
+        """(f [n], transition moments [n, 3]) of converged vectors Pp (device tensor)."""
+        w = np.ascontiguousarray(omega, dtype=np.float64)
+        n = len(w)
+        f = np.zeros(n)
+        D = np.zeros((n, 3))
+        rc = lib().tddft_oscillator_strengths(self._h, n, _ptr(w, C.c_double), _dev(Pp, "Pp"),
+                                              _ptr(f, C.c_double), _ptr(D, C.c_double))
+        if rc != TDDFT_OK:
+            raise self._err(rc)
+        return f, D
 
     def tddft_project(self, L, P=None):
         """Pi(L) (Eq. auxiliary) for device tensors [n_states, nnz_p] FP64."""

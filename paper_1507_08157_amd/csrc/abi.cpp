@@ -256,6 +256,23 @@ int tddft_apply_noalloc(tddft_handle *hd, int32_t n, const double *Pp, const dou
 
 int64_t tddft_apply_noalloc_limit(void) { return (int64_t)scratch_capacity(); }
 
+int tddft_oscillator_strengths(tddft_handle *hd, int32_t n, const double *omega, const double *Pp,
+                               double *f, double *moments) {
+  if (!hd) return TDDFT_E_INVALID;
+  Handle &h = hd->h;
+  h.last_error.clear();
+  if (n < 1 || n > 32 || !omega || !Pp || !f) {
+    h.last_error = "tddft_oscillator_strengths: n_states in [1, 32], omega, Pp and f non-null";
+    return TDDFT_E_INVALID;
+  }
+  for (int i = 0; i < n; ++i)
+    if (!(omega[i] > 0.0)) {
+      h.last_error = "tddft_oscillator_strengths: excitation energies must be positive";
+      return TDDFT_E_INVALID;
+    }
+  return guarded(h.last_error, [&] { oscillator_strengths(h, n, omega, Pp, f, moments); });
+}
+
 int tddft_pcg_solve(tddft_handle *hd, int32_t n, const tddft_options *opts, double *omega,
                     double *Pp, double *Pq, tddft_stats *stats) {
   if (!hd) return TDDFT_E_INVALID;

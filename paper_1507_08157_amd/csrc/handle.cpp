@@ -409,6 +409,7 @@ void create_handle(Handle &h, const tddft_system &sys, const tddft_options &o) {
   }
 
   build_features(h, Su, Hu, So, Ho, sys);
+  build_gradient_integrals(h, sys.vir, sys.occ);
 
   // ---- functions and tiles
   HostSetTiles tu = build_set_tiles(sys.vir, h.uoff, h.BU, h.n, h.geom.ntx, h.geom.nty, h.geom.ntz);

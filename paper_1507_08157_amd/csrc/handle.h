@@ -100,6 +100,10 @@ struct Handle {
   std::vector<int64_t> r_voff_host;
   std::vector<int32_t> r_shape_host;
 
+  // gradient integrals G^alpha_ab = <u_a| d_alpha |o_b> on R (C-ABI layout, alpha-major),
+  // for the oscillator strengths
+  DevBuf<double> grad_uo;
+
   // ground state
   DevBuf<double> fxc64;
   DevBuf<float> fxc32;
@@ -158,6 +162,10 @@ void project_t_sets(Handle &h, int ncol, const T *X, int ldx, int x0, T *F, int 
 
 int pcg_solve(Handle &h, int n, const tddft_options &o, double *omega, double *Pp, double *Pq,
               tddft_stats *stats);
+// oscillator strengths, velocity form (spectra.hip)
+void build_gradient_integrals(Handle &h, const tddft_functions &vir, const tddft_functions &occ);
+void oscillator_strengths(Handle &h, int n, const double *omega, const double *Pp, double *f,
+                          double *moments);
 // Eq. precond by CG in the S metric for n states in the C-ABI layout (complete M)
 void precondition(Handle &h, int n, const double *g, double *G, double eps_tol, int max_inner);
 
