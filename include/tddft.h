@@ -137,6 +137,10 @@ typedef struct {
                                 constraint then holds only approximately, Sec. III.A after
                                 Eq. auxiliary); 0: R is the pattern the exact product
                                 reaches from M.  Fixed at tddft_create */
+  int32_t  graphs;           /* 1 (default): a solve captures each distinct operator
+                                application (its kernels on the handle's two streams) in a
+                                HIP graph once and replays it; 0: direct launches.  Results
+                                are identical either way */
 } tddft_options;
 
 /* Per-solve statistics (host memory, caller-owned).  The log arrays are optional. */
@@ -154,6 +158,7 @@ typedef struct {
   double *log_omega;         /* [log_capacity * n_states] ascending omega per iteration */
   double *log_time_ms;       /* [log_capacity] wall time since solve entry              */
   double *log_gnorm;         /* [log_capacity] max_i ||g_i||_S                          */
+  int32_t graph_replays;     /* operator applications replayed from captured HIP graphs */
 } tddft_stats;
 
 /* Sizes of the structures a handle built (for work and traffic accounting). */
@@ -188,7 +193,7 @@ typedef struct tddft_handle tddft_handle;
 
 /* Defaults: FP64, ALDA exchange, rho_floor 1e-10, coupling 1, KSDIFF_CG, eps_tol 1e-4,
  * tol_omega 1e-7, max_iter 300, max_inner 50, refresh 10, restart 20, seed 0, eps_loose 0,
- * tda 0, truncate_p 0. */
+ * tda 0, truncate_p 0, graphs 1. */
 void tddft_default_options(tddft_options *opts);
 
 /* Build a handle for one system (Sec. III.A: sparse K^v, K^c, S and H, the cutoff

@@ -54,7 +54,7 @@ class tddft_options(C.Structure):
                 ("max_inner", C.c_int32), ("refresh", C.c_int32), ("restart", C.c_int32),
                 ("seed", C.c_uint64), ("model", C.c_void_p), ("model_bytes", C.c_int64),
                 ("stream", C.c_void_p), ("eps_loose", C.c_double), ("tda", C.c_int32),
-                ("truncate_p", C.c_int32)]
+                ("truncate_p", C.c_int32), ("graphs", C.c_int32)]
 
 
 class tddft_info(C.Structure):
@@ -77,7 +77,7 @@ class tddft_stats(C.Structure):
                 ("inner_total", C.c_int32), ("applies", C.c_int32), ("fallbacks", C.c_int32),
                 ("setup_ms", C.c_double), ("solve_ms", C.c_double), ("apply_ms", C.c_double),
                 ("log_capacity", C.c_int32), ("log_len", C.c_int32), ("log_omega", _f64p),
-                ("log_time_ms", _f64p), ("log_gnorm", _f64p)]
+                ("log_time_ms", _f64p), ("log_gnorm", _f64p), ("graph_replays", C.c_int32)]
 
 
 _LIB = None
@@ -407,7 +407,8 @@ class Handle:
         k = st.log_len
         stats = dict(iterations=st.iterations, converged=bool(st.converged),
                      inner_total=st.inner_total, applies=st.applies, fallbacks=st.fallbacks,
-                     setup_ms=st.setup_ms, solve_ms=st.solve_ms, apply_ms=st.apply_ms)
+                     setup_ms=st.setup_ms, solve_ms=st.solve_ms, apply_ms=st.apply_ms,
+                     graph_replays=st.graph_replays)
         if log_capacity:
             stats["log_omega"] = logs["omega"][:k * n_states].reshape(k, n_states)
             stats["log_time_ms"] = logs["t"][:k]
@@ -441,7 +442,8 @@ def tddft_pcg_solve_batched(handles, n_states, options=None, Pp=None, Pq=None,
         out.append((omegas[k], int(status[k]),
                     dict(iterations=s.iterations, converged=bool(s.converged),
                          inner_total=s.inner_total, applies=s.applies, fallbacks=s.fallbacks,
-                         setup_ms=s.setup_ms, solve_ms=s.solve_ms, apply_ms=s.apply_ms)))
+                         setup_ms=s.setup_ms, solve_ms=s.solve_ms, apply_ms=s.apply_ms,
+                         graph_replays=s.graph_replays)))
     return out
 
 

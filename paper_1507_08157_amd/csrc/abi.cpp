@@ -79,6 +79,7 @@ void tddft_default_options(tddft_options *o) {
   o->eps_loose = 0.0;
   o->tda = 0;
   o->truncate_p = 0;
+  o->graphs = 1;
 }
 
 int tddft_abi_version(void) { return TDDFT_ABI_VERSION; }
@@ -307,6 +308,22 @@ int tddft_pcg_solve(tddft_handle *hd, int32_t n, const tddft_options *opts, doub
     if (os != h.stream) {
       TD_HIP(hipEventRecord(h.ev_fork, os));
       TD_HIP(hipStreamWaitEvent(h.stream, h.ev_fork, 0));
+    }
+    // graph capture needs a stream other than the legacy default one: a handle on the
+    // default stream solves on a private non-blocking stream ordered after it (the solve
+    // returns only once its stream has finished)
+    if (h.stream == nullptr && o.graphs) {
+      if (!h.solve_stream) TD_HIP(hipStreamCreateWithFlags(&h.solve_stream, hipStreamNonBlocking));
+      TD_HIP(hipEventRecord(h.ev_fork, nullptr));
+      TD_HIP(hipStreamWaitEvent(h.solve_stream, h.ev_fork, 0));
+      struct Swap {
+        Handle &h;
+        ~Swap() { h.stream = nullptr; }
+      } swap{h};
+      h.stream = h.solve_stream;
+      const int rc = pcg_solve(h, n, o, omega, Pp, Pq, stats);
+      TD_HIP(hipStreamSynchronize(h.solve_stream));
+      return rc;
     }
     return pcg_solve(h, n, o, omega, Pp, Pq, stats);
   } catch (const Error &e) {

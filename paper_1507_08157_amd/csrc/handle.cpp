@@ -16,6 +16,7 @@ Handle::~Handle() {
   if (ev_fork) (void)hipEventDestroy(ev_fork);
   if (ev_join) (void)hipEventDestroy(ev_join);
   if (side) (void)hipStreamDestroy(side);
+  if (solve_stream) (void)hipStreamDestroy(solve_stream);
 }
 
 const void *Handle::usamp() const {

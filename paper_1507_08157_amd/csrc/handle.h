@@ -118,6 +118,8 @@ struct Handle {
   // second stream of the handle: the K-shift products of an application run there beside
   // the grid pipeline of the coupling term (fork and join through ev_fork / ev_join)
   hipStream_t side = nullptr;
+  // private stream of solves on a handle created on the default stream (graph capture)
+  hipStream_t solve_stream = nullptr;
   hipEvent_t ev_fork = nullptr, ev_join = nullptr;
 
   // timing

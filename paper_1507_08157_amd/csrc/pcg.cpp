@@ -483,10 +483,67 @@ static int solve_impl(Handle &h, int n, const tddft_options &o, double *omega, d
     TD_HIP(hipStreamSynchronize(s));
   }
   float apply_ms = 0.0f;
-  auto apply = [&](const T *X, T *Fo) {
-    TD_HIP(hipEventRecord(h.ev0, s));
+  // Operator applications replay HIP graphs: the sets a solve applies the operator to
+  // (trial vectors, directions) keep their addresses for the whole solve, so each (X, F)
+  // pair is captured once (all of its launches, the K-shift products' fork to the handle's
+  // second stream included) and replayed afterwards.  Profiling runs stay direct launches
+  // (their events are recorded between stages), as does any capture the runtime refuses.
+  struct Captured {
+    const T *X;
+    T *F;
+    hipGraphExec_t exec;
+  };
+  std::vector<Captured> graphs;
+  struct GraphGuard {
+    std::vector<Captured> &g;
+    ~GraphGuard() {
+      for (auto &c : g) (void)hipGraphExecDestroy(c.exec);
+    }
+  } graph_guard{graphs};
+  bool use_graphs = o.graphs != 0 && !h.prof.on;
+  auto launch_apply = [&](const T *X, T *Fo) {
     // Tamm-Dancoff: p and q hold the same vectors throughout (same start, same updates)
     apply_sets<T>(h, n, X, nc, 0, n, Fo, nc, 0, n, true, h.opts.tda != 0);
+  };
+  int graph_replays = 0;
+  auto apply_graph = [&](const T *X, T *Fo) -> bool {
+    for (auto &c : graphs)
+      if (c.X == X && c.F == Fo) {
+        TD_HIP(hipGraphLaunch(c.exec, s));
+        ++graph_replays;
+        return true;
+      }
+    // the workspace is sized before capture, so no allocation happens inside it
+    (void)h.w_apply.get(apply_layout(h, n, sizeof(T)).total);
+    if (hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+      (void)hipGetLastError();
+      return false;
+    }
+    bool ok = true;
+    try {
+      launch_apply(X, Fo);
+    } catch (const Error &) {
+      ok = false;
+    }
+    hipGraph_t g = nullptr;
+    const hipError_t ec = hipStreamEndCapture(s, &g);
+    hipGraphExec_t ex = nullptr;
+    if (ok && ec == hipSuccess && g && hipGraphInstantiate(&ex, g, nullptr, nullptr, 0) == hipSuccess) {
+      (void)hipGraphDestroy(g);
+      graphs.push_back({X, Fo, ex});
+      TD_HIP(hipGraphLaunch(ex, s));
+      return true;
+    }
+    if (g) (void)hipGraphDestroy(g);
+    (void)hipGetLastError();
+    return false;
+  };
+  auto apply = [&](const T *X, T *Fo) {
+    TD_HIP(hipEventRecord(h.ev0, s));
+    if (!(use_graphs && apply_graph(X, Fo))) {
+      use_graphs = false;
+      launch_apply(X, Fo);
+    }
     TD_HIP(hipEventRecord(h.ev1, s));
     TD_HIP(hipEventSynchronize(h.ev1));
     float ms = 0.0f;
@@ -881,6 +938,7 @@ static int solve_impl(Handle &h, int n, const tddft_options &o, double *omega, d
     st->converged = converged ? 1 : 0;
     st->inner_total = inner_total;
     st->applies = applies;
+    st->graph_replays = graph_replays;
     st->fallbacks = fallbacks;
     st->setup_ms = h.setup_ms;
     st->solve_ms = elapsed_ms();

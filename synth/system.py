@@ -318,12 +318,13 @@ def _mcweeny(K, S, atom_mask, b, steps):
     return K
 
 
-def build_system(cfg: Config, max_tries: int = 8) -> System:
-    """Build a system; redraw with seed+1 if too few u-states lie above the threshold."""
+def build_system(cfg: Config, max_tries: int = 8, progress=None) -> System:
+    """Build a system; redraw with seed+1 if too few u-states lie above the threshold.
+    progress(msg), if given, is called as the stages of a build complete."""
     last = None
     for t in range(max_tries):
         try:
-            sysm = _build(cfg, cfg.seed + t)
+            sysm = _build(cfg, cfg.seed + t, progress)
             sysm.tries = t
             return sysm
         except _NotEnoughStates as e:
@@ -335,7 +336,10 @@ class _NotEnoughStates(Exception):
     pass
 
 
-def _build(cfg: Config, seed: int) -> System:
+def _build(cfg: Config, seed: int, progress=None) -> System:
+    def report(msg):
+        if progress is not None:
+            progress(f"{cfg.name}: {msg}")
     ss = np.random.SeedSequence(seed).spawn(4)
     rng_geo, rng_fn, rng_well = (np.random.default_rng(s) for s in ss[:3])
     h, N = cfg.h, cfg.N
@@ -355,6 +359,7 @@ def _build(cfg: Config, seed: int) -> System:
         allv.append(v)
     depth = rng_well.uniform(cfg.depth_lo, cfg.depth_hi, nA)
     Vw = _well_potential(cfg, pos, depth)
+    report(f"{nA} atoms, functions and wells on the {N}^3 grid")
 
     # H f on each atom box
     Hv = []
@@ -370,7 +375,10 @@ def _build(cfg: Config, seed: int) -> System:
     S = np.zeros((nA * nf, nA * nf))
     H = np.zeros((nA * nf, nA * nf))
     h3 = h ** 3
+    quarter = max(1, nA // 4)
     for I in range(nA):
+        if I and I % quarter == 0:
+            report(f"overlap and Hamiltonian integrals of {I} of {nA} atoms")
         for J in np.nonzero(dist[I] <= reach)[0]:
             if J < I:
                 continue
@@ -397,6 +405,7 @@ def _build(cfg: Config, seed: int) -> System:
     S_u, H_u = S[np.ix_(u_sel, u_sel)], H[np.ix_(u_sel, u_sel)]
     S_uo = S[np.ix_(u_sel, o_sel)]
 
+    report("integrals done")
     eps_o, B = scipy.linalg.eigh(H_o, S_o)
     occ_idx = np.arange(cfg.n_occ)
     homo = eps_o[cfg.n_occ - 1]

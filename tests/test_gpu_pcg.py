@@ -170,3 +170,16 @@ def test_pcg_adaptive_inner_tolerance(name, request):
     w, rc, st, _, _ = _solve(s, tol_omega=1e-10, eps_loose=0.1)
     assert st["converged"]
     assert np.max(np.abs(w - Casida(s).omega_hermitian()[:s.cfg.n_states])) < 1e-9
+
+
+@pytest.mark.parametrize("name", ["small_dense", "small_kt"])
+def test_pcg_graph_replay_is_identical(name, request):
+    """Operator applications replayed from captured HIP graphs give bit-identical
+    trajectories to direct launches (same kernels, same order of every sum)."""
+    s = request.getfixturevalue(name)
+    wg, rcg, stg, _, _ = _solve(s, precision="fp32", tol_omega=1e-9, max_iter=60, graphs=1)
+    wd, rcd, std, _, _ = _solve(s, precision="fp32", tol_omega=1e-9, max_iter=60, graphs=0)
+    assert stg["graph_replays"] > 0 and std["graph_replays"] == 0
+    assert stg["iterations"] == std["iterations"]
+    assert np.array_equal(stg["log_omega"], std["log_omega"])
+    assert np.array_equal(wg, wd)
