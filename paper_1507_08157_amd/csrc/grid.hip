@@ -412,6 +412,133 @@ __global__ __launch_bounds__(256) void k_vint_mfma(DevTiles tl, const int64_t *_
   }
 }
 
+// BF16 variant on BF16 MFMA (v_mfma_f32_16x16x32_bf16, FP32 accumulation): the u-row
+// fragments are the stored BF16 samples themselves (32 contiguous bytes per lane), and the
+// (o-row, state) operand w = o_b V_s is formed in FP32 from the staged o-rows and
+// potentials and rounded to BF16 (nearest even) once.  Each MFMA contracts 32 points; lane
+// group q supplies points 16 q + 8 t + e (e = 0..7) in call t = 0, 1 for both operands, so
+// two calls cover the tile's 64 points.  Everything else as in k_vint_mfma.
+typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
+
+template <int BL, int BR>
+__global__ __launch_bounds__(256) void k_vint_mfma_bf16(DevTiles tl, const int64_t *__restrict__ tbase,
+                                                        const __hip_bfloat16 *__restrict__ usamp,
+                                                        const __hip_bfloat16 *__restrict__ osamp,
+                                                        const float *__restrict__ V, int64_t pair_stride,
+                                                        int ns, float *__restrict__ partial, float scale) {
+  extern __shared__ unsigned char lds_raw[];
+  constexpr int LD = TP + 4;
+  constexpr int MG = 2;
+  const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  const int t = blockIdx.x * (blockDim.x >> 6) + w;
+  float *lo = reinterpret_cast<float *>(lds_raw) + (size_t)w * (tl.maxrows_r + ns) * LD;
+  float *lv = lo + (size_t)tl.maxrows_r * LD;
+  int u0 = 0, nua = 0, o0 = 0, noa = 0;
+  if (t < tl.nt) {
+    u0 = tl.uptr[t];
+    nua = tl.uptr[t + 1] - u0;
+    o0 = tl.optr[t];
+    noa = tl.optr[t + 1] - o0;
+  }
+  const int rows_u = nua * BL, rows_o = noa * BR;
+  const int items = rows_o * ns;
+  const int q = lane >> 4, c16 = lane & 15;
+  const __hip_bfloat16 *ut = usamp + (int64_t)u0 * BL * TP;
+  v8bf a[MG][2];
+  auto load_u = [&](int mg) {
+#pragma unroll
+    for (int mb = 0; mb < MG; ++mb) {
+      const int m = mg + mb * 16 + c16;
+      if (m < rows_u) {
+        const uint4 *src = reinterpret_cast<const uint4 *>(ut + (int64_t)m * TP + 16 * q);
+        a[mb][0] = __builtin_bit_cast(v8bf, src[0]);
+        a[mb][1] = __builtin_bit_cast(v8bf, src[1]);
+      } else {
+        a[mb][0] = __builtin_bit_cast(v8bf, make_uint4(0u, 0u, 0u, 0u));
+        a[mb][1] = a[mb][0];
+      }
+    }
+  };
+  load_u(0);
+  {
+    const __hip_bfloat16 *ot = osamp + (int64_t)o0 * BR * TP;
+    const float *vt = V + (int64_t)t * TP * 2;
+    const int n_o4 = rows_o * (TP / 4);
+    const int n_v2 = t < tl.nt ? ((ns + 1) / 2) * TP : 0;
+    for (int i0 = lane; i0 < n_o4 || i0 < n_v2; i0 += 4 * 64) {
+      float o4[4][4];
+      float2 v2[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int i = i0 + 64 * u;
+        if (i < n_o4) load4<float, __hip_bfloat16>(ot + 4 * i, o4[u]);
+        if (i < n_v2) {
+          const int sp = i / TP, p = i % TP;
+          v2[u] = *reinterpret_cast<const float2 *>(vt + (int64_t)sp * pair_stride + 2 * p);
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int i = i0 + 64 * u;
+        if (i < n_o4) {
+          float *d = lo + (i / (TP / 4)) * LD + 4 * (i % (TP / 4));
+          *reinterpret_cast<float4 *>(d) = make_float4(o4[u][0], o4[u][1], o4[u][2], o4[u][3]);
+        }
+        if (i < n_v2) {
+          const int sp = i / TP, p = i % TP;
+          lv[(2 * sp) * LD + p] = v2[u].x;
+          if (2 * sp + 1 < ns) lv[(2 * sp + 1) * LD + p] = v2[u].y;
+        }
+      }
+    }
+  }
+  __syncthreads();
+  if (t >= tl.nt) return;
+  float *dst = partial + tbase[t] * ns;
+  for (int mg = 0; mg < rows_u; mg += 16 * MG) {
+    if (mg > 0) load_u(mg);
+    for (int n0 = 0; n0 < items; n0 += 16) {
+      const int n = n0 + c16;
+      const bool active = n < items;
+      const int b = active ? n / ns : 0;
+      const int sidx = active ? n - (n / ns) * ns : 0;
+      v8bf bf[2];
+      {
+        const float *orow = lo + b * LD + 16 * q;
+        const float *vrow = lv + sidx * LD + 16 * q;
+#pragma unroll
+        for (int k = 0; k < 16; k += 4) {
+          const float4 o4 = *reinterpret_cast<const float4 *>(orow + k);
+          const float4 v4 = *reinterpret_cast<const float4 *>(vrow + k);
+          bf[k >> 3][(k & 7)] = (__bf16)(active ? o4.x * v4.x : 0.0f);
+          bf[k >> 3][(k & 7) + 1] = (__bf16)(active ? o4.y * v4.y : 0.0f);
+          bf[k >> 3][(k & 7) + 2] = (__bf16)(active ? o4.z * v4.z : 0.0f);
+          bf[k >> 3][(k & 7) + 3] = (__bf16)(active ? o4.w * v4.w : 0.0f);
+        }
+      }
+#pragma unroll
+      for (int mb = 0; mb < MG; ++mb) {
+        if (mg + mb * 16 >= rows_u) break;
+        v4f acc = {0.0f, 0.0f, 0.0f, 0.0f};
+        acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[mb][0], bf[0], acc, 0, 0, 0);
+        acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[mb][1], bf[1], acc, 0, 0, 0);
+        if (active) {
+          const int jo = b / BR, c = b - (b / BR) * BR;
+#pragma unroll
+          for (int j = 0; j < 4; ++j) {
+            const int m = mg + mb * 16 + 4 * q + j;
+            if (m < rows_u) {
+              const int io = m / BL, r = m - (m / BL) * BL;
+              dst[((((int64_t)io * noa + jo) * BL + r) * BR + c) * ns + sidx] = scale * acc[j];
+            }
+          }
+        }
+      }
+    }
+  }
+}
+
 // Vout[ob][ldv][E] (columns 0..ns) = sum over the contributions of block ob.  Each
 // contribution is a contiguous run of per = E * ns partial sums, read as per / V vectors
 // of V elements.  One wave per overlap block: when a run needs at most 64 lanes, the wave
@@ -532,7 +659,10 @@ void potential_integrals(const DevTiles &tl, const DevPartials &pa, int stype, i
   if constexpr (std::is_same<T, float>::value) {
     const size_t lds = 4 * (size_t)(tl.maxrows_r + ns) * (TP + 4) * sizeof(float);
     if (lds > tl.lds_limit) throw Error{TDDFT_E_INVALID, "too many functions per grid tile for the LDS budget"};
-    TD_SAMPLE(T, stype, TD_GRID_BDIM(BL, BR, hipLaunchKernelGGL((k_vint_mfma<S, BL, BR>), dim3(grid), dim3(256), lds, s, tl, pa.tbase, reinterpret_cast<const S *>(tl.usamp), reinterpret_cast<const S *>(tl.osamp), V, pair_stride, ns, partial, (float)scale)));
+    if (stype == SAMPLE_BF16)
+      TD_GRID_BDIM(BL, BR, hipLaunchKernelGGL((k_vint_mfma_bf16<BL, BR>), dim3(grid), dim3(256), lds, s, tl, pa.tbase, reinterpret_cast<const __hip_bfloat16 *>(tl.usamp), reinterpret_cast<const __hip_bfloat16 *>(tl.osamp), V, pair_stride, ns, partial, (float)scale));
+    else
+      TD_SAMPLE(T, stype, TD_GRID_BDIM(BL, BR, hipLaunchKernelGGL((k_vint_mfma<S, BL, BR>), dim3(grid), dim3(256), lds, s, tl, pa.tbase, reinterpret_cast<const S *>(tl.usamp), reinterpret_cast<const S *>(tl.osamp), V, pair_stride, ns, partial, (float)scale)));
   } else {
     TD_SAMPLE(T, stype, TD_GRID_BDIM(BL, BR, hipLaunchKernelGGL((k_vint<T, S, BL, BR>), dim3(grid), dim3(256), 0, s, tl, pa.tbase, reinterpret_cast<const S *>(tl.usamp), reinterpret_cast<const S *>(tl.osamp), V, pair_stride, ns, partial, (T)scale)));
   }
