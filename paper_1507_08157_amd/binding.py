@@ -54,7 +54,7 @@ class tddft_options(C.Structure):
                 ("max_inner", C.c_int32), ("refresh", C.c_int32), ("restart", C.c_int32),
                 ("seed", C.c_uint64), ("model", C.c_void_p), ("model_bytes", C.c_int64),
                 ("stream", C.c_void_p), ("eps_loose", C.c_double), ("tda", C.c_int32),
-                ("truncate_p", C.c_int32), ("graphs", C.c_int32)]
+                ("truncate_p", C.c_int32), ("graphs", C.c_int32), ("autotune", C.c_int32)]
 
 
 class tddft_info(C.Structure):
@@ -69,7 +69,8 @@ class tddft_info(C.Structure):
                 ("pairs_covariant", C.c_int64), ("pairs_sandwich", C.c_int64),
                 ("partial_pairs", C.c_int64), ("setup_ms", C.c_double),
                 ("samples_u_nz", C.c_int64), ("samples_o_nz", C.c_int64),
-                ("pair_points_nz", C.c_int64)]
+                ("pair_points_nz", C.c_int64), ("fft_threads", C.c_int32 * 3),
+                ("density_waves", C.c_int32), ("kshift_cw", C.c_int32 * 2)]
 
 
 class tddft_stats(C.Structure):
@@ -367,6 +368,8 @@ class Handle:
             raise self._err(rc)
         d = {k: getattr(inf, k) for k, _ in tddft_info._fields_}
         d["n"] = list(inf.n)
+        d["fft_threads"] = list(inf.fft_threads)
+        d["kshift_cw"] = list(inf.kshift_cw)
         return d
 
     def tddft_profile(self, enable: bool):

@@ -80,6 +80,7 @@ void tddft_default_options(tddft_options *o) {
   o->tda = 0;
   o->truncate_p = 0;
   o->graphs = 1;
+  o->autotune = 1;
 }
 
 int tddft_abi_version(void) { return TDDFT_ABI_VERSION; }
@@ -171,6 +172,10 @@ int tddft_get_info(const tddft_handle *hd, tddft_info *o) {
   o->samples_u_nz = h.samples_u_nz;
   o->samples_o_nz = h.samples_o_nz;
   o->pair_points_nz = h.pair_points_nz;
+  for (int d = 0; d < 3; ++d) o->fft_threads[d] = h.fft.nt[d];
+  o->density_waves = h.tiles_uo.waves;
+  o->kshift_cw[0] = h.pT_left.cw;
+  o->kshift_cw[1] = h.pT_right.cw;
   return TDDFT_OK;
 }
 

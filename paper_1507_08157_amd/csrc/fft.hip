@@ -506,20 +506,21 @@ __global__ __launch_bounds__(NT) void k_fft_x_inv(GeomDev g, AxisDev ax,
 // 256 its radix-8 passes would need two buffers, halving the workgroups a CU holds); 0 when
 // none does (a factor 7, or an axis longer than 1024 threads can cover), and then the pass
 // takes two buffers on 256 threads.
-static int axis_threads(const AxisFFT &a) {
+std::vector<int> fft_inplace_threads(const AxisFFT &a) {
+  std::vector<int> out;
   for (int nt : {256, 512, 1024}) {
     bool fits = true;
     for (int R : a.radix)
       if (R == 7 || 16 * (a.n / R) > (R >= 8 ? 1 : 8 / R) * nt) fits = false;
-    if (fits) return nt;
+    if (fits) out.push_back(nt);
   }
-  return 0;
+  return out;
 }
-static bool axis_inplace(const AxisFFT &a) { return axis_threads(a) > 0; }
 
-// LDS of one workgroup of an axis pass (line buffers of odd stride n + 1)
-static size_t axis_lds_bytes(const AxisFFT &a, int lines, size_t elem) {
-  return (axis_inplace(a) ? 1 : 2) * (size_t)lines * (a.n + 1) * elem;
+// LDS of one workgroup of an axis pass with `nt` threads (0: two buffers; line buffers of
+// odd stride n + 1)
+static size_t axis_lds_bytes(const AxisFFT &a, int nt, int lines, size_t elem) {
+  return (nt > 0 ? 1 : 2) * (size_t)lines * (a.n + 1) * elem;
 }
 
 #define TD_COMMA(x) , x
@@ -536,8 +537,9 @@ static size_t axis_lds_bytes(const AxisFFT &a, int lines, size_t elem) {
   } while (0)
 
 size_t fft_lds_bytes(const FFTPlan &plan, size_t elem) {
-  return std::max({axis_lds_bytes(plan.ax[0], 16, elem), axis_lds_bytes(plan.ax[1], XB, elem),
-                   axis_lds_bytes(plan.ax[2], XB, elem)});
+  return std::max({axis_lds_bytes(plan.ax[0], plan.nt[0], 16, elem),
+                   axis_lds_bytes(plan.ax[1], plan.nt[1], XB, elem),
+                   axis_lds_bytes(plan.ax[2], plan.nt[2], XB, elem)});
 }
 
 static AxisDev axis_dev(const AxisFFT &a) {
@@ -574,12 +576,12 @@ void hartree_xc(const GridGeom &gg, const FFTPlan &plan, int npair, T *fields, T
   const double scale = 4.0 * pi / ((double)gg.n[0] * gg.n[1] * gg.n[2]);
   const unsigned rows = (unsigned)(gg.nty * gg.ntz);
   const unsigned nxb = (unsigned)((gg.n[0] + XB - 1) / XB);
-  const size_t lx = axis_lds_bytes(plan.ax[0], 16, sizeof(T2));
-  const size_t ly = axis_lds_bytes(plan.ax[1], XB, sizeof(T2));
-  const size_t lz = axis_lds_bytes(plan.ax[2], XB, sizeof(T2));
+  const size_t lx = axis_lds_bytes(plan.ax[0], plan.nt[0], 16, sizeof(T2));
+  const size_t ly = axis_lds_bytes(plan.ax[1], plan.nt[1], XB, sizeof(T2));
+  const size_t lz = axis_lds_bytes(plan.ax[2], plan.nt[2], XB, sizeof(T2));
   Prof dummy;
   Prof &pf = prof ? *prof : dummy;
-  const int tx = axis_threads(plan.ax[0]), ty = axis_threads(plan.ax[1]), tz = axis_threads(plan.ax[2]);
+  const int tx = plan.nt[0], ty = plan.nt[1], tz = plan.nt[2];
   pf.begin(ST_FFT_X_FWD, s);
   TD_FFT_LAUNCH(k_fft_x_fwd, T, tx, dim3(rows, npair), lx, s, g, ax, tw + off[0], F, W);
   TD_HIP(hipGetLastError());

@@ -90,7 +90,7 @@ __device__ __forceinline__ void density_chunk(const int32_t *__restrict__ pid, i
 }
 
 template <class T, class S, int BL, int BR, int NSC>
-__global__ __launch_bounds__(256) void k_density(DevTiles tl, const S *__restrict__ usamp,
+__global__ __launch_bounds__(512) void k_density(DevTiles tl, const S *__restrict__ usamp,
                                                  const S *__restrict__ osamp,
                                                  const int32_t *__restrict__ pidx,
                                                  const T *__restrict__ X, int ldx, int xc0, int ns,
@@ -636,7 +636,7 @@ template <class T>
 void density(const DevTiles &tl, int stype, int BL, int BR, const T *X, int ldx, int xc0, int ns,
              T *out, int64_t pair_stride, double scale, hipStream_t s) {
   if (tl.nt == 0 || ns == 0) return;
-  const int waves = 4;
+  const int waves = tl.waves;
   const size_t lds = 0;
   const unsigned grid = (unsigned)((tl.nt + waves - 1) / waves);
   if (ns <= 2)

@@ -566,6 +566,7 @@ void create_handle(Handle &h, const tddft_system &sys, const tddft_options &o) {
     h.os64.release();
     h.tiles_oo.usamp = h.tiles_oo.osamp = nullptr;
   }
+  if (o.autotune) autotune(h);
   h.setup_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
 }
 

@@ -164,6 +164,9 @@ void project_t_sets(Handle &h, int ncol, const T *X, int ldx, int x0, T *F, int 
 
 int pcg_solve(Handle &h, int n, const tddft_options &o, double *omega, double *Pp, double *Pq,
               tddft_stats *stats);
+// launch-shape autotuner (tune.cpp): FFT threads per axis, density waves, sparse-product
+// columns per thread, timed on the handle's data at creation
+void autotune(Handle &h);
 // oscillator strengths, velocity form (spectra.hip)
 void build_gradient_integrals(Handle &h, const tddft_functions &vir, const tddft_functions &occ);
 void oscillator_strengths(Handle &h, int n, const double *omega, const double *Pp, double *f,

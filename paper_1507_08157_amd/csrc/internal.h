@@ -111,6 +111,7 @@ HostBsr host_transpose(const HostBsr &A);
 struct DevPlan {
   int64_t nout = 0, npairs = 0;
   int di = 0, dk = 0, dj = 0;    // complete patterns (see Plan)
+  int cw = 1;                    // columns per thread of the sparse form (1, 2 or 4; tuned)
   DevBuf<int64_t> ptr;
   DevBuf<int2> pairs;
   void upload(const Plan &p, hipStream_t s);
@@ -141,6 +142,10 @@ struct AxisFFT {
 
 struct FFTPlan {
   AxisFFT ax[3];                   // x, y, z
+  // threads per workgroup of each axis's passes: 256, 512 or 1024 in place (one LDS
+  // buffer), 0 for the two-buffer form on 256 threads; set by build_fft_plan to the
+  // smallest in-place count that fits, possibly changed by the tuner
+  int nt[3] = {0, 0, 0};
   DevBuf<double> tw64;             // [sum tw_len] complex interleaved (re, im)
   DevBuf<float> tw32;
 };

@@ -80,6 +80,7 @@ struct DevTiles {
   const int32_t *pidx = nullptr;                    // pair -> block index (or -1)
   const void *usamp = nullptr, *osamp = nullptr;    // rows of TP samples
   size_t lds_limit = 65536;                          // device LDS bytes per workgroup
+  int waves = 4;                                     // density: tiles (waves) per workgroup
 };
 
 // Per-tile partial sums of the potential integrals ([function pair][state], tiles in order,
@@ -127,5 +128,8 @@ void hartree_xc(const GridGeom &g, const FFTPlan &plan, int npair, T *fields, T 
 
 // largest LDS request of the FFT passes for complex values of `elem` bytes
 size_t fft_lds_bytes(const FFTPlan &plan, size_t elem);
+// thread counts per workgroup with which an axis's passes run in place (ascending; empty
+// when none), and the default choice
+std::vector<int> fft_inplace_threads(const AxisFFT &a);
 
 }  // namespace tddft

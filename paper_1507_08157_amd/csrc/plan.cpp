@@ -224,6 +224,8 @@ void build_fft_plan(FFTPlan &pl, const int n[3], hipStream_t s) {
     }
     a.tw_len = len;
     tw.insert(tw.end(), axis.begin(), axis.end());
+    const std::vector<int> ip = fft_inplace_threads(a);
+    pl.nt[d] = ip.empty() ? 0 : ip.front();
   }
   pl.tw64.upload(tw, s);
   std::vector<float> twf(tw.begin(), tw.end());

@@ -387,12 +387,16 @@ void spmm_left(const DevPlan &pl, int bu, int bo, const T *A, const T *X, int ld
     TD_HIP(hipGetLastError());
     return;
   }
-  constexpr int CW = 1;   // one column per thread: grouping columns measured slower here
-  const int64_t n = pl.nout * ((ncol + CW - 1) / CW);
-  TD_BDIM_DISPATCH(bu, bo, hipLaunchKernelGGL((k_spmm_left<T, BU, BO, CW>), dim3(nblocks(n, 256)),
-                                              dim3(256), 0, s, pl.nout, ncol, pl.ptr.p,
-                                              pl.pairs.p, A, X, ldx, xc0, C, ldc, cc0, alpha,
-                                              acc ? 1 : 0));
+  // columns per thread from the plan (tuned at creation; the sum over pairs has the same
+  // order for every choice)
+  const int cw = pl.cw;
+  const int64_t n = pl.nout * ((ncol + cw - 1) / cw);
+  if (cw == 4)
+    TD_BDIM_DISPATCH(bu, bo, hipLaunchKernelGGL((k_spmm_left<T, BU, BO, 4>), dim3(nblocks(n, 256)), dim3(256), 0, s, pl.nout, ncol, pl.ptr.p, pl.pairs.p, A, X, ldx, xc0, C, ldc, cc0, alpha, acc ? 1 : 0));
+  else if (cw == 2)
+    TD_BDIM_DISPATCH(bu, bo, hipLaunchKernelGGL((k_spmm_left<T, BU, BO, 2>), dim3(nblocks(n, 256)), dim3(256), 0, s, pl.nout, ncol, pl.ptr.p, pl.pairs.p, A, X, ldx, xc0, C, ldc, cc0, alpha, acc ? 1 : 0));
+  else
+    TD_BDIM_DISPATCH(bu, bo, hipLaunchKernelGGL((k_spmm_left<T, BU, BO, 1>), dim3(nblocks(n, 256)), dim3(256), 0, s, pl.nout, ncol, pl.ptr.p, pl.pairs.p, A, X, ldx, xc0, C, ldc, cc0, alpha, acc ? 1 : 0));
   TD_HIP(hipGetLastError());
 }
 
@@ -409,12 +413,14 @@ void spmm_right(const DevPlan &pl, int bu, int bo, const T *X, int ldx, int xc0,
     TD_HIP(hipGetLastError());
     return;
   }
-  constexpr int CW = 1;   // one column per thread: grouping columns measured slower here
-  const int64_t n = pl.nout * ((ncol + CW - 1) / CW);
-  TD_BDIM_DISPATCH(bu, bo, hipLaunchKernelGGL((k_spmm_right<T, BU, BO, CW>), dim3(nblocks(n, 256)),
-                                              dim3(256), 0, s, pl.nout, ncol, pl.ptr.p,
-                                              pl.pairs.p, X, ldx, xc0, B, C, ldc, cc0, alpha,
-                                              acc ? 1 : 0));
+  const int cw = pl.cw;
+  const int64_t n = pl.nout * ((ncol + cw - 1) / cw);
+  if (cw == 4)
+    TD_BDIM_DISPATCH(bu, bo, hipLaunchKernelGGL((k_spmm_right<T, BU, BO, 4>), dim3(nblocks(n, 256)), dim3(256), 0, s, pl.nout, ncol, pl.ptr.p, pl.pairs.p, X, ldx, xc0, B, C, ldc, cc0, alpha, acc ? 1 : 0));
+  else if (cw == 2)
+    TD_BDIM_DISPATCH(bu, bo, hipLaunchKernelGGL((k_spmm_right<T, BU, BO, 2>), dim3(nblocks(n, 256)), dim3(256), 0, s, pl.nout, ncol, pl.ptr.p, pl.pairs.p, X, ldx, xc0, B, C, ldc, cc0, alpha, acc ? 1 : 0));
+  else
+    TD_BDIM_DISPATCH(bu, bo, hipLaunchKernelGGL((k_spmm_right<T, BU, BO, 1>), dim3(nblocks(n, 256)), dim3(256), 0, s, pl.nout, ncol, pl.ptr.p, pl.pairs.p, X, ldx, xc0, B, C, ldc, cc0, alpha, acc ? 1 : 0));
   TD_HIP(hipGetLastError());
 }
 

@@ -165,3 +165,26 @@ def test_info_counts_nonzero_work(small_kt):
     assert info["samples_o_nz"] == int(no.sum())
     assert info["pair_points_nz"] == int((nu.astype(np.int64) * no).sum())
     assert info["pair_points"] >= info["pair_points_nz"]
+
+
+@pytest.mark.parametrize("name,precision", [("small_kt", "fp32"), ("small_trunc", "fp64"),
+                                            ("small_dense", "bf16")])
+def test_autotuned_launch_shapes_give_identical_results(name, precision, request):
+    """The launch shapes the creation-time tuner picks (FFT threads per axis, density tiles
+    per workgroup, sparse-product columns per thread) change no arithmetic: the apply is
+    bit-identical to the fixed defaults."""
+    s = request.getfixturevalue(name)
+    print(f"[apply] autotune {name} {precision}", flush=True)
+    Pp = to_dev(sabi.dense_to_p(s, random_p(s, 4, 61)))
+    Pq = to_dev(sabi.dense_to_p(s, random_p(s, 4, 62)))
+    out = {}
+    for tune in (0, 1):
+        h = gpu_handle(s, precision=precision, autotune=tune)
+        info = h.tddft_get_info()
+        fp, fq = h.tddft_apply(Pp, Pq)
+        out[tune] = (fp.cpu().numpy(), fq.cpu().numpy(), info)
+        h.close()
+    assert np.array_equal(out[0][0], out[1][0]) and np.array_equal(out[0][1], out[1][1])
+    info = out[1][2]
+    assert all(t in (0, 256, 512, 1024) for t in info["fft_threads"])
+    assert info["density_waves"] in (2, 4, 8) and all(c in (1, 2, 4) for c in info["kshift_cw"])
