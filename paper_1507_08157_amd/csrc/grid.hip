@@ -70,21 +70,39 @@ __device__ __forceinline__ void load2<double, __hip_bfloat16>(const __hip_bfloat
 template <class T, class S, int NS, int BL, int BR, int JC, bool FULL>
 __device__ __forceinline__ void density_chunk(const int32_t *__restrict__ pid, int nj,
                                               const T *__restrict__ X, int64_t xoff, int ldx,
-                                              int nk, const T (&o)[JC][BR], T (&tmp)[NS][BL]) {
+                                              const T *__restrict__ zero, int nk,
+                                              const T (&o)[JC][BR], T (&tmp)[NS][BL]) {
   constexpr int E = BL * BR;
+  // The chunk's block indices arrive in one batch of scalar loads (the pair table carries
+  // padding past its end, so all JC are readable), then each pair costs one round trip for
+  // its P block; a pair with no P block reads the zero block.
+  int pbs[JC];
+#pragma unroll
+  for (int j = 0; j < JC; ++j) pbs[j] = pid[j];
 #pragma unroll
   for (int j = 0; j < JC; ++j) {
     if (j >= nj) break;
-    const int pb = pid[j];
-    if (pb < 0) continue;
-    const T *Pj = X + ((int64_t)pb * ldx) * E + xoff;
+    const int pb = pbs[j];
+    const T *Pj = pb >= 0 ? X + ((int64_t)pb * ldx) * E + xoff : zero;
+    if constexpr (FULL) {
+      T pv[NS * E];
 #pragma unroll
-    for (int k = 0; k < NS; ++k) {
-      if (!FULL && k >= nk) break;
+      for (int q = 0; q < NS * E; ++q) pv[q] = Pj[q];
 #pragma unroll
-      for (int r = 0; r < BL; ++r)
+      for (int k = 0; k < NS; ++k)
 #pragma unroll
-        for (int c = 0; c < BR; ++c) tmp[k][r] += Pj[k * E + r * BR + c] * o[j][c];
+        for (int r = 0; r < BL; ++r)
+#pragma unroll
+          for (int c = 0; c < BR; ++c) tmp[k][r] += pv[k * E + r * BR + c] * o[j][c];
+    } else {
+#pragma unroll
+      for (int k = 0; k < NS; ++k) {
+        if (k >= nk) break;
+#pragma unroll
+        for (int r = 0; r < BL; ++r)
+#pragma unroll
+          for (int c = 0; c < BR; ++c) tmp[k][r] += Pj[k * E + r * BR + c] * o[j][c];
+      }
     }
   }
 }
@@ -105,6 +123,7 @@ __global__ __launch_bounds__(512) void k_density(DevTiles tl, const S *__restric
   constexpr int NS = NSf < NSC ? NSf : NSC;
   // o-atoms per register chunk: 8 x BR rows in FP32, 4 x BR in FP64
   constexpr int JC = sizeof(T) == 8 ? 4 : 8;
+  static_assert(NS * BL * BR * sizeof(T) <= kZeroBlock * sizeof(double), "zero block too small");
   const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
   const int t = blockIdx.x * (blockDim.x >> 6) + w;
@@ -114,6 +133,7 @@ __global__ __launch_bounds__(512) void k_density(DevTiles tl, const S *__restric
   const S *os = osamp + (int64_t)o0 * BR * TP;
   using T2 = typename Vec2<T>::type;
   const int32_t *pid = pidx + tl.pptr[t];
+  const T *zero = reinterpret_cast<const T *>(tl.zero);
   for (int s0 = 0; s0 < ns; s0 += NS) {
     const int nk = min(NS, ns - s0);
     const int64_t xoff = (int64_t)(xc0 + s0) * BL * BR;
@@ -150,9 +170,9 @@ __global__ __launch_bounds__(512) void k_density(DevTiles tl, const S *__restric
 #pragma unroll
           for (int r = 0; r < BL; ++r) tmp[k][r] = T(0);
         if (nk == NS)
-          density_chunk<T, S, NS, BL, BR, JC, true>(pid + i * noa + j0, nj, X, xoff, ldx, nk, o, tmp);
+          density_chunk<T, S, NS, BL, BR, JC, true>(pid + i * noa + j0, nj, X, xoff, ldx, zero, nk, o, tmp);
         else
-          density_chunk<T, S, NS, BL, BR, JC, false>(pid + i * noa + j0, nj, X, xoff, ldx, nk, o, tmp);
+          density_chunk<T, S, NS, BL, BR, JC, false>(pid + i * noa + j0, nj, X, xoff, ldx, zero, nk, o, tmp);
 #pragma unroll
         for (int r = 0; r < BL; ++r)
 #pragma unroll

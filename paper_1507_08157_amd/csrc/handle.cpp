@@ -442,6 +442,8 @@ void create_handle(Handle &h, const tddft_system &sys, const tddft_options &o) {
     pptr_uo[t + 1] = (int64_t)pidx_uo.size();
     pptr_oo[t + 1] = (int64_t)pidx_oo.size();
   }
+  pidx_uo.insert(pidx_uo.end(), kPairPad, -1);
+  pidx_oo.insert(pidx_oo.end(), kPairPad, -1);
   h.pair_points = pp * TP;
   h.sample_rows_u = (int64_t)tu.ptr[nt] * h.BU;
   h.sample_rows_o = (int64_t)to.ptr[nt] * h.BO;
@@ -499,10 +501,14 @@ void create_handle(Handle &h, const tddft_system &sys, const tddft_options &o) {
     upload_bf16(h.us16, tu.samples, s);
     upload_bf16(h.os16, to.samples, s);
   }
+  const std::vector<double> zeros(kZeroBlock, 0.0);
+  h.zero_block.upload(zeros, s);
+  TD_HIP(hipStreamSynchronize(s));
   h.tiles_uo = DevTiles{nt, h.maxrows_uo, maxpairs_uo, maxrows_r, h.t_uptr.p, h.t_optr.p,
                         h.t_pptr_uo.p, h.t_pidx_uo.p, h.usamp(), h.osamp(), h.lds_limit};
   h.tiles_oo = DevTiles{nt, h.maxrows_oo, maxpairs_oo, maxrows_r, h.t_optr.p, h.t_optr.p,
                         h.t_pptr_oo.p, h.t_pidx_oo.p, h.os64.p, h.os64.p, h.lds_limit};
+  h.tiles_uo.zero = h.tiles_oo.zero = h.zero_block.p;
   TD_REQUIRE((size_t)maxrows_r * TP * sizeof(double) <= h.lds_limit,
              "too many functions per grid tile for the LDS budget");
 

@@ -69,6 +69,12 @@ template <class T>
 void gather_blocks(int64_t nout, int blk_elems, const int32_t *map, const T *X, T *Y, hipStream_t s);
 
 // ---- grid ----------------------------------------------------------------------------------
+// entries of -1 after the end of a tile set's pair table, so that a kernel may read a few
+// indices past a tile's last pair without a bounds test
+constexpr int kPairPad = 16;
+// doubles in the zero block that stands in for a missing P block (NS * BL * BR values of the
+// density's widest pass, at most 48)
+constexpr int kZeroBlock = 64;
 // device view of a tile set (lists and sample rows of two function sets)
 struct DevTiles {
   int nt = 0;
@@ -77,10 +83,13 @@ struct DevTiles {
   int maxrows_r = 0;        // max over tiles of n_right_atoms * BR
   const int32_t *uptr = nullptr, *optr = nullptr;   // [nt + 1]
   const int64_t *pptr = nullptr;                    // [nt + 1]
-  const int32_t *pidx = nullptr;                    // pair -> block index (or -1)
+  const int32_t *pidx = nullptr;                    // pair -> block index (or -1), followed
+                                                    // by kPairPad entries of -1
   const void *usamp = nullptr, *osamp = nullptr;    // rows of TP samples
   size_t lds_limit = 65536;                          // device LDS bytes per workgroup
   int waves = 4;                                     // density: tiles (waves) per workgroup
+  const void *zero = nullptr;                        // kZeroBlock zeros (the block read for
+                                                     // a pair with no P block)
 };
 
 // Per-tile partial sums of the potential integrals ([function pair][state], tiles in order,
