@@ -165,6 +165,29 @@ struct HostSetTiles {
   int B = 0;
 };
 
+// Tiles (raster numbering x fastest) listed along a Z-order curve of their coordinates:
+// consecutive entries are spatial neighbours, so the waves in flight share atom pairs and
+// their P blocks stay in cache.
+static std::vector<int32_t> tile_order(int ntx, int nty, int ntz) {
+  const int64_t nt = (int64_t)ntx * nty * ntz;
+  auto spread = [](uint64_t v) {  // bits of v at every third position
+    uint64_t r = 0;
+    for (int b = 0; b < 21; ++b) r |= ((v >> b) & 1ull) << (3 * b);
+    return r;
+  };
+  std::vector<std::pair<uint64_t, int32_t>> key((size_t)nt);
+  for (int z = 0; z < ntz; ++z)
+    for (int y = 0; y < nty; ++y)
+      for (int x = 0; x < ntx; ++x) {
+        const int32_t t = x + ntx * (y + nty * z);
+        key[t] = {spread(x) | (spread(y) << 1) | (spread(z) << 2), t};
+      }
+  std::sort(key.begin(), key.end());
+  std::vector<int32_t> order((size_t)nt);
+  for (int64_t k = 0; k < nt; ++k) order[k] = key[k].second;
+  return order;
+}
+
 static HostSetTiles build_set_tiles(const tddft_functions &fs, const std::vector<int> &off,
                                     int B, const int n[3], int ntx, int nty, int ntz) {
   const int nt = ntx * nty * ntz;
@@ -503,12 +526,15 @@ void create_handle(Handle &h, const tddft_system &sys, const tddft_options &o) {
   }
   const std::vector<double> zeros(kZeroBlock, 0.0);
   h.zero_block.upload(zeros, s);
+  const std::vector<int32_t> order = tile_order(h.geom.ntx, h.geom.nty, h.geom.ntz);
+  h.t_order.upload(order, s);
   TD_HIP(hipStreamSynchronize(s));
   h.tiles_uo = DevTiles{nt, h.maxrows_uo, maxpairs_uo, maxrows_r, h.t_uptr.p, h.t_optr.p,
                         h.t_pptr_uo.p, h.t_pidx_uo.p, h.usamp(), h.osamp(), h.lds_limit};
   h.tiles_oo = DevTiles{nt, h.maxrows_oo, maxpairs_oo, maxrows_r, h.t_optr.p, h.t_optr.p,
                         h.t_pptr_oo.p, h.t_pidx_oo.p, h.os64.p, h.os64.p, h.lds_limit};
   h.tiles_uo.zero = h.tiles_oo.zero = h.zero_block.p;
+  h.tiles_uo.order = h.tiles_oo.order = h.t_order.p;
   TD_REQUIRE((size_t)maxrows_r * TP * sizeof(double) <= h.lds_limit,
              "too many functions per grid tile for the LDS budget");
 

@@ -80,6 +80,7 @@ struct Handle {
   // tiles and partial-sum tables
   DevBuf<int32_t> t_uptr, t_optr, t_pidx_uo, t_pidx_oo;
   DevBuf<double> zero_block;   // kZeroBlock zeros
+  DevBuf<int32_t> t_order;     // tiles along a Z-order curve of their coordinates
   DevBuf<int64_t> t_pptr_uo, t_pptr_oo;
   DevBuf<double> us64, os64;
   DevBuf<float> us32, os32;

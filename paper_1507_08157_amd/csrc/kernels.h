@@ -90,6 +90,8 @@ struct DevTiles {
   int waves = 4;                                     // density: tiles (waves) per workgroup
   const void *zero = nullptr;                        // kZeroBlock zeros (the block read for
                                                      // a pair with no P block)
+  const int32_t *order = nullptr;                    // [nt] density: tiles in processing
+                                                     // order (Z-order of tile coordinates)
 };
 
 // Per-tile partial sums of the potential integrals ([function pair][state], tiles in order,
