@@ -126,11 +126,9 @@ __global__ __launch_bounds__(512) void k_density(DevTiles tl, const S *__restric
   static_assert(NS * BL * BR * sizeof(T) <= kZeroBlock * sizeof(double), "zero block too small");
   const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
-  // Workgroups are dispatched round-robin over the 8 XCDs; XCD x takes the x-th eighth of
-  // the Z-ordered tile list, so each XCD's L2 holds the P blocks of one compact region.
-  const int G = gridDim.x, b = blockIdx.x, xcd = b & 7, per = G >> 3, rem = G & 7;
-  const int L = xcd * per + min(xcd, rem) + (b >> 3);
-  const int lt = L * (blockDim.x >> 6) + w;
+  // each XCD takes one contiguous eighth of the Z-ordered tile list, so its L2 holds the P
+  // blocks of one compact region
+  const int lt = xcd_block(blockIdx.x, gridDim.x) * (blockDim.x >> 6) + w;
   if (lt >= tl.nt) return;
   const int t = tl.order[lt];
   const int u0 = tl.uptr[t], nua = tl.uptr[t + 1] - u0;

@@ -14,6 +14,14 @@ __host__ __device__ inline uint32_t div_magic(int d) {
 }
 #ifdef __HIPCC__
 __device__ __forceinline__ uint32_t fdiv(uint32_t q, uint32_t m) { return m ? __umulhi(q, m) : q; }
+
+// Workgroups are dispatched round-robin over the chip's 8 XCDs, each with its own L2.  This
+// renumbers workgroup b of G so that XCD x runs the x-th contiguous eighth of [0, G): work
+// items that are neighbours in the numbering (and share operands) then meet in one L2.
+__device__ __forceinline__ int xcd_block(int b, int G) {
+  const int x = b & 7, per = G >> 3, rem = G & 7;
+  return x * per + min(x, rem) + (b >> 3);
+}
 #endif
 
 // ---- column-set linear combinations ------------------------------------------------------
