@@ -148,6 +148,11 @@ typedef struct {
                                 the fastest; choices are remembered per process for
                                 systems of the same shapes.  No choice changes a result.
                                 0: fixed defaults */
+  int32_t  density_pbcast;   /* -1 (default): the tuner's choice (scalar P when autotune
+                                is 0); 0: the response density keeps P blocks in scalar
+                                registers; 1: in vector registers shared by DPP row
+                                broadcasts (FP32 and BF16-sample handles; FP64 always
+                                takes 0).  Results are identical either way */
 } tddft_options;
 
 /* Per-solve statistics (host memory, caller-owned).  The log arrays are optional. */
@@ -194,16 +199,19 @@ typedef struct {
   int64_t pair_points_nz;    /* sum over grid points of (u-functions nonzero there) x
                                 (o-functions nonzero there): the method's own work unit of
                                 the response density and the potential integrals          */
-  int32_t fft_threads[3];    /* launch shapes in use (see tddft_options.autotune): FFT    */
-  int32_t density_waves;     /* threads per workgroup per axis (0 = two-buffer form),     */
-  int32_t kshift_cw[2];      /* density tiles per workgroup, K-shift columns per thread   */
+  /* launch shapes in use (see tddft_options.autotune) */
+  int32_t fft_threads[3];    /* FFT threads per workgroup per axis (0 = two-buffer form)  */
+  int32_t density_waves;     /* response density: tiles per workgroup                    */
+  int32_t kshift_cw[2];      /* K-shift products: columns per thread (left, right)       */
+  int32_t density_pbcast;    /* response density (FP32): 1 = P blocks in vector registers
+                                shared by DPP row broadcasts, 0 = P in scalar registers   */
 } tddft_info;
 
 typedef struct tddft_handle tddft_handle;
 
 /* Defaults: FP64, ALDA exchange, rho_floor 1e-10, coupling 1, KSDIFF_CG, eps_tol 1e-4,
  * tol_omega 1e-7, max_iter 300, max_inner 50, refresh 10, restart 20, seed 0, eps_loose 0,
- * tda 0, truncate_p 0, graphs 1, autotune 1. */
+ * tda 0, truncate_p 0, graphs 1, autotune 1, density_pbcast -1. */
 void tddft_default_options(tddft_options *opts);
 
 /* Build a handle for one system (Sec. III.A: sparse K^v, K^c, S and H, the cutoff

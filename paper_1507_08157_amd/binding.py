@@ -54,7 +54,8 @@ class tddft_options(C.Structure):
                 ("max_inner", C.c_int32), ("refresh", C.c_int32), ("restart", C.c_int32),
                 ("seed", C.c_uint64), ("model", C.c_void_p), ("model_bytes", C.c_int64),
                 ("stream", C.c_void_p), ("eps_loose", C.c_double), ("tda", C.c_int32),
-                ("truncate_p", C.c_int32), ("graphs", C.c_int32), ("autotune", C.c_int32)]
+                ("truncate_p", C.c_int32), ("graphs", C.c_int32), ("autotune", C.c_int32),
+                ("density_pbcast", C.c_int32)]
 
 
 class tddft_info(C.Structure):
@@ -70,7 +71,8 @@ class tddft_info(C.Structure):
                 ("partial_pairs", C.c_int64), ("setup_ms", C.c_double),
                 ("samples_u_nz", C.c_int64), ("samples_o_nz", C.c_int64),
                 ("pair_points_nz", C.c_int64), ("fft_threads", C.c_int32 * 3),
-                ("density_waves", C.c_int32), ("kshift_cw", C.c_int32 * 2)]
+                ("density_waves", C.c_int32), ("kshift_cw", C.c_int32 * 2),
+                ("density_pbcast", C.c_int32)]
 
 
 class tddft_stats(C.Structure):

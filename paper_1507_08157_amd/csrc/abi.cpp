@@ -81,6 +81,7 @@ void tddft_default_options(tddft_options *o) {
   o->truncate_p = 0;
   o->graphs = 1;
   o->autotune = 1;
+  o->density_pbcast = -1;
 }
 
 int tddft_abi_version(void) { return TDDFT_ABI_VERSION; }
@@ -176,6 +177,7 @@ int tddft_get_info(const tddft_handle *hd, tddft_info *o) {
   o->density_waves = h.tiles_uo.waves;
   o->kshift_cw[0] = h.pT_left.cw;
   o->kshift_cw[1] = h.pT_right.cw;
+  o->density_pbcast = h.tiles_uo.pbcast;
   return TDDFT_OK;
 }
 

@@ -16,6 +16,7 @@
 // imaginary part of field k, so the Hartree FFT transforms two states at once.
 #include <algorithm>
 #include <type_traits>
+#include <utility>
 
 #include "internal.h"
 #include "kernels.h"
@@ -107,7 +108,62 @@ __device__ __forceinline__ void density_chunk(const int32_t *__restrict__ pid, i
   }
 }
 
-template <class T, class S, int BL, int BR, int NSC>
+// FP32 pair loop with P in vector registers.  Every 16-lane row of the wave loads the same
+// NS * BL * BR values of a P block, value q in lane q % 16 of register q / 16, and each FMA
+// takes its P factor from lane q % 16 of its own row by a DPP row broadcast (row_newbcast),
+// so the P operand costs no extra instruction.  The loads are vector loads, which complete
+// in order: the P blocks of all pairs of the chunk are requested before the first FMA,
+// where the scalar form waits for each block in turn.  A DPP read needs its source register
+// written by a load, not by an ALU instruction, in the two cycles before it; the P registers
+// are only ever written by loads.
+template <int K>
+__device__ __forceinline__ void fmac_row_bcast(float &acc, float v, float o) {
+  asm("v_fmac_f32_dpp %0, %1, %2 row_newbcast:%3 row_mask:0xf bank_mask:0xf"
+      : "+v"(acc) : "v"(v), "v"(o), "n"(K));
+}
+
+template <int NS, int BL, int BR, int JC, int NV, int Q0, int... Q>
+__device__ __forceinline__ void bcast_pair(std::integer_sequence<int, Q...>, const float (&pv)[NV],
+                                           const float (&o)[BR], float (&tmp)[NS][BL]) {
+  constexpr int E = BL * BR;
+  (fmac_row_bcast<(Q0 + Q) % 16>(tmp[(Q0 + Q) / E][((Q0 + Q) % E) / BR], pv[(Q0 + Q) / 16],
+                                 o[(Q0 + Q) % BR]), ...);
+}
+
+template <int NS, int BL, int BR, int JC>
+__device__ __forceinline__ void density_chunk_bcast(const int32_t *__restrict__ pid, int nj,
+                                                    const float *__restrict__ X, int64_t xoff,
+                                                    int ldx, const float *__restrict__ zero,
+                                                    int l16, const float (&o)[JC][BR],
+                                                    float (&tmp)[NS][BL]) {
+  constexpr int E = BL * BR, Q = NS * E, NV = (Q + 15) / 16;
+  int pbs[JC];
+#pragma unroll
+  for (int j = 0; j < JC; ++j) pbs[j] = pid[j];
+  // lane l16 of a row holds values l16, 16 + l16, ...; lanes past the block's end repeat
+  // its last value (never broadcast), so every load stays inside the block
+  int qi[NV];
+#pragma unroll
+  for (int v = 0; v < NV; ++v) qi[v] = min(16 * v + l16, Q - 1);
+  // all JC blocks requested in one straight run (pairs past the chunk's end read the zero
+  // block), so the wait before pair j's FMAs counts only the loads issued after it
+  float pv[JC][NV];
+#pragma unroll
+  for (int j = 0; j < JC; ++j) {
+    const float *Pj = j < nj && pbs[j] >= 0 ? X + ((int64_t)pbs[j] * ldx) * E + xoff : zero;
+#pragma unroll
+    for (int v = 0; v < NV; ++v) pv[j][v] = Pj[qi[v]];
+  }
+  // keeps the compiler from sinking each pair's loads down to its FMAs
+  asm volatile("" ::: "memory");
+#pragma unroll
+  for (int j = 0; j < JC; ++j) {
+    if (j >= nj) break;
+    bcast_pair<NS, BL, BR, JC, NV, 0>(std::make_integer_sequence<int, Q>{}, pv[j], o[j], tmp);
+  }
+}
+
+template <class T, class S, int BL, int BR, int NSC, bool PB>
 __global__ __launch_bounds__(512) void k_density(DevTiles tl, const S *__restrict__ usamp,
                                                  const S *__restrict__ osamp,
                                                  const int32_t *__restrict__ pidx,
@@ -172,7 +228,12 @@ __global__ __launch_bounds__(512) void k_density(DevTiles tl, const S *__restric
         for (int k = 0; k < NS; ++k)
 #pragma unroll
           for (int r = 0; r < BL; ++r) tmp[k][r] = T(0);
-        if (nk == NS)
+        if constexpr (PB) {
+          if (nk == NS)
+            density_chunk_bcast<NS, BL, BR, JC>(pid + i * noa + j0, nj, X, xoff, ldx, zero, lane & 15, o, tmp);
+          else
+            density_chunk<T, S, NS, BL, BR, JC, false>(pid + i * noa + j0, nj, X, xoff, ldx, zero, nk, o, tmp);
+        } else if (nk == NS)
           density_chunk<T, S, NS, BL, BR, JC, true>(pid + i * noa + j0, nj, X, xoff, ldx, zero, nk, o, tmp);
         else
           density_chunk<T, S, NS, BL, BR, JC, false>(pid + i * noa + j0, nj, X, xoff, ldx, zero, nk, o, tmp);
@@ -662,12 +723,22 @@ void density(const DevTiles &tl, int stype, int BL, int BR, const T *X, int ldx,
   const int waves = tl.waves;
   const size_t lds = 0;
   const unsigned grid = (unsigned)((tl.nt + waves - 1) / waves);
-  if (ns <= 2)
-    TD_SAMPLE(T, stype, TD_GRID_BDIM(BL, BR, hipLaunchKernelGGL((k_density<T, S, BL, BR, 2>), dim3(grid), dim3(64 * waves), lds, s, tl, reinterpret_cast<const S *>(tl.usamp), reinterpret_cast<const S *>(tl.osamp), tl.pidx, X, ldx, xc0, ns, out, pair_stride, (T)scale)));
-  else if (ns <= 4)
-    TD_SAMPLE(T, stype, TD_GRID_BDIM(BL, BR, hipLaunchKernelGGL((k_density<T, S, BL, BR, 4>), dim3(grid), dim3(64 * waves), lds, s, tl, reinterpret_cast<const S *>(tl.usamp), reinterpret_cast<const S *>(tl.osamp), tl.pidx, X, ldx, xc0, ns, out, pair_stride, (T)scale)));
-  else
-    TD_SAMPLE(T, stype, TD_GRID_BDIM(BL, BR, hipLaunchKernelGGL((k_density<T, S, BL, BR, 8>), dim3(grid), dim3(64 * waves), lds, s, tl, reinterpret_cast<const S *>(tl.usamp), reinterpret_cast<const S *>(tl.osamp), tl.pidx, X, ldx, xc0, ns, out, pair_stride, (T)scale)));
+#define TD_DENSITY_LAUNCH(NSC_, PB_) \
+  TD_SAMPLE(T, stype, TD_GRID_BDIM(BL, BR, hipLaunchKernelGGL((k_density<T, S, BL, BR, NSC_, PB_>), dim3(grid), dim3(64 * waves), lds, s, tl, reinterpret_cast<const S *>(tl.usamp), reinterpret_cast<const S *>(tl.osamp), tl.pidx, X, ldx, xc0, ns, out, pair_stride, (T)scale)))
+  bool bcast = false;
+  if constexpr (std::is_same<T, float>::value) bcast = tl.pbcast != 0;
+  if (bcast) {
+    if constexpr (std::is_same<T, float>::value) {
+      if (ns <= 2) TD_DENSITY_LAUNCH(2, true);
+      else if (ns <= 4) TD_DENSITY_LAUNCH(4, true);
+      else TD_DENSITY_LAUNCH(8, true);
+    }
+  } else {
+    if (ns <= 2) TD_DENSITY_LAUNCH(2, false);
+    else if (ns <= 4) TD_DENSITY_LAUNCH(4, false);
+    else TD_DENSITY_LAUNCH(8, false);
+  }
+#undef TD_DENSITY_LAUNCH
   TD_HIP(hipGetLastError());
 }
 

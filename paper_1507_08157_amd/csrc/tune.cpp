@@ -4,7 +4,8 @@
 // that decide it, so that handles of like systems reuse the choice without timing:
 //   * FFT passes: threads per workgroup of each axis (256, 512 or 1024 in place, or the
 //     two-buffer form), per axis from the stage times of the five passes;
-//   * response density: tiles (waves) per workgroup, 2, 4 or 8;
+//   * response density: tiles (waves) per workgroup, 2, 4 or 8, and (FP32) P blocks in
+//     scalar registers or in vector registers shared by DPP row broadcasts;
 //   * sparse products: columns per thread, 1, 2 or 4, per product plan.
 // No candidate changes an arithmetic operation or the order of any sum, so results are the
 // same whatever is chosen.
@@ -124,21 +125,26 @@ void tune_typed(Handle &h) {
     std::vector<int> choice;
     if (!cached(k.str(), choice)) {
       float best = 1e30f;
-      int pick = tl.waves;
-      for (int wv : {2, 4, 8}) {
-        tl.waves = wv;
-        const float ms = best_ms(s, h.ev0, h.ev1, 3, [&]() {
-          density<T>(tl, st, h.BU, h.BO, X, nc, n, n, fields, pstride, 1.0, s);
-        });
-        if (ms < best) {
-          best = ms;
-          pick = wv;
+      choice = {tl.waves, tl.pbcast};
+      const bool fp32 = std::is_same<T, float>::value;
+      for (int pb : {0, 1}) {
+        if (pb && !fp32) continue;
+        for (int wv : {2, 4, 8}) {
+          tl.waves = wv;
+          tl.pbcast = pb;
+          const float ms = best_ms(s, h.ev0, h.ev1, 3, [&]() {
+            density<T>(tl, st, h.BU, h.BO, X, nc, n, n, fields, pstride, 1.0, s);
+          });
+          if (ms < best) {
+            best = ms;
+            choice = {wv, pb};
+          }
         }
       }
-      choice = {pick};
       remember(k.str(), choice);
     }
     h.tiles_uo.waves = choice[0];
+    h.tiles_uo.pbcast = choice[1];
   }
 
   // ---- sparse products: columns per thread, per plan

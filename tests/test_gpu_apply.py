@@ -188,3 +188,32 @@ def test_autotuned_launch_shapes_give_identical_results(name, precision, request
     info = out[1][2]
     assert all(t in (0, 256, 512, 1024) for t in info["fft_threads"])
     assert info["density_waves"] in (2, 4, 8) and all(c in (1, 2, 4) for c in info["kshift_cw"])
+    assert info["density_pbcast"] in ((0,) if precision == "fp64" else (0, 1))
+
+
+@pytest.mark.parametrize("name,precision", [("small_kt", "fp32"), ("small_odd", "fp32"),
+                                            ("small_joint", "fp32"), ("small_crowded", "fp32"),
+                                            ("small_dense", "bf16")])
+def test_density_p_forms_are_identical(name, precision):
+    """The response density keeps a pass's P block either in scalar registers or in vector
+    registers read through DPP row broadcasts; both run the same FMAs in the same order, so
+    applies are bit-identical (the scalar form is the one the parity tests pin), over the
+    block shapes 3x2 (small_kt), the odd-sized grid, 5x2 (joint u-set) and crowded tiles."""
+    from conftest import cached_system
+    s = cached_system(name)
+    print(f"[apply] density P forms {name} {precision}", flush=True)
+    Pp = to_dev(sabi.dense_to_p(s, random_p(s, 4, 71)))
+    Pq = to_dev(sabi.dense_to_p(s, random_p(s, 4, 72)))
+    out = {}
+    for form in (0, 1):
+        h = gpu_handle(s, precision=precision, density_pbcast=form)
+        assert h.tddft_get_info()["density_pbcast"] == form
+        fp, fq = h.tddft_apply(Pp, Pq)
+        out[form] = (fp.cpu().numpy(), fq.cpu().numpy())
+        # 2 states (the two-state kernel) and 3 (a pass with fewer states than its kernel)
+        for m in (2, 3):
+            fpm, fqm = h.tddft_apply(Pp[:m].contiguous(), Pq[:m].contiguous())
+            out[form] += (fpm.cpu().numpy(), fqm.cpu().numpy())
+        h.close()
+    for a, b in zip(out[0], out[1]):
+        assert np.array_equal(a, b)
