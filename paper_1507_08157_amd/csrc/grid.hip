@@ -131,15 +131,13 @@ __device__ __forceinline__ void bcast_pair(std::integer_sequence<int, Q...>, con
 }
 
 template <int NS, int BL, int BR, int JC>
-__device__ __forceinline__ void density_chunk_bcast(const int32_t *__restrict__ pid, int nj,
-                                                    const float *__restrict__ X, int64_t xoff,
-                                                    int ldx, const float *__restrict__ zero,
-                                                    int l16, const float (&o)[JC][BR],
+__device__ __forceinline__ void density_chunk_bcast(int (&pbs)[JC], const int32_t *__restrict__ pid_next,
+                                                    int nj, const float *__restrict__ X,
+                                                    int64_t xoff, int ldx,
+                                                    const float *__restrict__ zero, int l16,
+                                                    const float (&o)[JC][BR],
                                                     float (&tmp)[NS][BL]) {
   constexpr int E = BL * BR, Q = NS * E, NV = (Q + 15) / 16;
-  int pbs[JC];
-#pragma unroll
-  for (int j = 0; j < JC; ++j) pbs[j] = pid[j];
   // lane l16 of a row holds values l16, 16 + l16, ...; lanes past the block's end repeat
   // its last value (never broadcast), so every load stays inside the block
   int qi[NV];
@@ -154,7 +152,12 @@ __device__ __forceinline__ void density_chunk_bcast(const int32_t *__restrict__ 
 #pragma unroll
     for (int v = 0; v < NV; ++v) pv[j][v] = Pj[qi[v]];
   }
-  // keeps the compiler from sinking each pair's loads down to its FMAs
+  // the next left atom's block indices are in flight during this atom's FMAs
+  if (pid_next) {
+#pragma unroll
+    for (int j = 0; j < JC; ++j) pbs[j] = pid_next[j];
+  }
+  // keeps the compiler from sinking the loads down to their first use
   asm volatile("" ::: "memory");
 #pragma unroll
   for (int j = 0; j < JC; ++j) {
@@ -215,6 +218,15 @@ __global__ __launch_bounds__(512) void k_density(DevTiles tl, const S *__restric
 #pragma unroll
         for (int r = 0; r < BL; ++r) un[r] = us[r * TP];
       }
+      // block indices of the first left atom's pairs (the bcast form requests each next
+      // atom's indices during the current atom's FMAs; the table is padded past its end)
+      int pbs[JC];
+      if constexpr (PB) {
+        if (nk == NS && nua > 0) {
+#pragma unroll
+          for (int j = 0; j < JC; ++j) pbs[j] = pid[j0 + j];
+        }
+      }
       for (int i = 0; i < nua; ++i) {
         T u[BL];
 #pragma unroll
@@ -230,7 +242,8 @@ __global__ __launch_bounds__(512) void k_density(DevTiles tl, const S *__restric
           for (int r = 0; r < BL; ++r) tmp[k][r] = T(0);
         if constexpr (PB) {
           if (nk == NS)
-            density_chunk_bcast<NS, BL, BR, JC>(pid + i * noa + j0, nj, X, xoff, ldx, zero, lane & 15, o, tmp);
+            density_chunk_bcast<NS, BL, BR, JC>(pbs, i + 1 < nua ? pid + (i + 1) * noa + j0 : nullptr,
+                                                nj, X, xoff, ldx, zero, lane & 15, o, tmp);
           else
             density_chunk<T, S, NS, BL, BR, JC, false>(pid + i * noa + j0, nj, X, xoff, ldx, zero, nk, o, tmp);
         } else if (nk == NS)
