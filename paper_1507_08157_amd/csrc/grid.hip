@@ -204,12 +204,18 @@ __global__ __launch_bounds__(512) void k_density(DevTiles tl, const S *__restric
     for (int k = 0; k < NS; ++k) acc[k] = T(0);
     for (int j0 = 0; j0 < noa; j0 += JC) {
       const int nj = min(JC, noa - j0);
+      // the chunk's o-rows in one run of loads (rows past the chunk's end re-read its last
+      // row and are zeroed after conversion), so a chunk costs one memory round trip
+      S oraw[JC][BR];
+#pragma unroll
+      for (int j = 0; j < JC; ++j)
+#pragma unroll
+        for (int c = 0; c < BR; ++c) oraw[j][c] = os[((j0 + min(j, nj - 1)) * BR + c) * TP + lane];
       T o[JC][BR];
 #pragma unroll
       for (int j = 0; j < JC; ++j)
 #pragma unroll
-        for (int c = 0; c < BR; ++c)
-          o[j][c] = j < nj ? cvt<T>(os[((j0 + j) * BR + c) * TP + lane]) : T(0);
+        for (int c = 0; c < BR; ++c) o[j][c] = j < nj ? cvt<T>(oraw[j][c]) : T(0);
       // u-rows of the next left atom are requested before this atom's pair loop, so their
       // round trip overlaps the scalar loads and FMAs of the pairs
       const S *us = usamp + ((int64_t)u0 * BL) * TP + lane;
