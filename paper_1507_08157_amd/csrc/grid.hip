@@ -382,6 +382,15 @@ __global__ __launch_bounds__(256) void k_vint(DevTiles tl, const int64_t *__rest
 // (o-row, state) blocks stream by.
 typedef float v4f __attribute__((ext_vector_type(4)));
 
+// Each wave stages into and reads back from its own LDS region only, so after staging it
+// waits for its own LDS writes (and keeps the compiler from hoisting the reads above them)
+// instead of meeting the workgroup's other waves at a barrier.
+__device__ __forceinline__ void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+}
+
 template <class S>
 __device__ __forceinline__ void load16(const S *p, float (&o)[16]) {
 #pragma unroll
@@ -468,7 +477,7 @@ __global__ __launch_bounds__(256) void k_vint_mfma(DevTiles tl, const int64_t *_
       }
     }
   }
-  __syncthreads();
+  wave_lds_sync();
   if (t >= tl.nt) return;
   float *dst = partial + tbase[t] * ns;
   for (int mg = 0; mg < rows_u; mg += 16 * MG) {
@@ -596,7 +605,7 @@ __global__ __launch_bounds__(256) void k_vint_mfma_bf16(DevTiles tl, const int64
       }
     }
   }
-  __syncthreads();
+  wave_lds_sync();
   if (t >= tl.nt) return;
   float *dst = partial + tbase[t] * ns;
   for (int mg = 0; mg < rows_u; mg += 16 * MG) {
