@@ -153,6 +153,11 @@ typedef struct {
                                 registers; 1: in vector registers shared by DPP row
                                 broadcasts (FP32 and BF16-sample handles; FP64 always
                                 takes 0).  Results are identical either way */
+  int32_t  gemm_tile;        /* -1 (default): the tuner's choice (0 when autotune is 0);
+                                0, 1, 2: the output tile shape of every dense
+                                (complete-pattern) MFMA product (left: 128x64, 64x64,
+                                64x128; right: 64x64, 128x64, 64x128 rows x columns).  All
+                                shapes share the k-slab depth: results are identical */
 } tddft_options;
 
 /* Per-solve statistics (host memory, caller-owned).  The log arrays are optional. */
@@ -205,13 +210,15 @@ typedef struct {
   int32_t kshift_cw[2];      /* K-shift products: columns per thread (left, right)       */
   int32_t density_pbcast;    /* response density (FP32): 1 = P blocks in vector registers
                                 shared by DPP row broadcasts, 0 = P in scalar registers   */
+  int32_t kshift_tile[2];    /* K-shift products in the dense form: output tile shape
+                                (tddft_options.gemm_tile numbering; 0 for sparse forms)   */
 } tddft_info;
 
 typedef struct tddft_handle tddft_handle;
 
 /* Defaults: FP64, ALDA exchange, rho_floor 1e-10, coupling 1, KSDIFF_CG, eps_tol 1e-4,
  * tol_omega 1e-7, max_iter 300, max_inner 50, refresh 10, restart 20, seed 0, eps_loose 0,
- * tda 0, truncate_p 0, graphs 1, autotune 1, density_pbcast -1. */
+ * tda 0, truncate_p 0, graphs 1, autotune 1, density_pbcast -1, gemm_tile -1. */
 void tddft_default_options(tddft_options *opts);
 
 /* Build a handle for one system (Sec. III.A: sparse K^v, K^c, S and H, the cutoff

@@ -55,7 +55,7 @@ class tddft_options(C.Structure):
                 ("seed", C.c_uint64), ("model", C.c_void_p), ("model_bytes", C.c_int64),
                 ("stream", C.c_void_p), ("eps_loose", C.c_double), ("tda", C.c_int32),
                 ("truncate_p", C.c_int32), ("graphs", C.c_int32), ("autotune", C.c_int32),
-                ("density_pbcast", C.c_int32)]
+                ("density_pbcast", C.c_int32), ("gemm_tile", C.c_int32)]
 
 
 class tddft_info(C.Structure):
@@ -72,7 +72,7 @@ class tddft_info(C.Structure):
                 ("samples_u_nz", C.c_int64), ("samples_o_nz", C.c_int64),
                 ("pair_points_nz", C.c_int64), ("fft_threads", C.c_int32 * 3),
                 ("density_waves", C.c_int32), ("kshift_cw", C.c_int32 * 2),
-                ("density_pbcast", C.c_int32)]
+                ("density_pbcast", C.c_int32), ("kshift_tile", C.c_int32 * 2)]
 
 
 class tddft_stats(C.Structure):
@@ -372,6 +372,7 @@ class Handle:
         d["n"] = list(inf.n)
         d["fft_threads"] = list(inf.fft_threads)
         d["kshift_cw"] = list(inf.kshift_cw)
+        d["kshift_tile"] = list(inf.kshift_tile)
         return d
 
     def tddft_profile(self, enable: bool):

@@ -82,6 +82,7 @@ void tddft_default_options(tddft_options *o) {
   o->graphs = 1;
   o->autotune = 1;
   o->density_pbcast = -1;
+  o->gemm_tile = -1;
 }
 
 int tddft_abi_version(void) { return TDDFT_ABI_VERSION; }
@@ -178,6 +179,8 @@ int tddft_get_info(const tddft_handle *hd, tddft_info *o) {
   o->kshift_cw[0] = h.pT_left.cw;
   o->kshift_cw[1] = h.pT_right.cw;
   o->density_pbcast = h.tiles_uo.pbcast;
+  o->kshift_tile[0] = h.pT_left.tile;
+  o->kshift_tile[1] = h.pT_right.tile;
   return TDDFT_OK;
 }
 

@@ -314,6 +314,7 @@ void create_handle(Handle &h, const tddft_system &sys, const tddft_options &o) {
   h.precision = o.precision;
   TD_REQUIRE(o.precision >= TDDFT_FP64 && o.precision <= TDDFT_BF16_GRID, "unknown precision mode");
   TD_REQUIRE(o.density_pbcast >= -1 && o.density_pbcast <= 1, "density_pbcast must be -1, 0 or 1");
+  TD_REQUIRE(o.gemm_tile >= -1 && o.gemm_tile <= 2, "gemm_tile must be -1, 0, 1 or 2");
   TD_REQUIRE(o.xc >= TDDFT_XC_ALDA_X && o.xc <= TDDFT_HXC_NONE, "unknown coupling kernel");
   h.stype = o.precision == TDDFT_FP64 ? SAMPLE_F64 : (o.precision == TDDFT_FP32 ? SAMPLE_F32 : SAMPLE_BF16);
   h.stream = (hipStream_t)o.stream;
@@ -601,6 +602,10 @@ void create_handle(Handle &h, const tddft_system &sys, const tddft_options &o) {
   }
   if (o.autotune) autotune(h);
   if (o.density_pbcast >= 0) h.tiles_uo.pbcast = h.stype == SAMPLE_F64 ? 0 : o.density_pbcast;
+  if (o.gemm_tile >= 0)
+    for (DevPlan *pl : {&h.pT_left, &h.pT_right, &h.pSw1, &h.pSw2, &h.pPi1, &h.pPi2, &h.pPt1,
+                        &h.pPt2, &h.pCov1, &h.pCov2})
+      pl->tile = o.gemm_tile;
   h.setup_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
 }
 

@@ -173,6 +173,13 @@ __device__ __forceinline__ typename MfmaAcc<T>::type mfma16x16x4(T a, T b, typen
 // tile shapes of the two products
 struct GemmLeft { static constexpr int GM = 128, GN = 64, GK = 16, WMW = 4, WNW = 2; static constexpr bool AROW = false; };
 struct GemmRight { static constexpr int GM = 64, GN = 64, GK = 16, WMW = 2, WNW = 2; static constexpr bool AROW = true; };
+// alternative output tiles the creation-time tuner may pick per product (DevPlan::tile).
+// The k-slab depth GK fixes which products each MFMA sums, so every shape here keeps
+// GK = 16 and gives bit-identical results.
+struct GemmLeft64 { static constexpr int GM = 64, GN = 64, GK = 16, WMW = 2, WNW = 2; static constexpr bool AROW = false; };
+struct GemmLeftWide { static constexpr int GM = 64, GN = 128, GK = 16, WMW = 2, WNW = 2; static constexpr bool AROW = false; };
+struct GemmRightTall { static constexpr int GM = 128, GN = 64, GK = 16, WMW = 4, WNW = 2; static constexpr bool AROW = true; };
+struct GemmRightWide { static constexpr int GM = 64, GN = 128, GK = 16, WMW = 2, WNW = 2; static constexpr bool AROW = true; };
 
 template <class T, int BU, int BO, bool LEFT, class G>
 __global__ __launch_bounds__(64 * G::WMW * G::WNW) void k_gemm_blocks(int di, int dk, int dj, int ncol,
@@ -379,11 +386,16 @@ void spmm_left(const DevPlan &pl, int bu, int bo, const T *A, const T *X, int ld
                T *C, int ldc, int cc0, int ncol, double alpha, bool acc, hipStream_t s) {
   if (pl.nout == 0 || ncol == 0) return;
   if (pl.di > 0) {
-    using G = GemmLeft;
-    const dim3 grid((unsigned)((pl.dj * ncol * bo + G::GN - 1) / G::GN), (unsigned)((pl.di * bu + G::GM - 1) / G::GM));
-    TD_BDIM_DISPATCH(bu, bo, hipLaunchKernelGGL((k_gemm_blocks<T, BU, BO, true, G>), grid, dim3(64 * G::WMW * G::WNW), 0, s,
-                                                pl.di, pl.dk, pl.dj, ncol, A, X, ldx, xc0, C, ldc,
-                                                cc0, (T)alpha, acc ? 1 : 0));
+    auto launch = [&](auto g) {
+      using G = decltype(g);
+      const dim3 grid((unsigned)((pl.dj * ncol * bo + G::GN - 1) / G::GN), (unsigned)((pl.di * bu + G::GM - 1) / G::GM));
+      TD_BDIM_DISPATCH(bu, bo, hipLaunchKernelGGL((k_gemm_blocks<T, BU, BO, true, G>), grid, dim3(64 * G::WMW * G::WNW), 0, s,
+                                                  pl.di, pl.dk, pl.dj, ncol, A, X, ldx, xc0, C, ldc,
+                                                  cc0, (T)alpha, acc ? 1 : 0));
+    };
+    if (pl.tile == 1) launch(GemmLeft64{});
+    else if (pl.tile == 2) launch(GemmLeftWide{});
+    else launch(GemmLeft{});
     TD_HIP(hipGetLastError());
     return;
   }
@@ -405,11 +417,16 @@ void spmm_right(const DevPlan &pl, int bu, int bo, const T *X, int ldx, int xc0,
                 T *C, int ldc, int cc0, int ncol, double alpha, bool acc, hipStream_t s) {
   if (pl.nout == 0 || ncol == 0) return;
   if (pl.di > 0) {
-    using G = GemmRight;
-    const dim3 grid((unsigned)((pl.dj * bo + G::GN - 1) / G::GN), (unsigned)((pl.di * bu * ncol + G::GM - 1) / G::GM));
-    TD_BDIM_DISPATCH(bu, bo, hipLaunchKernelGGL((k_gemm_blocks<T, BU, BO, false, G>), grid, dim3(64 * G::WMW * G::WNW), 0, s,
-                                                pl.di, pl.dk, pl.dj, ncol, X, B, ldx, xc0, C, ldc,
-                                                cc0, (T)alpha, acc ? 1 : 0));
+    auto launch = [&](auto g) {
+      using G = decltype(g);
+      const dim3 grid((unsigned)((pl.dj * bo + G::GN - 1) / G::GN), (unsigned)((pl.di * bu * ncol + G::GM - 1) / G::GM));
+      TD_BDIM_DISPATCH(bu, bo, hipLaunchKernelGGL((k_gemm_blocks<T, BU, BO, false, G>), grid, dim3(64 * G::WMW * G::WNW), 0, s,
+                                                  pl.di, pl.dk, pl.dj, ncol, X, B, ldx, xc0, C, ldc,
+                                                  cc0, (T)alpha, acc ? 1 : 0));
+    };
+    if (pl.tile == 1) launch(GemmRightTall{});
+    else if (pl.tile == 2) launch(GemmRightWide{});
+    else launch(GemmRight{});
     TD_HIP(hipGetLastError());
     return;
   }

@@ -6,7 +6,9 @@
 //     two-buffer form), per axis from the stage times of the five passes;
 //   * response density: tiles (waves) per workgroup, 2, 4 or 8, and (FP32) P blocks in
 //     scalar registers or in vector registers shared by DPP row broadcasts;
-//   * sparse products: columns per thread, 1, 2 or 4, per product plan.
+//   * sparse products: columns per thread, 1, 2 or 4, per product plan;
+//   * dense (complete-pattern) MFMA products: output tile shape (three shapes with the same
+//     k-slab depth), per product plan.
 // No candidate changes an arithmetic operation or the order of any sum, so results are the
 // same whatever is chosen.
 #include <map>
@@ -193,6 +195,36 @@ void tune_typed(Handle &h) {
       remember(k.str(), choice);
     }
     pl.cw = choice[0];
+  }
+
+  // ---- dense (complete-pattern) products: output tile shape, per plan
+  for (const PlanRef &r : plans) {
+    DevPlan &pl = *r.pl;
+    if (pl.nout == 0 || pl.di == 0) continue;   // empty, or the sparse form (tuned above)
+    std::ostringstream k;
+    k << "gemm " << prec << " " << (r.left ? "L " : "R ") << h.BU << "x" << h.BO << " "
+      << pl.di << " " << pl.dk << " " << pl.dj;
+    std::vector<int> choice;
+    if (!cached(k.str(), choice)) {
+      float best = 1e30f;
+      int pick = 0;
+      for (int tile : {0, 1, 2}) {
+        pl.tile = tile;
+        const float ms = best_ms(s, h.ev0, h.ev1, 3, [&]() {
+          if (r.left)
+            spmm_left<T>(pl, h.BU, h.BO, r.op, A, nc, 0, B, nc, 0, nc, 1.0, false, s);
+          else
+            spmm_right<T>(pl, h.BU, h.BO, A, nc, 0, r.op, B, nc, 0, nc, 1.0, false, s);
+        });
+        if (ms < best) {
+          best = ms;
+          pick = tile;
+        }
+      }
+      choice = {pick};
+      remember(k.str(), choice);
+    }
+    pl.tile = choice[0];
   }
   TD_HIP(hipStreamSynchronize(s));
 }

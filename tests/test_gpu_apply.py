@@ -189,6 +189,7 @@ def test_autotuned_launch_shapes_give_identical_results(name, precision, request
     assert all(t in (0, 256, 512, 1024) for t in info["fft_threads"])
     assert info["density_waves"] in (2, 4, 8) and all(c in (1, 2, 4) for c in info["kshift_cw"])
     assert info["density_pbcast"] in ((0,) if precision == "fp64" else (0, 1))
+    assert all(t in (0, 1, 2) for t in info["kshift_tile"])
 
 
 @pytest.mark.parametrize("name,precision", [("small_kt", "fp32"), ("small_odd", "fp32"),
@@ -217,3 +218,29 @@ def test_density_p_forms_are_identical(name, precision):
         h.close()
     for a, b in zip(out[0], out[1]):
         assert np.array_equal(a, b)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_dense_product_tiles_are_identical(small_dense, precision):
+    """The dense (complete-pattern) MFMA products run in three output tile shapes that share
+    the k-slab depth, so each MFMA sums the same products: applies and a whole solve are
+    bit-identical across the shapes."""
+    s = small_dense
+    print(f"[apply] dense product tiles {precision}", flush=True)
+    Pp = to_dev(sabi.dense_to_p(s, random_p(s, 4, 81)))
+    Pq = to_dev(sabi.dense_to_p(s, random_p(s, 4, 82)))
+    L0 = to_dev(sabi.dense_to_p(s, s.guess()))
+    from paper_1507_08157_amd import binding
+    out = {}
+    for tile in (0, 1, 2):
+        h = gpu_handle(s, precision=precision, gemm_tile=tile)
+        info = h.tddft_get_info()
+        assert info["kshift_tile"] == [tile, tile]
+        fp, fq = h.tddft_apply(Pp, Pq)
+        o = binding.tddft_default_options(precision=precision, tol_omega=1e-8)
+        w, rc, st = h.tddft_pcg_solve(3, o, L0.clone(), L0.clone())
+        out[tile] = (fp.cpu().numpy(), fq.cpu().numpy(), w)
+        h.close()
+    for tile in (1, 2):
+        for a, b in zip(out[0], out[tile]):
+            assert np.array_equal(a, b)
