@@ -116,9 +116,13 @@ def evaluate(model: bytes, systems: int = 50, atoms: int = 100, seed0: int = 400
     import concurrent.futures as cf
     import multiprocessing as mp
     import os
+    members = []
     with cf.ProcessPoolExecutor(max_workers=min(16, os.cpu_count() or 1),
                                 mp_context=mp.get_context("fork")) as ex:
-        members = list(ex.map(_gen_member, [(i, atoms, seed0, states) for i in range(systems)]))
+        for m in ex.map(_gen_member, [(i, atoms, seed0, states) for i in range(systems)]):
+            members.append(m)
+            if log:
+                log(f"held-out system {len(members)} of {systems} generated")
     import torch
     rows = []
     for seed, arrays, guess in members:
@@ -174,9 +178,6 @@ def _main():
     import json
     import os
     sys.path.insert(0, os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
-    from synth import abi as sabi
-    from synth import build_system, configs
-
     def log(msg):
         print(f"[train] {msg}", flush=True)
 
@@ -192,15 +193,26 @@ def _main():
     if not a.out:
         ap.error("--out (training) or --evaluate MODEL")
 
+    # the systems are generated by worker processes forked before this process touches
+    # the GPU; the solves that label them run here, one after another
+    import concurrent.futures as cf
+    import multiprocessing as mp
+    t0 = time.perf_counter()
+    members = []
+    with cf.ProcessPoolExecutor(max_workers=min(16, os.cpu_count() or 1),
+                                mp_context=mp.get_context("fork")) as ex:
+        for m in ex.map(_gen_member, [(i, a.atoms, a.seed, a.states) for i in range(a.systems)]):
+            members.append(m)
+            log(f"system {len(members)} of {a.systems} generated")
+    log(f"{len(members)} systems generated in {time.perf_counter() - t0:.1f} s")
     data = []
-    for i in range(a.systems):
+    for i, (seed, arrays, _) in enumerate(members):
         t0 = time.perf_counter()
-        s = build_system(configs.training_member(i, a.atoms, a.seed))
-        h = binding.tddft_create(sabi.system_arrays(s), precision="fp64")
+        h = binding.tddft_create(arrays, precision="fp64")
         d = collect(h, a.states, a.samples, seed=a.seed + i)
         h.close()
         data.append(d)
-        log(f"system {i}: {s.cfg.n_atoms} atoms, {d['X'].shape[0]} rows, solve "
+        log(f"system {i} (seed {seed}): {d['X'].shape[0]} rows, solve "
             f"{d['iterations']} iterations, {time.perf_counter() - t0:.1f} s")
     m, hist = train(data, epochs=a.epochs, seed=a.seed, log=log)
     with open(a.out, "wb") as f:
