@@ -151,8 +151,7 @@ typedef struct {
   int32_t  density_pbcast;   /* -1 (default): the tuner's choice (scalar P when autotune
                                 is 0); 0: the response density keeps P blocks in scalar
                                 registers; 1: in vector registers shared by DPP row
-                                broadcasts (FP32 and BF16-sample handles; FP64 always
-                                takes 0).  Results are identical either way */
+                                broadcasts.  Results are identical either way */
   int32_t  gemm_tile;        /* -1 (default): the tuner's choice (0 when autotune is 0);
                                 0, 1, 2: the output tile shape of every dense
                                 (complete-pattern) MFMA product (left: 128x64, 64x64,
@@ -208,7 +207,7 @@ typedef struct {
   int32_t fft_threads[3];    /* FFT threads per workgroup per axis (0 = two-buffer form)  */
   int32_t density_waves;     /* response density: tiles per workgroup                    */
   int32_t kshift_cw[2];      /* K-shift products: columns per thread (left, right)       */
-  int32_t density_pbcast;    /* response density (FP32): 1 = P blocks in vector registers
+  int32_t density_pbcast;    /* response density: 1 = P blocks in vector registers
                                 shared by DPP row broadcasts, 0 = P in scalar registers   */
   int32_t kshift_tile[2];    /* K-shift products in the dense form: output tile shape
                                 (tddft_options.gemm_tile numbering; 0 for sparse forms)   */

@@ -108,7 +108,7 @@ __device__ __forceinline__ void density_chunk(const int32_t *__restrict__ pid, i
   }
 }
 
-// FP32 pair loop with P in vector registers.  Every 16-lane row of the wave loads the same
+// Pair loop with P in vector registers (FP32 and FP64).  Every 16-lane row of the wave loads the same
 // NS * BL * BR values of a P block, value q in lane q % 16 of register q / 16, and each FMA
 // takes its P factor from lane q % 16 of its own row by a DPP row broadcast (row_newbcast),
 // so the P operand costs no extra instruction.  The loads are vector loads, which complete
@@ -121,22 +121,28 @@ __device__ __forceinline__ void fmac_row_bcast(float &acc, float v, float o) {
   asm("v_fmac_f32_dpp %0, %1, %2 row_newbcast:%3 row_mask:0xf bank_mask:0xf"
       : "+v"(acc) : "v"(v), "v"(o), "n"(K));
 }
+// the FP64 ALU takes DPP with the row broadcast on its 64-bit operands as well
+template <int K>
+__device__ __forceinline__ void fmac_row_bcast(double &acc, double v, double o) {
+  asm("v_fmac_f64_dpp %0, %1, %2 row_newbcast:%3 row_mask:0xf bank_mask:0xf"
+      : "+v"(acc) : "v"(v), "v"(o), "n"(K));
+}
 
-template <int NS, int BL, int BR, int JC, int NV, int Q0, int... Q>
-__device__ __forceinline__ void bcast_pair(std::integer_sequence<int, Q...>, const float (&pv)[NV],
-                                           const float (&o)[BR], float (&tmp)[NS][BL]) {
+template <class T, int NS, int BL, int BR, int JC, int NV, int Q0, int... Q>
+__device__ __forceinline__ void bcast_pair(std::integer_sequence<int, Q...>, const T (&pv)[NV],
+                                           const T (&o)[BR], T (&tmp)[NS][BL]) {
   constexpr int E = BL * BR;
   (fmac_row_bcast<(Q0 + Q) % 16>(tmp[(Q0 + Q) / E][((Q0 + Q) % E) / BR], pv[(Q0 + Q) / 16],
                                  o[(Q0 + Q) % BR]), ...);
 }
 
-template <int NS, int BL, int BR, int JC>
+template <class T, int NS, int BL, int BR, int JC>
 __device__ __forceinline__ void density_chunk_bcast(int (&pbs)[JC], const int32_t *__restrict__ pid_next,
-                                                    int nj, const float *__restrict__ X,
+                                                    int nj, const T *__restrict__ X,
                                                     int64_t xoff, int ldx,
-                                                    const float *__restrict__ zero, int l16,
-                                                    const float (&o)[JC][BR],
-                                                    float (&tmp)[NS][BL]) {
+                                                    const T *__restrict__ zero, int l16,
+                                                    const T (&o)[JC][BR],
+                                                    T (&tmp)[NS][BL]) {
   constexpr int E = BL * BR, Q = NS * E, NV = (Q + 15) / 16;
   // lane l16 of a row holds values l16, 16 + l16, ...; lanes past the block's end repeat
   // its last value (never broadcast), so every load stays inside the block
@@ -145,10 +151,10 @@ __device__ __forceinline__ void density_chunk_bcast(int (&pbs)[JC], const int32_
   for (int v = 0; v < NV; ++v) qi[v] = min(16 * v + l16, Q - 1);
   // all JC blocks requested in one straight run (pairs past the chunk's end read the zero
   // block), so the wait before pair j's FMAs counts only the loads issued after it
-  float pv[JC][NV];
+  T pv[JC][NV];
 #pragma unroll
   for (int j = 0; j < JC; ++j) {
-    const float *Pj = j < nj && pbs[j] >= 0 ? X + ((int64_t)pbs[j] * ldx) * E + xoff : zero;
+    const T *Pj = j < nj && pbs[j] >= 0 ? X + ((int64_t)pbs[j] * ldx) * E + xoff : zero;
 #pragma unroll
     for (int v = 0; v < NV; ++v) pv[j][v] = Pj[qi[v]];
   }
@@ -162,7 +168,7 @@ __device__ __forceinline__ void density_chunk_bcast(int (&pbs)[JC], const int32_
 #pragma unroll
   for (int j = 0; j < JC; ++j) {
     if (j >= nj) break;
-    bcast_pair<NS, BL, BR, JC, NV, 0>(std::make_integer_sequence<int, Q>{}, pv[j], o[j], tmp);
+    bcast_pair<T, NS, BL, BR, JC, NV, 0>(std::make_integer_sequence<int, Q>{}, pv[j], o[j], tmp);
   }
 }
 
@@ -248,7 +254,7 @@ __global__ __launch_bounds__(512) void k_density(DevTiles tl, const S *__restric
           for (int r = 0; r < BL; ++r) tmp[k][r] = T(0);
         if constexpr (PB) {
           if (nk == NS)
-            density_chunk_bcast<NS, BL, BR, JC>(pbs, i + 1 < nua ? pid + (i + 1) * noa + j0 : nullptr,
+            density_chunk_bcast<T, NS, BL, BR, JC>(pbs, i + 1 < nua ? pid + (i + 1) * noa + j0 : nullptr,
                                                 nj, X, xoff, ldx, zero, lane & 15, o, tmp);
           else
             density_chunk<T, S, NS, BL, BR, JC, false>(pid + i * noa + j0, nj, X, xoff, ldx, zero, nk, o, tmp);
@@ -753,13 +759,19 @@ void density(const DevTiles &tl, int stype, int BL, int BR, const T *X, int ldx,
   const unsigned grid = (unsigned)((tl.nt + waves - 1) / waves);
 #define TD_DENSITY_LAUNCH(NSC_, PB_) \
   TD_SAMPLE(T, stype, TD_GRID_BDIM(BL, BR, hipLaunchKernelGGL((k_density<T, S, BL, BR, NSC_, PB_>), dim3(grid), dim3(64 * waves), lds, s, tl, reinterpret_cast<const S *>(tl.usamp), reinterpret_cast<const S *>(tl.osamp), tl.pidx, X, ldx, xc0, ns, out, pair_stride, (T)scale)))
-  bool bcast = false;
-  if constexpr (std::is_same<T, float>::value) bcast = tl.pbcast != 0;
+#define TD_DENSITY_LAUNCH_F64(NSC_) \
+  TD_GRID_BDIM(BL, BR, hipLaunchKernelGGL((k_density<T, double, BL, BR, NSC_, true>), dim3(grid), dim3(64 * waves), lds, s, tl, reinterpret_cast<const double *>(tl.usamp), reinterpret_cast<const double *>(tl.osamp), tl.pidx, X, ldx, xc0, ns, out, pair_stride, (T)scale))
+  // the broadcast form: FP32 with any samples, FP64 with FP64 samples (the FP64 handles)
+  const bool bcast = tl.pbcast != 0 && (std::is_same<T, float>::value || stype == SAMPLE_F64);
   if (bcast) {
     if constexpr (std::is_same<T, float>::value) {
       if (ns <= 2) TD_DENSITY_LAUNCH(2, true);
       else if (ns <= 4) TD_DENSITY_LAUNCH(4, true);
       else TD_DENSITY_LAUNCH(8, true);
+    } else {
+      if (ns <= 2) TD_DENSITY_LAUNCH_F64(2);
+      else if (ns <= 4) TD_DENSITY_LAUNCH_F64(4);
+      else TD_DENSITY_LAUNCH_F64(8);
     }
   } else {
     if (ns <= 2) TD_DENSITY_LAUNCH(2, false);
@@ -767,6 +779,7 @@ void density(const DevTiles &tl, int stype, int BL, int BR, const T *X, int ldx,
     else TD_DENSITY_LAUNCH(8, false);
   }
 #undef TD_DENSITY_LAUNCH
+#undef TD_DENSITY_LAUNCH_F64
   TD_HIP(hipGetLastError());
 }
 

@@ -601,7 +601,7 @@ void create_handle(Handle &h, const tddft_system &sys, const tddft_options &o) {
     h.tiles_oo.usamp = h.tiles_oo.osamp = nullptr;
   }
   if (o.autotune) autotune(h);
-  if (o.density_pbcast >= 0) h.tiles_uo.pbcast = h.stype == SAMPLE_F64 ? 0 : o.density_pbcast;
+  if (o.density_pbcast >= 0) h.tiles_uo.pbcast = o.density_pbcast;
   if (o.gemm_tile >= 0)
     for (DevPlan *pl : {&h.pT_left, &h.pT_right, &h.pSw1, &h.pSw2, &h.pPi1, &h.pPi2, &h.pPt1,
                         &h.pPt2, &h.pCov1, &h.pCov2})

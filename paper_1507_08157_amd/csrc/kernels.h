@@ -96,9 +96,9 @@ struct DevTiles {
   const void *usamp = nullptr, *osamp = nullptr;    // rows of TP samples
   size_t lds_limit = 65536;                          // device LDS bytes per workgroup
   int waves = 4;                                     // density: tiles (waves) per workgroup
-  int pbcast = 0;                                    // density (FP32): P blocks in vector
-                                                     // registers with DPP row broadcasts (1)
-                                                     // or in scalar registers (0)
+  int pbcast = 0;                                    // density: P blocks in vector registers
+                                                     // with DPP row broadcasts (1) or in
+                                                     // scalar registers (0)
   const void *zero = nullptr;                        // kZeroBlock zeros (the block read for
                                                      // a pair with no P block)
   const int32_t *order = nullptr;                    // [nt] density: tiles in processing

@@ -4,8 +4,8 @@
 // that decide it, so that handles of like systems reuse the choice without timing:
 //   * FFT passes: threads per workgroup of each axis (256, 512 or 1024 in place, or the
 //     two-buffer form), per axis from the stage times of the five passes;
-//   * response density: tiles (waves) per workgroup, 2, 4 or 8, and (FP32) P blocks in
-//     scalar registers or in vector registers shared by DPP row broadcasts;
+//   * response density: tiles (waves) per workgroup, 2, 4 or 8, and P blocks in scalar
+//     registers or in vector registers shared by DPP row broadcasts;
 //   * sparse products: columns per thread, 1, 2 or 4, per product plan;
 //   * dense (complete-pattern) MFMA products: output tile shape (three shapes with the same
 //     k-slab depth), per product plan.
@@ -128,9 +128,7 @@ void tune_typed(Handle &h) {
     if (!cached(k.str(), choice)) {
       float best = 1e30f;
       choice = {tl.waves, tl.pbcast};
-      const bool fp32 = std::is_same<T, float>::value;
       for (int pb : {0, 1}) {
-        if (pb && !fp32) continue;
         for (int wv : {2, 4, 8}) {
           tl.waves = wv;
           tl.pbcast = pb;

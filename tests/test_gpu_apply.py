@@ -188,13 +188,14 @@ def test_autotuned_launch_shapes_give_identical_results(name, precision, request
     info = out[1][2]
     assert all(t in (0, 256, 512, 1024) for t in info["fft_threads"])
     assert info["density_waves"] in (2, 4, 8) and all(c in (1, 2, 4) for c in info["kshift_cw"])
-    assert info["density_pbcast"] in ((0,) if precision == "fp64" else (0, 1))
+    assert info["density_pbcast"] in (0, 1)
     assert all(t in (0, 1, 2) for t in info["kshift_tile"])
 
 
 @pytest.mark.parametrize("name,precision", [("small_kt", "fp32"), ("small_odd", "fp32"),
                                             ("small_joint", "fp32"), ("small_crowded", "fp32"),
-                                            ("small_dense", "bf16")])
+                                            ("small_dense", "bf16"), ("small_kt", "fp64"),
+                                            ("small_joint", "fp64"), ("small_odd", "fp64")])
 def test_density_p_forms_are_identical(name, precision):
     """The response density keeps a pass's P block either in scalar registers or in vector
     registers read through DPP row broadcasts; both run the same FMAs in the same order, so
