@@ -108,10 +108,10 @@ __device__ __forceinline__ void density_chunk(const int32_t *__restrict__ pid, i
   }
 }
 
-// Pair loop with P in vector registers (FP32 and FP64).  Every 16-lane row of the wave loads the same
-// NS * BL * BR values of a P block, value q in lane q % 16 of register q / 16, and each FMA
-// takes its P factor from lane q % 16 of its own row by a DPP row broadcast (row_newbcast),
-// so the P operand costs no extra instruction.  The loads are vector loads, which complete
+// Pair loop with P in vector registers (FP32 and FP64).  Every 16-lane row of the wave
+// loads the same NS * BL * BR values of a P block, value q in lane q % 16 of register q / 16,
+// and each FMA takes its P factor from lane q % 16 of its own row by a DPP row broadcast
+// (row_newbcast), so the P operand costs no extra instruction.  The loads are vector loads, which complete
 // in order: the P blocks of all pairs of the chunk are requested before the first FMA,
 // where the scalar form waits for each block in turn.  A DPP read needs its source register
 // written by a load, not by an ALU instruction, in the two cycles before it; the P registers
