@@ -530,6 +530,125 @@ __global__ __launch_bounds__(256) void k_vint_mfma(DevTiles tl, const int64_t *_
   }
 }
 
+// FP64 variant on v_mfma_f64_16x16x4f64: the same per-tile product with FP64 samples, LDS
+// rows and potentials (two samples per 16-byte load; rows padded by two values so that the
+// 16-byte reads of neighbouring rows fall on different banks).  The FP64 accumulator holds
+// rows 4 j + lane / 16 of the 16 x 16 block (FP32: 4 (lane / 16) + j).  One 16-row block of
+// u-rows is held in registers at a time.
+typedef double v4d_vint __attribute__((ext_vector_type(4)));
+
+template <int BL, int BR>
+__global__ __launch_bounds__(128) void k_vint_mfma64(DevTiles tl, const int64_t *__restrict__ tbase,
+                                                     const double *__restrict__ usamp,
+                                                     const double *__restrict__ osamp,
+                                                     const double *__restrict__ V,
+                                                     int64_t pair_stride, int ns,
+                                                     double *__restrict__ partial, double scale) {
+  extern __shared__ unsigned char lds_raw[];
+  constexpr int LD = TP + 2;
+  const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  const int t = blockIdx.x * (blockDim.x >> 6) + w;
+  double *lo = reinterpret_cast<double *>(lds_raw) + (size_t)w * (tl.maxrows_r + ns) * LD;
+  double *lv = lo + (size_t)tl.maxrows_r * LD;
+  int u0 = 0, nua = 0, o0 = 0, noa = 0;
+  if (t < tl.nt) {
+    u0 = tl.uptr[t];
+    nua = tl.uptr[t + 1] - u0;
+    o0 = tl.optr[t];
+    noa = tl.optr[t + 1] - o0;
+  }
+  const int rows_u = nua * BL, rows_o = noa * BR;
+  const int items = rows_o * ns;
+  const int q = lane >> 4, c16 = lane & 15;
+  const double *ut = usamp + (int64_t)u0 * BL * TP;
+  double a[16];
+  auto load_u = [&](int mg) {
+    const int m = mg + c16;
+    if (m < rows_u) {
+      const double2 *p = reinterpret_cast<const double2 *>(ut + (int64_t)m * TP + 16 * q);
+#pragma unroll
+      for (int k = 0; k < 8; ++k) {
+        const double2 v = p[k];
+        a[2 * k] = v.x;
+        a[2 * k + 1] = v.y;
+      }
+    } else {
+#pragma unroll
+      for (int k = 0; k < 16; ++k) a[k] = 0.0;
+    }
+  };
+  // the first u-row block is requested before the staging loads, so that both are in flight
+  load_u(0);
+  {
+    const double *ot = osamp + (int64_t)o0 * BR * TP;
+    const double *vt = V + (int64_t)t * TP * 2;
+    const int n_o2 = rows_o * (TP / 2);
+    const int n_v2 = t < tl.nt ? ((ns + 1) / 2) * TP : 0;
+    for (int i0 = lane; i0 < n_o2 || i0 < n_v2; i0 += 4 * 64) {
+      double2 o2[4], v2[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int i = i0 + 64 * u;
+        if (i < n_o2) o2[u] = reinterpret_cast<const double2 *>(ot)[i];
+        if (i < n_v2) {
+          const int sp = i / TP, p = i % TP;
+          v2[u] = *reinterpret_cast<const double2 *>(vt + (int64_t)sp * pair_stride + 2 * p);
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int i = i0 + 64 * u;
+        if (i < n_o2) *reinterpret_cast<double2 *>(lo + (i / (TP / 2)) * LD + 2 * (i % (TP / 2))) = o2[u];
+        if (i < n_v2) {
+          const int sp = i / TP, p = i % TP;
+          lv[(2 * sp) * LD + p] = v2[u].x;
+          if (2 * sp + 1 < ns) lv[(2 * sp + 1) * LD + p] = v2[u].y;
+        }
+      }
+    }
+  }
+  wave_lds_sync();
+  if (t >= tl.nt) return;
+  double *dst = partial + tbase[t] * ns;
+  for (int mg = 0; mg < rows_u; mg += 16) {
+    if (mg > 0) load_u(mg);
+    for (int n0 = 0; n0 < items; n0 += 16) {
+      const int n = n0 + c16;
+      const bool active = n < items;
+      const int b = active ? n / ns : 0;
+      const int sidx = active ? n - (n / ns) * ns : 0;
+      double bf[16];
+      {
+        const double *orow = lo + b * LD + 16 * q;
+        const double *vrow = lv + sidx * LD + 16 * q;
+#pragma unroll
+        for (int k = 0; k < 16; k += 2) {
+          const double2 o2 = *reinterpret_cast<const double2 *>(orow + k);
+          const double2 v2 = *reinterpret_cast<const double2 *>(vrow + k);
+          bf[k] = active ? o2.x * v2.x : 0.0;
+          bf[k + 1] = active ? o2.y * v2.y : 0.0;
+        }
+      }
+      v4d_vint acc = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+      for (int k = 0; k < 16; ++k) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a[k], bf[k], acc, 0, 0, 0);
+      if (active) {
+        // contribution-major: [(u-atom, o-atom)][r][c][state]
+        const int jo = b / BR, c = b - (b / BR) * BR;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          const int m = mg + 4 * j + q;
+          if (m < rows_u) {
+            const int io = m / BL, r = m - (m / BL) * BL;
+            dst[((((int64_t)io * noa + jo) * BL + r) * BR + c) * ns + sidx] = scale * acc[j];
+          }
+        }
+      }
+    }
+  }
+}
+
 // BF16 variant on BF16 MFMA (v_mfma_f32_16x16x32_bf16, FP32 accumulation): the u-row
 // fragments are the stored BF16 samples themselves (32 contiguous bytes per lane), and the
 // (o-row, state) operand w = o_b V_s is formed in FP32 from the staged o-rows and
@@ -799,7 +918,13 @@ void potential_integrals(const DevTiles &tl, const DevPartials &pa, int stype, i
     else
       TD_SAMPLE(T, stype, TD_GRID_BDIM(BL, BR, hipLaunchKernelGGL((k_vint_mfma<S, BL, BR>), dim3(grid), dim3(256), lds, s, tl, pa.tbase, reinterpret_cast<const S *>(tl.usamp), reinterpret_cast<const S *>(tl.osamp), V, pair_stride, ns, partial, (float)scale)));
   } else {
-    TD_SAMPLE(T, stype, TD_GRID_BDIM(BL, BR, hipLaunchKernelGGL((k_vint<T, S, BL, BR>), dim3(grid), dim3(256), 0, s, tl, pa.tbase, reinterpret_cast<const S *>(tl.usamp), reinterpret_cast<const S *>(tl.osamp), V, pair_stride, ns, partial, (T)scale)));
+    // FP64 samples on FP64 MFMA when the staged rows fit the LDS; the vector form otherwise.
+    // Two tiles (waves) per workgroup: a wave's FP64 rows take twice the LDS of FP32 ones.
+    const size_t lds = 2 * (size_t)(tl.maxrows_r + ns) * (TP + 2) * sizeof(double);
+    if (stype == SAMPLE_F64 && lds <= tl.lds_limit)
+      TD_GRID_BDIM(BL, BR, hipLaunchKernelGGL((k_vint_mfma64<BL, BR>), dim3((unsigned)((tl.nt + 1) / 2)), dim3(128), lds, s, tl, pa.tbase, reinterpret_cast<const double *>(tl.usamp), reinterpret_cast<const double *>(tl.osamp), reinterpret_cast<const double *>(V), pair_stride, ns, reinterpret_cast<double *>(partial), (double)scale));
+    else
+      TD_SAMPLE(T, stype, TD_GRID_BDIM(BL, BR, hipLaunchKernelGGL((k_vint<T, S, BL, BR>), dim3(grid), dim3(256), 0, s, tl, pa.tbase, reinterpret_cast<const S *>(tl.usamp), reinterpret_cast<const S *>(tl.osamp), V, pair_stride, ns, partial, (T)scale)));
   }
   TD_HIP(hipGetLastError());
   if (prof) prof->end(ST_VINT, s);
