@@ -261,7 +261,11 @@ int tddft_apply(tddft_handle *h, int32_t n_states, const double *Pp, const doubl
  * at 32 FP32 states) fails with TDDFT_E_INVALID and a message naming the bytes needed.
  * Every call on a GPU shares that GPU's array: calls that overlap on one GPU (other
  * threads, other handles, other streams) race.  Nothing in it needs to start at zero.
- * The handle's GPU must be current. */
+ * The handle's GPU must be current.  While the handle's stream (a non-default stream
+ * given at tddft_create) is being captured into a HIP graph, the call records its kernels
+ * (on that stream and the handle's second stream, joined back) and returns without
+ * waiting; every replay then applies the operator to what Pp and Pq hold at that time.
+ * Otherwise it returns after the work completes. */
 int tddft_apply_noalloc(tddft_handle *h, int32_t n_states, const double *Pp, const double *Pq,
                         double *fp, double *fq);
 int64_t tddft_apply_noalloc_limit(void);

@@ -252,7 +252,10 @@ int tddft_apply_noalloc(tddft_handle *hd, int32_t n, const double *Pp, const dou
       apply_sets<T>(h, n, X, nc, 0, n, F, nc, 0, n, true, false, base + xf);
       unpack<T>(h.nR, h.BU, h.BO, n, F, nc, 0, h.r_voff.p, h.r_shape.p, fp, h.nnzR, h.stream);
       unpack<T>(h.nR, h.BU, h.BO, n, F, nc, n, h.r_voff.p, h.r_shape.p, fq, h.nnzR, h.stream);
-      TD_HIP(hipStreamSynchronize(h.stream));
+      // under stream capture the kernels are recorded into the caller's graph: no wait
+      hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+      TD_HIP(hipStreamIsCapturing(h.stream, &cap));
+      if (cap == hipStreamCaptureStatusNone) TD_HIP(hipStreamSynchronize(h.stream));
     };
     if (h.precision == TDDFT_FP64) run(double{}); else run(float{});
     return TDDFT_OK;

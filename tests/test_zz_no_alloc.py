@@ -52,3 +52,39 @@ def test_noalloc_refuses_oversized_workspace():
     h.close()
     assert e.value.code == binding.TDDFT_E_INVALID and "limit" in str(e.value)
     assert binding.tddft_apply_noalloc_limit() == 256 << 20
+
+
+def test_noalloc_under_graph_capture(small_kt):
+    """tddft_apply_noalloc captured into a HIP graph on the handle's own stream: every replay
+    (new inputs copied into the captured buffers, eager work and synchronisation between
+    replays) equals tddft_apply on those inputs."""
+    import torch
+    s = small_kt
+    print("[noalloc] graph capture small_kt fp32 n=4", flush=True)
+    st = torch.cuda.Stream()
+    h = gpu_handle(s, precision="fp32", stream=st.cuda_stream)
+    n = 4
+    Pp = to_dev(sabi.dense_to_p(s, random_p(s, n, 91)))
+    Pq = to_dev(sabi.dense_to_p(s, random_p(s, n, 92)))
+    fp, fq = torch.empty_like(Pp), torch.empty_like(Pq)
+    torch.cuda.synchronize()
+    with torch.cuda.stream(st):
+        h.tddft_apply_noalloc(Pp, Pq, fp, fq)          # warm-up outside the capture
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g, stream=st):
+        h.tddft_apply_noalloc(Pp, Pq, fp, fq)
+    torch.cuda.synchronize()
+    for seed in (93, 95, 97):
+        Pp.copy_(to_dev(sabi.dense_to_p(s, random_p(s, n, seed))))
+        Pq.copy_(to_dev(sabi.dense_to_p(s, random_p(s, n, seed + 1))))
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        rp, rq = h.tddft_apply(Pp, Pq)                  # eager reference between replays
+        torch.cuda.synchronize()
+        assert np.array_equal(fp.cpu().numpy(), rp.cpu().numpy())
+        assert np.array_equal(fq.cpu().numpy(), rq.cpu().numpy())
+        print(f"[noalloc] replay with inputs {seed} equals the eager apply", flush=True)
+    del g
+    h.close()
