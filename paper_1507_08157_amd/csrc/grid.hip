@@ -793,7 +793,10 @@ __global__ __launch_bounds__(256) void k_vint_reduce(int64_t nblk, int ns, int E
   using TV = T __attribute__((ext_vector_type(V)));
   const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
-  const int64_t ob = (int64_t)blockIdx.x * (blockDim.x >> 6) + w;
+  // consecutive overlap blocks on one XCD: their contribution runs share 128-byte lines
+  // (runs of neighbouring blocks are neighbours in each tile's range), so a line fetched
+  // for one block serves its neighbour from that XCD's L2
+  const int64_t ob = (int64_t)xcd_block(blockIdx.x, gridDim.x) * (blockDim.x >> 6) + w;
   if (ob >= nblk) return;
   const int per = ns * E;
   const int lpc = per / V;
