@@ -22,8 +22,9 @@ namespace tddft {
 
 // ---------------------------------------------------------------------------------------
 // One thread per (output block, group of CW columns): every operand block pair is read once
-// for CW columns (the fixed block of A or B is shared, the column-set blocks are contiguous).
-template <class T, int BU, int BO, int CW>
+// for CW columns (the fixed block of A or B is shared, the column-set blocks are contiguous),
+// U pairs at a time.
+template <class T, int BU, int BO, int CW, int U>
 __global__ __launch_bounds__(256) void k_spmm_left(int64_t nout, int ncol,
                                                    const int64_t *__restrict__ ptr,
                                                    const int2 *__restrict__ pairs,
@@ -44,29 +45,49 @@ __global__ __launch_bounds__(256) void k_spmm_left(int64_t nout, int ncol,
 #pragma unroll
     for (int e = 0; e < E; ++e) acc[u][e] = T(0);
   const int64_t q0 = ptr[k], q1 = ptr[k + 1];
-  // the next pair's indices are requested with this pair's operand loads, so a pair costs
-  // one memory round trip instead of two dependent ones
-  int2 pr_next = q0 < q1 ? pairs[q0] : make_int2(0, 0);
-  for (int64_t q = q0; q < q1; ++q) {
-    const int2 pr = pr_next;
-    if (q + 1 < q1) pr_next = pairs[q + 1];
-    const T *a = A + (int64_t)pr.x * (BU * BU);
-    T av[BU * BU];
+  // pairs in batches of U: the operand loads of a batch (and the next batch's indices) are
+  // issued before its first FMA, so a batch costs one memory round trip; the FMAs still
+  // take the pairs one after another in list order (the sum's order depends on neither U
+  // nor CW).  Loads past the list's end re-read its last pair, and columns past the call's
+  // re-read its last column; neither enters a sum.
+  int2 prn[U];
+  if (q0 < q1) {
 #pragma unroll
-    for (int i = 0; i < BU * BU; ++i) av[i] = a[i];
-    const T *x = X + ((int64_t)pr.y * ldx + xc0 + m0) * E;
+    for (int u = 0; u < U; ++u) prn[u] = pairs[min(q0 + u, q1 - 1)];
+  }
+  for (int64_t qb = q0; qb < q1; qb += U) {
+    T av[U][BU * BU], xv[U][CW][E];
 #pragma unroll
-    for (int u = 0; u < CW; ++u) {
-      if (u < nm) {
-        T xv[E];
+    for (int u = 0; u < U; ++u) {
+      const T *a = A + (int64_t)prn[u].x * (BU * BU);
 #pragma unroll
-        for (int e = 0; e < E; ++e) xv[e] = x[u * E + e];
+      for (int i = 0; i < BU * BU; ++i) av[u][i] = a[i];
+      const T *x = X + ((int64_t)prn[u].y * ldx + xc0 + m0) * E;
 #pragma unroll
-        for (int r = 0; r < BU; ++r)
+      for (int w = 0; w < CW; ++w)
 #pragma unroll
-          for (int t = 0; t < BU; ++t)
+        for (int e = 0; e < E; ++e) xv[u][w][e] = x[min(w, nm - 1) * E + e];
+    }
+    if (qb + U < q1) {
 #pragma unroll
-            for (int c = 0; c < BO; ++c) acc[u][r * BO + c] += av[r * BU + t] * xv[t * BO + c];
+      for (int u = 0; u < U; ++u) prn[u] = pairs[min(qb + U + u, q1 - 1)];
+    }
+    // keeps the compiler from sinking the loads down to their first use
+    asm volatile("" ::: "memory");
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      if (qb + u < q1) {
+#pragma unroll
+        for (int w = 0; w < CW; ++w) {
+          if (w < nm) {
+#pragma unroll
+            for (int r = 0; r < BU; ++r)
+#pragma unroll
+              for (int t = 0; t < BU; ++t)
+#pragma unroll
+                for (int c = 0; c < BO; ++c) acc[w][r * BO + c] += av[u][r * BU + t] * xv[u][w][t * BO + c];
+          }
+        }
       }
     }
   }
@@ -81,7 +102,7 @@ __global__ __launch_bounds__(256) void k_spmm_left(int64_t nout, int ncol,
   }
 }
 
-template <class T, int BU, int BO, int CW>
+template <class T, int BU, int BO, int CW, int U>
 __global__ __launch_bounds__(256) void k_spmm_right(int64_t nout, int ncol,
                                                     const int64_t *__restrict__ ptr,
                                                     const int2 *__restrict__ pairs,
@@ -102,28 +123,45 @@ __global__ __launch_bounds__(256) void k_spmm_right(int64_t nout, int ncol,
 #pragma unroll
     for (int e = 0; e < E; ++e) acc[u][e] = T(0);
   const int64_t q0 = ptr[k], q1 = ptr[k + 1];
-  // next pair's indices requested with this pair's operand loads (one round trip per pair)
-  int2 pr_next = q0 < q1 ? pairs[q0] : make_int2(0, 0);
-  for (int64_t q = q0; q < q1; ++q) {
-    const int2 pr = pr_next;
-    if (q + 1 < q1) pr_next = pairs[q + 1];
-    const T *b = B + (int64_t)pr.y * (BO * BO);
-    T bv[BO * BO];
+  // pairs in batches of U, as in k_spmm_left
+  int2 prn[U];
+  if (q0 < q1) {
 #pragma unroll
-    for (int i = 0; i < BO * BO; ++i) bv[i] = b[i];
-    const T *x = X + ((int64_t)pr.x * ldx + xc0 + m0) * E;
+    for (int u = 0; u < U; ++u) prn[u] = pairs[min(q0 + u, q1 - 1)];
+  }
+  for (int64_t qb = q0; qb < q1; qb += U) {
+    T bv[U][BO * BO], xv[U][CW][E];
 #pragma unroll
-    for (int u = 0; u < CW; ++u) {
-      if (u < nm) {
-        T xv[E];
+    for (int u = 0; u < U; ++u) {
+      const T *b = B + (int64_t)prn[u].y * (BO * BO);
 #pragma unroll
-        for (int e = 0; e < E; ++e) xv[e] = x[u * E + e];
+      for (int i = 0; i < BO * BO; ++i) bv[u][i] = b[i];
+      const T *x = X + ((int64_t)prn[u].x * ldx + xc0 + m0) * E;
 #pragma unroll
-        for (int t = 0; t < BO; ++t)
+      for (int w = 0; w < CW; ++w)
 #pragma unroll
-          for (int c = 0; c < BO; ++c)
+        for (int e = 0; e < E; ++e) xv[u][w][e] = x[min(w, nm - 1) * E + e];
+    }
+    if (qb + U < q1) {
 #pragma unroll
-            for (int r = 0; r < BU; ++r) acc[u][r * BO + c] += xv[r * BO + t] * bv[t * BO + c];
+      for (int u = 0; u < U; ++u) prn[u] = pairs[min(qb + U + u, q1 - 1)];
+    }
+    // keeps the compiler from sinking the loads down to their first use
+    asm volatile("" ::: "memory");
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      if (qb + u < q1) {
+#pragma unroll
+        for (int w = 0; w < CW; ++w) {
+          if (w < nm) {
+#pragma unroll
+            for (int t = 0; t < BO; ++t)
+#pragma unroll
+              for (int c = 0; c < BO; ++c)
+#pragma unroll
+                for (int r = 0; r < BU; ++r) acc[w][r * BO + c] += xv[u][w][r * BO + t] * bv[u][t * BO + c];
+          }
+        }
       }
     }
   }
@@ -381,6 +419,24 @@ __global__ __launch_bounds__(64 * G::WMW * G::WNW) void k_gemm_blocks(int di, in
 
 static inline unsigned nblocks(int64_t n, int bs) { return (unsigned)((n + bs - 1) / bs); }
 
+// the sparse form's (columns per thread, pairs per batch) variants: (1, 1), (1, 2), (1, 4),
+// (2, 1), (2, 2), (4, 1)
+template <class F>
+static void spmm_variant(const DevPlan &pl, F &&launch) {
+  using I1 = std::integral_constant<int, 1>;
+  using I2 = std::integral_constant<int, 2>;
+  using I4 = std::integral_constant<int, 4>;
+  if (pl.cw == 4) launch(I4{}, I1{});
+  else if (pl.cw == 2) {
+    if (pl.pb >= 2) launch(I2{}, I2{});
+    else launch(I2{}, I1{});
+  } else {
+    if (pl.pb >= 4) launch(I1{}, I4{});
+    else if (pl.pb == 2) launch(I1{}, I2{});
+    else launch(I1{}, I1{});
+  }
+}
+
 template <class T>
 void spmm_left(const DevPlan &pl, int bu, int bo, const T *A, const T *X, int ldx, int xc0,
                T *C, int ldc, int cc0, int ncol, double alpha, bool acc, hipStream_t s) {
@@ -399,16 +455,13 @@ void spmm_left(const DevPlan &pl, int bu, int bo, const T *A, const T *X, int ld
     TD_HIP(hipGetLastError());
     return;
   }
-  // columns per thread from the plan (tuned at creation; the sum over pairs has the same
-  // order for every choice)
-  const int cw = pl.cw;
-  const int64_t n = pl.nout * ((ncol + cw - 1) / cw);
-  if (cw == 4)
-    TD_BDIM_DISPATCH(bu, bo, hipLaunchKernelGGL((k_spmm_left<T, BU, BO, 4>), dim3(nblocks(n, 256)), dim3(256), 0, s, pl.nout, ncol, pl.ptr.p, pl.pairs.p, A, X, ldx, xc0, C, ldc, cc0, alpha, acc ? 1 : 0));
-  else if (cw == 2)
-    TD_BDIM_DISPATCH(bu, bo, hipLaunchKernelGGL((k_spmm_left<T, BU, BO, 2>), dim3(nblocks(n, 256)), dim3(256), 0, s, pl.nout, ncol, pl.ptr.p, pl.pairs.p, A, X, ldx, xc0, C, ldc, cc0, alpha, acc ? 1 : 0));
-  else
-    TD_BDIM_DISPATCH(bu, bo, hipLaunchKernelGGL((k_spmm_left<T, BU, BO, 1>), dim3(nblocks(n, 256)), dim3(256), 0, s, pl.nout, ncol, pl.ptr.p, pl.pairs.p, A, X, ldx, xc0, C, ldc, cc0, alpha, acc ? 1 : 0));
+  // columns per thread and pairs per batch from the plan (tuned at creation; the sum over
+  // pairs has the same order for every choice)
+  const int64_t n = pl.nout * ((ncol + pl.cw - 1) / pl.cw);
+  auto launch = [&](auto cw, auto u) {
+    TD_BDIM_DISPATCH(bu, bo, hipLaunchKernelGGL((k_spmm_left<T, BU, BO, decltype(cw)::value, decltype(u)::value>), dim3(nblocks(n, 256)), dim3(256), 0, s, pl.nout, ncol, pl.ptr.p, pl.pairs.p, A, X, ldx, xc0, C, ldc, cc0, alpha, acc ? 1 : 0));
+  };
+  spmm_variant(pl, launch);
   TD_HIP(hipGetLastError());
 }
 
@@ -430,14 +483,11 @@ void spmm_right(const DevPlan &pl, int bu, int bo, const T *X, int ldx, int xc0,
     TD_HIP(hipGetLastError());
     return;
   }
-  const int cw = pl.cw;
-  const int64_t n = pl.nout * ((ncol + cw - 1) / cw);
-  if (cw == 4)
-    TD_BDIM_DISPATCH(bu, bo, hipLaunchKernelGGL((k_spmm_right<T, BU, BO, 4>), dim3(nblocks(n, 256)), dim3(256), 0, s, pl.nout, ncol, pl.ptr.p, pl.pairs.p, X, ldx, xc0, B, C, ldc, cc0, alpha, acc ? 1 : 0));
-  else if (cw == 2)
-    TD_BDIM_DISPATCH(bu, bo, hipLaunchKernelGGL((k_spmm_right<T, BU, BO, 2>), dim3(nblocks(n, 256)), dim3(256), 0, s, pl.nout, ncol, pl.ptr.p, pl.pairs.p, X, ldx, xc0, B, C, ldc, cc0, alpha, acc ? 1 : 0));
-  else
-    TD_BDIM_DISPATCH(bu, bo, hipLaunchKernelGGL((k_spmm_right<T, BU, BO, 1>), dim3(nblocks(n, 256)), dim3(256), 0, s, pl.nout, ncol, pl.ptr.p, pl.pairs.p, X, ldx, xc0, B, C, ldc, cc0, alpha, acc ? 1 : 0));
+  const int64_t n = pl.nout * ((ncol + pl.cw - 1) / pl.cw);
+  auto launch = [&](auto cw, auto u) {
+    TD_BDIM_DISPATCH(bu, bo, hipLaunchKernelGGL((k_spmm_right<T, BU, BO, decltype(cw)::value, decltype(u)::value>), dim3(nblocks(n, 256)), dim3(256), 0, s, pl.nout, ncol, pl.ptr.p, pl.pairs.p, X, ldx, xc0, B, C, ldc, cc0, alpha, acc ? 1 : 0));
+  };
+  spmm_variant(pl, launch);
   TD_HIP(hipGetLastError());
 }
 

@@ -147,7 +147,7 @@ void tune_typed(Handle &h) {
     h.tiles_uo.pbcast = choice[1];
   }
 
-  // ---- sparse products: columns per thread, per plan
+  // ---- sparse products: columns per thread and pairs per batch, per plan
   struct PlanRef {
     DevPlan *pl;
     bool left;
@@ -175,9 +175,11 @@ void tune_typed(Handle &h) {
     std::vector<int> choice;
     if (!cached(k.str(), choice)) {
       float best = 1e30f;
-      int pick = 1;
-      for (int cw : {1, 2, 4}) {
-        pl.cw = cw;
+      choice = {1, 1};
+      const int variants[][2] = {{1, 1}, {1, 2}, {1, 4}, {2, 1}, {2, 2}, {4, 1}};
+      for (const auto &v : variants) {
+        pl.cw = v[0];
+        pl.pb = v[1];
         const float ms = best_ms(s, h.ev0, h.ev1, 3, [&]() {
           if (r.left)
             spmm_left<T>(pl, h.BU, h.BO, r.op, A, nc, 0, B, nc, 0, nc, 1.0, false, s);
@@ -186,13 +188,13 @@ void tune_typed(Handle &h) {
         });
         if (ms < best) {
           best = ms;
-          pick = cw;
+          choice = {v[0], v[1]};
         }
       }
-      choice = {pick};
       remember(k.str(), choice);
     }
     pl.cw = choice[0];
+    pl.pb = choice[1];
   }
 
   // ---- dense (complete-pattern) products: output tile shape, per plan
