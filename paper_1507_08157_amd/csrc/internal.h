@@ -112,7 +112,7 @@ struct DevPlan {
   int64_t nout = 0, npairs = 0;
   int di = 0, dk = 0, dj = 0;    // complete patterns (see Plan)
   int cw = 1;                    // columns per thread of the sparse form (1, 2 or 4; tuned)
-  int pb = 4;                    // pairs per batch of the sparse form (1, 2 or 4; tuned)
+  int pb = 4;                    // pairs per batch of the sparse form (1, 2, 4 or 8; tuned)
   int tile = 0;                  // output tile shape of the dense form (0, 1 or 2; tuned)
   DevBuf<int64_t> ptr;
   DevBuf<int2> pairs;

@@ -420,18 +420,22 @@ __global__ __launch_bounds__(64 * G::WMW * G::WNW) void k_gemm_blocks(int di, in
 static inline unsigned nblocks(int64_t n, int bs) { return (unsigned)((n + bs - 1) / bs); }
 
 // the sparse form's (columns per thread, pairs per batch) variants: (1, 1), (1, 2), (1, 4),
-// (2, 1), (2, 2), (4, 1)
+// (1, 8), (2, 1), (2, 2), (2, 4), (4, 1), (4, 2)
 template <class F>
 static void spmm_variant(const DevPlan &pl, F &&launch) {
   using I1 = std::integral_constant<int, 1>;
   using I2 = std::integral_constant<int, 2>;
   using I4 = std::integral_constant<int, 4>;
-  if (pl.cw == 4) launch(I4{}, I1{});
-  else if (pl.cw == 2) {
-    if (pl.pb >= 2) launch(I2{}, I2{});
+  if (pl.cw == 4) {
+    if (pl.pb >= 2) launch(I4{}, I2{});
+    else launch(I4{}, I1{});
+  } else if (pl.cw == 2) {
+    if (pl.pb >= 4) launch(I2{}, I4{});
+    else if (pl.pb == 2) launch(I2{}, I2{});
     else launch(I2{}, I1{});
   } else {
-    if (pl.pb >= 4) launch(I1{}, I4{});
+    if (pl.pb >= 8) launch(I1{}, std::integral_constant<int, 8>{});
+    else if (pl.pb == 4) launch(I1{}, I4{});
     else if (pl.pb == 2) launch(I1{}, I2{});
     else launch(I1{}, I1{});
   }

@@ -6,7 +6,8 @@
 //     two-buffer form), per axis from the stage times of the five passes;
 //   * response density: tiles (waves) per workgroup, 2, 4 or 8, and P blocks in scalar
 //     registers or in vector registers shared by DPP row broadcasts;
-//   * sparse products: columns per thread, 1, 2 or 4, per product plan;
+//   * sparse products: columns per thread (1, 2 or 4) and operand pairs per memory round
+//     trip (1 to 8), per product plan, at the column count an application passes it;
 //   * dense (complete-pattern) MFMA products: output tile shape (three shapes with the same
 //     k-slab depth), per product plan.
 // No candidate changes an arithmetic operation or the order of any sum, so results are the
@@ -148,18 +149,21 @@ void tune_typed(Handle &h) {
   }
 
   // ---- sparse products: columns per thread and pairs per batch, per plan
+  // columns per trial: what an application of n states passes (the K-shift and the
+  // solver's products take the p and q sets together, the coupling sandwich the q set)
   struct PlanRef {
     DevPlan *pl;
     bool left;
     const T *op;
     int64_t out_blocks;
+    int cols;
   };
   const PlanRef plans[] = {
-      {&h.pT_left, true, h.KcHu.ptr<T>(), h.nR}, {&h.pT_right, false, h.HoKv.ptr<T>(), h.nR},
-      {&h.pSw1, true, h.Kc.ptr<T>(), h.nM2},     {&h.pSw2, false, h.Kv.ptr<T>(), h.nR},
-      {&h.pPi1, true, h.KcSu.ptr<T>(), h.nM3},   {&h.pPi2, false, h.SoKv.ptr<T>(), h.nR},
-      {&h.pPt1, true, h.KcSuT.ptr<T>(), h.nM5},  {&h.pPt2, false, h.SoKvT.ptr<T>(), h.nM},
-      {&h.pCov1, true, h.Su.ptr<T>(), h.nM4},    {&h.pCov2, false, h.So.ptr<T>(), h.nR}};
+      {&h.pT_left, true, h.KcHu.ptr<T>(), h.nR, nc}, {&h.pT_right, false, h.HoKv.ptr<T>(), h.nR, nc},
+      {&h.pSw1, true, h.Kc.ptr<T>(), h.nM2, n},      {&h.pSw2, false, h.Kv.ptr<T>(), h.nR, n},
+      {&h.pPi1, true, h.KcSu.ptr<T>(), h.nM3, nc},   {&h.pPi2, false, h.SoKv.ptr<T>(), h.nR, nc},
+      {&h.pPt1, true, h.KcSuT.ptr<T>(), h.nM5, nc},  {&h.pPt2, false, h.SoKvT.ptr<T>(), h.nM, nc},
+      {&h.pCov1, true, h.Su.ptr<T>(), h.nM4, nc},    {&h.pCov2, false, h.So.ptr<T>(), h.nR, nc}};
   // operands: a column set that covers every input block index of these plans
   const int64_t maxblk = std::max({h.nR, h.nM, h.nM2, h.nM3, h.nM4, h.nM5, h.nO});
   const size_t big = (size_t)maxblk * nc * h.E;
@@ -171,20 +175,20 @@ void tune_typed(Handle &h) {
     if (pl.nout == 0 || pl.di > 0) continue;   // empty, or the dense MFMA form
     std::ostringstream k;
     k << "spmm " << prec << " " << (r.left ? "L " : "R ") << h.BU << "x" << h.BO << " "
-      << pl.nout << " " << pl.npairs;
+      << pl.nout << " " << pl.npairs << " " << r.cols;
     std::vector<int> choice;
     if (!cached(k.str(), choice)) {
       float best = 1e30f;
       choice = {1, 1};
-      const int variants[][2] = {{1, 1}, {1, 2}, {1, 4}, {2, 1}, {2, 2}, {4, 1}};
+      const int variants[][2] = {{1, 1}, {1, 2}, {1, 4}, {1, 8}, {2, 1}, {2, 2}, {2, 4}, {4, 1}, {4, 2}};
       for (const auto &v : variants) {
         pl.cw = v[0];
         pl.pb = v[1];
         const float ms = best_ms(s, h.ev0, h.ev1, 3, [&]() {
           if (r.left)
-            spmm_left<T>(pl, h.BU, h.BO, r.op, A, nc, 0, B, nc, 0, nc, 1.0, false, s);
+            spmm_left<T>(pl, h.BU, h.BO, r.op, A, r.cols, 0, B, r.cols, 0, r.cols, 1.0, false, s);
           else
-            spmm_right<T>(pl, h.BU, h.BO, A, nc, 0, r.op, B, nc, 0, nc, 1.0, false, s);
+            spmm_right<T>(pl, h.BU, h.BO, A, r.cols, 0, r.op, B, r.cols, 0, r.cols, 1.0, false, s);
         });
         if (ms < best) {
           best = ms;
@@ -203,7 +207,7 @@ void tune_typed(Handle &h) {
     if (pl.nout == 0 || pl.di == 0) continue;   // empty, or the sparse form (tuned above)
     std::ostringstream k;
     k << "gemm " << prec << " " << (r.left ? "L " : "R ") << h.BU << "x" << h.BO << " "
-      << pl.di << " " << pl.dk << " " << pl.dj;
+      << pl.di << " " << pl.dk << " " << pl.dj << " " << r.cols;
     std::vector<int> choice;
     if (!cached(k.str(), choice)) {
       float best = 1e30f;
@@ -212,9 +216,9 @@ void tune_typed(Handle &h) {
         pl.tile = tile;
         const float ms = best_ms(s, h.ev0, h.ev1, 3, [&]() {
           if (r.left)
-            spmm_left<T>(pl, h.BU, h.BO, r.op, A, nc, 0, B, nc, 0, nc, 1.0, false, s);
+            spmm_left<T>(pl, h.BU, h.BO, r.op, A, r.cols, 0, B, r.cols, 0, r.cols, 1.0, false, s);
           else
-            spmm_right<T>(pl, h.BU, h.BO, A, nc, 0, r.op, B, nc, 0, nc, 1.0, false, s);
+            spmm_right<T>(pl, h.BU, h.BO, A, r.cols, 0, r.op, B, r.cols, 0, r.cols, 1.0, false, s);
         });
         if (ms < best) {
           best = ms;
