@@ -211,6 +211,8 @@ typedef struct {
                                 shared by DPP row broadcasts, 0 = P in scalar registers   */
   int32_t kshift_tile[2];    /* K-shift products in the dense form: output tile shape
                                 (tddft_options.gemm_tile numbering; 0 for sparse forms)   */
+  int32_t kshift_pairs[2];   /* K-shift products in the sparse form: operand block pairs
+                                loaded per memory round trip (1, 2, 4 or 8)               */
 } tddft_info;
 
 typedef struct tddft_handle tddft_handle;

@@ -72,7 +72,8 @@ class tddft_info(C.Structure):
                 ("samples_u_nz", C.c_int64), ("samples_o_nz", C.c_int64),
                 ("pair_points_nz", C.c_int64), ("fft_threads", C.c_int32 * 3),
                 ("density_waves", C.c_int32), ("kshift_cw", C.c_int32 * 2),
-                ("density_pbcast", C.c_int32), ("kshift_tile", C.c_int32 * 2)]
+                ("density_pbcast", C.c_int32), ("kshift_tile", C.c_int32 * 2),
+                ("kshift_pairs", C.c_int32 * 2)]
 
 
 class tddft_stats(C.Structure):
@@ -373,6 +374,7 @@ class Handle:
         d["fft_threads"] = list(inf.fft_threads)
         d["kshift_cw"] = list(inf.kshift_cw)
         d["kshift_tile"] = list(inf.kshift_tile)
+        d["kshift_pairs"] = list(inf.kshift_pairs)
         return d
 
     def tddft_profile(self, enable: bool):

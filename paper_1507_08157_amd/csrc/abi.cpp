@@ -181,6 +181,8 @@ int tddft_get_info(const tddft_handle *hd, tddft_info *o) {
   o->density_pbcast = h.tiles_uo.pbcast;
   o->kshift_tile[0] = h.pT_left.tile;
   o->kshift_tile[1] = h.pT_right.tile;
+  o->kshift_pairs[0] = h.pT_left.pb;
+  o->kshift_pairs[1] = h.pT_right.pb;
   return TDDFT_OK;
 }
 

@@ -188,6 +188,7 @@ def test_autotuned_launch_shapes_give_identical_results(name, precision, request
     info = out[1][2]
     assert all(t in (0, 256, 512, 1024) for t in info["fft_threads"])
     assert info["density_waves"] in (2, 4, 8) and all(c in (1, 2, 4) for c in info["kshift_cw"])
+    assert all(p in (1, 2, 4, 8) for p in info["kshift_pairs"])
     assert info["density_pbcast"] in (0, 1)
     assert all(t in (0, 1, 2) for t in info["kshift_tile"])
 
