@@ -143,8 +143,9 @@ typedef struct {
                                 are identical either way */
   int32_t  autotune;         /* 1 (default): tddft_create times the candidate launch shapes
                                 of the FFT passes (threads per workgroup), the response
-                                density (tiles per workgroup) and the sparse products
-                                (columns per thread) on the system's own data and keeps
+                                density (tiles per workgroup), the sparse products
+                                (columns per thread, pairs per round trip) and the dense
+                                products (output tile) on the system's own data and keeps
                                 the fastest; choices are remembered per process for
                                 systems of the same shapes.  No choice changes a result.
                                 0: fixed defaults */
@@ -157,6 +158,14 @@ typedef struct {
                                 (complete-pattern) MFMA product (left: 128x64, 64x64,
                                 64x128; right: 64x64, 128x64, 64x128 rows x columns).  All
                                 shapes share the k-slab depth: results are identical */
+  int32_t  sparse_cw;        /* -1 (default, with sparse_pairs -1): the tuner's choice
+                                (1 column, 4 pairs when autotune is 0).  Otherwise every
+                                sparse-pattern product takes sparse_cw columns per thread
+                                and sparse_pairs operand block pairs per memory round
+                                trip, one of (1, 1), (1, 2), (1, 4), (1, 8), (2, 1),
+                                (2, 2), (2, 4), (4, 1), (4, 2); both -1 or neither.  The
+                                pairs are summed in the same order: results are identical */
+  int32_t  sparse_pairs;
 } tddft_options;
 
 /* Per-solve statistics (host memory, caller-owned).  The log arrays are optional. */
@@ -219,7 +228,8 @@ typedef struct tddft_handle tddft_handle;
 
 /* Defaults: FP64, ALDA exchange, rho_floor 1e-10, coupling 1, KSDIFF_CG, eps_tol 1e-4,
  * tol_omega 1e-7, max_iter 300, max_inner 50, refresh 10, restart 20, seed 0, eps_loose 0,
- * tda 0, truncate_p 0, graphs 1, autotune 1, density_pbcast -1, gemm_tile -1. */
+ * tda 0, truncate_p 0, graphs 1, autotune 1, density_pbcast -1, gemm_tile -1,
+ * sparse_cw -1, sparse_pairs -1. */
 void tddft_default_options(tddft_options *opts);
 
 /* Build a handle for one system (Sec. III.A: sparse K^v, K^c, S and H, the cutoff

@@ -55,7 +55,8 @@ class tddft_options(C.Structure):
                 ("seed", C.c_uint64), ("model", C.c_void_p), ("model_bytes", C.c_int64),
                 ("stream", C.c_void_p), ("eps_loose", C.c_double), ("tda", C.c_int32),
                 ("truncate_p", C.c_int32), ("graphs", C.c_int32), ("autotune", C.c_int32),
-                ("density_pbcast", C.c_int32), ("gemm_tile", C.c_int32)]
+                ("density_pbcast", C.c_int32), ("gemm_tile", C.c_int32),
+                ("sparse_cw", C.c_int32), ("sparse_pairs", C.c_int32)]
 
 
 class tddft_info(C.Structure):

@@ -83,6 +83,8 @@ void tddft_default_options(tddft_options *o) {
   o->autotune = 1;
   o->density_pbcast = -1;
   o->gemm_tile = -1;
+  o->sparse_cw = -1;
+  o->sparse_pairs = -1;
 }
 
 int tddft_abi_version(void) { return TDDFT_ABI_VERSION; }

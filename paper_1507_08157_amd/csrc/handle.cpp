@@ -315,6 +315,14 @@ void create_handle(Handle &h, const tddft_system &sys, const tddft_options &o) {
   TD_REQUIRE(o.precision >= TDDFT_FP64 && o.precision <= TDDFT_BF16_GRID, "unknown precision mode");
   TD_REQUIRE(o.density_pbcast >= -1 && o.density_pbcast <= 1, "density_pbcast must be -1, 0 or 1");
   TD_REQUIRE(o.gemm_tile >= -1 && o.gemm_tile <= 2, "gemm_tile must be -1, 0, 1 or 2");
+  {
+    const int cw = o.sparse_cw, pb = o.sparse_pairs;
+    const bool tuned = cw == -1 && pb == -1;
+    const bool known = (cw == 1 && (pb == 1 || pb == 2 || pb == 4 || pb == 8)) ||
+                       (cw == 2 && (pb == 1 || pb == 2 || pb == 4)) || (cw == 4 && (pb == 1 || pb == 2));
+    TD_REQUIRE(tuned || known,
+               "sparse_cw/sparse_pairs must both be -1 or one of (1,1) (1,2) (1,4) (1,8) (2,1) (2,2) (2,4) (4,1) (4,2)");
+  }
   TD_REQUIRE(o.xc >= TDDFT_XC_ALDA_X && o.xc <= TDDFT_HXC_NONE, "unknown coupling kernel");
   h.stype = o.precision == TDDFT_FP64 ? SAMPLE_F64 : (o.precision == TDDFT_FP32 ? SAMPLE_F32 : SAMPLE_BF16);
   h.stream = (hipStream_t)o.stream;
@@ -606,6 +614,12 @@ void create_handle(Handle &h, const tddft_system &sys, const tddft_options &o) {
     for (DevPlan *pl : {&h.pT_left, &h.pT_right, &h.pSw1, &h.pSw2, &h.pPi1, &h.pPi2, &h.pPt1,
                         &h.pPt2, &h.pCov1, &h.pCov2})
       pl->tile = o.gemm_tile;
+  if (o.sparse_cw > 0)
+    for (DevPlan *pl : {&h.pT_left, &h.pT_right, &h.pSw1, &h.pSw2, &h.pPi1, &h.pPi2, &h.pPt1,
+                        &h.pPt2, &h.pCov1, &h.pCov2}) {
+      pl->cw = o.sparse_cw;
+      pl->pb = o.sparse_pairs;
+    }
   h.setup_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
 }
 

@@ -40,6 +40,8 @@ def test_default_options():
     assert o.precond == binding.TDDFT_PC_KSDIFF_CG
     assert o.eps_tol == 1e-4 and o.tol_omega == 1e-7 and o.max_iter == 300
     assert o.rho_floor == 1e-10 and o.coupling_scale == 1.0 and o.refresh == 10
+    assert o.density_pbcast == -1 and o.gemm_tile == -1
+    assert o.sparse_cw == -1 and o.sparse_pairs == -1
 
 
 def _c_layout(struct, fields):
@@ -165,3 +167,12 @@ def test_rejects_uncovered_block_shape(arrays):
     with pytest.raises(binding.TddftError) as e:
         binding.tddft_create(a)
     assert e.value.code == binding.TDDFT_E_INVALID
+
+
+@pytest.mark.parametrize("cw,pb", [(3, 1), (1, -1), (-1, 4), (4, 4), (2, 8), (1, 3)])
+def test_rejects_unknown_sparse_variant(arrays, cw, pb):
+    """Forced sparse-product variants must be one of the built (columns, pairs) forms; the
+    check runs before any device call."""
+    with pytest.raises(binding.TddftError) as e:
+        binding.tddft_create(arrays, sparse_cw=cw, sparse_pairs=pb)
+    assert e.value.code == binding.TDDFT_E_INVALID and "sparse_cw" in str(e.value)

@@ -246,3 +246,34 @@ def test_dense_product_tiles_are_identical(small_dense, precision):
     for tile in (1, 2):
         for a, b in zip(out[0], out[tile]):
             assert np.array_equal(a, b)
+
+
+SPARSE_VARIANTS = [(1, 1), (1, 2), (1, 4), (1, 8), (2, 1), (2, 2), (2, 4), (4, 1), (4, 2)]
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_sparse_product_variants_are_identical(small_kt, precision):
+    """Every (columns per thread, operand pairs per round trip) form of the sparse-pattern
+    products sums the pairs in list order: applies and a 15-iteration truncated solve are
+    bit-identical across the forms."""
+    s = small_kt
+    print(f"[apply] sparse product variants {precision}", flush=True)
+    Pp = to_dev(sabi.dense_to_p(s, random_p(s, 4, 83)))
+    Pq = to_dev(sabi.dense_to_p(s, random_p(s, 4, 84)))
+    from paper_1507_08157_amd import binding
+    out = {}
+    for cw, pb in SPARSE_VARIANTS:
+        h = gpu_handle(s, precision=precision, autotune=0, sparse_cw=cw, sparse_pairs=pb)
+        info = h.tddft_get_info()
+        assert info["kshift_cw"] == [cw, cw] and info["kshift_pairs"] == [pb, pb]
+        fp, fq = h.tddft_apply(Pp, Pq)
+        L0 = to_dev(sabi.dense_to_p(s, s.guess(4)))
+        o = binding.tddft_default_options(precision=precision, truncate_p=int(s.cfg.mask_p),
+                                          max_iter=15, tol_omega=1e-12)
+        w, rc, st = h.tddft_pcg_solve(4, o, L0.clone(), L0.clone())
+        out[(cw, pb)] = (fp.cpu().numpy(), fq.cpu().numpy(), np.asarray(w))
+        h.close()
+    assert np.max(np.abs(out[(1, 1)][1])) > 0
+    for v in SPARSE_VARIANTS[1:]:
+        for a, b in zip(out[(1, 1)], out[v]):
+            assert np.array_equal(a, b), v
