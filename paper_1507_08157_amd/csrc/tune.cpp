@@ -7,7 +7,7 @@
 //   * response density: tiles (waves) per workgroup, 2, 4 or 8, and P blocks in scalar
 //     registers or in vector registers shared by DPP row broadcasts;
 //   * sparse products: columns per thread (1, 2 or 4) and operand pairs per memory round
-//     trip (1 to 8), per product plan, at the column count an application passes it;
+//     trip (1 to 8), per product plan, at the column count a 4-state application passes it;
 //   * dense (complete-pattern) MFMA products: output tile shape (three shapes with the same
 //     k-slab depth), per product plan.
 // No candidate changes an arithmetic operation or the order of any sum, so results are the
@@ -149,7 +149,7 @@ void tune_typed(Handle &h) {
   }
 
   // ---- sparse products: columns per thread and pairs per batch, per plan
-  // columns per trial: what an application of n states passes (the K-shift and the
+  // columns per trial: what an application of n = 4 states passes (the K-shift and the
   // solver's products take the p and q sets together, the coupling sandwich the q set)
   struct PlanRef {
     DevPlan *pl;
