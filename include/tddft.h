@@ -221,7 +221,8 @@ typedef struct {
   int32_t kshift_tile[2];    /* K-shift products in the dense form: output tile shape
                                 (tddft_options.gemm_tile numbering; 0 for sparse forms)   */
   int32_t kshift_pairs[2];   /* K-shift products in the sparse form: operand block pairs
-                                loaded per memory round trip (1, 2, 4 or 8)               */
+                                loaded per memory round trip (1, 2, 4 or 8; the dense
+                                form does not use it, like kshift_cw)                    */
 } tddft_info;
 
 typedef struct tddft_handle tddft_handle;
